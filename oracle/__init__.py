@@ -1,0 +1,638 @@
+"""Plain, slow FP64 CPU oracle for the H-matrix hot path.
+
+TEST INFRASTRUCTURE.  Only the tests, ``__graft_entry__.smoke()`` and the CPU
+baseline leg of ``bench.py`` may import this package.  It shares no code with
+the library (``paper_1706_09384_amd``) and never imports it.
+
+Contents, each following the paper (arXiv 1706.09384):
+
+* ``green_block`` / ``dense`` / ``matvec_rows`` -- the Green's tensors U and T
+  (Section 1, eqs. elasto_U / elasto_T) and the dense system of eq. syst_a,
+  evaluated in C (``green.c``) in FP64.
+* ``lu_solve`` -- dense LU solve of eq. syst_a (the O(N^3) direct solution of
+  Section 1), via LAPACK.
+* ``cluster_tree`` / ``block_tree`` -- geometric bisection clustering
+  (Section 2.1) and the block partition with the box admissibility condition
+  (Section 6.1, eq. admissibility_cond_bis).
+* ``vector_aca`` -- partially pivoted ACA (the six steps of Section 2.2) with
+  the rank-3 vector update and largest-sigma_3 pivot of Section 2.3, and the
+  stagnation stopping test eq. stop_part.
+* ``recompress`` -- QR of both factors then a truncated SVD of R_U R_V^*
+  (Section 3.2, recompression paragraph).
+* ``hmatvec`` -- the leaf-level H-matrix-vector product of Section 3.1.
+* ``gmres`` -- a textbook restarted GMRES on an explicit operator.
+* ``mlp_*`` -- FP64 reference of the 6-64-64-1 rank-predictor network.
+
+Readings of the paper where it is silent or ambiguous are listed in the
+module-level docstrings of each function and in the design notes.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+KERNEL_U = 0
+KERNEL_T = 1
+DENSE = 0
+LOWRANK = 1
+
+
+def _lib():
+    global _LIB
+    if _LIB is None:
+        path = os.path.join(_HERE, "liboracle.so")
+        if not os.path.exists(path):
+            from . import build as _b
+            _b.build()
+        lib = ctypes.CDLL(path)
+        d, i64, i32 = ctypes.c_double, ctypes.c_int64, ctypes.c_int
+        p = ctypes.c_void_p
+        lib.oracle_green_block.argtypes = [i32, p, p, p, d, d, d, d, p]
+        lib.oracle_green_block.restype = i32
+        lib.oracle_radial.argtypes = [d, d, p]
+        lib.oracle_radial_branch.argtypes = [d, d, i32, p]
+        lib.oracle_dense.argtypes = [i32, i64, p, i64, p, p, i32, d, d, d, d, d, d, p]
+        lib.oracle_dense.restype = i64
+        lib.oracle_matvec_rows.argtypes = [i32, i64, p, i64, p, p, i32, d, d, d, d, d, d, i64, p,
+                                           i64, p, p]
+        lib.oracle_matvec_rows.restype = i64
+        lib.oracle_num_threads.restype = i32
+        _LIB = lib
+    return _LIB
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _f64(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+
+
+def num_threads() -> int:
+    return int(_lib().oracle_num_threads())
+
+
+# --------------------------------------------------------------------------
+# Green's tensors (Section 1, eqs. elasto_U, elasto_T; Section 5.3)
+# --------------------------------------------------------------------------
+
+def radial(a: float, q: float, branch: str = "auto") -> np.ndarray:
+    """Radial coefficient functions {A, B, aA', aB'} of the U/T closed forms."""
+    out = np.zeros(4, dtype=np.complex128)
+    if branch == "auto":
+        _lib().oracle_radial(float(a), float(q), _ptr(out))
+    else:
+        _lib().oracle_radial_branch(float(a), float(q), 1 if branch == "series" else 0, _ptr(out))
+    return out
+
+
+def green_block(kind, x, y, n=None, omega=1.0, lam=2.0, mu=1.0, rho=1.0) -> np.ndarray:
+    """3x3 complex block U(x, y) (kind 0) or T(x, y) with normal n at y (kind 1)."""
+    out = np.zeros(9, dtype=np.complex128)
+    xx, yy = _f64(x), _f64(y)
+    nn = _f64(n) if n is not None else np.zeros(3)
+    rc = _lib().oracle_green_block(int(kind), _ptr(xx), _ptr(yy), _ptr(nn), float(omega),
+                                   float(lam), float(mu), float(rho), _ptr(out))
+    if rc != 0:
+        raise ZeroDivisionError("kernel evaluated at coincident points")
+    return out.reshape(3, 3)
+
+
+@dataclass
+class Problem:
+    """The system of eq. syst_a: kernel, clouds and material parameters."""
+    kind: int
+    X: np.ndarray
+    Y: np.ndarray
+    N: np.ndarray | None
+    omega: float
+    lam: float = 2.0
+    mu: float = 1.0
+    rho: float = 1.0
+    same: bool = True
+    self_re: float = 0.0
+    self_im: float = 0.0
+
+    @staticmethod
+    def from_workload(w, X=None, N=None):
+        if X is None:
+            X, N = w.points()
+        return Problem(w.kernel, X, X, N, w.omega, w.lam, w.mu, w.rho, True, w.self_re, w.self_im)
+
+    def _args(self):
+        X, Y = _f64(self.X), _f64(self.Y)
+        N = _f64(self.N) if self.kind == KERNEL_T else None
+        return X, Y, N
+
+
+def dense(pb: Problem) -> np.ndarray:
+    """Dense complex128 matrix of eq. syst_a, shape (3 nx, 3 ny)."""
+    X, Y, N = pb._args()
+    nx, ny = X.shape[0], Y.shape[0]
+    out = np.empty((3 * nx, 3 * ny), dtype=np.complex128)
+    bad = _lib().oracle_dense(int(pb.kind), nx, _ptr(X), ny, _ptr(Y), _ptr(N), int(pb.same),
+                              pb.omega, pb.lam, pb.mu, pb.rho, pb.self_re, pb.self_im, _ptr(out))
+    if bad:
+        raise ZeroDivisionError(f"{bad} coincident point pairs")
+    return out
+
+
+def matvec_rows(pb: Problem, b: np.ndarray, rows=None) -> np.ndarray:
+    """Rows of A b for the given row points (all if None), never storing A.
+
+    b has shape (3 ny, nrhs) (or (3 ny,)); the result has shape
+    (3 len(rows), nrhs) (or 1-d).
+    """
+    X, Y, N = pb._args()
+    nx, ny = X.shape[0], Y.shape[0]
+    vec = b.ndim == 1
+    bb = np.ascontiguousarray(b.reshape(3 * ny, -1), dtype=np.complex128)
+    nrhs = bb.shape[1]
+    rows = np.arange(nx, dtype=np.int64) if rows is None else np.ascontiguousarray(rows, np.int64)
+    out = np.empty((3 * rows.size, nrhs), dtype=np.complex128)
+    bad = _lib().oracle_matvec_rows(int(pb.kind), nx, _ptr(X), ny, _ptr(Y), _ptr(N), int(pb.same),
+                                    pb.omega, pb.lam, pb.mu, pb.rho, pb.self_re, pb.self_im,
+                                    rows.size, _ptr(rows), nrhs, _ptr(bb), _ptr(out))
+    if bad:
+        raise ZeroDivisionError(f"{bad} coincident point pairs")
+    return out[:, 0] if vec else out
+
+
+def lu_solve(A: np.ndarray, b: np.ndarray):
+    """Dense LU solve with partial pivoting; returns (x, rcond estimate)."""
+    import scipy.linalg as sla
+    lu, piv = sla.lu_factor(A, check_finite=False)
+    x = sla.lu_solve((lu, piv), b, check_finite=False)
+    anorm = np.linalg.norm(A, 1)
+    rcond, info = sla.lapack.zgecon(lu, anorm, norm="1")
+    return x, float(rcond)
+
+
+# --------------------------------------------------------------------------
+# Cluster tree and block partition (Section 2.1, Section 6.1)
+# --------------------------------------------------------------------------
+
+@dataclass
+class ClusterTree:
+    perm: np.ndarray      # int64[n]: cluster position -> original point index
+    begin: np.ndarray     # int64[nodes]
+    end: np.ndarray
+    left: np.ndarray      # child node ids, -1 for leaves
+    right: np.ndarray
+    depth: np.ndarray
+    lo: np.ndarray        # (nodes, 3) tight bounding box
+    hi: np.ndarray
+
+    @property
+    def n_nodes(self):
+        return self.begin.size
+
+    def is_leaf(self, t):
+        return self.left[t] < 0
+
+    def levels(self):
+        return int(self.depth.max()) + 1
+
+
+def cluster_tree(P: np.ndarray, leaf: int) -> ClusterTree:
+    """Geometric bisection of a point cloud (Section 2.1, clustering paragraph).
+
+    Reading of the splitting rule (the paper fixes only "bisect the enclosing
+    box along its largest dimension, stop at a minimum size"):
+    tight FP64 box per node; a node with at most ``leaf`` points is a leaf;
+    the split axis is the largest box extent (lowest axis on ties); a zero
+    extent makes a leaf; the split value is (lo + hi) * 0.5 on that axis; the
+    left child takes the points with coordinate < split value, the right child
+    the rest, both keeping their incoming order; if either side is empty the
+    node is a leaf.  Nodes are numbered in pre-order, left before right.
+    """
+    P = np.asarray(P, dtype=np.float64)
+    n = P.shape[0]
+    perm = np.arange(n, dtype=np.int64)
+    begin, end, left, right, depth, lo, hi = [], [], [], [], [], [], []
+
+    def rec(b, e, d):
+        idx = perm[b:e]
+        pts = P[idx]
+        node = len(begin)
+        begin.append(b); end.append(e); left.append(-1); right.append(-1); depth.append(d)
+        l3, h3 = pts.min(axis=0), pts.max(axis=0)
+        lo.append(l3); hi.append(h3)
+        if e - b <= leaf:
+            return node
+        ext = h3 - l3
+        ax = int(np.argmax(ext))          # first maximum: lowest axis on ties
+        if ext[ax] == 0.0:
+            return node
+        mid = (l3[ax] + h3[ax]) * 0.5
+        mask = pts[:, ax] < mid
+        nl = int(mask.sum())
+        if nl == 0 or nl == e - b:
+            return node
+        perm[b:e] = np.concatenate([idx[mask], idx[~mask]])
+        lc = rec(b, b + nl, d + 1)
+        rc = rec(b + nl, e, d + 1)
+        left[node] = lc
+        right[node] = rc
+        return node
+
+    rec(0, n, 0)
+    return ClusterTree(perm, np.array(begin, np.int64), np.array(end, np.int64),
+                       np.array(left, np.int64), np.array(right, np.int64),
+                       np.array(depth, np.int64), np.array(lo), np.array(hi))
+
+
+def admissible(tx: ClusterTree, t: int, ty: ClusterTree, s: int, eta: float) -> bool:
+    """Box admissibility, eq. admissibility_cond_bis, in squared form.
+
+    Reading: the printed box distance omits positive parts; here
+    dist2 = sum_a [max(0, loY_a - hiX_a)^2 + max(0, loX_a - hiY_a)^2] and
+    diam2 = sum_a (hi_a - lo_a)^2, summed over a = 0, 1, 2 in that order;
+    admissible iff min(diam2X, diam2Y) < (eta*eta) * dist2 (strict).
+    """
+    lx, hx, ly, hy = tx.lo[t], tx.hi[t], ty.lo[s], ty.hi[s]
+    dx = [float(hx[a]) - float(lx[a]) for a in range(3)]
+    dy = [float(hy[a]) - float(ly[a]) for a in range(3)]
+    diam2x = dx[0] * dx[0] + dx[1] * dx[1] + dx[2] * dx[2]
+    diam2y = dy[0] * dy[0] + dy[1] * dy[1] + dy[2] * dy[2]
+    g = []
+    for a in range(3):
+        u = max(0.0, float(ly[a]) - float(hx[a]))
+        v = max(0.0, float(lx[a]) - float(hy[a]))
+        g.append(u * u + v * v)
+    dist2 = g[0] + g[1] + g[2]
+    return min(diam2x, diam2y) < (eta * eta) * dist2
+
+
+def block_tree(tx: ClusterTree, ty: ClusterTree, eta: float):
+    """Partition P of the block cluster tree (Section 2.1, subdivision paragraph).
+
+    Reading of the recursion: an admissible pair is a low-rank leaf; a pair
+    of two leaves is a dense leaf; if exactly one side is a leaf only the
+    other side is split; otherwise the 4 children pairs are visited with the
+    row child in the outer loop; depth-first.  Returns an (nb, 3) int64 array
+    of (row node, column node, kind) with kind 0 = dense, 1 = low-rank.
+    """
+    out = []
+
+    def rec(t, s):
+        if admissible(tx, t, ty, s, eta):
+            out.append((t, s, LOWRANK)); return
+        tl, sl = tx.is_leaf(t), ty.is_leaf(s)
+        if tl and sl:
+            out.append((t, s, DENSE)); return
+        if tl:
+            rec(t, int(ty.left[s])); rec(t, int(ty.right[s]))
+        elif sl:
+            rec(int(tx.left[t]), s); rec(int(tx.right[t]), s)
+        else:
+            for tc in (int(tx.left[t]), int(tx.right[t])):
+                for sc in (int(ty.left[s]), int(ty.right[s])):
+                    rec(tc, sc)
+
+    rec(0, 0)
+    return np.array(out, dtype=np.int64).reshape(-1, 3)
+
+
+def sparsity_constant(blocks: np.ndarray, nx_nodes: int, ny_nodes: int) -> int:
+    """C_sp of Section 2.1: max number of partition blocks per row or column cluster."""
+    cr = np.bincount(blocks[:, 0], minlength=nx_nodes)
+    cc = np.bincount(blocks[:, 1], minlength=ny_nodes)
+    return int(max(cr.max(), cc.max()))
+
+
+# --------------------------------------------------------------------------
+# Vector ACA (Sections 2.2 and 2.3) and recompression (Section 3.2)
+# --------------------------------------------------------------------------
+
+@dataclass
+class ACAResult:
+    U: np.ndarray
+    V: np.ndarray
+    rank: int
+    steps: int
+    row_pivots: list
+    col_pivots: list
+    fallbacks: int
+    norm2: float          # recursive ||B_k||_F^2
+    converged: bool
+
+
+def _sv3(blocks):
+    """Singular values (descending) of a stack of 3x3 complex blocks."""
+    return np.linalg.svd(blocks, compute_uv=False)
+
+
+def vector_aca(A: np.ndarray, eps: float, tau_piv: float = 1e-8, max_rank=None) -> ACAResult:
+    """Partially pivoted vector ACA on an explicit 3m x 3n block.
+
+    Follows the six steps of Section 2.2 with the vector variant of Section
+    2.3: each step adds a rank-3 term built on the 3x3 pivot block with the
+    largest smallest singular value sigma_3.
+
+    Readings (the paper leaves these open):
+    * the first row pivot is the block's first point;
+    * pivots already used are excluded; ties go to the smallest index;
+    * step 4 (next row) uses the residual column before the update, step 5
+      uses the current row pivot;
+    * a residual row that is zero on all unused columns marks that row used
+      and moves to the next unused row without adding a term;
+    * if the largest sigma_3 over the candidates is <= tau_piv times their
+      largest Frobenius norm (all candidate blocks numerically singular, as
+      for coplanar T blocks), the candidate with the largest Frobenius norm
+      is taken and the update uses the truncated pseudo-inverse of the pivot
+      keeping singular values > tau_piv * sigma_1, giving a rank p < 3 term;
+    * stopping test eq. stop_part for the rank-3 term:
+      ||U_k V_k^*||_F <= eps ||B_k||_F, with the Frobenius norms from the
+      recurrences ||U_k V_k^*||_F^2 = tr((U_k^* U_k)(V_k^* V_k)) and
+      ||B_k||^2 = ||B_{k-1}||^2 + 2 Re sum_{l<k} tr((U_l^* U_k)(V_k^* V_l)) + ||U_k V_k^*||^2;
+    * at most min(m, n) steps.
+    """
+    A = np.asarray(A, dtype=np.complex128)
+    m3, n3 = A.shape
+    m, n = m3 // 3, n3 // 3
+    cap = min(m, n)
+    U = np.zeros((m3, 0), dtype=np.complex128)
+    V = np.zeros((n3, 0), dtype=np.complex128)
+    used_i = np.zeros(m, bool)
+    used_j = np.zeros(n, bool)
+    i_hat = 0
+    norm2 = 0.0
+    steps = 0
+    fallbacks = 0
+    rows, cols = [], []
+    converged = False
+    while steps < cap:
+        if max_rank is not None and U.shape[1] + 3 > max_rank:
+            break
+        # Step 1: residual row.
+        R_row = A[3 * i_hat:3 * i_hat + 3, :] - U[3 * i_hat:3 * i_hat + 3, :] @ V.conj().T
+        used_i[i_hat] = True
+        blk = R_row.reshape(3, n, 3).transpose(1, 0, 2)       # blk[j] = R_row[:, 3j:3j+3]
+        cand = ~used_j
+        if not cand.any():
+            converged = True
+            break
+        fro = np.sqrt((np.abs(blk) ** 2).sum(axis=(1, 2)))
+        if fro[cand].max() == 0.0:
+            nxt = np.flatnonzero(~used_i)
+            if nxt.size == 0:
+                converged = True
+                break
+            i_hat = int(nxt[0])
+            continue
+        s3 = _sv3(blk)[:, 2]
+        s3c = np.where(cand, s3, -1.0)
+        froc = np.where(cand, fro, -1.0)
+        degenerate = s3c.max() <= tau_piv * froc.max()
+        # Step 2: column pivot.
+        j_hat = int(np.argmax(froc)) if degenerate else int(np.argmax(s3c))
+        M = blk[j_hat]
+        # Step 3: residual column.
+        R_col = A[:, 3 * j_hat:3 * j_hat + 3] - U @ V[3 * j_hat:3 * j_hat + 3, :].conj().T
+        used_j[j_hat] = True
+        rows.append(i_hat); cols.append(j_hat)
+        # Step 4: next row pivot from the residual column.
+        cb = R_col.reshape(m, 3, 3)
+        candi = ~used_i
+        next_i = -1
+        if candi.any():
+            fr = np.sqrt((np.abs(cb) ** 2).sum(axis=(1, 2)))
+            s3r = np.where(candi, _sv3(cb)[:, 2], -1.0)
+            frc = np.where(candi, fr, -1.0)
+            next_i = int(np.argmax(frc)) if s3r.max() <= tau_piv * frc.max() else int(np.argmax(s3r))
+        # Step 5: new factors.
+        W, S, Zh = np.linalg.svd(M)
+        if S[2] > tau_piv * S[0]:
+            Un = R_col @ np.linalg.inv(M)
+            Vn = R_row.conj().T
+        else:
+            fallbacks += 1
+            p = int((S > tau_piv * S[0]).sum())
+            Z = Zh.conj().T
+            Un = (R_col @ Z[:, :p]) / S[:p]
+            Vn = R_row.conj().T @ W[:, :p]
+        # Step 6 and stopping test (FP64 norm recurrences).
+        nu2 = float(np.real(np.trace((Un.conj().T @ Un) @ (Vn.conj().T @ Vn))))
+        cross = 0.0
+        if U.shape[1]:
+            cross = 2.0 * float(np.real(np.trace((U.conj().T @ Un) @ (Vn.conj().T @ V))))
+        norm2 += cross + nu2
+        U = np.concatenate([U, Un], axis=1)
+        V = np.concatenate([V, Vn], axis=1)
+        steps += 1
+        if math.sqrt(max(nu2, 0.0)) <= eps * math.sqrt(max(norm2, 0.0)):
+            converged = True
+            break
+        if next_i < 0:
+            converged = True
+            break
+        i_hat = next_i
+    if steps == cap:
+        converged = True
+    return ACAResult(U, V, U.shape[1], steps, rows, cols, fallbacks, norm2, converged)
+
+
+def truncation_rank(S: np.ndarray, eps: float) -> int:
+    """Smallest r with sqrt(sum_{i>=r} S_i^2) <= eps * sqrt(sum S_i^2) (Frobenius tail)."""
+    tot = float(np.sum(S.astype(np.float64) ** 2))
+    if tot == 0.0:
+        return 0
+    tail = np.concatenate([np.cumsum((S[::-1].astype(np.float64)) ** 2)[::-1], [0.0]])
+    thr = (eps * eps) * tot
+    for r in range(S.size + 1):
+        if tail[r] <= thr:
+            return r
+    return S.size
+
+
+def recompress(U: np.ndarray, V: np.ndarray, eps: float):
+    """QR of U and V, truncated SVD of R_U R_V^* (Section 3.2).
+
+    U' = Q_U P S^{1/2}, V' = Q_V L S^{1/2}, keeping the singular values whose
+    Frobenius tail exceeds eps times the total (reading of how eps selects
+    the singular values).  Returns (U', V', singular values).
+    """
+    if U.shape[1] == 0:
+        return U.copy(), V.copy(), np.zeros(0)
+    Qu, Ru = np.linalg.qr(U)
+    Qv, Rv = np.linalg.qr(V)
+    P, S, Lh = np.linalg.svd(Ru @ Rv.conj().T)
+    r = truncation_rank(S, eps)
+    sq = np.sqrt(S[:r])
+    return (Qu @ P[:, :r]) * sq, (Qv @ Lh.conj().T[:, :r]) * sq, S
+
+
+def numerical_rank(A: np.ndarray, eps: float) -> int:
+    """r(eps) of eq. num_rank with the Frobenius norm (truncated SVD)."""
+    S = np.linalg.svd(A, compute_uv=False)
+    return truncation_rank(S, eps)
+
+
+# --------------------------------------------------------------------------
+# H-matrix-vector product from exported blocks (Section 3.1)
+# --------------------------------------------------------------------------
+
+def hmatvec(blocks, tx: ClusterTree, ty: ClusterTree, x: np.ndarray) -> np.ndarray:
+    """y = A_H x from a list of exported leaf blocks, in FP64/complex128.
+
+    ``blocks`` is an iterable of (row node, col node, kind, data) where data
+    is the dense 3m x 3n tile or the pair (U, V) with block = U V^*, both in
+    cluster-local ordering (row 3p + a is point perm[begin + p]).
+    x has shape (3 ny, nrhs) in original point order.
+    """
+    x = np.asarray(x, dtype=np.complex128)
+    vec = x.ndim == 1
+    X = x.reshape(x.shape[0], -1)
+    nrhs = X.shape[1]
+    nx = tx.perm.size
+    y = np.zeros((3 * nx, nrhs), dtype=np.complex128)
+    for t, s, kind, data in blocks:
+        ri = tx.perm[tx.begin[t]:tx.end[t]]
+        ci = ty.perm[ty.begin[s]:ty.end[s]]
+        rdof = (3 * ri[:, None] + np.arange(3)).ravel()
+        cdof = (3 * ci[:, None] + np.arange(3)).ravel()
+        xs = X[cdof]
+        if kind == DENSE:
+            y[rdof] += data @ xs
+        else:
+            Uf, Vf = data
+            y[rdof] += Uf @ (Vf.conj().T @ xs)
+    return y[:, 0] if vec else y
+
+
+def densify(blocks, tx: ClusterTree, ty: ClusterTree) -> np.ndarray:
+    """Explicit dense matrix of an H-matrix given by its exported leaf blocks."""
+    nx, ny = tx.perm.size, ty.perm.size
+    A = np.zeros((3 * nx, 3 * ny), dtype=np.complex128)
+    for t, s, kind, data in blocks:
+        ri = tx.perm[tx.begin[t]:tx.end[t]]
+        ci = ty.perm[ty.begin[s]:ty.end[s]]
+        rdof = (3 * ri[:, None] + np.arange(3)).ravel()
+        cdof = (3 * ci[:, None] + np.arange(3)).ravel()
+        blk = data if kind == DENSE else data[0] @ data[1].conj().T
+        A[np.ix_(rdof, cdof)] = blk
+    return A
+
+
+# --------------------------------------------------------------------------
+# GMRES (textbook restarted GMRES with modified Gram-Schmidt and Givens)
+# --------------------------------------------------------------------------
+
+def gmres(apply, b: np.ndarray, tol: float, restart: int = 50, maxit: int = 1000):
+    """Restarted GMRES(m), x0 = 0, no preconditioner; returns (x, iters, relres)."""
+    b = np.asarray(b, dtype=np.complex128)
+    n = b.size
+    x = np.zeros(n, dtype=np.complex128)
+    bn = np.linalg.norm(b)
+    if bn == 0:
+        return x, 0, 0.0
+    it = 0
+    while it < maxit:
+        r = b - apply(x)
+        beta = np.linalg.norm(r)
+        if beta / bn <= tol:
+            return x, it, beta / bn
+        Q = np.zeros((n, restart + 1), dtype=np.complex128)
+        H = np.zeros((restart + 1, restart), dtype=np.complex128)
+        Q[:, 0] = r / beta
+        g = np.zeros(restart + 1, dtype=np.complex128)
+        g[0] = beta
+        k_used = 0
+        for k in range(restart):
+            w = apply(Q[:, k])
+            for j in range(k + 1):
+                H[j, k] = np.vdot(Q[:, j], w)
+                w = w - H[j, k] * Q[:, j]
+            H[k + 1, k] = np.linalg.norm(w)
+            if H[k + 1, k] != 0:
+                Q[:, k + 1] = w / H[k + 1, k]
+            it += 1
+            k_used = k + 1
+            y, *_ = np.linalg.lstsq(H[:k + 2, :k + 1], g[:k + 2], rcond=None)
+            res = np.linalg.norm(g[:k + 2] - H[:k + 2, :k + 1] @ y)
+            if res / bn <= tol or it >= maxit:
+                break
+        x = x + Q[:, :k_used] @ y
+    r = b - apply(x)
+    return x, it, float(np.linalg.norm(r) / bn)
+
+
+# --------------------------------------------------------------------------
+# Storage estimate (Section 5.1)
+# --------------------------------------------------------------------------
+
+def storage_entries(blocks_kind_sizes_ranks) -> int:
+    """N_st in DOF units: sum 9 m n over dense + sum r (3m + 3n) over low-rank blocks."""
+    tot = 0
+    for kind, m, n, r in blocks_kind_sizes_ranks:
+        tot += 9 * m * n if kind == DENSE else r * 3 * (m + n)
+    return tot
+
+
+# --------------------------------------------------------------------------
+# Rank-predictor MLP reference (FP64): 6 -> 64 -> 64 -> 1, ReLU, MSE, Adam
+# --------------------------------------------------------------------------
+
+def mlp_init(seed: int = 0, sizes=(6, 64, 64, 1)):
+    rng = np.random.default_rng(seed)
+    params = []
+    for fi, fo in zip(sizes[:-1], sizes[1:]):
+        lim = math.sqrt(6.0 / fi)
+        params.append(rng.uniform(-lim, lim, size=(fo, fi)).astype(np.float64))
+        params.append(np.zeros(fo, dtype=np.float64))
+    return params
+
+
+def mlp_forward(params, X):
+    """Returns (prediction (B,), cache).  X has shape (B, 6)."""
+    W1, b1, W2, b2, W3, b3 = params
+    z1 = X @ W1.T + b1
+    h1 = np.maximum(z1, 0.0)
+    z2 = h1 @ W2.T + b2
+    h2 = np.maximum(z2, 0.0)
+    out = (h2 @ W3.T + b3)[:, 0]
+    return out, (X, z1, h1, z2, h2)
+
+
+def mlp_loss_grad(params, X, t):
+    """Mean squared error and its gradient with respect to every parameter."""
+    W1, b1, W2, b2, W3, b3 = params
+    out, (X, z1, h1, z2, h2) = mlp_forward(params, X)
+    B = X.shape[0]
+    diff = out - t
+    loss = float(np.mean(diff * diff))
+    g_out = (2.0 / B) * diff[:, None]            # (B, 1)
+    gW3 = g_out.T @ h2
+    gb3 = g_out.sum(axis=0)
+    g_h2 = g_out @ W3
+    g_z2 = g_h2 * (z2 > 0)
+    gW2 = g_z2.T @ h1
+    gb2 = g_z2.sum(axis=0)
+    g_h1 = g_z2 @ W2
+    g_z1 = g_h1 * (z1 > 0)
+    gW1 = g_z1.T @ X
+    gb1 = g_z1.sum(axis=0)
+    return loss, [gW1, gb1, gW2, gb2, gW3, gb3]
+
+
+def adam_step(params, grads, m, v, step, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam update (bias-corrected), returns new (params, m, v)."""
+    out_p, out_m, out_v = [], [], []
+    for p, g, mm, vv in zip(params, grads, m, v):
+        mm = b1 * mm + (1 - b1) * g
+        vv = b2 * vv + (1 - b2) * g * g
+        mh = mm / (1 - b1 ** step)
+        vh = vv / (1 - b2 ** step)
+        out_p.append(p - lr * mh / (np.sqrt(vh) + eps))
+        out_m.append(mm)
+        out_v.append(vv)
+    return out_p, out_m, out_v
