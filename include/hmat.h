@@ -1,0 +1,254 @@
+/*
+ * hmat.h -- C ABI of the MI355X H-matrix library for 3D elastodynamic
+ * Green's tensors (Chaillat, Desiderio, Ciarlet, arXiv 1706.09384).
+ *
+ * The library assembles an H-matrix approximation of the dense complex
+ * 3Nx x 3Ny matrix of eq. (syst_a), whose 3x3 block (i, j) is the Green's
+ * tensor U_w(x_i, y_j) (eq. elasto_U) or its traction T_w(x_i, y_j)
+ * (eq. elasto_T, normal taken at y_j), and applies it in matrix-vector
+ * products (Section 3.1) and in restarted GMRES.
+ *
+ * Assembly (hm_build) runs: geometric-bisection cluster trees (Section 2.1),
+ * the block partition with the box admissibility condition (Section 6.1,
+ * eq. admissibility_cond_bis), dense near-field tiles for non-admissible
+ * leaf pairs, partially pivoted vector ACA with rank-3 updates and the
+ * largest-sigma_3 pivot rule (Sections 2.2 and 2.3, stopping test eq.
+ * stop_part), and recompression of every ACA block by QR + truncated SVD
+ * (Section 3.2).  Everything after the trees runs in HIP kernels on the GPU.
+ *
+ * Conventions shared by all calls
+ * -------------------------------
+ * Points, normals: (n, 3) row-major float64 arrays.
+ * Vectors: 3 degrees of freedom per point, interleaved (row 3i + alpha is
+ *   component alpha at point i, original point order), nrhs columns stored
+ *   row-major: element (row, c) at row * nrhs + c.  Complex numbers are
+ *   interleaved (re, im) pairs: complex64 = 2 x float32, complex128 =
+ *   2 x float64.
+ * Streams: a hipStream_t passed as void*; NULL is the default stream.
+ * Errors: every call returns an hm_status; nothing is thrown across the ABI.
+ *   On error a message is available from hm_last_error() (thread-local) and
+ *   output handles are left NULL.  No call leaks memory on error.
+ * Threading: distinct matrices may be used from distinct threads; calls on
+ *   one matrix must not overlap (it owns one set of work buffers).
+ */
+#ifndef HMAT_H
+#define HMAT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HM_OK = 0,
+    HM_ERR_ARG = 1,       /* invalid argument (sizes, NaN coordinates, parameters) */
+    HM_ERR_ALLOC = 2,     /* device or host allocation failed */
+    HM_ERR_HIP = 3,       /* a HIP runtime call or kernel launch failed */
+    HM_ERR_SINGULAR = 4,  /* kernel evaluated at coincident points x_i == y_j (r = 0) */
+    HM_ERR_NOCONV = 5,    /* GMRES reached maxit before tol; info is filled */
+    HM_ERR_STATE = 6      /* call not valid for this object (e.g. matvec on a plan-only build) */
+} hm_status;
+
+typedef enum { HM_KERNEL_U = 0, HM_KERNEL_T = 1 } hm_kernel;
+
+/* Storage and compute precision of the operator. */
+typedef enum {
+    HM_C128 = 0,  /* complex128 everywhere (the plain FP64 form) */
+    HM_C64 = 1    /* complex64 kernel evaluation, ACA updates, storage and matvec;
+                     ACA norm recurrences, recompression and GMRES refinement in FP64 */
+} hm_prec;
+
+typedef struct {
+    int32_t kernel;        /* hm_kernel */
+    int32_t prec;          /* hm_prec */
+    double omega;          /* circular frequency (>= 0), Section 1 */
+    double lambda, mu;     /* Lame parameters (mu > 0, lambda + 2 mu > 0) */
+    double rho;            /* density (> 0); kappa_s^2 = rho w^2/mu, kappa_p^2 = rho w^2/(lambda+2mu) */
+    double eta;            /* admissibility parameter eta-hat (>= 0), eq. admissibility_cond_bis */
+    double eps;            /* ACA and recompression tolerance, 0 < eps < 1 (Sections 2.2, 3.2) */
+    int32_t leaf;          /* maximum number of points in a leaf cluster (>= 1) */
+    int32_t same;          /* 1: the column cloud is the row cloud (y ignored, one tree) */
+    double self_re;        /* when same: the 3x3 diagonal blocks i == j are (self_re + i self_im) I3 */
+    double self_im;
+    int32_t points_on_host;/* 1: x, y, normals are host pointers; 0: device pointers */
+    int32_t plan_only;     /* 1: build trees and block list only (no GPU work, no GPU needed) */
+    int32_t rank_budget;   /* initial ACA column budget per block, 0 = library default */
+    int32_t recompress;    /* 1: recompress ACA blocks (default); 0: keep the ACA factors */
+    double tau_piv;        /* singular-pivot threshold on sigma_3/|M|_F, 0 = default per precision */
+    const float *rank_model;   /* optional host pointer to rank-model weights
+                                  (HM_RANK_MODEL_PARAMS floats), NULL = none */
+    int32_t reserved[8];
+} hm_params;
+
+/* Fill p with the defaults: U kernel, complex128, w = 1, lambda = 2, mu = rho = 1,
+ * eta = 3, eps = 1e-4, leaf = 32, same = 1, everything else 0 / NULL. */
+hm_status hm_params_default(hm_params *p);
+
+typedef struct hm_matrix hm_matrix;   /* opaque; owns all device memory it allocates */
+
+/*
+ * Assemble the H-matrix.
+ *   x        (nx, 3) float64 row points
+ *   y        (ny, 3) float64 column points, ignored when p->same (then ny must equal nx)
+ *   normals  (ny, 3) float64 unit normals at the column points; required for
+ *            HM_KERNEL_T, ignored (may be NULL) for HM_KERNEL_U
+ *   stream   HIP stream for all device work; the call synchronizes it before returning
+ *   out      receives the new matrix
+ * Errors: HM_ERR_ARG for nx < 1, ny < 1, non-finite coordinates, leaf < 1,
+ *   eta < 0, eps outside (0, 1), mu <= 0, rho <= 0, lambda + 2 mu <= 0,
+ *   omega < 0, missing normals for T; HM_ERR_SINGULAR if a non-self block
+ *   pairs two coincident points; HM_ERR_ALLOC / HM_ERR_HIP on device failure.
+ * The library copies everything it needs; no caller pointer is retained.
+ */
+hm_status hm_build(const double *x, int64_t nx, const double *y, int64_t ny, const double *normals,
+                   const hm_params *p, void *stream, hm_matrix **out);
+
+/*
+ * y = A_H x, Section 3.1 (leaf blocks: dense O(mn), low-rank O(r(m+n))).
+ *   x  device, (3 ny, nrhs), complex64 for HM_C64 or complex128 for HM_C128
+ *   y  device, (3 nx, nrhs), same type; overwritten.  x and y must not overlap.
+ * Asynchronous on stream.  HM_ERR_ARG for nrhs < 1 or NULL pointers.
+ */
+hm_status hm_matvec(const hm_matrix *A, const void *x, void *y, int32_t nrhs, void *stream);
+
+/*
+ * r = b - A_H x evaluated with FP64 arithmetic from the stored factors
+ * (complex64 or complex128 storage), the outer residual of iterative
+ * refinement.  b, x, r: device complex128, (3n, nrhs).  Asynchronous.
+ */
+hm_status hm_residual(const hm_matrix *A, const void *b, const void *x, void *r, int32_t nrhs,
+                      void *stream);
+
+typedef struct {
+    int32_t iters;         /* total inner Krylov iterations (max over right-hand sides) */
+    int32_t restarts;      /* GMRES cycles started */
+    int32_t refinements;   /* outer FP64 refinement steps (0 for complex128 operators) */
+    int32_t converged;     /* number of right-hand sides that met tol */
+    double relres;         /* max over columns of |b - A_H x| / |b|, recomputed in FP64 */
+    double relres_inner;   /* last inner recursive residual estimate (max over columns) */
+} hm_gmres_info;
+
+/*
+ * Solve A_H x = b by restarted GMRES(restart), x0 = 0, no preconditioner.
+ * Each of the nrhs columns is an independent GMRES run; all columns share
+ * one multi-right-hand-side H-matvec per iteration.  Complex128 operators
+ * iterate in FP64 until the recursive residual is below tol, then confirm
+ * with an explicit residual.  Complex64 operators run iterative refinement:
+ * an FP64 residual (hm_residual), an inner complex64 GMRES on it, an FP64
+ * update, until |b - A_H x| / |b| <= tol in FP64.
+ *   b, x   device complex128, (3 nx, nrhs); x is overwritten.
+ * Synchronous.  HM_ERR_NOCONV when maxit total inner iterations pass without
+ * reaching tol (x then holds the last iterate and info is filled).
+ */
+hm_status hm_gmres(const hm_matrix *A, const void *b, void *x, int32_t nrhs, double tol,
+                   int32_t restart, int32_t maxit, void *stream, hm_gmres_info *info);
+
+typedef struct {
+    int64_t nx, ny;                    /* points */
+    int32_t nodes_x, nodes_y;          /* cluster tree sizes */
+    int32_t leaves_x, leaves_y;
+    int32_t levels_x, levels_y;        /* depth + 1 */
+    int64_t n_blocks, n_dense, n_lowrank;
+    int32_t c_sp;                      /* sparsity constant C_sp (Section 2.1) */
+    int32_t prec;
+    int64_t dense_entries;             /* complex entries in dense tiles */
+    int64_t lowrank_entries;           /* complex entries in low-rank factors U, V */
+    int64_t storage_bytes;             /* dense + low-rank bytes as stored */
+    int32_t max_rank_aca, max_rank;    /* largest ACA rank, largest rank after recompression */
+    int64_t sum_rank_aca, sum_rank;
+    int32_t n_overflow;                /* blocks re-run because they outgrew their first budget */
+    int32_t n_fallback;                /* ACA steps that used the singular-pivot fallback */
+    int32_t n_model_hits;              /* blocks whose predicted budget sufficed */
+    double t_tree, t_upload, t_nearfield, t_aca, t_recompress, t_plan, t_total; /* seconds */
+    int64_t matvec_bytes;              /* algorithmic bytes of one 1-RHS matvec */
+} hm_stats;
+
+hm_status hm_info(const hm_matrix *A, hm_stats *s);
+
+/*
+ * Measurement helper: runs the 1-RHS matvec kernels (gather, project,
+ * accumulate) `reps` times on `stream` with HIP events between the launches.
+ *   x, y          device vectors of the operator's type, (3 ny) and (3 nx)
+ *   kernel_ms     host double[3]: mean duration of each kernel (ms)
+ *   kernel_bytes  host int64[3]: algorithmic HBM bytes of each kernel
+ *                 (x read; V factors; dense tiles + U factors + y write)
+ * Synchronous.
+ */
+hm_status hm_profile_matvec(const hm_matrix *A, const void *x, void *y, int32_t reps, void *stream,
+                            double *kernel_ms, int64_t *kernel_bytes);
+
+/*
+ * Copy a cluster tree to host buffers (which = 0: row tree, 1: column tree).
+ *   perm   int32[n]: cluster position -> original point index
+ *   nodes  int32[nodes * 5]: begin, end, left child, right child (-1 for
+ *          leaves), depth; nodes numbered in pre-order
+ *   boxes  float64[nodes * 6]: lo[3], hi[3] tight bounding boxes
+ * Any pointer may be NULL to skip it.
+ */
+hm_status hm_export_tree(const hm_matrix *A, int32_t which, int32_t *perm, int32_t *nodes,
+                         double *boxes);
+
+/*
+ * Copy the block partition to host buffers, in the order of a depth-first
+ * traversal of the block cluster tree.
+ *   blocks    int32[n_blocks * 3]: row node, column node, kind (0 dense, 1 low-rank)
+ *   rank      int32[n_blocks]: stored rank (-1 for dense blocks)
+ *   rank_aca  int32[n_blocks]: rank produced by ACA before recompression (-1 dense)
+ */
+hm_status hm_export_blocklist(const hm_matrix *A, int32_t *blocks, int32_t *rank,
+                              int32_t *rank_aca);
+
+/*
+ * Copy one stored block to a host buffer in the operator's complex type,
+ * rows/columns in cluster-local order (row 3p + alpha = point perm[begin + p]):
+ * dense: the 3m x 3n tile, column-major; low-rank: U (3m x r, column-major)
+ * followed by V (3n x r, column-major), block = U V^*.
+ */
+hm_status hm_export_block(const hm_matrix *A, int64_t block, void *host_buf);
+
+void hm_destroy(hm_matrix *A);
+
+/* Thread-local description of the last error, "" if none. */
+const char *hm_last_error(void);
+
+/* ---------------------------------------------------------------------
+ * Rank model: a 6 -> 64 -> 64 -> 1 ReLU network predicting the ACA rank of
+ * an admissible block from (log|X|, log|Y|, k_s diam X, k_s diam Y,
+ * k_s dist(X,Y), log10 eps), diam/dist from the bounding boxes.  The
+ * target is log2(1 + r_ACA/3).  A prediction only sizes the first ACA
+ * budget of a block; ACA's own stopping test still decides the rank.
+ * Weights are float32, packed W1(64x6) b1(64) W2(64x64) b2(64) W3(1x64) b3(1).
+ * --------------------------------------------------------------------- */
+#define HM_RANK_MODEL_PARAMS (64 * 6 + 64 + 64 * 64 + 64 + 64 + 1)
+
+/* Features and ACA ranks of every admissible block of a built matrix:
+ * feats float32[n_lowrank * 6], ranks int32[n_lowrank] (host buffers). */
+hm_status hm_rank_samples(const hm_matrix *A, float *feats, int32_t *ranks);
+
+/*
+ * Train the rank model on the GPU with the library's own FP32 forward,
+ * backward and Adam kernels (mean squared error on log2(1 + r/3)).
+ *   feats    host float32[n * 6];  ranks  host int32[n]
+ *   weights  host float32[HM_RANK_MODEL_PARAMS], in: initial, out: trained
+ *   loss_out host float32[epochs] (may be NULL): mean loss per epoch
+ */
+hm_status hm_rank_model_train(const float *feats, const int32_t *ranks, int64_t n,
+                              float *weights, int32_t epochs, int32_t batch, float lr,
+                              uint64_t seed, float *loss_out, void *stream);
+
+/* Forward pass on device: feats (n x 6) -> pred (n), all device float32. */
+hm_status hm_rank_model_predict(const float *weights_host, const float *feats, float *pred,
+                                int64_t n, void *stream);
+
+/* One forward+backward pass on device for checking gradients: device
+ * feats (n x 6), device targets (n), host weights; returns the loss and the
+ * gradient (host float32[HM_RANK_MODEL_PARAMS]). */
+hm_status hm_rank_model_grad(const float *weights_host, const float *feats, const float *targets,
+                             int64_t n, float *loss, float *grad_host, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HMAT_H */

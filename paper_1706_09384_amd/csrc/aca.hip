@@ -1,0 +1,518 @@
+// Batched partially pivoted vector ACA (Sections 2.2 and 2.3).
+//
+// One 256-thread workgroup runs the whole greedy loop of one admissible
+// block tau x sigma (m row points, n column points).  Step k, with row pivot
+// point i^ known:
+//   1. residual row  R(i^, :) = A(i^, :) - U(i^, :) V^*   (3 x 3n: n kernel
+//      evaluations, the pivot row of U staged in LDS); it is written straight
+//      into the next three columns of V as its conjugate transpose;
+//   2. column pivot j^ = argmax over unused j of sigma_3 of the 3x3 block
+//      R(i^, j) (ties -> smallest j), computed in FP64 from the invariants of
+//      M^* M (Newton on the characteristic cubic from 0, which converges
+//      monotonically to the smallest eigenvalue);
+//   3. residual column R(:, j^) (3m x 3, the pivot row of V staged in LDS);
+//   4. next row pivot = argmax over unused i of sigma_3 of R(i, j^);
+//   5. U_new = R(:, j^) M^-1, V_new = R(i^, :)^* with M = R(i^, j^);
+//   6. stopping test ||U_k V_k^*||_F <= eps ||B_k||_F with both norms from
+//      FP64 recurrences over the 3x3 Gram blocks.
+// Rows/columns whose every candidate 3x3 block is numerically singular
+// (sigma_3 <= tau_piv |block|_F, e.g. T between coplanar points) fall back
+// to the largest-Frobenius candidate and a rank-p pseudo-inverse update.
+// A residual row that vanishes on all unused columns marks the row used and
+// moves to the next unused row without adding a term.
+#include <climits>
+
+#include "internal.hpp"
+
+namespace hm {
+
+constexpr int kAcaThreads = 256;
+constexpr int kAcaWaves = kAcaThreads / 64;
+
+struct Inv3 {
+    double s3sq, fro2;
+};
+
+// sigma_3^2 and |M|_F^2 of a 3x3 complex matrix (scaled to avoid under/overflow).
+__device__ inline Inv3 invariants3(const cplx<double> M[9]) {
+    double mx = 0;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) mx = fmax(mx, fmax(fabs(M[k].re), fabs(M[k].im)));
+    if (mx == 0.0) return {0.0, 0.0};
+    const double sc = 1.0 / mx;
+    cplx<double> a[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) a[k] = sc * M[k];
+    double e1 = 0;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) e1 += abs2(a[k]);
+    // cofactors (2x2 minors up to sign)
+    const cplx<double> c00 = a[4] * a[8] - a[5] * a[7];
+    const cplx<double> c01 = a[5] * a[6] - a[3] * a[8];
+    const cplx<double> c02 = a[3] * a[7] - a[4] * a[6];
+    const cplx<double> c10 = a[2] * a[7] - a[1] * a[8];
+    const cplx<double> c11 = a[0] * a[8] - a[2] * a[6];
+    const cplx<double> c12 = a[1] * a[6] - a[0] * a[7];
+    const cplx<double> c20 = a[1] * a[5] - a[2] * a[4];
+    const cplx<double> c21 = a[2] * a[3] - a[0] * a[5];
+    const cplx<double> c22 = a[0] * a[4] - a[1] * a[3];
+    const double e2 = abs2(c00) + abs2(c01) + abs2(c02) + abs2(c10) + abs2(c11) + abs2(c12) +
+                      abs2(c20) + abs2(c21) + abs2(c22);
+    const cplx<double> det = a[0] * c00 + a[1] * c01 + a[2] * c02;
+    const double e3 = abs2(det);
+    double t = 0.0;
+    for (int it = 0; it < 16; ++it) {
+        const double p = ((t - e1) * t + e2) * t - e3;
+        const double dp = (3.0 * t - 2.0 * e1) * t + e2;
+        if (!(dp > 0.0)) break;
+        const double dt = p / dp;
+        t -= dt;
+        if (fabs(dt) <= 1e-15 * t) break;
+    }
+    return {fmax(t, 0.0) * mx * mx, e1 * mx * mx};
+}
+
+// Candidate comparison: larger value wins, ties -> smaller index.
+__device__ inline void cand_better(double &v, int &i, double v2, int i2) {
+    if (v2 > v || (v2 == v && i2 < i)) {
+        v = v2;
+        i = i2;
+    }
+}
+
+struct Best2 {
+    double s3;
+    int i3;
+    double fro;
+    int ifro;
+};
+
+__device__ inline Best2 block_best2(Best2 b, Best2 *sh) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const double s3 = __shfl_xor(b.s3, o, 64);
+        const int i3 = __shfl_xor(b.i3, o, 64);
+        const double fr = __shfl_xor(b.fro, o, 64);
+        const int ifr = __shfl_xor(b.ifro, o, 64);
+        cand_better(b.s3, b.i3, s3, i3);
+        cand_better(b.fro, b.ifro, fr, ifr);
+    }
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    if (lane == 0) sh[wave] = b;
+    __syncthreads();
+    Best2 r = sh[0];
+    for (int w = 1; w < kAcaWaves; ++w) {
+        cand_better(r.s3, r.i3, sh[w].s3, sh[w].i3);
+        cand_better(r.fro, r.ifro, sh[w].fro, sh[w].ifro);
+    }
+    __syncthreads();
+    return r;
+}
+
+// Eigen-decomposition of a 3x3 Hermitian matrix by cyclic Jacobi; on exit
+// lam (descending) and unit eigenvectors in the columns of Z (row-major).
+__device__ inline void herm3_eig(cplx<double> G[9], double lam[3], cplx<double> Z[9]) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) Z[k] = {0.0, 0.0};
+    Z[0] = Z[4] = Z[8] = {1.0, 0.0};
+    for (int sweep = 0; sweep < 12; ++sweep) {
+        double off = abs2(G[1]) + abs2(G[2]) + abs2(G[5]);
+        double dia = G[0].re * G[0].re + G[4].re * G[4].re + G[8].re * G[8].re;
+        if (off <= 1e-34 * dia) break;
+        for (int pq = 0; pq < 3; ++pq) {
+            const int p = (pq == 2) ? 1 : 0, q = (pq == 0) ? 1 : 2;
+            const cplx<double> gpq = G[3 * p + q];
+            const double ag = sqrt(abs2(gpq));
+            if (ag == 0.0) continue;
+            const double app = G[3 * p + p].re, aqq = G[3 * q + q].re;
+            const double tau = (aqq - app) / (2.0 * ag);
+            const double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+            const double c = 1.0 / sqrt(1.0 + t * t), s = t * c;
+            const cplx<double> ph = {gpq.re / ag, -gpq.im / ag};  // e^{-i phi}
+            // V = [[c, s], [-s e^{-i phi}, c e^{-i phi}]] on columns p, q
+            const cplx<double> v00 = {c, 0}, v01 = {s, 0};
+            const cplx<double> v10 = (-s) * ph, v11 = c * ph;
+            // G <- G V (columns)
+            for (int r = 0; r < 3; ++r) {
+                const cplx<double> gp = G[3 * r + p], gq = G[3 * r + q];
+                G[3 * r + p] = gp * v00 + gq * v10;
+                G[3 * r + q] = gp * v01 + gq * v11;
+                const cplx<double> zp = Z[3 * r + p], zq = Z[3 * r + q];
+                Z[3 * r + p] = zp * v00 + zq * v10;
+                Z[3 * r + q] = zp * v01 + zq * v11;
+            }
+            // G <- V^* G (rows)
+            for (int cc = 0; cc < 3; ++cc) {
+                const cplx<double> gp = G[3 * p + cc], gq = G[3 * q + cc];
+                G[3 * p + cc] = cmul(v00, gp) + cmul(v10, gq);
+                G[3 * q + cc] = cmul(v01, gp) + cmul(v11, gq);
+            }
+            G[3 * p + q] = {0.0, 0.0};
+            G[3 * q + p] = {0.0, 0.0};
+            G[3 * p + p].im = 0.0;
+            G[3 * q + q].im = 0.0;
+        }
+    }
+    for (int k = 0; k < 3; ++k) lam[k] = G[4 * k].re;
+    // sort descending (3 elements)
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2 - a; ++b)
+            if (lam[b] < lam[b + 1]) {
+                const double tl = lam[b];
+                lam[b] = lam[b + 1];
+                lam[b + 1] = tl;
+                for (int r = 0; r < 3; ++r) {
+                    const cplx<double> tz = Z[3 * r + b];
+                    Z[3 * r + b] = Z[3 * r + b + 1];
+                    Z[3 * r + b + 1] = tz;
+                }
+            }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kAcaThreads)
+    aca_kernel(Geometry g, GreenParams<R> gp, const AcaBlk *__restrict__ blks,
+               cplx<R> *__restrict__ fac, uint8_t *__restrict__ flags,
+               AcaOut *__restrict__ outs, double eps, double tau_piv) {
+    extern __shared__ unsigned char smem_raw[];
+    cplx<R> *piv = reinterpret_cast<cplx<R> *>(smem_raw);  // 3 x budget pivot row
+    __shared__ Best2 sh_best[kAcaWaves];
+    __shared__ double sh_red[2 * kAcaWaves];
+    __shared__ cplx<double> sh_T[9];   // M^-1 (mode 0) or Z_p Sigma_p^-1 (mode 1)
+    __shared__ cplx<double> sh_W[9];   // W_p (mode 1)
+    __shared__ int sh_ctl[8];          // 0 ihat, 1 jhat, 2 mode, 3 p, 4 next_i, 5 stop, 6 zero-row
+    __shared__ double sh_norm2;
+
+    const AcaBlk b = blks[blockIdx.x];
+    const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+    const int m = b.m, n = b.n;
+    const int64_t ldu = 3 * (int64_t)m, ldv = 3 * (int64_t)n;
+    cplx<R> *U = fac + b.uoff;
+    cplx<R> *V = fac + b.voff;
+    uint8_t *used_i = flags + b.foff;
+    uint8_t *used_j = used_i + m;
+    for (int k = tid; k < m + n; k += kAcaThreads) used_i[k] = 0;
+    if (tid == 0) {
+        sh_ctl[0] = 0;
+        sh_ctl[5] = 0;
+        sh_norm2 = 0.0;
+    }
+    __syncthreads();
+
+    const bool isT = gp.kind == 1;
+    int r = 0, steps = 0, fallbacks = 0, status = 0;
+    const int cap = min(m, n);
+    double norm2 = 0.0;
+    while (true) {
+        if (steps >= cap) {
+            status = 2;
+            break;
+        }
+        if (r + 3 > b.budget) {
+            status = 1;
+            break;
+        }
+        const int ih = sh_ctl[0];
+        // ---- 1. residual row --------------------------------------------
+        for (int k = tid; k < 3 * r; k += kAcaThreads) {
+            const int a = k / r, l = k - a * r;
+            piv[a * r + l] = U[l * ldu + 3 * ih + a];
+        }
+        __syncthreads();
+        const int pi = b.rb + ih;
+        const double xi0 = g.x[0][pi], xi1 = g.x[1][pi], xi2 = g.x[2][pi];
+        Best2 best = {-1.0, INT_MAX, -1.0, INT_MAX};
+        for (int j = tid; j < n; j += kAcaThreads) {
+            const int pj = b.cb + j;
+            cplx<R> K[9];
+            R nx = 0, ny = 0, nz = 0;
+            if (isT) {
+                nx = R(g.n[0][pj]);
+                ny = R(g.n[1][pj]);
+                nz = R(g.n[2][pj]);
+            }
+            green_block<R>(gp, R(xi0 - g.y[0][pj]), R(xi1 - g.y[1][pj]), R(xi2 - g.y[2][pj]), nx,
+                           ny, nz, K);
+            for (int l = 0; l < r; ++l) {
+                const cplx<R> *vc = V + l * ldv + 3 * j;
+                const cplx<R> v0 = vc[0], v1 = vc[1], v2 = vc[2];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const cplx<R> u = piv[a * r + l];
+                    fms_conj(K[3 * a + 0], u, v0);
+                    fms_conj(K[3 * a + 1], u, v1);
+                    fms_conj(K[3 * a + 2], u, v2);
+                }
+            }
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                cplx<R> *vn = V + (r + a) * ldv + 3 * j;
+#pragma unroll
+                for (int be = 0; be < 3; ++be) vn[be] = conj(K[3 * a + be]);
+            }
+            if (!used_j[j]) {
+                cplx<double> Md[9];
+#pragma unroll
+                for (int e = 0; e < 9; ++e) Md[e] = cvt<double>(K[e]);
+                const Inv3 iv = invariants3(Md);
+                cand_better(best.s3, best.i3, iv.s3sq, j);
+                cand_better(best.fro, best.ifro, iv.fro2, j);
+            }
+        }
+        best = block_best2(best, sh_best);
+        if (tid == 0) used_i[ih] = 1;
+        if (best.ifro == INT_MAX) {  // no unused column left
+            status = 0;
+            break;
+        }
+        if (best.fro == 0.0) {
+            // Zero residual row: move to the next unused row, no new term.
+            __syncthreads();
+            int cand = INT_MAX;
+            for (int i = tid; i < m; i += kAcaThreads)
+                if (!used_i[i]) {
+                    cand = i;
+                    break;
+                }
+            // equal values everywhere: the reduction returns the smallest index
+            const Best2 bb = block_best2({0.0, cand, 0.0, cand}, sh_best);
+            if (bb.i3 == INT_MAX) {
+                status = 0;
+                break;
+            }
+            if (tid == 0) sh_ctl[0] = bb.i3;
+            __syncthreads();
+            continue;
+        }
+        const bool degenerate = best.s3 <= tau_piv * tau_piv * best.fro;
+        const int jh = degenerate ? best.ifro : best.i3;
+        // ---- pivot block and its (pseudo-)inverse ------------------------
+        if (jh % kAcaThreads == tid) {
+            // This thread wrote V(3jh + be, r + a) above; read back M(a, be).
+            for (int a = 0; a < 3; ++a)
+                for (int be = 0; be < 3; ++be)
+                    sh_W[3 * a + be] = cvt<double>(conj(V[(r + a) * ldv + 3 * jh + be]));
+            used_j[jh] = 1;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            cplx<double> M[9], G[9], Z[9];
+            for (int e = 0; e < 9; ++e) M[e] = sh_W[e];
+            for (int a = 0; a < 3; ++a)
+                for (int c = 0; c < 3; ++c) {
+                    cplx<double> s = {0, 0};
+                    for (int k = 0; k < 3; ++k) s = s + cmul(M[3 * k + a], M[3 * k + c]);
+                    G[3 * a + c] = s;
+                }
+            double lam[3];
+            herm3_eig(G, lam, Z);
+            const double s1 = sqrt(fmax(lam[0], 0.0));
+            double sv[3];
+            int p = 0;
+            for (int k = 0; k < 3; ++k) {
+                sv[k] = sqrt(fmax(lam[k], 0.0));
+                if (sv[k] > tau_piv * s1) ++p;
+            }
+            if (p == 3) {
+                // M^-1 = adj(M) / det(M)
+                const cplx<double> c00 = M[4] * M[8] - M[5] * M[7];
+                const cplx<double> c01 = M[5] * M[6] - M[3] * M[8];
+                const cplx<double> c02 = M[3] * M[7] - M[4] * M[6];
+                const cplx<double> c10 = M[2] * M[7] - M[1] * M[8];
+                const cplx<double> c11 = M[0] * M[8] - M[2] * M[6];
+                const cplx<double> c12 = M[1] * M[6] - M[0] * M[7];
+                const cplx<double> c20 = M[1] * M[5] - M[2] * M[4];
+                const cplx<double> c21 = M[2] * M[3] - M[0] * M[5];
+                const cplx<double> c22 = M[0] * M[4] - M[1] * M[3];
+                const cplx<double> det = M[0] * c00 + M[1] * c01 + M[2] * c02;
+                const double dd = abs2(det);
+                const cplx<double> idet = {det.re / dd, -det.im / dd};
+                const cplx<double> C[9] = {c00, c01, c02, c10, c11, c12, c20, c21, c22};
+                for (int a = 0; a < 3; ++a)
+                    for (int c = 0; c < 3; ++c) sh_T[3 * a + c] = C[3 * c + a] * idet;
+                sh_ctl[2] = 0;
+                sh_ctl[3] = 3;
+            } else {
+                if (p == 0) p = 1;  // best.fro > 0 guarantees sigma_1 > 0
+                for (int c = 0; c < 3; ++c) {
+                    const double is = c < p ? 1.0 / sv[c] : 0.0;
+                    for (int a = 0; a < 3; ++a) {
+                        sh_T[3 * a + c] = is * Z[3 * a + c];
+                        cplx<double> w = {0, 0};
+                        for (int k = 0; k < 3; ++k) w = w + M[3 * a + k] * Z[3 * k + c];
+                        sh_W[3 * a + c] = is * w;
+                    }
+                }
+                sh_ctl[2] = 1;
+                sh_ctl[3] = p;
+            }
+            sh_ctl[1] = jh;
+        }
+        __syncthreads();
+        const int mode = sh_ctl[2], p = sh_ctl[3];
+        if (mode == 1) {
+            ++fallbacks;
+            // V_new = R_row^* W_p: rows 3j + be of V columns r..r+2 hold conj(R_row)^T.
+            for (int j = tid; j < n; j += kAcaThreads) {
+                cplx<double> v[3][3];
+                for (int a = 0; a < 3; ++a)
+                    for (int be = 0; be < 3; ++be)
+                        v[a][be] = cvt<double>(V[(r + a) * ldv + 3 * j + be]);
+                for (int c = 0; c < 3; ++c)
+                    for (int be = 0; be < 3; ++be) {
+                        cplx<double> s = {0, 0};
+                        if (c < p)
+                            for (int a = 0; a < 3; ++a) s = s + v[a][be] * sh_W[3 * a + c];
+                        V[(r + c) * ldv + 3 * j + be] = cvt<R>(s);
+                    }
+            }
+        }
+        // ---- 3. residual column, 4. next row pivot, 5. U_new --------------
+        for (int k = tid; k < 3 * r; k += kAcaThreads) {
+            const int be = k / r, l = k - be * r;
+            piv[be * r + l] = V[l * ldv + 3 * jh + be];
+        }
+        __syncthreads();
+        const int pj = b.cb + jh;
+        const double yj0 = g.y[0][pj], yj1 = g.y[1][pj], yj2 = g.y[2][pj];
+        R njx = 0, njy = 0, njz = 0;
+        if (isT) {
+            njx = R(g.n[0][pj]);
+            njy = R(g.n[1][pj]);
+            njz = R(g.n[2][pj]);
+        }
+        best = {-1.0, INT_MAX, -1.0, INT_MAX};
+        for (int i = tid; i < m; i += kAcaThreads) {
+            const int pii = b.rb + i;
+            cplx<R> K[9];
+            green_block<R>(gp, R(g.x[0][pii] - yj0), R(g.x[1][pii] - yj1), R(g.x[2][pii] - yj2),
+                           njx, njy, njz, K);
+            for (int l = 0; l < r; ++l) {
+                const cplx<R> *uc = U + l * ldu + 3 * i;
+                const cplx<R> u0 = uc[0], u1 = uc[1], u2 = uc[2];
+#pragma unroll
+                for (int be = 0; be < 3; ++be) {
+                    const cplx<R> v = piv[be * r + l];
+                    fms_conj(K[0 + be], u0, v);
+                    fms_conj(K[3 + be], u1, v);
+                    fms_conj(K[6 + be], u2, v);
+                }
+            }
+            if (!used_i[i]) {
+                cplx<double> Md[9];
+#pragma unroll
+                for (int e = 0; e < 9; ++e) Md[e] = cvt<double>(K[e]);
+                const Inv3 iv = invariants3(Md);
+                cand_better(best.s3, best.i3, iv.s3sq, i);
+                cand_better(best.fro, best.ifro, iv.fro2, i);
+            }
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                cplx<double> kd[3];
+#pragma unroll
+                for (int be = 0; be < 3; ++be) kd[be] = cvt<double>(K[3 * a + be]);
+                for (int c = 0; c < p; ++c) {
+                    const cplx<double> s = kd[0] * sh_T[0 * 3 + c] + kd[1] * sh_T[1 * 3 + c] +
+                                           kd[2] * sh_T[2 * 3 + c];
+                    U[(r + c) * ldu + 3 * i + a] = cvt<R>(s);
+                }
+            }
+        }
+        best = block_best2(best, sh_best);
+        int next_i = -1;
+        if (best.ifro != INT_MAX)
+            next_i = (best.s3 <= tau_piv * tau_piv * best.fro) ? best.ifro : best.i3;
+        // ---- 6. FP64 norm recurrences ------------------------------------
+        double cross = 0.0, nrm = 0.0;
+        for (int a = wave; a < r + p; a += kAcaWaves) {
+            double cu[6] = {0, 0, 0, 0, 0, 0}, cv[6] = {0, 0, 0, 0, 0, 0};
+            const cplx<R> *ua = U + a * ldu;
+            for (int64_t i = lane; i < ldu; i += 64) {
+                const cplx<double> x = cvt<double>(ua[i]);
+                for (int c = 0; c < p; ++c) {
+                    const cplx<double> y = cvt<double>(U[(r + c) * ldu + i]);
+                    cu[2 * c] += x.re * y.re + x.im * y.im;
+                    cu[2 * c + 1] += x.re * y.im - x.im * y.re;
+                }
+            }
+            const cplx<R> *va = V + a * ldv;
+            for (int64_t j = lane; j < ldv; j += 64) {
+                const cplx<double> x = cvt<double>(va[j]);
+                for (int c = 0; c < p; ++c) {
+                    const cplx<double> y = cvt<double>(V[(r + c) * ldv + j]);
+                    cv[2 * c] += x.re * y.re + x.im * y.im;
+                    cv[2 * c + 1] += x.re * y.im - x.im * y.re;
+                }
+            }
+            double contrib = 0.0;
+            for (int c = 0; c < p; ++c) {
+                double ur = cu[2 * c], ui = cu[2 * c + 1], vr = cv[2 * c], vi = cv[2 * c + 1];
+#pragma unroll
+                for (int o = 32; o > 0; o >>= 1) {
+                    ur += __shfl_xor(ur, o, 64);
+                    ui += __shfl_xor(ui, o, 64);
+                    vr += __shfl_xor(vr, o, 64);
+                    vi += __shfl_xor(vi, o, 64);
+                }
+                contrib += ur * vr + ui * vi;  // Re(cu * conj(cv))
+            }
+            if (a < r)
+                cross += 2.0 * contrib;
+            else
+                nrm += contrib;
+        }
+        if (lane == 0) {
+            sh_red[wave] = cross;
+            sh_red[kAcaWaves + wave] = nrm;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double cs = 0, ns = 0;
+            for (int w = 0; w < kAcaWaves; ++w) {
+                cs += sh_red[w];
+                ns += sh_red[kAcaWaves + w];
+            }
+            sh_norm2 += cs + ns;
+            const bool stop = (ns <= eps * eps * sh_norm2) || next_i < 0;
+            sh_ctl[5] = stop ? 1 : 0;
+            sh_ctl[0] = next_i;
+        }
+        __syncthreads();
+        r += p;
+        ++steps;
+        norm2 = sh_norm2;
+        if (sh_ctl[5]) {
+            status = (steps >= cap) ? 2 : 0;
+            break;
+        }
+    }
+    if (tid == 0) {
+        AcaOut o;
+        o.rank = r;
+        o.status = status;
+        o.fallbacks = fallbacks;
+        o.steps = steps;
+        o.norm2 = norm2;
+        outs[blockIdx.x] = o;
+    }
+}
+
+template <typename R>
+void run_aca(const Geometry &g, const GreenParams<R> &gp, const std::vector<AcaBlk> &blk,
+             AcaBlk *d_blk, cplx<R> *scratch, uint8_t *flags, AcaOut *d_out, double eps,
+             double tau_piv, int32_t max_budget, hipStream_t st) {
+    if (blk.empty()) return;
+    const size_t smem = 3 * (size_t)max_budget * sizeof(cplx<R>);
+    hipLaunchKernelGGL(aca_kernel<R>, dim3((unsigned)blk.size()), dim3(kAcaThreads), smem, st, g,
+                       gp, d_blk, scratch, flags, d_out, eps, tau_piv);
+    HM_HIP_CHECK(hipGetLastError());
+}
+
+template void run_aca<float>(const Geometry &, const GreenParams<float> &,
+                             const std::vector<AcaBlk> &, AcaBlk *, cplx<float> *, uint8_t *,
+                             AcaOut *, double, double, int32_t, hipStream_t);
+template void run_aca<double>(const Geometry &, const GreenParams<double> &,
+                              const std::vector<AcaBlk> &, AcaBlk *, cplx<double> *, uint8_t *,
+                              AcaOut *, double, double, int32_t, hipStream_t);
+
+}  // namespace hm

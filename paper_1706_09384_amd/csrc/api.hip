@@ -1,0 +1,710 @@
+// C ABI entry points: argument validation, host planning, device assembly
+// orchestration, matvec dispatch and exports.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+
+#include "internal.hpp"
+
+namespace {
+thread_local std::string g_last_error;
+
+double now_s() {
+    using namespace std::chrono;
+    return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+}  // namespace
+
+namespace hm {
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+void DeviceBuf::alloc(size_t b) {
+    reset();
+    if (b == 0) return;
+    const char *inj = std::getenv("HM_FAULT_ALLOC");
+    if (inj) {
+        static thread_local long counter = 0;
+        if (++counter == std::atol(inj)) throw StatusError(HM_ERR_ALLOC, "injected allocation failure");
+    }
+    hipError_t e = hipMalloc(&p, b);
+    if (e != hipSuccess) {
+        p = nullptr;
+        (void)hipGetLastError();
+        throw StatusError(HM_ERR_ALLOC, "hipMalloc of " + std::to_string(b) + " bytes failed: " +
+                                            hipGetErrorString(e));
+    }
+    bytes = b;
+}
+
+size_t elem_bytes(int prec) { return prec == HM_C64 ? 8 : 16; }
+
+template <typename T>
+static void upload(DeviceBuf &buf, const std::vector<T> &v, hipStream_t st) {
+    buf.alloc(std::max<size_t>(v.size(), 1) * sizeof(T));
+    if (!v.empty()) {
+        // The source is pageable host memory that may be freed right after
+        // this call returns, so the copy completes before returning.
+        HM_HIP_CHECK(hipMemcpyAsync(buf.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
+        HM_HIP_CHECK(hipStreamSynchronize(st));
+    }
+}
+
+// Copies the leading r columns of ACA factors into the final slab.
+template <typename R>
+__global__ void copy_factors_kernel(const RcBlk *__restrict__ blks, const cplx<R> *__restrict__ src,
+                                    const int64_t *__restrict__ outu,
+                                    const int64_t *__restrict__ outv, cplx<R> *__restrict__ dst) {
+    const RcBlk b = blks[blockIdx.y];
+    const int64_t nu = 3 * (int64_t)b.m * b.r, nv = 3 * (int64_t)b.n * b.r;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nu + nv;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        if (k < nu)
+            dst[outu[blockIdx.y] + k] = src[b.uoff + k];
+        else
+            dst[outv[blockIdx.y] + (k - nu)] = src[b.voff + (k - nu)];
+    }
+}
+
+}  // namespace hm
+
+using namespace hm;
+
+hm::Geometry hm_matrix::geometry() const {
+    Geometry g{};
+    const double *base = geo.as<double>();
+    for (int a = 0; a < 3; ++a) g.x[a] = base + a * nx;
+    if (p.same) {
+        for (int a = 0; a < 3; ++a) g.y[a] = g.x[a];
+    } else {
+        for (int a = 0; a < 3; ++a) g.y[a] = base + 3 * nx + a * ny;
+    }
+    const double *nb = base + 3 * nx + (p.same ? 0 : 3 * ny);
+    for (int a = 0; a < 3; ++a) g.n[a] = (p.kernel == HM_KERNEL_T) ? nb + a * ny : nullptr;
+    g.same = p.same;
+    return g;
+}
+
+#define HM_API_BEGIN try {
+#define HM_API_END                                               \
+    }                                                            \
+    catch (const hm::StatusError &e) {                           \
+        hm::set_error(e.msg);                                    \
+        return e.status;                                         \
+    }                                                            \
+    catch (const hm::HipError &e) {                              \
+        hm::set_error(e.msg);                                    \
+        (void)hipGetLastError();                                 \
+        return HM_ERR_HIP;                                       \
+    }                                                            \
+    catch (const std::bad_alloc &) {                             \
+        hm::set_error("host allocation failed");                 \
+        return HM_ERR_ALLOC;                                     \
+    }                                                            \
+    catch (const std::exception &e) {                            \
+        hm::set_error(e.what());                                 \
+        return HM_ERR_ARG;                                       \
+    }
+
+static void require(bool ok, const std::string &msg) {
+    if (!ok) throw StatusError(HM_ERR_ARG, msg);
+}
+
+extern "C" hm_status hm_params_default(hm_params *p) {
+    if (!p) return HM_ERR_ARG;
+    std::memset(p, 0, sizeof(*p));
+    p->kernel = HM_KERNEL_U;
+    p->prec = HM_C128;
+    p->omega = 1.0;
+    p->lambda = 2.0;
+    p->mu = 1.0;
+    p->rho = 1.0;
+    p->eta = 3.0;
+    p->eps = 1e-4;
+    p->leaf = 32;
+    p->same = 1;
+    p->recompress = 1;
+    return HM_OK;
+}
+
+extern "C" const char *hm_last_error(void) { return g_last_error.c_str(); }
+
+namespace {
+
+std::vector<double> fetch_points(const double *ptr, int64_t n, bool on_host, const char *what) {
+    std::vector<double> h(3 * n);
+    if (on_host) {
+        std::memcpy(h.data(), ptr, h.size() * sizeof(double));
+    } else {
+        HM_HIP_CHECK(hipMemcpy(h.data(), ptr, h.size() * sizeof(double), hipMemcpyDeviceToHost));
+    }
+    for (double v : h) require(std::isfinite(v), std::string("non-finite value in ") + what);
+    return h;
+}
+
+// Leaves of the subtree rooted at v (pre-order numbering: subtree = v..).
+void leaves_under(const ClusterTree &t, int32_t v, std::vector<int32_t> &out) {
+    std::vector<int32_t> st{v};
+    while (!st.empty()) {
+        const int32_t u = st.back();
+        st.pop_back();
+        if (t.is_leaf(u)) {
+            out.push_back(u);
+        } else {
+            st.push_back(t.right[u]);
+            st.push_back(t.left[u]);
+        }
+    }
+}
+
+template <typename R>
+void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vector<double> &Y,
+                     const std::vector<double> &Nrm, hipStream_t st);
+
+}  // namespace
+
+extern "C" hm_status hm_build(const double *x, int64_t nx, const double *y, int64_t ny,
+                              const double *normals, const hm_params *p, void *stream,
+                              hm_matrix **out) {
+    if (out) *out = nullptr;
+    hm::set_error("");
+    HM_API_BEGIN
+    require(out != nullptr, "out is NULL");
+    require(p != nullptr, "params is NULL");
+    require(x != nullptr && nx >= 1, "x must be non-NULL with nx >= 1");
+    require(p->kernel == HM_KERNEL_U || p->kernel == HM_KERNEL_T, "unknown kernel");
+    require(p->prec == HM_C128 || p->prec == HM_C64, "unknown precision");
+    require(std::isfinite(p->omega) && p->omega >= 0, "omega must be finite and >= 0");
+    require(std::isfinite(p->mu) && p->mu > 0, "mu must be > 0");
+    require(std::isfinite(p->rho) && p->rho > 0, "rho must be > 0");
+    require(std::isfinite(p->lambda) && p->lambda + 2 * p->mu > 0, "lambda + 2 mu must be > 0");
+    require(std::isfinite(p->eta) && p->eta >= 0, "eta must be >= 0");
+    require(std::isfinite(p->eps) && p->eps > 0 && p->eps < 1, "eps must lie in (0, 1)");
+    require(p->leaf >= 1, "leaf must be >= 1");
+    require(nx < (int64_t)1 << 30, "too many points");
+    if (p->same) {
+        ny = nx;
+    } else {
+        require(y != nullptr && ny >= 1, "y must be non-NULL with ny >= 1 when same == 0");
+        require(ny < (int64_t)1 << 30, "too many points");
+    }
+    if (p->kernel == HM_KERNEL_T) require(normals != nullptr, "normals are required for T");
+    const bool on_host = p->points_on_host != 0;
+    auto M = std::make_unique<hm_matrix>();
+    M->p = *p;
+    M->nx = nx;
+    M->ny = ny;
+    M->plan_only = p->plan_only != 0;
+    const double t0 = now_s();
+    std::vector<double> X = fetch_points(x, nx, on_host, "x");
+    std::vector<double> Y, Nrm;
+    if (!p->same) Y = fetch_points(y, ny, on_host, "y");
+    if (p->kernel == HM_KERNEL_T) Nrm = fetch_points(normals, ny, on_host, "normals");
+    M->tx = build_cluster_tree(X.data(), nx, p->leaf);
+    if (!p->same) M->ty = build_cluster_tree(Y.data(), ny, p->leaf);
+    M->blocks = build_block_tree(M->tx, M->coltree(), p->eta);
+    const double t1 = now_s();
+    const ClusterTree &tx = M->rowtree(), &ty = M->coltree();
+    const int64_t nb = (int64_t)M->blocks.size();
+    M->rank.assign(nb, -1);
+    M->rank_aca.assign(nb, -1);
+    hm_stats &S = M->stats;
+    S.nx = nx;
+    S.ny = ny;
+    S.nodes_x = tx.nodes();
+    S.nodes_y = ty.nodes();
+    auto count_leaves = [](const ClusterTree &t) {
+        int32_t c = 0;
+        for (int32_t v = 0; v < t.nodes(); ++v) c += t.is_leaf(v);
+        return c;
+    };
+    S.leaves_x = count_leaves(tx);
+    S.leaves_y = count_leaves(ty);
+    S.levels_x = 1 + *std::max_element(tx.depth.begin(), tx.depth.end());
+    S.levels_y = 1 + *std::max_element(ty.depth.begin(), ty.depth.end());
+    S.n_blocks = nb;
+    std::vector<int32_t> crow(tx.nodes(), 0), ccol(ty.nodes(), 0);
+    for (const auto &b : M->blocks) {
+        (b.kind == BLOCK_DENSE ? S.n_dense : S.n_lowrank)++;
+        crow[b.row]++;
+        ccol[b.col]++;
+    }
+    S.c_sp = std::max(*std::max_element(crow.begin(), crow.end()),
+                      *std::max_element(ccol.begin(), ccol.end()));
+    S.prec = p->prec;
+    S.t_tree = t1 - t0;
+    if (!M->plan_only) {
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        if (p->prec == HM_C64)
+            assemble_device<float>(M.get(), X, Y, Nrm, st);
+        else
+            assemble_device<double>(M.get(), X, Y, Nrm, st);
+    }
+    S.t_total = now_s() - t0;
+    *out = M.release();
+    return HM_OK;
+    HM_API_END
+}
+
+namespace {
+
+template <typename R>
+void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vector<double> &Y,
+                     const std::vector<double> &Nrm, hipStream_t st) {
+    const hm_params &p = M->p;
+    const ClusterTree &tx = M->rowtree(), &ty = M->coltree();
+    hm_stats &S = M->stats;
+    const int64_t nx = M->nx, ny = M->ny;
+    double t = now_s();
+    // ---- geometry in cluster order, SoA float64 ------------------------
+    {
+        const size_t n_geo = 3 * nx + (p.same ? 0 : 3 * ny) + (p.kernel == HM_KERNEL_T ? 3 * ny : 0);
+        std::vector<double> h(n_geo);
+        for (int a = 0; a < 3; ++a)
+            for (int64_t k = 0; k < nx; ++k) h[a * nx + k] = X[3 * (int64_t)tx.perm[k] + a];
+        size_t off = 3 * nx;
+        if (!p.same) {
+            for (int a = 0; a < 3; ++a)
+                for (int64_t k = 0; k < ny; ++k) h[off + a * ny + k] = Y[3 * (int64_t)ty.perm[k] + a];
+            off += 3 * ny;
+        }
+        if (p.kernel == HM_KERNEL_T)
+            for (int a = 0; a < 3; ++a)
+                for (int64_t k = 0; k < ny; ++k) h[off + a * ny + k] = Nrm[3 * (int64_t)ty.perm[k] + a];
+        upload(M->geo, h, st);
+        upload(M->perm_x, tx.perm, st);
+        if (!p.same) upload(M->perm_y, ty.perm, st);
+    }
+    const Geometry g = M->geometry();
+    const GreenParams<R> gp = make_green_params<R>(p.kernel, p.omega, p.lambda, p.mu, p.rho);
+    HM_HIP_CHECK(hipStreamSynchronize(st));
+    S.t_upload = now_s() - t;
+    t = now_s();
+    const int64_t nb = (int64_t)M->blocks.size();
+    M->block_slot.assign(nb, -1);
+    M->off_a.assign(nb, -1);
+    M->off_v.assign(nb, -1);
+    // ---- dense near-field tiles ------------------------------------------
+    int64_t dense_entries = 0;
+    for (int64_t b = 0; b < nb; ++b) {
+        const Block &B = M->blocks[b];
+        if (B.kind != BLOCK_DENSE) continue;
+        DenseBlk d;
+        d.off = dense_entries;
+        d.rb = tx.begin[B.row];
+        d.m = tx.size(B.row);
+        d.cb = ty.begin[B.col];
+        d.n = ty.size(B.col);
+        M->block_slot[b] = (int32_t)M->h_dblk.size();
+        M->off_a[b] = d.off;
+        M->h_dblk.push_back(d);
+        dense_entries += 9 * (int64_t)d.m * d.n;
+    }
+    M->n_dblk = (int32_t)M->h_dblk.size();
+    M->dense.alloc(std::max<int64_t>(dense_entries, 1) * sizeof(cplx<R>));
+    upload(M->d_dblk, M->h_dblk, st);
+    DeviceBuf derr;
+    derr.alloc(sizeof(int32_t));
+    HM_HIP_CHECK(hipMemsetAsync(derr.p, 0, sizeof(int32_t), st));
+    launch_nearfield<R>(g, gp, M->d_dblk.as<DenseBlk>(), M->n_dblk, M->dense.as<cplx<R>>(),
+                        R(p.self_re), R(p.self_im), derr.as<int32_t>(), st);
+    int32_t nerr = 0;
+    HM_HIP_CHECK(hipMemcpyAsync(&nerr, derr.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HM_HIP_CHECK(hipStreamSynchronize(st));
+    if (nerr) throw StatusError(HM_ERR_SINGULAR, std::to_string(nerr) +
+                                                     " coincident point pairs outside self blocks");
+    S.dense_entries = dense_entries;
+    S.t_nearfield = now_s() - t;
+    t = now_s();
+    // ---- vector ACA on admissible blocks -----------------------------------
+    std::vector<int64_t> lr_ids;
+    for (int64_t b = 0; b < nb; ++b)
+        if (M->blocks[b].kind == BLOCK_LOWRANK) lr_ids.push_back(b);
+    const int64_t nlr = (int64_t)lr_ids.size();
+    double tau_piv = p.tau_piv > 0 ? p.tau_piv : (sizeof(R) == 4 ? 1e-4 : 1e-8);
+    const int32_t def_budget = p.rank_budget > 0 ? p.rank_budget : 96;
+    std::vector<int32_t> budget(nlr), lm(nlr), ln(nlr);
+    for (int64_t k = 0; k < nlr; ++k) {
+        const Block &B = M->blocks[lr_ids[k]];
+        lm[k] = tx.size(B.row);
+        ln[k] = ty.size(B.col);
+        const int32_t full = 3 * std::min(lm[k], ln[k]);
+        budget[k] = std::min(full, std::max(def_budget, 3));
+        budget[k] = std::max(3, budget[k] - budget[k] % 3);
+    }
+    // Per low-rank block: which pass holds its factors, and where.
+    std::vector<int32_t> pass_of(nlr, -1), aca_rank(nlr, 0);
+    std::vector<int64_t> aca_u(nlr), aca_v(nlr);
+    std::vector<std::unique_ptr<DeviceBuf>> pass_scratch;
+    std::vector<std::vector<int64_t>> pass_members;
+    std::vector<int64_t> todo(nlr);
+    std::iota(todo.begin(), todo.end(), 0);
+    int32_t overflow = 0, fallbacks = 0;
+    while (!todo.empty()) {
+        // longest first (cost ~ budget * (m + n))
+        std::stable_sort(todo.begin(), todo.end(), [&](int64_t a, int64_t b) {
+            return (int64_t)(lm[a] + ln[a]) * budget[a] > (int64_t)(lm[b] + ln[b]) * budget[b];
+        });
+        std::vector<AcaBlk> ab(todo.size());
+        int64_t fac = 0, flg = 0;
+        int32_t maxb = 3;
+        for (size_t q = 0; q < todo.size(); ++q) {
+            const int64_t k = todo[q];
+            const Block &B = M->blocks[lr_ids[k]];
+            AcaBlk &a = ab[q];
+            a.rb = tx.begin[B.row];
+            a.m = lm[k];
+            a.cb = ty.begin[B.col];
+            a.n = ln[k];
+            a.budget = budget[k];
+            a.uoff = fac;
+            fac += 3 * (int64_t)a.m * a.budget;
+            a.voff = fac;
+            fac += 3 * (int64_t)a.n * a.budget;
+            a.foff = flg;
+            flg += a.m + a.n;
+            maxb = std::max(maxb, a.budget);
+        }
+        auto scratch = std::make_unique<DeviceBuf>();
+        scratch->alloc(std::max<int64_t>(fac, 1) * sizeof(cplx<R>));
+        DeviceBuf flags, d_ab, d_out;
+        flags.alloc(std::max<int64_t>(flg, 1));
+        upload(d_ab, ab, st);
+        d_out.alloc(ab.size() * sizeof(AcaOut));
+        run_aca<R>(g, gp, ab, d_ab.as<AcaBlk>(), scratch->as<cplx<R>>(), flags.as<uint8_t>(),
+                   d_out.as<AcaOut>(), p.eps, tau_piv, maxb, st);
+        std::vector<AcaOut> res(ab.size());
+        HM_HIP_CHECK(hipMemcpyAsync(res.data(), d_out.p, res.size() * sizeof(AcaOut),
+                                    hipMemcpyDeviceToHost, st));
+        HM_HIP_CHECK(hipStreamSynchronize(st));
+        std::vector<int64_t> next;
+        const int32_t pass = (int32_t)pass_scratch.size();
+        pass_members.emplace_back();
+        for (size_t q = 0; q < todo.size(); ++q) {
+            const int64_t k = todo[q];
+            if (res[q].status == 1) {
+                ++overflow;
+                budget[k] = std::min(3 * std::min(lm[k], ln[k]), 2 * budget[k]);
+                next.push_back(k);
+                continue;
+            }
+            pass_of[k] = pass;
+            aca_rank[k] = res[q].rank;
+            aca_u[k] = ab[q].uoff;
+            aca_v[k] = ab[q].voff;
+            fallbacks += res[q].fallbacks;
+            pass_members[pass].push_back(k);
+        }
+        pass_scratch.push_back(std::move(scratch));
+        todo.swap(next);
+    }
+    S.n_overflow = overflow;
+    S.n_fallback = fallbacks;
+    HM_HIP_CHECK(hipStreamSynchronize(st));
+    S.t_aca = now_s() - t;
+    t = now_s();
+    // ---- recompression -------------------------------------------------------
+    std::vector<int32_t> final_rank(nlr);
+    std::vector<std::unique_ptr<DeviceBuf>> pass_work(pass_scratch.size());
+    std::vector<std::unique_ptr<DeviceBuf>> pass_newrank(pass_scratch.size());
+    std::vector<std::vector<RcBlk>> pass_rc(pass_scratch.size());
+    std::vector<std::unique_ptr<DeviceBuf>> pass_drc(pass_scratch.size());
+    for (size_t ps = 0; ps < pass_scratch.size(); ++ps) {
+        auto &mem = pass_members[ps];
+        auto &rc = pass_rc[ps];
+        int64_t goff = 0;
+        for (int64_t k : mem) {
+            RcBlk c;
+            c.uoff = aca_u[k];
+            c.voff = aca_v[k];
+            c.m = lm[k];
+            c.n = ln[k];
+            c.r = aca_rank[k];
+            c.goff = goff;
+            goff += 7 * (int64_t)c.r * c.r;
+            rc.push_back(c);
+        }
+        pass_drc[ps] = std::make_unique<DeviceBuf>();
+        upload(*pass_drc[ps], rc, st);
+        pass_newrank[ps] = std::make_unique<DeviceBuf>();
+        pass_newrank[ps]->alloc(std::max<size_t>(rc.size(), 1) * sizeof(int32_t));
+        if (p.recompress && !rc.empty()) {
+            pass_work[ps] = std::make_unique<DeviceBuf>();
+            pass_work[ps]->alloc(std::max<int64_t>(goff, 1) * sizeof(cplx<double>));
+            run_recompress<R>(rc, pass_drc[ps]->as<RcBlk>(), pass_scratch[ps]->as<cplx<R>>(),
+                              pass_work[ps]->as<double>(), pass_newrank[ps]->as<int32_t>(), p.eps,
+                              0, st);
+            std::vector<int32_t> nr(rc.size());
+            HM_HIP_CHECK(hipMemcpyAsync(nr.data(), pass_newrank[ps]->p, nr.size() * sizeof(int32_t),
+                                        hipMemcpyDeviceToHost, st));
+            HM_HIP_CHECK(hipStreamSynchronize(st));
+            for (size_t q = 0; q < mem.size(); ++q) final_rank[mem[q]] = nr[q];
+        } else {
+            for (size_t q = 0; q < mem.size(); ++q) final_rank[mem[q]] = aca_rank[mem[q]];
+        }
+    }
+    // Final compact slab in block order.
+    int64_t lr_entries = 0, t_len = 0;
+    std::vector<int64_t> fu(nlr), fv(nlr);
+    for (int64_t k = 0; k < nlr; ++k) {
+        fu[k] = lr_entries;
+        lr_entries += 3 * (int64_t)lm[k] * final_rank[k];
+        fv[k] = lr_entries;
+        lr_entries += 3 * (int64_t)ln[k] * final_rank[k];
+    }
+    M->lowrank.alloc(std::max<int64_t>(lr_entries, 1) * sizeof(cplx<R>));
+    for (size_t ps = 0; ps < pass_scratch.size(); ++ps) {
+        auto &mem = pass_members[ps];
+        if (mem.empty()) continue;
+        std::vector<int64_t> ou(mem.size()), ov(mem.size());
+        int32_t maxrows = 0;
+        for (size_t q = 0; q < mem.size(); ++q) {
+            ou[q] = fu[mem[q]];
+            ov[q] = fv[mem[q]];
+            maxrows = std::max(maxrows, 3 * std::max(lm[mem[q]], ln[mem[q]]));
+        }
+        DeviceBuf d_ou, d_ov;
+        upload(d_ou, ou, st);
+        upload(d_ov, ov, st);
+        if (p.recompress) {
+            run_recompress_apply<R>(pass_rc[ps], pass_drc[ps]->as<RcBlk>(),
+                                    pass_scratch[ps]->as<cplx<R>>(), pass_work[ps]->as<double>(),
+                                    d_ou.as<int64_t>(), d_ov.as<int64_t>(),
+                                    pass_newrank[ps]->as<int32_t>(), M->lowrank.as<cplx<R>>(),
+                                    maxrows, st);
+        } else {
+            hipLaunchKernelGGL(copy_factors_kernel<R>, dim3(64, (unsigned)mem.size()), dim3(256), 0,
+                               st, pass_drc[ps]->as<RcBlk>(), pass_scratch[ps]->as<cplx<R>>(),
+                               d_ou.as<int64_t>(), d_ov.as<int64_t>(), M->lowrank.as<cplx<R>>());
+            HM_HIP_CHECK(hipGetLastError());
+        }
+        HM_HIP_CHECK(hipStreamSynchronize(st));
+        pass_work[ps].reset();
+        pass_scratch[ps].reset();
+    }
+    S.t_recompress = now_s() - t;
+    t = now_s();
+    // ---- matvec plan -----------------------------------------------------------
+    int32_t maxr_aca = 0, maxr = 0;
+    int64_t sr_aca = 0, sr = 0;
+    for (int64_t k = 0; k < nlr; ++k) {
+        const int64_t b = lr_ids[k];
+        const Block &B = M->blocks[b];
+        LowRankBlk L;
+        L.uoff = fu[k];
+        L.voff = fv[k];
+        L.toff = t_len;
+        L.rb = tx.begin[B.row];
+        L.m = lm[k];
+        L.cb = ty.begin[B.col];
+        L.n = ln[k];
+        L.r = final_rank[k];
+        L.pad = 0;
+        t_len += L.r;
+        M->block_slot[b] = (int32_t)M->h_lblk.size();
+        M->off_a[b] = L.uoff;
+        M->off_v[b] = L.voff;
+        M->h_lblk.push_back(L);
+        M->rank[b] = final_rank[k];
+        M->rank_aca[b] = aca_rank[k];
+        maxr_aca = std::max(maxr_aca, aca_rank[k]);
+        maxr = std::max(maxr, final_rank[k]);
+        sr_aca += aca_rank[k];
+        sr += final_rank[k];
+    }
+    M->n_lblk = (int32_t)M->h_lblk.size();
+    M->t_len = t_len;
+    // tasks per leaf row cluster
+    std::vector<int32_t> leaf_index(tx.nodes(), -1);
+    std::vector<LeafRow> leaves;
+    for (int32_t v = 0; v < tx.nodes(); ++v)
+        if (tx.is_leaf(v)) {
+            leaf_index[v] = (int32_t)leaves.size();
+            leaves.push_back({tx.begin[v], tx.size(v), 0, 0});
+        }
+    std::vector<std::vector<Task>> per_leaf(leaves.size());
+    std::vector<int32_t> lv;
+    for (int64_t b = 0; b < nb; ++b) {
+        const Block &B = M->blocks[b];
+        lv.clear();
+        leaves_under(tx, B.row, lv);
+        for (int32_t L : lv) {
+            Task tk;
+            tk.kind = B.kind == BLOCK_DENSE ? 0 : 1;
+            tk.idx = M->block_slot[b];
+            tk.rowoff = tx.begin[L] - tx.begin[B.row];
+            tk.pad = 0;
+            per_leaf[leaf_index[L]].push_back(tk);
+        }
+    }
+    std::vector<Task> tasks;
+    for (size_t l = 0; l < leaves.size(); ++l) {
+        leaves[l].tbeg = (int32_t)tasks.size();
+        tasks.insert(tasks.end(), per_leaf[l].begin(), per_leaf[l].end());
+        leaves[l].tend = (int32_t)tasks.size();
+    }
+    M->n_leaves = (int32_t)leaves.size();
+    upload(M->d_lblk, M->h_lblk, st);
+    upload(M->d_tasks, tasks, st);
+    upload(M->d_leaves, leaves, st);
+    M->ws_xc.alloc(3 * std::max(nx, ny) * sizeof(cplx<double>));
+    M->ws_t.alloc(std::max<int64_t>(t_len, 1) * sizeof(cplx<double>));
+    HM_HIP_CHECK(hipStreamSynchronize(st));
+    S.t_plan = now_s() - t;
+    S.lowrank_entries = lr_entries;
+    S.max_rank_aca = maxr_aca;
+    S.max_rank = maxr;
+    S.sum_rank_aca = sr_aca;
+    S.sum_rank = sr;
+    S.storage_bytes = (dense_entries + lr_entries) * (int64_t)sizeof(cplx<R>);
+    S.matvec_bytes = S.storage_bytes + (3 * nx + 3 * ny) * (int64_t)sizeof(cplx<R>);
+}
+
+}  // namespace
+
+extern "C" hm_status hm_matvec(const hm_matrix *A, const void *x, void *y, int32_t nrhs,
+                               void *stream) {
+    HM_API_BEGIN
+    require(A != nullptr && x != nullptr && y != nullptr, "NULL argument");
+    require(nrhs >= 1, "nrhs must be >= 1");
+    if (A->plan_only) throw StatusError(HM_ERR_STATE, "matrix was built with plan_only");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    for (int32_t c = 0; c < nrhs; ++c) {
+        if (A->p.prec == HM_C64)
+            launch_matvec_col<float, float>(A, x, nrhs, c, y, nrhs, nullptr, st);
+        else
+            launch_matvec_col<double, double>(A, x, nrhs, c, y, nrhs, nullptr, st);
+    }
+    return HM_OK;
+    HM_API_END
+}
+
+extern "C" hm_status hm_residual(const hm_matrix *A, const void *b, const void *x, void *r,
+                                 int32_t nrhs, void *stream) {
+    HM_API_BEGIN
+    require(A != nullptr && b != nullptr && x != nullptr && r != nullptr, "NULL argument");
+    require(nrhs >= 1, "nrhs must be >= 1");
+    if (A->plan_only) throw StatusError(HM_ERR_STATE, "matrix was built with plan_only");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    for (int32_t c = 0; c < nrhs; ++c) {
+        if (A->p.prec == HM_C64)
+            launch_matvec_col<float, double>(A, x, nrhs, c, r, nrhs,
+                                             static_cast<const double *>(b), st);
+        else
+            launch_matvec_col<double, double>(A, x, nrhs, c, r, nrhs,
+                                              static_cast<const double *>(b), st);
+    }
+    return HM_OK;
+    HM_API_END
+}
+
+extern "C" hm_status hm_profile_matvec(const hm_matrix *A, const void *x, void *y, int32_t reps,
+                                       void *stream, double *kernel_ms, int64_t *kernel_bytes) {
+    HM_API_BEGIN
+    require(A != nullptr && x != nullptr && y != nullptr && reps >= 1, "bad arguments");
+    if (A->plan_only) throw StatusError(HM_ERR_STATE, "matrix was built with plan_only");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    double ms[3] = {0, 0, 0};
+    for (int32_t k = 0; k < reps; ++k) {
+        if (A->p.prec == HM_C64)
+            profile_matvec_col<float>(A, x, y, st, ms);
+        else
+            profile_matvec_col<double>(A, x, y, st, ms);
+    }
+    const int64_t es = (int64_t)elem_bytes(A->p.prec);
+    int64_t vbytes = 0, ubytes = 0;
+    for (const auto &L : A->h_lblk) {
+        vbytes += 3 * (int64_t)L.n * L.r * es;
+        ubytes += 3 * (int64_t)L.m * L.r * es;
+    }
+    const int64_t dbytes = A->stats.dense_entries * es;
+    if (kernel_ms)
+        for (int k = 0; k < 3; ++k) kernel_ms[k] = ms[k] / reps;
+    if (kernel_bytes) {
+        kernel_bytes[0] = 3 * A->ny * es;               // x read
+        kernel_bytes[1] = vbytes;                       // V factors
+        kernel_bytes[2] = dbytes + ubytes + 3 * A->nx * es;  // tiles + U factors + y write
+    }
+    return HM_OK;
+    HM_API_END
+}
+
+extern "C" hm_status hm_info(const hm_matrix *A, hm_stats *s) {
+    if (!A || !s) return HM_ERR_ARG;
+    *s = A->stats;
+    return HM_OK;
+}
+
+extern "C" hm_status hm_export_tree(const hm_matrix *A, int32_t which, int32_t *perm,
+                                    int32_t *nodes, double *boxes) {
+    HM_API_BEGIN
+    require(A != nullptr, "NULL matrix");
+    require(which == 0 || which == 1, "which must be 0 or 1");
+    const ClusterTree &t = which == 0 ? A->rowtree() : A->coltree();
+    if (perm) std::memcpy(perm, t.perm.data(), t.perm.size() * sizeof(int32_t));
+    for (int32_t v = 0; v < t.nodes(); ++v) {
+        if (nodes) {
+            nodes[5 * v + 0] = t.begin[v];
+            nodes[5 * v + 1] = t.end[v];
+            nodes[5 * v + 2] = t.left[v];
+            nodes[5 * v + 3] = t.right[v];
+            nodes[5 * v + 4] = t.depth[v];
+        }
+        if (boxes)
+            for (int a = 0; a < 3; ++a) {
+                boxes[6 * v + a] = t.lo[3 * v + a];
+                boxes[6 * v + 3 + a] = t.hi[3 * v + a];
+            }
+    }
+    return HM_OK;
+    HM_API_END
+}
+
+extern "C" hm_status hm_export_blocklist(const hm_matrix *A, int32_t *blocks, int32_t *rank,
+                                         int32_t *rank_aca) {
+    HM_API_BEGIN
+    require(A != nullptr, "NULL matrix");
+    for (size_t b = 0; b < A->blocks.size(); ++b) {
+        if (blocks) {
+            blocks[3 * b] = A->blocks[b].row;
+            blocks[3 * b + 1] = A->blocks[b].col;
+            blocks[3 * b + 2] = A->blocks[b].kind;
+        }
+        if (rank) rank[b] = A->rank[b];
+        if (rank_aca) rank_aca[b] = A->rank_aca[b];
+    }
+    return HM_OK;
+    HM_API_END
+}
+
+extern "C" hm_status hm_export_block(const hm_matrix *A, int64_t b, void *host_buf) {
+    HM_API_BEGIN
+    require(A != nullptr && host_buf != nullptr, "NULL argument");
+    require(b >= 0 && b < (int64_t)A->blocks.size(), "block index out of range");
+    if (A->plan_only) throw StatusError(HM_ERR_STATE, "matrix was built with plan_only");
+    const size_t es = elem_bytes(A->p.prec);
+    const Block &B = A->blocks[b];
+    const int64_t m = A->rowtree().size(B.row), n = A->coltree().size(B.col);
+    if (B.kind == BLOCK_DENSE) {
+        HM_HIP_CHECK(hipMemcpy(host_buf, static_cast<char *>(A->dense.p) + A->off_a[b] * es,
+                               9 * m * n * es, hipMemcpyDeviceToHost));
+    } else {
+        const int64_t r = A->rank[b];
+        char *h = static_cast<char *>(host_buf);
+        if (r > 0) {
+            HM_HIP_CHECK(hipMemcpy(h, static_cast<char *>(A->lowrank.p) + A->off_a[b] * es,
+                                   3 * m * r * es, hipMemcpyDeviceToHost));
+            HM_HIP_CHECK(hipMemcpy(h + 3 * m * r * es,
+                                   static_cast<char *>(A->lowrank.p) + A->off_v[b] * es,
+                                   3 * n * r * es, hipMemcpyDeviceToHost));
+        }
+    }
+    return HM_OK;
+    HM_API_END
+}
+
+extern "C" void hm_destroy(hm_matrix *A) { delete A; }

@@ -1,0 +1,171 @@
+// Device evaluation of the 3x3 elastodynamic Green's tensors U and T.
+//
+// U = (1/mu)[G_ks I + ks^-2 Hess(G_ks - G_kp)] (eq. elasto_U rewritten with
+// curl curl = grad div - Laplace), G_k = e^{ikr}/(4 pi r).  With d = x - y,
+// r = |d|, dh = d/r, a = ks r, q = kp/ks:
+//   U_ab = (A delta_ab + B dh_a dh_b) / (4 pi mu r)
+//   A = e^{ia} + (E(a) - E(qa))/a^2,  B = (F(a) - F(qa))/a^2,
+//   E(z) = e^{iz}(iz - 1),  F(z) = e^{iz}(3 - 3iz - z^2).
+// T (traction in y of U with normal n(y), eq. elasto_T / Section 5.3):
+//   T_ab = -[c1 n_a dh_b + c2((dh.n) delta_ab + dh_a n_b) + c3 (dh.n) dh_a dh_b]/(4 pi r^2)
+//   c1 = (lambda/mu)(aA' - A + aB' + B) + 2B, c2 = aA' - A + B, c3 = 2(aB' - 3B).
+// For small a the differences above cancel catastrophically (about
+// 2 log10(1/a) digits), so below a threshold the Taylor series of the same
+// functions is summed instead; every series term carries a factor (1 - q^m)
+// and there is no cancellation.  Threshold / number of terms: 1.0 / 14 in
+// float32, 0.5 / 17 in float64 (truncation below the type's rounding).
+#pragma once
+
+#include "common.hpp"
+
+namespace hm {
+
+template <typename R>
+struct GreenParams {
+    R ks;        // S wavenumber
+    R q;         // kp / ks
+    R q2, q3;
+    R lam_mu;    // lambda / mu
+    R inv4pimu;  // 1 / (4 pi mu)
+    R inv4pi;
+    int kind;    // 0 = U, 1 = T
+};
+
+template <typename R>
+struct SeriesCfg;
+template <>
+struct SeriesCfg<float> {
+    static constexpr float below = 1.0f;
+    static constexpr int last = 15;
+};
+template <>
+struct SeriesCfg<double> {
+    static constexpr double below = 0.5;
+    static constexpr int last = 18;
+};
+
+__device__ inline void sincos_(float a, float *s, float *c) { sincosf(a, s, c); }
+__device__ inline void sincos_(double a, double *s, double *c) { sincos(a, s, c); }
+
+// Radial coefficient functions A, B, aA', aB' of the closed forms.
+template <typename R>
+__device__ inline void radial_coeffs(R a, const GreenParams<R> &g, cplx<R> &A, cplx<R> &B,
+                                     cplx<R> &aAp, cplx<R> &aBp) {
+    R sa, ca;
+    sincos_(a, &sa, &ca);
+    if (a < SeriesCfg<R>::below) {
+        // t_m = i^m (1 - q^m) a^{m-2}/m!, summed with weights (m-1), (m-1)(m-3),
+        // (m-1)(m-2), (m-1)(m-2)(m-3).
+        R sAr = 0, sAi = 0, sBr = 0, sBi = 0, sPr = 0, sPi = 0, sQr = 0, sQi = 0;
+        R qm = g.q2, am = 1, fact = 2;
+#pragma unroll
+        for (int m = 2; m <= SeriesCfg<R>::last; ++m) {
+            const R c = (R(1) - qm) * am / fact;
+            const R w1 = R(m - 1), w3 = R((m - 1) * (m - 3)), w2 = R((m - 1) * (m - 2)),
+                    w4 = R((m - 1) * (m - 2) * (m - 3));
+            switch (m & 3) {
+                case 0: sAr += w1 * c; sBr += w3 * c; sPr += w2 * c; sQr += w4 * c; break;
+                case 1: sAi += w1 * c; sBi += w3 * c; sPi += w2 * c; sQi += w4 * c; break;
+                case 2: sAr -= w1 * c; sBr -= w3 * c; sPr -= w2 * c; sQr -= w4 * c; break;
+                default: sAi -= w1 * c; sBi -= w3 * c; sPi -= w2 * c; sQi -= w4 * c; break;
+            }
+            qm *= g.q;
+            am *= a;
+            fact *= R(m + 1);
+        }
+        A = {ca + sAr, sa + sAi};
+        B = {sBr, sBi};
+        aAp = {-a * sa + sPr, a * ca + sPi};
+        aBp = {sQr, sQi};
+        return;
+    }
+    const R qa = g.q * a;
+    R sq, cq;
+    sincos_(qa, &sq, &cq);
+    const R ia2 = R(1) / (a * a);
+    // E(z) = e^{iz}(iz - 1)
+    const R Ear = -ca - a * sa, Eai = a * ca - sa;
+    const R Eqr = -cq - qa * sq, Eqi = qa * cq - sq;
+    const R dEr = (Ear - Eqr) * ia2, dEi = (Eai - Eqi) * ia2;
+    // F(z) = e^{iz}((3 - z^2) - 3iz)
+    const R a2 = a * a, qa2 = qa * qa;
+    const R Far = ca * (R(3) - a2) + R(3) * a * sa, Fai = sa * (R(3) - a2) - R(3) * a * ca;
+    const R Fqr = cq * (R(3) - qa2) + R(3) * qa * sq, Fqi = sq * (R(3) - qa2) - R(3) * qa * cq;
+    A = {ca + dEr, sa + dEi};
+    B = {(Far - Fqr) * ia2, (Fai - Fqi) * ia2};
+    // aA' = i a e^{ia} - e^{ia} + q^2 e^{iqa} - 2 dE
+    aAp = {-a * sa - ca + g.q2 * cq - R(2) * dEr, a * ca - sa + g.q2 * sq - R(2) * dEi};
+    // aB' = e^{ia}(1 - ia) - q^2 e^{iqa}(1 - iqa) - 2B
+    aBp = {(ca + a * sa) - g.q2 * (cq + qa * sq) - R(2) * B.re,
+           (sa - a * ca) - g.q2 * (sq - qa * cq) - R(2) * B.im};
+}
+
+// 3x3 block, row-major out[3a + b].  d = x - y (nonzero), n = unit normal at y.
+template <typename R>
+__device__ inline void green_block(const GreenParams<R> &g, R dx, R dy, R dz, R nx, R ny, R nz,
+                                   cplx<R> out[9]) {
+    const R r2 = dx * dx + dy * dy + dz * dz;
+    const R r = sqrt(r2);
+    const R ir = R(1) / r;
+    const R d[3] = {dx * ir, dy * ir, dz * ir};
+    cplx<R> A, B, aAp, aBp;
+    radial_coeffs<R>(g.ks * r, g, A, B, aAp, aBp);
+    if (g.kind == 0) {
+        const R s = g.inv4pimu * ir;
+        const cplx<R> sA = s * A, sB = s * B;
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = a; b < 3; ++b) {
+                const R dd = d[a] * d[b];
+                cplx<R> v = dd * sB;
+                if (a == b) v = v + sA;
+                out[3 * a + b] = v;
+                out[3 * b + a] = v;
+            }
+        return;
+    }
+    const R n[3] = {nx, ny, nz};
+    const R dn = d[0] * nx + d[1] * ny + d[2] * nz;
+    const cplx<R> c1 = g.lam_mu * (aAp - A + aBp + B) + R(2) * B;
+    const cplx<R> c2 = aAp - A + B;
+    const cplx<R> c3 = R(2) * (aBp - R(3) * B);
+    const R s = -g.inv4pi * ir * ir;
+    const cplx<R> s1 = s * c1, s2 = s * c2, s3 = (s * dn) * c3;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            cplx<R> v = (n[a] * d[b]) * s1 + (d[a] * n[b]) * s2 + (d[a] * d[b]) * s3;
+            if (a == b) v = v + dn * s2;
+            out[3 * a + b] = v;
+        }
+}
+
+template <typename R>
+inline GreenParams<R> make_green_params(int kind, double omega, double lambda, double mu,
+                                        double rho) {
+    const double ks = omega * std::sqrt(rho / mu);
+    const double kp = omega * std::sqrt(rho / (lambda + 2.0 * mu));
+    const double q = ks > 0 ? kp / ks : std::sqrt(mu / (lambda + 2.0 * mu));
+    GreenParams<R> g;
+    g.ks = R(ks);
+    g.q = R(q);
+    g.q2 = R(q * q);
+    g.q3 = R(q * q * q);
+    g.lam_mu = R(lambda / mu);
+    g.inv4pimu = R(1.0 / (4.0 * M_PI * mu));
+    g.inv4pi = R(1.0 / (4.0 * M_PI));
+    g.kind = kind;
+    return g;
+}
+
+// Cluster-ordered structure-of-arrays geometry in HBM.
+struct Geometry {
+    const double *x[3];   // row points
+    const double *y[3];   // column points
+    const double *n[3];   // normals at column points (T only)
+    int same;
+};
+
+}  // namespace hm

@@ -1,0 +1,144 @@
+// Internal structures of the hmat library shared by the API layer and the
+// kernel translation units.
+#pragma once
+
+#include <memory>
+#include <vector>
+
+#include "common.hpp"
+#include "green.hpp"
+#include "tree.hpp"
+
+namespace hm {
+
+// Dense near-field tile: rows rb..rb+m (row cluster order), cols cb..cb+n,
+// stored column-major (3m x 3n) at `off` complex elements into the dense slab.
+struct DenseBlk {
+    int64_t off;
+    int32_t rb, m, cb, n;
+};
+
+// Low-rank block U V^*: U (3m x r) at uoff, V (3n x r) at voff, column-major,
+// t-vector slot at toff (r entries per right-hand side).
+struct LowRankBlk {
+    int64_t uoff, voff, toff;
+    int32_t rb, m, cb, n, r, pad;
+};
+
+// Work item of a leaf row cluster: kind 0 = dense block index, 1 = low-rank
+// block index; rowoff = first row of the leaf inside the block (points).
+struct Task {
+    int32_t kind, idx, rowoff, pad;
+};
+
+struct LeafRow {
+    int32_t rb, m, tbeg, tend;
+};
+
+// ACA work description for one admissible block.
+struct AcaBlk {
+    int64_t uoff, voff;   // scratch factor offsets (complex elements)
+    int64_t foff;         // offset of the used-flag bytes (m + n)
+    int32_t rb, m, cb, n;
+    int32_t budget;       // column budget
+    int32_t pad;
+};
+
+struct AcaOut {
+    int32_t rank;
+    int32_t status;       // 0 converged, 1 budget exhausted, 2 full rank
+    int32_t fallbacks;
+    int32_t steps;
+    double norm2;         // recursive ||B_k||_F^2
+};
+
+// Recompression work description.
+struct RcBlk {
+    int64_t uoff, voff;   // ACA factors (scratch slab)
+    int64_t goff;         // r x r FP64 work matrices offset (complex doubles)
+    int32_t m, n, r, pad;
+};
+
+struct DeviceBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    DeviceBuf() = default;
+    DeviceBuf(const DeviceBuf &) = delete;
+    DeviceBuf &operator=(const DeviceBuf &) = delete;
+    ~DeviceBuf() { reset(); }
+    void reset() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    void alloc(size_t b);
+    template <typename T>
+    T *as() const { return static_cast<T *>(p); }
+};
+
+size_t elem_bytes(int prec);  // bytes of one complex element
+
+}  // namespace hm
+
+struct hm_matrix {
+    hm_params p{};
+    int64_t nx = 0, ny = 0;
+    bool plan_only = false;
+    hm::ClusterTree tx, ty;             // ty unused when same
+    std::vector<hm::Block> blocks;
+    std::vector<int32_t> rank, rank_aca;  // per block (-1 for dense)
+    std::vector<int64_t> off_a, off_v;    // per block storage offsets
+    hm_stats stats{};
+
+    // device data
+    hm::DeviceBuf geo;        // 9 SoA float64 arrays (x, y, n)
+    hm::DeviceBuf perm_x, perm_y;
+    hm::DeviceBuf dense;      // dense slab
+    hm::DeviceBuf lowrank;    // U and V factors
+    hm::DeviceBuf d_dblk, d_lblk, d_tasks, d_leaves;
+    int32_t n_dblk = 0, n_lblk = 0, n_leaves = 0;
+    int64_t t_len = 0;        // sum of ranks
+    std::vector<hm::DenseBlk> h_dblk;
+    std::vector<hm::LowRankBlk> h_lblk;
+    std::vector<int32_t> block_slot;  // block id -> index into h_dblk / h_lblk
+
+    // lazily sized work buffers for matvec
+    hm::DeviceBuf ws_xc, ws_t, ws_y;
+
+    const hm::ClusterTree &rowtree() const { return tx; }
+    const hm::ClusterTree &coltree() const { return p.same ? tx : ty; }
+    hm::Geometry geometry() const;
+};
+
+namespace hm {
+
+// ---- kernel launchers (implemented in the .hip files) ----
+template <typename R>
+void launch_nearfield(const Geometry &g, const GreenParams<R> &gp, const DenseBlk *d_blk,
+                      int32_t nblk, cplx<R> *slab, R self_re, R self_im, int32_t *d_err,
+                      hipStream_t st);
+
+// y = A x for one right-hand side column (c of nrhs), S = storage real, A = accumulation
+template <typename S, typename A>
+void launch_matvec_col(const hm_matrix *M, const void *x, int64_t ldx, int32_t col, void *y,
+                       int64_t ldy, const double *b, hipStream_t st);
+
+template <typename S>
+void profile_matvec_col(const hm_matrix *M, const void *x, void *y, hipStream_t st, double *ms3);
+
+template <typename R>
+void run_aca(const Geometry &g, const GreenParams<R> &gp, const std::vector<AcaBlk> &blk,
+             AcaBlk *d_blk, cplx<R> *scratchU, uint8_t *flags, AcaOut *d_out, double eps,
+             double tau_piv, int32_t max_budget, hipStream_t st);
+
+// Recompression of ACA factors in place into compact output.
+template <typename R>
+void run_recompress(const std::vector<RcBlk> &blk, RcBlk *d_blk, const cplx<R> *acaslab,
+                    double *work, int32_t *d_newrank, double eps, int32_t rmax, hipStream_t st);
+
+template <typename R>
+void run_recompress_apply(const std::vector<RcBlk> &blk, RcBlk *d_blk, const cplx<R> *acaslab,
+                          const double *work, const int64_t *d_outu, const int64_t *d_outv,
+                          const int32_t *d_newrank, cplx<R> *out, int32_t rmax, hipStream_t st);
+
+}  // namespace hm

@@ -1,0 +1,298 @@
+"""GPU parity of the HIP path against the FP64 CPU oracle (through the C ABI).
+
+Gates (relative 2-norm errors e = |y_H - y|/|y|):
+* all-dense partition (eta = 0): complex128 <= 1e-12, complex64 <= 2e-6;
+* H-matvec: e <= 5 eps against the dense oracle product;
+* the exported H-matrix re-applied by the oracle (independent CPU code)
+  equals the GPU product: complex128 <= 1e-12, complex64 <= 1e-5;
+* GMRES: FP64 residual of the exported operator <= tol, and on the small
+  case the solution equals the LU solution of the densified operator.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1706_09384_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def hm():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1706_09384_amd import hmat
+    return hmat
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def to_dev(a, dtype=None):
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    return t if dtype is None else t.to(dtype)
+
+
+def export_all(A):
+    blocks, rank, _ = A.export_blocklist()
+    _, nx, _ = A.export_tree(0)
+    _, ny, _ = A.export_tree(1)
+    out = []
+    for b in range(blocks.shape[0]):
+        t, s, k = blocks[b]
+        data = A.export_block(b, blocks, rank, nx, ny)
+        if k == 0:
+            data = data.astype(np.complex128)
+        else:
+            data = (data[0].astype(np.complex128), data[1].astype(np.complex128))
+        out.append((int(t), int(s), int(k), data))
+    return out
+
+
+class _T:
+    def __init__(self, perm, nodes):
+        self.perm = perm.astype(np.int64)
+        self.begin = nodes[:, 0]
+        self.end = nodes[:, 1]
+
+
+def oracle_trees(A):
+    p0, n0, _ = A.export_tree(0)
+    p1, n1, _ = A.export_tree(1)
+    return _T(p0, n0), _T(p1, n1)
+
+
+@pytest.fixture(scope="module")
+def sphere1k(orc):
+    w = W.plain_sphere_1k()
+    X, _ = w.points()
+    pb = orc.Problem.from_workload(w, X)
+    A = orc.dense(pb)
+    b = w.rhs()
+    return w, X, pb, A, b
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 2e-6)])
+def test_all_dense_partition_equals_dense_product(hm, orc, sphere1k, prec, tol):
+    w, X, pb, A, b = sphere1k
+    say(f"case all-dense eta=0 prec={prec} N=1000")
+    H = hm.build_workload(w, X=X, prec=prec, eta=0.0)
+    s = H.info()
+    assert s["n_lowrank"] == 0
+    xb = to_dev(b, H.complex_dtype)
+    y = H.matvec(xb).cpu().numpy().astype(np.complex128)
+    assert rel(y, A @ b) <= tol
+    # every stored tile equals the oracle's entries
+    blocks = export_all(H)
+    tx, ty = oracle_trees(H)
+    worst = 0.0
+    for t, sg, k, D in blocks[::7]:
+        ri = tx.perm[tx.begin[t]:tx.end[t]]
+        ci = ty.perm[ty.begin[sg]:ty.end[sg]]
+        rd = (3 * ri[:, None] + np.arange(3)).ravel()
+        cd = (3 * ci[:, None] + np.arange(3)).ravel()
+        ref = A[np.ix_(rd, cd)]
+        worst = max(worst, np.abs(D - ref).max() / np.abs(ref).max())
+    assert worst <= (1e-13 if prec == 0 else 3e-6)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_sphere1k_matvec_within_5eps(hm, orc, sphere1k, prec):
+    w, X, pb, A, b = sphere1k
+    say(f"case sphere1k matvec prec={prec}")
+    H = hm.build_workload(w, X=X, prec=prec)
+    s = H.info()
+    say("stats", {k: s[k] for k in ("n_dense", "n_lowrank", "max_rank_aca", "max_rank", "n_overflow",
+                                   "n_fallback", "storage_bytes")})
+    assert s["max_rank"] <= s["max_rank_aca"]
+    xb = to_dev(b, H.complex_dtype)
+    y = H.matvec(xb).cpu().numpy().astype(np.complex128)
+    e = rel(y, A @ b)
+    say("e =", e)
+    assert e <= 5 * w.eps
+    # the oracle re-applies the exported operator (independent CPU code)
+    blocks = export_all(H)
+    tx, ty = oracle_trees(H)
+    yo = orc.hmatvec(blocks, tx, ty, b.astype(np.complex64).astype(np.complex128) if prec else b)
+    assert rel(y, yo) <= (1e-12 if prec == 0 else 1e-5)
+    # representation error delta_H,F ~ eps
+    Ad = orc.densify(blocks, tx, ty)
+    dHF = np.linalg.norm(Ad - A) / np.linalg.norm(A)
+    say("delta_H,F =", dHF)
+    assert dHF <= 5 * w.eps
+    # ACA ranks are multiples of 3 when no pivot fallback fired
+    _, rank, rank_aca = H.export_blocklist()
+    lr = rank_aca[rank_aca >= 0]
+    if s["n_fallback"] == 0:
+        assert np.all(lr % 3 == 0)
+    assert np.all(rank[rank_aca >= 0] <= lr)
+
+
+def test_sphere1k_gmres_c128(hm, orc, sphere1k):
+    import torch
+    w, X, pb, A, b = sphere1k
+    say("case sphere1k gmres c128")
+    H = hm.build_workload(w, X=X, prec=0)
+    bb = to_dev(b[:, 0])
+    x, info = H.gmres(bb, tol=1e-6, restart=50, maxit=3000)
+    say("gmres", info)
+    x = x.cpu().numpy()
+    blocks = export_all(H)
+    tx, ty = oracle_trees(H)
+    r = b[:, 0] - orc.hmatvec(blocks, tx, ty, x)
+    assert np.linalg.norm(r) / np.linalg.norm(b) <= 1e-6 * 1.01        # G1
+    Ad = orc.densify(blocks, tx, ty)
+    xs, rcond = orc.lu_solve(Ad, b[:, 0])
+    kappa = 1.0 / rcond
+    assert rel(x, xs) <= 1e-6 * max(1.0, kappa / 1e3) * 10            # G2
+    # reported: backward error against the exact dense operator ~ eps
+    xl, _ = orc.lu_solve(A, b[:, 0])
+    say("backward error vs dense", np.linalg.norm(A @ x - b[:, 0]) / np.linalg.norm(b),
+        "forward vs LU", rel(x, xl))
+
+
+def test_sphere1k_gmres_c64_refined(hm, orc, sphere1k):
+    w, X, pb, A, b = sphere1k
+    say("case sphere1k gmres c64 + FP64 refinement")
+    H = hm.build_workload(w, X=X, prec=1)
+    x, info = H.gmres(to_dev(b[:, 0]), tol=1e-8, restart=50, maxit=6000)
+    say("gmres", info)
+    assert info["refinements"] >= 1
+    x = x.cpu().numpy()
+    blocks = export_all(H)
+    tx, ty = oracle_trees(H)
+    r = b[:, 0] - orc.hmatvec(blocks, tx, ty, x)
+    assert np.linalg.norm(r) / np.linalg.norm(b) <= 1.5e-8
+
+
+def test_residual_is_fp64(hm, orc, sphere1k):
+    w, X, pb, A, b = sphere1k
+    say("case residual fp64")
+    H = hm.build_workload(w, X=X, prec=1)
+    x = w.rhs(1)[:, 0] * 0.3 + 0.1
+    blocks = export_all(H)
+    tx, ty = oracle_trees(H)
+    ref = b[:, 0] - orc.hmatvec(blocks, tx, ty, x)
+    r = H.residual(to_dev(b[:, 0]), to_dev(x)).cpu().numpy()
+    assert rel(r, ref) <= 1e-12
+
+
+@pytest.mark.parametrize("kernel,n,leaf,omega", [(0, 300, 8, 3.0), (1, 300, 8, 3.0), (1, 513, 5, 9.0),
+                                                 (0, 97, 7, 0.5)])
+def test_small_ragged_cases(hm, orc, kernel, n, leaf, omega):
+    """Many tiles, ragged leaves, both kernels, against the dense oracle."""
+    say(f"case small kernel={kernel} n={n} leaf={leaf}")
+    w = W.small_sphere(n, kernel=kernel, omega=omega, leaf=leaf, eps=1e-5)
+    X, N = w.points()
+    pb = orc.Problem.from_workload(w, X, N)
+    A = orc.dense(pb)
+    b = W.complex_normal(3 * n, 2, seed=1)
+    for prec, tol in [(0, 5e-5), (1, 6e-5)]:
+        H = hm.build_workload(w, X=X, N=N, prec=prec)
+        y = H.matvec(to_dev(b, H.complex_dtype)).cpu().numpy().astype(np.complex128)
+        assert rel(y, A @ b) <= tol, (prec, rel(y, A @ b))
+
+
+def test_two_clouds_and_singular_pair(hm, orc):
+    say("case two clouds")
+    X = W.fibonacci_sphere(400)
+    Y = W.uniform_ball(300, seed=2) * 0.6 + np.array([2.2, 0.0, 0.1])
+    pb = orc.Problem(0, X, Y, None, 4.0, same=False)
+    A = orc.dense(pb)
+    b = W.complex_normal(900, 1, seed=3)
+    H = hm.build(to_dev(X), to_dev(Y), kernel=0, omega=4.0, leaf=16, eps=1e-5)
+    y = H.matvec(to_dev(b)).cpu().numpy()
+    assert rel(y, A @ b) <= 5e-5
+    say("case singular pair")
+    Y2 = Y.copy()
+    Y2[5] = X[17]
+    with pytest.raises(hm.HMError) as e:
+        hm.build(to_dev(X), to_dev(np.r_[Y2[:5], X[17:18], Y2[6:]]), kernel=0, omega=4.0, leaf=16,
+                 eta=0.0)
+    assert e.value.status == hm.HM_ERR_SINGULAR
+
+
+def test_edge_sizes(hm, orc):
+    for n in [1, 2, 5]:
+        say(f"case edge n={n}")
+        w = W.small_sphere(n, leaf=3)
+        X, _ = w.points()
+        pb = orc.Problem.from_workload(w, X)
+        A = orc.dense(pb)
+        b = W.complex_normal(3 * n, 1, seed=4)
+        H = hm.build_workload(w, X=X)
+        y = H.matvec(to_dev(b)).cpu().numpy()
+        assert rel(y, A @ b) <= 1e-12
+
+
+def test_tiny_eps_limit(hm, orc, sphere1k):
+    """eps -> 0: the H-matrix becomes exact (eq. stop_full as eps -> 0)."""
+    w, X, pb, A, b = sphere1k
+    say("case eps=1e-11")
+    H = hm.build_workload(w, X=X, prec=0, eps=1e-11)
+    y = H.matvec(to_dev(b)).cpu().numpy()
+    assert rel(y, A @ b) <= 1e-9
+
+
+def test_coplanar_T_uses_pivot_fallback(hm, orc):
+    say("case cube T coplanar")
+    P, Nrm = W.cube_surface(3000, seed=0)
+    w = W.Workload("cube3k", 3000, 1, omega=1.1547, eps=1e-4, leaf=32,
+                   self_re=W._t_self(W.CUBE_AREA, 3000), geometry="cube")
+    H = hm.build_workload(w, X=P, N=Nrm, prec=0)
+    s = H.info()
+    say("fallbacks", s["n_fallback"])
+    assert s["n_fallback"] > 0
+    pb = orc.Problem.from_workload(w, P, Nrm)
+    b = W.complex_normal(9000, 1, seed=5)
+    rows = np.arange(0, 3000, 7)
+    ref = orc.matvec_rows(pb, b, rows)
+    y = H.matvec(to_dev(b)).cpu().numpy()
+    idx = (3 * rows[:, None] + np.arange(3)).ravel()
+    assert rel(y[idx], ref) <= 5 * w.eps * 4     # T: the paper reports ~20 eps for T
+
+
+def test_build_is_deterministic(hm, sphere1k):
+    w, X, pb, A, b = sphere1k
+    say("case determinism")
+    H1 = hm.build_workload(w, X=X, prec=1)
+    H2 = hm.build_workload(w, X=X, prec=1)
+    b1, r1, a1 = H1.export_blocklist()
+    b2, r2, a2 = H2.export_blocklist()
+    assert np.array_equal(r1, r2) and np.array_equal(a1, a2)
+    for k in range(0, b1.shape[0], 37):
+        d1, d2 = H1.export_block(k), H2.export_block(k)
+        if isinstance(d1, tuple):
+            assert all(np.array_equal(u, v) for u, v in zip(d1, d2))
+        else:
+            assert np.array_equal(d1, d2)
+
+
+@pytest.mark.parametrize("eps", [1e-3, 1e-4, 1e-5])
+def test_sphere20k_sampled_rows(hm, orc, eps):
+    """Complex64 precision form at 20,000 points, checked on sampled rows."""
+    w = W.precision_sphere_20k(eps)
+    say(f"case sphere20k eps={eps}")
+    X, _ = w.points()
+    H = hm.build_workload(w, X=X, prec=1)
+    s = H.info()
+    say({k: s[k] for k in ("n_lowrank", "max_rank_aca", "max_rank", "n_overflow", "storage_bytes",
+                           "t_total", "t_aca", "t_recompress")})
+    b = w.rhs()
+    y = H.matvec(to_dev(b, H.complex_dtype)).cpu().numpy().astype(np.complex128)
+    rows = np.random.default_rng(0).choice(w.n_points, 512, replace=False)
+    pb = orc.Problem.from_workload(w, X)
+    ref = orc.matvec_rows(pb, b, rows)
+    idx = (3 * rows[:, None] + np.arange(3)).ravel()
+    e = rel(y[idx], ref)
+    say("sampled e =", e)
+    assert e <= 5 * eps
