@@ -68,6 +68,9 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-gmres", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=256)
+    ap.add_argument("--counters", action="store_true",
+                    help="profiling mode: one build, 10 matvecs, then a 256 MiB device copy "
+                         "(x3) whose known byte count calibrates FETCH_SIZE / WRITE_SIZE")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -90,6 +93,21 @@ def main():
             eta=w.eta, eps=w.eps, leaf=w.leaf, self_re=w.self_re, self_im=w.self_im)
         y = H.matvec(b64 if prec == hmat.C64 else bd)
         return H, y
+
+    if args.counters:
+        H, _ = step(hmat.C64)
+        for k in range(10):
+            H.matvec(b64)
+        torch.cuda.synchronize()
+        log(f"[counters] 10 matvecs done; matvec_bytes {H.info()['matvec_bytes']}")
+        src = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        for k in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("[counters] calibration copy: 3 x (268435456 B read + 268435456 B written)")
+        H.close()
+        return
 
     log(f"[bench] workload {w.name}: N_c={w.n_points}, warmup {args.warmup}, steps {args.steps}")
     for _ in range(args.warmup):
@@ -145,7 +163,7 @@ def main():
     }
     if not args.no_gmres:
         tg = time.perf_counter()
-        x, inf = H.gmres(bd, tol=1e-8, restart=50, maxit=20000, check=False)
+        x, inf = H.gmres(bd, tol=1e-8, restart=200, maxit=12000, check=False)
         torch.cuda.synchronize()
         out["gmres"] = {"tol": 1e-8, "s": round(time.perf_counter() - tg, 3), **inf}
         log(f"[bench] gmres {out['gmres']}")

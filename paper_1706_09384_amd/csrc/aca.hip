@@ -14,7 +14,10 @@
 //   4. next row pivot = argmax over unused i of sigma_3 of R(i, j^);
 //   5. U_new = R(:, j^) M^-1, V_new = R(i^, :)^* with M = R(i^, j^);
 //   6. stopping test ||U_k V_k^*||_F <= eps ||B_k||_F with both norms from
-//      FP64 recurrences over the 3x3 Gram blocks.
+//      FP64 recurrences over the 3x3 Gram blocks.  The Gram columns
+//      V^* V_new and U^* U_new are reduced right after each residual pass
+//      (each thread sums its own rows, the workgroup sums in FP64); the
+//      V-side results stay in LDS until the U side is reduced.
 // Rows/columns whose every candidate 3x3 block is numerically singular
 // (sigma_3 <= tau_piv |block|_F, e.g. T between coplanar points) fall back
 // to the largest-Frobenius candidate and a rank-p pseudo-inverse update.
@@ -169,22 +172,85 @@ __device__ inline void herm3_eig(cplx<double> G[9], double lam[3], cplx<double> 
             }
 }
 
+// Block-wide sum of NV doubles per thread (NV <= 24); the result is returned
+// in out[] (LDS) visible to all threads after the call.
+template <int NV>
+__device__ inline void block_sum(double (&v)[NV], double *sh /* [kAcaWaves][NV] */, double *out) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v[k] += __shfl_xor(v[k], o, 64);
+    }
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) sh[wave * NV + k] = v[k];
+    __syncthreads();
+    if (threadIdx.x < NV) {
+        double s = 0;
+        for (int w = 0; w < kAcaWaves; ++w) s += sh[w * NV + threadIdx.x];
+        out[threadIdx.x] = s;
+    }
+    __syncthreads();
+}
+
+// Gram of old and new factor columns over this thread's rows:
+// part[l][c] = sum over my rows q of conj(X[q, l]) X[q, base + c], for the
+// chunk l = l0..l0+3, c < 3, products in R, partial sums promoted to FP64.
+// X column-major with leading dimension ld; rows owned: 3*idx + a for idx
+// = tid, tid + 256, ... < npts.
+template <typename R>
+__device__ inline void gram_chunk(const cplx<R> *X, int64_t ld, int npts, int l0, int lmax,
+                                  int base, double (&part)[24]) {
+#pragma unroll
+    for (int k = 0; k < 24; ++k) part[k] = 0.0;
+    for (int idx = threadIdx.x; idx < npts; idx += kAcaThreads) {
+        R acc[24];
+#pragma unroll
+        for (int k = 0; k < 24; ++k) acc[k] = R(0);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const int64_t q = 3 * (int64_t)idx + a;
+            const cplx<R> n0 = X[(base + 0) * ld + q], n1 = X[(base + 1) * ld + q],
+                          n2 = X[(base + 2) * ld + q];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (l0 + u < lmax) {
+                    const cplx<R> o = X[(int64_t)(l0 + u) * ld + q];
+                    // conj(o) * n
+                    acc[6 * u + 0] += o.re * n0.re + o.im * n0.im;
+                    acc[6 * u + 1] += o.re * n0.im - o.im * n0.re;
+                    acc[6 * u + 2] += o.re * n1.re + o.im * n1.im;
+                    acc[6 * u + 3] += o.re * n1.im - o.im * n1.re;
+                    acc[6 * u + 4] += o.re * n2.re + o.im * n2.im;
+                    acc[6 * u + 5] += o.re * n2.im - o.im * n2.re;
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 24; ++k) part[k] += double(acc[k]);
+    }
+}
+
 template <typename R>
 __global__ void __launch_bounds__(kAcaThreads)
     aca_kernel(Geometry g, GreenParams<R> gp, const AcaBlk *__restrict__ blks,
                cplx<R> *__restrict__ fac, uint8_t *__restrict__ flags,
-               AcaOut *__restrict__ outs, double eps, double tau_piv) {
+               AcaOut *__restrict__ outs, double eps, double tau_piv, int32_t max_budget) {
     extern __shared__ unsigned char smem_raw[];
-    cplx<R> *piv = reinterpret_cast<cplx<R> *>(smem_raw);  // 3 x budget pivot row
+    // dynamic LDS: pivot row (3 x budget, type R) then cv (budget x 3 complex doubles)
+    cplx<double> *cv = reinterpret_cast<cplx<double> *>(smem_raw);
+    cplx<R> *piv = reinterpret_cast<cplx<R> *>(cv + 3 * (int64_t)max_budget);
     __shared__ Best2 sh_best[kAcaWaves];
-    __shared__ double sh_red[2 * kAcaWaves];
+    __shared__ double sh_sum[kAcaWaves * 24];
+    __shared__ double sh_out[24];
     __shared__ cplx<double> sh_T[9];   // M^-1 (mode 0) or Z_p Sigma_p^-1 (mode 1)
     __shared__ cplx<double> sh_W[9];   // W_p (mode 1)
-    __shared__ int sh_ctl[8];          // 0 ihat, 1 jhat, 2 mode, 3 p, 4 next_i, 5 stop, 6 zero-row
-    __shared__ double sh_norm2;
+    __shared__ int sh_ctl[8];          // 0 ihat, 2 mode, 3 p, 5 stop
+    __shared__ double sh_norm2, sh_cross, sh_new;
 
     const AcaBlk b = blks[blockIdx.x];
-    const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+    const int tid = threadIdx.x;
     const int m = b.m, n = b.n;
     const int64_t ldu = 3 * (int64_t)m, ldv = 3 * (int64_t)n;
     cplx<R> *U = fac + b.uoff;
@@ -233,15 +299,29 @@ __global__ void __launch_bounds__(kAcaThreads)
             }
             green_block<R>(gp, R(xi0 - g.y[0][pj]), R(xi1 - g.y[1][pj]), R(xi2 - g.y[2][pj]), nx,
                            ny, nz, K);
-            for (int l = 0; l < r; ++l) {
-                const cplx<R> *vc = V + l * ldv + 3 * j;
-                const cplx<R> v0 = vc[0], v1 = vc[1], v2 = vc[2];
+            const cplx<R> *vrow = V + 3 * j;
+            int l = 0;
+            for (; l + 4 <= r; l += 4) {
+                cplx<R> vv[4][3];
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int be = 0; be < 3; ++be) vv[u][be] = vrow[(l + u) * ldv + be];
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        const cplx<R> uu = piv[a * r + l + u];
+#pragma unroll
+                        for (int be = 0; be < 3; ++be) fms_conj(K[3 * a + be], uu, vv[u][be]);
+                    }
+            }
+            for (; l < r; ++l) {
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
-                    const cplx<R> u = piv[a * r + l];
-                    fms_conj(K[3 * a + 0], u, v0);
-                    fms_conj(K[3 * a + 1], u, v1);
-                    fms_conj(K[3 * a + 2], u, v2);
+                    const cplx<R> uu = piv[a * r + l];
+#pragma unroll
+                    for (int be = 0; be < 3; ++be) fms_conj(K[3 * a + be], uu, vrow[l * ldv + be]);
                 }
             }
 #pragma unroll
@@ -286,6 +366,17 @@ __global__ void __launch_bounds__(kAcaThreads)
         }
         const bool degenerate = best.s3 <= tau_piv * tau_piv * best.fro;
         const int jh = degenerate ? best.ifro : best.i3;
+        // ---- FP64 Gram of the raw new V columns against all V columns ------
+        // cv[l][c] = V[:, l]^* Vraw[:, r + c] for l < r + 3
+        for (int l0 = 0; l0 < r + 3; l0 += 4) {
+            double part[24];
+            gram_chunk<R>(V, ldv, n, l0, r + 3, r, part);
+            block_sum<24>(part, sh_sum, sh_out);
+            for (int k = tid; k < 12; k += kAcaThreads) {
+                const int u = k / 3, c = k % 3;
+                if (l0 + u < r + 3) cv[3 * (l0 + u) + c] = {sh_out[2 * k], sh_out[2 * k + 1]};
+            }
+        }
         // ---- pivot block and its (pseudo-)inverse ------------------------
         if (jh % kAcaThreads == tid) {
             // This thread wrote V(3jh + be, r + a) above; read back M(a, be).
@@ -330,6 +421,7 @@ __global__ void __launch_bounds__(kAcaThreads)
                 const cplx<double> C[9] = {c00, c01, c02, c10, c11, c12, c20, c21, c22};
                 for (int a = 0; a < 3; ++a)
                     for (int c = 0; c < 3; ++c) sh_T[3 * a + c] = C[3 * c + a] * idet;
+                for (int e = 0; e < 9; ++e) sh_W[e] = {e % 4 == 0 ? 1.0 : 0.0, 0.0};
                 sh_ctl[2] = 0;
                 sh_ctl[3] = 3;
             } else {
@@ -346,7 +438,6 @@ __global__ void __launch_bounds__(kAcaThreads)
                 sh_ctl[2] = 1;
                 sh_ctl[3] = p;
             }
-            sh_ctl[1] = jh;
         }
         __syncthreads();
         const int mode = sh_ctl[2], p = sh_ctl[3];
@@ -366,6 +457,26 @@ __global__ void __launch_bounds__(kAcaThreads)
                         V[(r + c) * ldv + 3 * j + be] = cvt<R>(s);
                     }
             }
+            // cv[l][:] <- cv[l][:] W for old columns; the new-new Gram block
+            // becomes W^* G W.
+            for (int l = tid; l < r + 3; l += kAcaThreads) {
+                cplx<double> row[3] = {cv[3 * l], cv[3 * l + 1], cv[3 * l + 2]};
+                for (int c = 0; c < 3; ++c) {
+                    cplx<double> s = {0, 0};
+                    for (int a = 0; a < 3; ++a) s = s + row[a] * sh_W[3 * a + c];
+                    cv[3 * l + c] = s;
+                }
+            }
+            __syncthreads();
+            if (tid < 9) {
+                const int a = tid / 3, c = tid % 3;
+                cplx<double> s = {0, 0};
+                for (int k = 0; k < 3; ++k) s = s + cmul(sh_W[3 * k + a], cv[3 * (r + k) + c]);
+                sh_out[2 * tid] = s.re;
+                sh_out[2 * tid + 1] = s.im;
+            }
+            __syncthreads();
+            if (tid < 9) cv[3 * (r + tid / 3) + tid % 3] = {sh_out[2 * tid], sh_out[2 * tid + 1]};
         }
         // ---- 3. residual column, 4. next row pivot, 5. U_new --------------
         for (int k = tid; k < 3 * r; k += kAcaThreads) {
@@ -387,15 +498,29 @@ __global__ void __launch_bounds__(kAcaThreads)
             cplx<R> K[9];
             green_block<R>(gp, R(g.x[0][pii] - yj0), R(g.x[1][pii] - yj1), R(g.x[2][pii] - yj2),
                            njx, njy, njz, K);
-            for (int l = 0; l < r; ++l) {
-                const cplx<R> *uc = U + l * ldu + 3 * i;
-                const cplx<R> u0 = uc[0], u1 = uc[1], u2 = uc[2];
+            const cplx<R> *urow = U + 3 * i;
+            int l = 0;
+            for (; l + 4 <= r; l += 4) {
+                cplx<R> uu[4][3];
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) uu[u][a] = urow[(l + u) * ldu + a];
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int be = 0; be < 3; ++be) {
+                        const cplx<R> v = piv[be * r + l + u];
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) fms_conj(K[3 * a + be], uu[u][a], v);
+                    }
+            }
+            for (; l < r; ++l) {
 #pragma unroll
                 for (int be = 0; be < 3; ++be) {
                     const cplx<R> v = piv[be * r + l];
-                    fms_conj(K[0 + be], u0, v);
-                    fms_conj(K[3 + be], u1, v);
-                    fms_conj(K[6 + be], u2, v);
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) fms_conj(K[3 * a + be], urow[l * ldu + a], v);
                 }
             }
             if (!used_i[i]) {
@@ -411,10 +536,10 @@ __global__ void __launch_bounds__(kAcaThreads)
                 cplx<double> kd[3];
 #pragma unroll
                 for (int be = 0; be < 3; ++be) kd[be] = cvt<double>(K[3 * a + be]);
-                for (int c = 0; c < p; ++c) {
+                for (int c = 0; c < 3; ++c) {
                     const cplx<double> s = kd[0] * sh_T[0 * 3 + c] + kd[1] * sh_T[1 * 3 + c] +
                                            kd[2] * sh_T[2 * 3 + c];
-                    U[(r + c) * ldu + 3 * i + a] = cvt<R>(s);
+                    U[(r + c) * ldu + 3 * i + a] = cvt<R>(c < p ? s : cplx<double>{0, 0});
                 }
             }
         }
@@ -423,57 +548,36 @@ __global__ void __launch_bounds__(kAcaThreads)
         if (best.ifro != INT_MAX)
             next_i = (best.s3 <= tau_piv * tau_piv * best.fro) ? best.ifro : best.i3;
         // ---- 6. FP64 norm recurrences ------------------------------------
-        double cross = 0.0, nrm = 0.0;
-        for (int a = wave; a < r + p; a += kAcaWaves) {
-            double cu[6] = {0, 0, 0, 0, 0, 0}, cv[6] = {0, 0, 0, 0, 0, 0};
-            const cplx<R> *ua = U + a * ldu;
-            for (int64_t i = lane; i < ldu; i += 64) {
-                const cplx<double> x = cvt<double>(ua[i]);
-                for (int c = 0; c < p; ++c) {
-                    const cplx<double> y = cvt<double>(U[(r + c) * ldu + i]);
-                    cu[2 * c] += x.re * y.re + x.im * y.im;
-                    cu[2 * c + 1] += x.re * y.im - x.im * y.re;
-                }
-            }
-            const cplx<R> *va = V + a * ldv;
-            for (int64_t j = lane; j < ldv; j += 64) {
-                const cplx<double> x = cvt<double>(va[j]);
-                for (int c = 0; c < p; ++c) {
-                    const cplx<double> y = cvt<double>(V[(r + c) * ldv + j]);
-                    cv[2 * c] += x.re * y.re + x.im * y.im;
-                    cv[2 * c + 1] += x.re * y.im - x.im * y.re;
-                }
-            }
-            double contrib = 0.0;
-            for (int c = 0; c < p; ++c) {
-                double ur = cu[2 * c], ui = cu[2 * c + 1], vr = cv[2 * c], vi = cv[2 * c + 1];
-#pragma unroll
-                for (int o = 32; o > 0; o >>= 1) {
-                    ur += __shfl_xor(ur, o, 64);
-                    ui += __shfl_xor(ui, o, 64);
-                    vr += __shfl_xor(vr, o, 64);
-                    vi += __shfl_xor(vi, o, 64);
-                }
-                contrib += ur * vr + ui * vi;  // Re(cu * conj(cv))
-            }
-            if (a < r)
-                cross += 2.0 * contrib;
-            else
-                nrm += contrib;
+        // cu[l][c] = U[:, l]^* U[:, r + c]; cross = 2 Re sum_{l<r,c} cu conj(cv),
+        // new = Re sum_{a,c < p} G_U[a][c] conj(G_V[a][c]).
+        if (tid == 0) {
+            sh_cross = 0.0;
+            sh_new = 0.0;
         }
-        if (lane == 0) {
-            sh_red[wave] = cross;
-            sh_red[kAcaWaves + wave] = nrm;
+        for (int l0 = 0; l0 < r + p; l0 += 4) {
+            double part[24];
+            gram_chunk<R>(U, ldu, m, l0, r + p, r, part);
+            block_sum<24>(part, sh_sum, sh_out);
+            if (tid == 0) {
+                for (int u = 0; u < 4 && l0 + u < r + p; ++u) {
+                    const int l = l0 + u;
+                    double s = 0;
+                    for (int c = 0; c < p; ++c) {
+                        const double cr = sh_out[2 * (3 * u + c)], ci = sh_out[2 * (3 * u + c) + 1];
+                        const cplx<double> v = cv[3 * l + c];
+                        s += cr * v.re + ci * v.im;   // Re(cu * conj(cv))
+                    }
+                    if (l < r)
+                        sh_cross += 2.0 * s;
+                    else
+                        sh_new += s;
+                }
+            }
         }
         __syncthreads();
         if (tid == 0) {
-            double cs = 0, ns = 0;
-            for (int w = 0; w < kAcaWaves; ++w) {
-                cs += sh_red[w];
-                ns += sh_red[kAcaWaves + w];
-            }
-            sh_norm2 += cs + ns;
-            const bool stop = (ns <= eps * eps * sh_norm2) || next_i < 0;
+            sh_norm2 += sh_cross + sh_new;
+            const bool stop = (sh_new <= eps * eps * sh_norm2) || next_i < 0;
             sh_ctl[5] = stop ? 1 : 0;
             sh_ctl[0] = next_i;
         }
@@ -502,9 +606,9 @@ void run_aca(const Geometry &g, const GreenParams<R> &gp, const std::vector<AcaB
              AcaBlk *d_blk, cplx<R> *scratch, uint8_t *flags, AcaOut *d_out, double eps,
              double tau_piv, int32_t max_budget, hipStream_t st) {
     if (blk.empty()) return;
-    const size_t smem = 3 * (size_t)max_budget * sizeof(cplx<R>);
+    const size_t smem = 3 * (size_t)max_budget * (sizeof(cplx<R>) + sizeof(cplx<double>));
     hipLaunchKernelGGL(aca_kernel<R>, dim3((unsigned)blk.size()), dim3(kAcaThreads), smem, st, g,
-                       gp, d_blk, scratch, flags, d_out, eps, tau_piv);
+                       gp, d_blk, scratch, flags, d_out, eps, tau_piv, max_budget);
     HM_HIP_CHECK(hipGetLastError());
 }
 

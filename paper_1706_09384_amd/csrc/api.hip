@@ -63,10 +63,14 @@ __global__ void copy_factors_kernel(const RcBlk *__restrict__ blks, const cplx<R
     const int64_t nu = 3 * (int64_t)b.m * b.r, nv = 3 * (int64_t)b.n * b.r;
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nu + nv;
          k += (int64_t)gridDim.x * blockDim.x) {
-        if (k < nu)
+        if (k < nu) {
             dst[outu[blockIdx.y] + k] = src[b.uoff + k];
-        else
-            dst[outv[blockIdx.y] + (k - nu)] = src[b.voff + (k - nu)];
+        } else {
+            // V: column-major scratch -> row-major final layout
+            const int64_t q = k - nu, rows = 3 * (int64_t)b.n;
+            const int64_t row = q % rows, c = q / rows;
+            dst[outv[blockIdx.y] + row * b.r + c] = src[b.voff + q];
+        }
     }
 }
 
@@ -333,7 +337,11 @@ void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vect
         lm[k] = tx.size(B.row);
         ln[k] = ty.size(B.col);
         const int32_t full = 3 * std::min(lm[k], ln[k]);
-        budget[k] = std::min(full, std::max(def_budget, 3));
+        // Size-aware first budget (a rank prediction, when given, replaces it).
+        const int32_t big = std::max(lm[k], ln[k]);
+        int32_t b0 = def_budget;
+        if (p.rank_budget <= 0) b0 = big < 400 ? 96 : (big < 1000 ? 192 : 288);
+        budget[k] = std::min(full, std::max(b0, 3));
         budget[k] = std::max(3, budget[k] - budget[k] % 3);
     }
     // Per low-rank block: which pass holds its factors, and where.
@@ -343,7 +351,14 @@ void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vect
     std::vector<std::vector<int64_t>> pass_members;
     std::vector<int64_t> todo(nlr);
     std::iota(todo.begin(), todo.end(), 0);
-    int32_t overflow = 0, fallbacks = 0;
+    int32_t overflow = 0, fallbacks = 0, capped = 0;
+    // The ACA kernel keeps the pivot row (3 x budget, compute type) and the V
+    // Gram column (budget x 3, complex FP64) in LDS: cap the budget so that
+    // both fit in 64 KiB.  A block still unconverged at the cap keeps its
+    // capped-rank approximation (counted in hm_stats.n_overflow as well).
+    const int32_t budget_cap =
+        (int32_t)((60 * 1024) / (3 * (sizeof(cplx<R>) + sizeof(cplx<double>)))) / 3 * 3;
+    for (auto &bg : budget) bg = std::min(bg, budget_cap);
     while (!todo.empty()) {
         // longest first (cost ~ budget * (m + n))
         std::stable_sort(todo.begin(), todo.end(), [&](int64_t a, int64_t b) {
@@ -386,12 +401,13 @@ void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vect
         pass_members.emplace_back();
         for (size_t q = 0; q < todo.size(); ++q) {
             const int64_t k = todo[q];
-            if (res[q].status == 1) {
+            if (res[q].status == 1 && budget[k] < budget_cap) {
                 ++overflow;
-                budget[k] = std::min(3 * std::min(lm[k], ln[k]), 2 * budget[k]);
+                budget[k] = std::min({3 * std::min(lm[k], ln[k]), 2 * budget[k], budget_cap});
                 next.push_back(k);
                 continue;
             }
+            if (res[q].status == 1) ++capped;
             pass_of[k] = pass;
             aca_rank[k] = res[q].rank;
             aca_u[k] = ab[q].uoff;
@@ -402,7 +418,10 @@ void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vect
         pass_scratch.push_back(std::move(scratch));
         todo.swap(next);
     }
-    S.n_overflow = overflow;
+    S.n_overflow = overflow + capped;
+    if (capped)
+        std::fprintf(stderr, "hmat: %d admissible blocks reached the ACA rank cap %d\n", capped,
+                     budget_cap);
     S.n_fallback = fallbacks;
     HM_HIP_CHECK(hipStreamSynchronize(st));
     S.t_aca = now_s() - t;
@@ -425,7 +444,7 @@ void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vect
             c.n = ln[k];
             c.r = aca_rank[k];
             c.goff = goff;
-            goff += 7 * (int64_t)c.r * c.r;
+            goff += 7 * (int64_t)c.r * c.r + 2 * (int64_t)c.r;
             rc.push_back(c);
         }
         pass_drc[ps] = std::make_unique<DeviceBuf>();
@@ -525,6 +544,7 @@ void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vect
         if (tx.is_leaf(v)) {
             leaf_index[v] = (int32_t)leaves.size();
             leaves.push_back({tx.begin[v], tx.size(v), 0, 0});
+            M->max_leaf = std::max(M->max_leaf, tx.size(v));
         }
     std::vector<std::vector<Task>> per_leaf(leaves.size());
     std::vector<int32_t> lv;
@@ -548,6 +568,33 @@ void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vect
         leaves[l].tend = (int32_t)tasks.size();
     }
     M->n_leaves = (int32_t)leaves.size();
+    std::vector<ProjTask> ptasks;
+    std::vector<ProjReduce> preduce;
+    int32_t nslots = 0;
+    for (int32_t i = 0; i < M->n_lblk; ++i) {
+        const int32_t rows = 3 * M->h_lblk[i].n;
+        const int32_t nch = (int32_t)ceil_div(rows, kProjRows);
+        for (int32_t c0 = 0; c0 < M->h_lblk[i].r; c0 += 64) {
+            if (nch == 1) {
+                ptasks.push_back({i, c0, 0, rows, -1, 0});
+                continue;
+            }
+            preduce.push_back({i, c0, nslots, nch});
+            for (int32_t ch = 0; ch < nch; ++ch)
+                ptasks.push_back({i, c0, ch * kProjRows, std::min(kProjRows, rows - ch * kProjRows),
+                                  nslots++, 0});
+        }
+    }
+    // biggest chunks first
+    std::stable_sort(ptasks.begin(), ptasks.end(), [&](const ProjTask &a, const ProjTask &b) {
+        return (int64_t)a.nrows * std::min(64, M->h_lblk[a.blk].r - a.col0) >
+               (int64_t)b.nrows * std::min(64, M->h_lblk[b.blk].r - b.col0);
+    });
+    M->n_ptasks = (int32_t)ptasks.size();
+    M->n_preduce = (int32_t)preduce.size();
+    upload(M->d_ptasks, ptasks, st);
+    upload(M->d_preduce, preduce, st);
+    M->tpart.alloc(std::max<int64_t>(nslots, 1) * 64 * sizeof(cplx<double>));
     upload(M->d_lblk, M->h_lblk, st);
     upload(M->d_tasks, tasks, st);
     upload(M->d_leaves, leaves, st);
@@ -698,9 +745,14 @@ extern "C" hm_status hm_export_block(const hm_matrix *A, int64_t b, void *host_b
         if (r > 0) {
             HM_HIP_CHECK(hipMemcpy(h, static_cast<char *>(A->lowrank.p) + A->off_a[b] * es,
                                    3 * m * r * es, hipMemcpyDeviceToHost));
-            HM_HIP_CHECK(hipMemcpy(h + 3 * m * r * es,
-                                   static_cast<char *>(A->lowrank.p) + A->off_v[b] * es,
-                                   3 * n * r * es, hipMemcpyDeviceToHost));
+            // V is stored row-major; export it column-major.
+            std::vector<char> tmp(3 * n * r * es);
+            HM_HIP_CHECK(hipMemcpy(tmp.data(), static_cast<char *>(A->lowrank.p) + A->off_v[b] * es,
+                                   tmp.size(), hipMemcpyDeviceToHost));
+            char *hv = h + 3 * m * r * es;
+            for (int64_t row = 0; row < 3 * n; ++row)
+                for (int64_t c = 0; c < r; ++c)
+                    std::memcpy(hv + (c * 3 * n + row) * es, tmp.data() + (row * r + c) * es, es);
         }
     }
     return HM_OK;

@@ -18,8 +18,8 @@ struct DenseBlk {
     int32_t rb, m, cb, n;
 };
 
-// Low-rank block U V^*: U (3m x r) at uoff, V (3n x r) at voff, column-major,
-// t-vector slot at toff (r entries per right-hand side).
+// Low-rank block U V^*: U (3m x r) column-major at uoff, V (3n x r) row-major
+// at voff, t-vector slot at toff (r entries per right-hand side).
 struct LowRankBlk {
     int64_t uoff, voff, toff;
     int32_t rb, m, cb, n, r, pad;
@@ -30,6 +30,21 @@ struct LowRankBlk {
 struct Task {
     int32_t kind, idx, rowoff, pad;
 };
+
+// Projection work item: one wave computes the contribution of rows
+// row0..row0+nrows of a block to t for columns col0..col0+63; single-chunk
+// items write t directly (slot < 0), the others write partial sums to
+// tpart[slot * 64 + c] which a reduction pass adds up.
+struct ProjTask {
+    int32_t blk, col0, row0, nrows, slot, pad;
+};
+
+// Reduction of the partial projections of one (block, col0) group.
+struct ProjReduce {
+    int32_t blk, col0, slot0, nslots;
+};
+
+constexpr int32_t kProjRows = 512;
 
 struct LeafRow {
     int32_t rb, m, tbeg, tend;
@@ -95,8 +110,9 @@ struct hm_matrix {
     hm::DeviceBuf perm_x, perm_y;
     hm::DeviceBuf dense;      // dense slab
     hm::DeviceBuf lowrank;    // U and V factors
-    hm::DeviceBuf d_dblk, d_lblk, d_tasks, d_leaves;
-    int32_t n_dblk = 0, n_lblk = 0, n_leaves = 0;
+    hm::DeviceBuf d_dblk, d_lblk, d_tasks, d_leaves, d_ptasks, d_preduce, tpart;
+    int32_t n_dblk = 0, n_lblk = 0, n_leaves = 0, n_ptasks = 0, n_preduce = 0;
+    int32_t max_leaf = 1;     // largest leaf row cluster (points)
     int64_t t_len = 0;        // sum of ranks
     std::vector<hm::DenseBlk> h_dblk;
     std::vector<hm::LowRankBlk> h_lblk;

@@ -1,29 +1,28 @@
 // H-matrix-vector product (Section 3.1): y = sum over leaf blocks of the
 // dense tile times x_sigma, or U (V^* x_sigma) for low-rank blocks.
 //
+// Storage: dense tiles 3m x 3n column-major; U (3m x r) column-major; V
+// stored row-major (3n x r, the r coefficients of one row contiguous).
 // Three passes, no atomics, every output row written exactly once:
 //   gather   x (original order, one column) -> xc (column-cluster order)
-//   project  t_b = V_b^* xc[sigma_b] for every low-rank block (one workgroup
-//            per block, one wave per column of V, lanes stream the column)
+//   project  t_b = V_b^* xc[sigma_b]: one wave per (block, group of up to 64
+//            columns); lanes own columns (floor(64/r) row groups of r lanes
+//            when r < 64), so each iteration of the wave reads one contiguous
+//            segment of the row-major V; the row groups are summed in LDS
 //   accum    one workgroup per leaf row cluster L: the sum over the dense
 //            tiles of L and over the rows of every low-rank U whose row
 //            cluster contains L; lanes own rows, waves split the task list,
-//            LDS combines the waves; the result is scattered to original
-//            order (or subtracted from b for the FP64 residual).
-// Column-major tiles and factors make every inner load a coalesced column
-// segment.  S is the storage real type, A the accumulation real type.
+//            8-way unrolled column loops keep loads in flight, LDS combines
+//            the waves, and the result is scattered to original order (or
+//            subtracted from b for the FP64 residual).
+// S is the storage real type, A the accumulation real type.
+#include <algorithm>
+
 #include "internal.hpp"
 
 namespace hm {
 
 constexpr int kWave = 64;
-
-template <typename A>
-__device__ inline A wave_sum(A v) {
-#pragma unroll
-    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-    return v;
-}
 
 template <typename S, typename A>
 __global__ void gather_kernel(const cplx<S> *__restrict__ x, int64_t ldx, int32_t col,
@@ -37,41 +36,132 @@ __global__ void gather_kernel(const cplx<S> *__restrict__ x, int64_t ldx, int32_
 
 template <typename S, typename A>
 __global__ void __launch_bounds__(256) project_kernel(const LowRankBlk *__restrict__ blk,
+                                                      const ProjTask *__restrict__ ptasks,
+                                                      int32_t ntasks,
                                                       const cplx<S> *__restrict__ fac,
                                                       const cplx<A> *__restrict__ xc,
-                                                      cplx<A> *__restrict__ t) {
-    const LowRankBlk b = blk[blockIdx.x];
+                                                      cplx<A> *__restrict__ t,
+                                                      cplx<A> *__restrict__ tpart) {
+    __shared__ cplx<A> part[256];
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    const int nw = blockDim.x / kWave;
-    const int64_t rows = 3 * (int64_t)b.n;
-    const cplx<A> *xs = xc + 3 * (int64_t)b.cb;
-    for (int l = wave; l < b.r; l += nw) {
-        const cplx<S> *v = fac + b.voff + l * rows;
-        A re = 0, im = 0;
-        for (int64_t i = lane; i < rows; i += kWave) {
-            const cplx<A> vv = cvt<A>(v[i]);
-            const cplx<A> xv = xs[i];
-            // conj(v) * x
-            re += vv.re * xv.re + vv.im * xv.im;
-            im += vv.re * xv.im - vv.im * xv.re;
+    const int32_t ti = blockIdx.x * (blockDim.x / kWave) + wave;
+    const bool live = ti < ntasks;
+    A re = 0, im = 0;
+    int width = 1, G = 1;
+    LowRankBlk b;
+    ProjTask pt = {0, 0, 0, 0, -1, 0};
+    if (live) {
+        pt = ptasks[ti];
+        b = blk[pt.blk];
+        const int r = b.r;
+        width = min(64, r - pt.col0);
+        // G row groups of `width` lanes: for a fixed iteration the wave reads
+        // G consecutive rows of the row-major V, i.e. one contiguous segment.
+        G = kWave / width;
+        const int g = lane / width, c = lane - g * width;
+        if (g < G) {
+            const int32_t rows = pt.nrows;
+            const cplx<S> *v = fac + b.voff + (int64_t)pt.row0 * r + pt.col0 + c;
+            const cplx<A> *xs = xc + 3 * (int64_t)b.cb + pt.row0;
+            int32_t i = g;
+            for (; i + 7 * G < rows; i += 8 * G) {
+                cplx<S> vv[8];
+                cplx<A> xv[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    vv[u] = v[(int64_t)(i + u * G) * r];
+                    xv[u] = xs[i + u * G];
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const cplx<A> a = cvt<A>(vv[u]);
+                    re += a.re * xv[u].re + a.im * xv[u].im;
+                    im += a.re * xv[u].im - a.im * xv[u].re;
+                }
+            }
+            for (; i < rows; i += G) {
+                const cplx<A> a = cvt<A>(v[(int64_t)i * r]);
+                const cplx<A> xv = xs[i];
+                re += a.re * xv.re + a.im * xv.im;
+                im += a.re * xv.im - a.im * xv.re;
+            }
         }
-        re = wave_sum(re);
-        im = wave_sum(im);
-        if (lane == 0) t[b.toff + l] = {re, im};
+    }
+    // sum the G row groups of each column through LDS (per-wave region)
+    part[threadIdx.x] = {re, im};
+    __syncthreads();
+    if (live && lane < width) {
+        cplx<A> s = {A(0), A(0)};
+        for (int q = 0; q < G; ++q) s = s + part[wave * kWave + q * width + lane];
+        if (pt.slot < 0)
+            t[b.toff + pt.col0 + lane] = s;
+        else
+            tpart[(int64_t)pt.slot * kWave + lane] = s;
     }
 }
 
+// t = sum of the row-chunk partial projections (fixed order: deterministic).
+template <typename A>
+__global__ void project_reduce_kernel(const LowRankBlk *__restrict__ blk,
+                                      const ProjReduce *__restrict__ red, int32_t nred,
+                                      const cplx<A> *__restrict__ tpart, cplx<A> *__restrict__ t) {
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int32_t k = blockIdx.x * (blockDim.x / kWave) + wave;
+    if (k >= nred) return;
+    const ProjReduce pr = red[k];
+    const LowRankBlk b = blk[pr.blk];
+    if (lane >= min(64, b.r - pr.col0)) return;
+    cplx<A> s = {A(0), A(0)};
+    for (int q = 0; q < pr.nslots; ++q) s = s + tpart[(int64_t)(pr.slot0 + q) * kWave + lane];
+    t[b.toff + pr.col0 + lane] = s;
+}
+
+// acc[k] += sum_j col_j[row_k] * w_j over `ncol` columns of a column-major
+// panel starting at `base` with leading dimension ld; w_j read from `wv`.
+template <typename S, typename A, int RPL>
+__device__ inline void panel_accum(cplx<A> (&acc)[RPL], const cplx<S> *__restrict__ base,
+                                   int64_t ld, const cplx<A> *__restrict__ wv, int32_t ncol,
+                                   int32_t r0, int32_t rows, int lane) {
+    int32_t j = 0;
+    for (; j + 8 <= ncol; j += 8) {
+        cplx<A> w[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) w[u] = wv[j + u];
+#pragma unroll
+        for (int k = 0; k < RPL; ++k) {
+            const int32_t row = r0 + lane + k * kWave;
+            if (row < rows) {
+                cplx<S> c[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) c[u] = base[(j + u) * ld + row];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) fma_(acc[k], cvt<A>(c[u]), w[u]);
+            }
+        }
+    }
+    for (; j < ncol; ++j) {
+        const cplx<A> w = wv[j];
+#pragma unroll
+        for (int k = 0; k < RPL; ++k) {
+            const int32_t row = r0 + lane + k * kWave;
+            if (row < rows) fma_(acc[k], cvt<A>(base[j * ld + row]), w);
+        }
+    }
+}
+
+constexpr int kAccWaves = 8;
+
 // OUT = 0: y (type S) = A x; OUT = 1: r (double) = b - A x.
-template <typename S, typename A, int OUT>
-__global__ void __launch_bounds__(256) accum_kernel(
+// RPL rows per lane per chunk (64 * RPL rows), kAccWaves waves per leaf.
+template <typename S, typename A, int OUT, int RPL>
+__global__ void __launch_bounds__(64 * kAccWaves) accum_kernel(
     const LeafRow *__restrict__ leaves, const Task *__restrict__ tasks,
     const DenseBlk *__restrict__ dblk, const LowRankBlk *__restrict__ lblk,
     const cplx<S> *__restrict__ dense, const cplx<S> *__restrict__ fac,
     const cplx<A> *__restrict__ xc, const cplx<A> *__restrict__ t,
     const int32_t *__restrict__ perm, void *__restrict__ yout, int64_t ldy, int32_t col,
     const double *__restrict__ bvec) {
-    constexpr int RPL = 4;  // rows per lane per chunk
-    __shared__ cplx<A> red[4][kWave * RPL];
+    __shared__ cplx<A> red[kAccWaves][kWave * RPL];
     const LeafRow L = leaves[blockIdx.x];
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int nw = blockDim.x / kWave;
@@ -84,33 +174,13 @@ __global__ void __launch_bounds__(256) accum_kernel(
             const Task tk = tasks[ti];
             if (tk.kind == 0) {
                 const DenseBlk d = dblk[tk.idx];
-                const int64_t ld = 3 * (int64_t)d.m;
-                const cplx<S> *tile = dense + d.off + 3 * (int64_t)tk.rowoff;
-                const cplx<A> *xs = xc + 3 * (int64_t)d.cb;
-                const int32_t ncol = 3 * d.n;
-                for (int32_t jj = 0; jj < ncol; ++jj) {
-                    const cplx<A> xv = xs[jj];
-                    const cplx<S> *c = tile + jj * ld;
-#pragma unroll
-                    for (int k = 0; k < RPL; ++k) {
-                        const int32_t row = r0 + lane + k * kWave;
-                        if (row < rows) fma_(acc[k], cvt<A>(c[row]), xv);
-                    }
-                }
+                panel_accum<S, A, RPL>(acc, dense + d.off + 3 * (int64_t)tk.rowoff,
+                                       3 * (int64_t)d.m, xc + 3 * (int64_t)d.cb, 3 * d.n, r0,
+                                       rows, lane);
             } else {
                 const LowRankBlk b = lblk[tk.idx];
-                const int64_t ld = 3 * (int64_t)b.m;
-                const cplx<S> *u = fac + b.uoff + 3 * (int64_t)tk.rowoff;
-                const cplx<A> *tv = t + b.toff;
-                for (int32_t l = 0; l < b.r; ++l) {
-                    const cplx<A> tl = tv[l];
-                    const cplx<S> *c = u + l * ld;
-#pragma unroll
-                    for (int k = 0; k < RPL; ++k) {
-                        const int32_t row = r0 + lane + k * kWave;
-                        if (row < rows) fma_(acc[k], cvt<A>(c[row]), tl);
-                    }
-                }
+                panel_accum<S, A, RPL>(acc, fac + b.uoff + 3 * (int64_t)tk.rowoff,
+                                       3 * (int64_t)b.m, t + b.toff, b.r, r0, rows, lane);
             }
         }
 #pragma unroll
@@ -136,6 +206,46 @@ __global__ void __launch_bounds__(256) accum_kernel(
 }
 
 template <typename S, typename A>
+static void launch_project(const hm_matrix *M, const cplx<A> *xc, cplx<A> *tb, hipStream_t st) {
+    if (M->n_ptasks == 0) return;
+    auto *tp = M->tpart.as<cplx<A>>();
+    hipLaunchKernelGGL((project_kernel<S, A>), dim3((unsigned)ceil_div(M->n_ptasks, 4)), dim3(256),
+                       0, st, M->d_lblk.as<LowRankBlk>(), M->d_ptasks.as<ProjTask>(),
+                       M->n_ptasks, M->lowrank.as<cplx<S>>(), xc, tb, tp);
+    HM_HIP_CHECK(hipGetLastError());
+    if (M->n_preduce > 0) {
+        hipLaunchKernelGGL((project_reduce_kernel<A>), dim3((unsigned)ceil_div(M->n_preduce, 4)),
+                           dim3(256), 0, st, M->d_lblk.as<LowRankBlk>(),
+                           M->d_preduce.as<ProjReduce>(), M->n_preduce, tp, tb);
+        HM_HIP_CHECK(hipGetLastError());
+    }
+}
+
+template <typename S, typename A, int OUT, int RPL>
+static void launch_accum_rpl(const hm_matrix *M, const cplx<A> *xc, const cplx<A> *tb, void *y,
+                             int64_t ldy, int32_t col, const double *b, hipStream_t st) {
+    hipLaunchKernelGGL((accum_kernel<S, A, OUT, RPL>), dim3(M->n_leaves), dim3(64 * kAccWaves), 0,
+                       st, M->d_leaves.as<LeafRow>(), M->d_tasks.as<Task>(),
+                       M->d_dblk.as<DenseBlk>(), M->d_lblk.as<LowRankBlk>(),
+                       M->dense.as<cplx<S>>(), M->lowrank.as<cplx<S>>(), xc, tb,
+                       M->perm_x.as<int32_t>(), y, ldy, col, b);
+    HM_HIP_CHECK(hipGetLastError());
+}
+
+// Rows per lane chosen so that the largest leaf is covered in one chunk.
+template <typename S, typename A, int OUT>
+static void launch_accum(const hm_matrix *M, const cplx<A> *xc, const cplx<A> *tb, void *y,
+                         int64_t ldy, int32_t col, const double *b, hipStream_t st) {
+    const int rpl = (int)std::min<int64_t>(4, std::max<int64_t>(1, ceil_div(3 * M->max_leaf, 64)));
+    switch (rpl) {
+        case 1: launch_accum_rpl<S, A, OUT, 1>(M, xc, tb, y, ldy, col, b, st); break;
+        case 2: launch_accum_rpl<S, A, OUT, 2>(M, xc, tb, y, ldy, col, b, st); break;
+        case 3: launch_accum_rpl<S, A, OUT, 3>(M, xc, tb, y, ldy, col, b, st); break;
+        default: launch_accum_rpl<S, A, OUT, 4>(M, xc, tb, y, ldy, col, b, st); break;
+    }
+}
+
+template <typename S, typename A>
 void launch_matvec_col(const hm_matrix *M, const void *x, int64_t ldx, int32_t col, void *y,
                        int64_t ldy, const double *b, hipStream_t st) {
     const int64_t ny = M->ny;
@@ -150,26 +260,11 @@ void launch_matvec_col(const hm_matrix *M, const void *x, int64_t ldx, int32_t c
         hipLaunchKernelGGL((gather_kernel<double, A>), dim3(ceil_div(3 * ny, 256)), dim3(256), 0,
                            st, static_cast<const cplx<double> *>(x), ldx, col, perm_y, ny, xc);
     HM_HIP_CHECK(hipGetLastError());
-    const auto *fac = M->lowrank.as<cplx<S>>();
-    if (M->n_lblk > 0) {
-        hipLaunchKernelGGL((project_kernel<S, A>), dim3(M->n_lblk), dim3(256), 0, st,
-                           M->d_lblk.as<LowRankBlk>(), fac, xc, tb);
-        HM_HIP_CHECK(hipGetLastError());
-    }
-    if (b == nullptr) {
-        hipLaunchKernelGGL((accum_kernel<S, A, 0>), dim3(M->n_leaves), dim3(256), 0, st,
-                           M->d_leaves.as<LeafRow>(), M->d_tasks.as<Task>(),
-                           M->d_dblk.as<DenseBlk>(), M->d_lblk.as<LowRankBlk>(),
-                           M->dense.as<cplx<S>>(), fac, xc, tb, M->perm_x.as<int32_t>(), y, ldy,
-                           col, nullptr);
-    } else {
-        hipLaunchKernelGGL((accum_kernel<S, A, 1>), dim3(M->n_leaves), dim3(256), 0, st,
-                           M->d_leaves.as<LeafRow>(), M->d_tasks.as<Task>(),
-                           M->d_dblk.as<DenseBlk>(), M->d_lblk.as<LowRankBlk>(),
-                           M->dense.as<cplx<S>>(), fac, xc, tb, M->perm_x.as<int32_t>(), y, ldy,
-                           col, b);
-    }
-    HM_HIP_CHECK(hipGetLastError());
+    launch_project<S, A>(M, xc, tb, st);
+    if (b == nullptr)
+        launch_accum<S, A, 0>(M, xc, tb, y, ldy, col, nullptr, st);
+    else
+        launch_accum<S, A, 1>(M, xc, tb, y, ldy, col, b, st);
 }
 
 // Same three launches with HIP events between them; adds each kernel's
@@ -187,21 +282,15 @@ void profile_matvec_col(const hm_matrix *M, const void *x, void *y, hipStream_t 
     hipLaunchKernelGGL((gather_kernel<S, A>), dim3(ceil_div(3 * ny, 256)), dim3(256), 0, st,
                        static_cast<const cplx<S> *>(x), 1, 0, perm_y, ny, xc);
     HM_HIP_CHECK(hipEventRecord(ev[1], st));
-    const auto *fac = M->lowrank.as<cplx<S>>();
-    if (M->n_lblk > 0)
-        hipLaunchKernelGGL((project_kernel<S, A>), dim3(M->n_lblk), dim3(256), 0, st,
-                           M->d_lblk.as<LowRankBlk>(), fac, xc, tb);
+    launch_project<S, A>(M, xc, tb, st);
     HM_HIP_CHECK(hipEventRecord(ev[2], st));
-    hipLaunchKernelGGL((accum_kernel<S, A, 0>), dim3(M->n_leaves), dim3(256), 0, st,
-                       M->d_leaves.as<LeafRow>(), M->d_tasks.as<Task>(), M->d_dblk.as<DenseBlk>(),
-                       M->d_lblk.as<LowRankBlk>(), M->dense.as<cplx<S>>(), fac, xc, tb,
-                       M->perm_x.as<int32_t>(), y, 1, 0, nullptr);
+    launch_accum<S, A, 0>(M, xc, tb, y, 1, 0, nullptr, st);
     HM_HIP_CHECK(hipEventRecord(ev[3], st));
     HM_HIP_CHECK(hipEventSynchronize(ev[3]));
     for (int k = 0; k < 3; ++k) {
-        float t = 0;
-        HM_HIP_CHECK(hipEventElapsedTime(&t, ev[k], ev[k + 1]));
-        ms3[k] += t;
+        float tms = 0;
+        HM_HIP_CHECK(hipEventElapsedTime(&tms, ev[k], ev[k + 1]));
+        ms3[k] += tms;
     }
     for (auto &e : ev) HM_HIP_CHECK(hipEventDestroy(e));
 }
@@ -210,7 +299,6 @@ template void profile_matvec_col<float>(const hm_matrix *, const void *, void *,
                                         double *);
 template void profile_matvec_col<double>(const hm_matrix *, const void *, void *, hipStream_t,
                                          double *);
-
 template void launch_matvec_col<float, float>(const hm_matrix *, const void *, int64_t, int32_t,
                                               void *, int64_t, const double *, hipStream_t);
 template void launch_matvec_col<double, double>(const hm_matrix *, const void *, int64_t, int32_t,

@@ -16,15 +16,17 @@
 //   apply    U' = U W_U, V' = V W_V written to the compact final slab.
 // A Cholesky pivot that is not positive (numerically dependent ACA columns)
 // zeroes that row of R: the dependent column adds nothing to the range.
+#include <algorithm>
 #include <climits>
 
 #include "internal.hpp"
 
 namespace hm {
 
-// Per-block FP64 work area (complex doubles), 7 r x r column-major slots:
+// Per-block FP64 work area (complex doubles): 7 r x r column-major slots
 // 0 R_U (from G_U), 1 R_V (from G_V), 2 M (then M J), 3 J, 4 W_U, 5 W_V,
-// 6 singular values and their ranking.
+// 6 column scales, singular values and their ranking (6 holds r^2 + 2r
+// complex doubles, enough for 3r doubles and r ints for every r >= 1).
 __host__ __device__ inline int64_t rc_slot(int32_t r, int s) { return (int64_t)s * r * r; }
 
 struct GramItem {
@@ -84,26 +86,37 @@ __global__ void __launch_bounds__(256) gram_kernel(const RcBlk *__restrict__ blk
     }
 }
 
-// In-place upper Cholesky G = R^* R of an r x r Hermitian PSD matrix
-// (column-major); entries below the diagonal are zeroed.
-__device__ void chol_upper(cplx<double> *G, int r, double *sh_scalar) {
-    const int tid = threadIdx.x;
-    double dmax = 0;
-    for (int k = 0; k < r; ++k) dmax = fmax(dmax, G[k + (int64_t)k * r].re);
+__device__ inline double wave_sumd(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// In-place upper Cholesky G = R^* R of an r x r Hermitian PSD matrix with
+// unit diagonal (column-major); entries below the diagonal are zeroed.
+// A pivot <= tol marks a numerically dependent column: its row of R is zero.
+__device__ void chol_upper(cplx<double> *G, int r, double tol, double *sh) {
+    const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
     for (int k = 0; k < r; ++k) {
-        if (tid == 0) {
-            double d = G[k + (int64_t)k * r].re;
-            for (int i = 0; i < k; ++i) d -= abs2(G[i + (int64_t)k * r]);
-            const double rk = (d > 1e-15 * dmax && d > 0.0) ? sqrt(d) : 0.0;
-            G[k + (int64_t)k * r] = {rk, 0.0};
-            sh_scalar[0] = rk;
+        if (wave == 0) {
+            double d = 0;
+            for (int i = lane; i < k; i += 64) d += abs2(G[i + (int64_t)k * r]);
+            d = wave_sumd(d);
+            if (lane == 0) {
+                d = G[k + (int64_t)k * r].re - d;
+                const double rk = d > tol ? sqrt(d) : 0.0;
+                G[k + (int64_t)k * r] = {rk, 0.0};
+                sh[0] = rk;
+            }
         }
         __syncthreads();
-        const double rk = sh_scalar[0];
+        const double rk = sh[0];
+        const cplx<double> *rkcol = G + (int64_t)k * r;
         for (int j = k + 1 + tid; j < r; j += blockDim.x) {
-            cplx<double> s = G[k + (int64_t)j * r];
-            for (int i = 0; i < k; ++i) s = s - cmul(G[i + (int64_t)k * r], G[i + (int64_t)j * r]);
-            G[k + (int64_t)j * r] = rk > 0.0 ? (1.0 / rk) * s : cplx<double>{0, 0};
+            cplx<double> *cj = G + (int64_t)j * r;
+            cplx<double> s = cj[k];
+            for (int i = 0; i < k; ++i) s = s - cmul(rkcol[i], cj[i]);
+            cj[k] = rk > 0.0 ? (1.0 / rk) * s : cplx<double>{0, 0};
         }
         __syncthreads();
     }
@@ -114,97 +127,214 @@ __device__ void chol_upper(cplx<double> *G, int r, double *sh_scalar) {
     __syncthreads();
 }
 
-__device__ inline double wave_sumd(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+// One rotation of the one-sided Jacobi method on columns x, y (length r, LDS)
+// with the matching columns jx, jy of J, executed by a group of gs lanes
+// (gs a power of two dividing 64; gl = lane index inside the group).
+// Returns true if a rotation was applied.
+__device__ inline bool jacobi_pair(cplx<double> *x, cplx<double> *y, cplx<double> *jx,
+                                   cplx<double> *jy, int r, double tol, int gl, int gs) {
+    double al = 0, be = 0, gr = 0, gi = 0;
+    for (int i = gl; i < r; i += gs) {
+        const cplx<double> a = x[i], b = y[i];
+        al += abs2(a);
+        be += abs2(b);
+        gr += a.re * b.re + a.im * b.im;
+        gi += a.re * b.im - a.im * b.re;
+    }
+    for (int o = gs / 2; o > 0; o >>= 1) {
+        al += __shfl_xor(al, o, gs);
+        be += __shfl_xor(be, o, gs);
+        gr += __shfl_xor(gr, o, gs);
+        gi += __shfl_xor(gi, o, gs);
+    }
+    const double ag = sqrt(gr * gr + gi * gi);
+    if (!(ag > tol * sqrt(al * be))) return false;
+    // Unitary [[c, s], [-s e^{-i phi}, c e^{-i phi}]] diagonalising the 2x2 Gram.
+    const double tau = (be - al) / (2.0 * ag);
+    const double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+    const double c = 1.0 / sqrt(1.0 + t * t), s = t * c;
+    const cplx<double> ph = {gr / ag, -gi / ag};
+    const cplx<double> v10 = (-s) * ph, v11 = c * ph;
+    for (int i = gl; i < r; i += gs) {
+        const cplx<double> a = x[i], b = y[i];
+        x[i] = c * a + b * v10;
+        y[i] = s * a + b * v11;
+        const cplx<double> ja = jx[i], jb = jy[i];
+        jx[i] = c * ja + jb * v10;
+        jy[i] = s * ja + jb * v11;
+    }
+    return true;
+}
+
+// Position -> column of the round-robin tournament over `n` (even) slots.
+__device__ inline int rr_slot(int pos, int round, int n) {
+    return pos == 0 ? 0 : 1 + (pos - 1 + round) % (n - 1);
+}
+
+// One sweep over all column pairs of the `nc` columns held in LDS at
+// lds (column-major, leading dimension r) with the matching columns of J at
+// ldj; the pairs of one round are disjoint and run concurrently, each on a
+// group of gs lanes sized so that a round fills the workgroup.  Returns
+// whether anything rotated.
+__device__ bool lds_sweep(cplx<double> *lds, cplx<double> *ldj, int nc, int r, double tol,
+                          int *sh_flag) {
+    const int ne = (nc + 1) & ~1;
+    const int npairs = ne / 2;
+    int gs = 64;
+    while (gs > 1 && npairs * gs > (int)blockDim.x) gs >>= 1;
+    const int ngroups = blockDim.x / gs;
+    const int grp = threadIdx.x / gs, gl = threadIdx.x % gs;
+    if (threadIdx.x == 0) *sh_flag = 0;
+    __syncthreads();
+    bool any = false;
+    for (int round = 0; round < ne - 1; ++round) {
+        for (int pr = grp; pr < npairs; pr += ngroups) {
+            int p = rr_slot(pr, round, ne), q = rr_slot(ne - 1 - pr, round, ne);
+            if (p >= nc || q >= nc) continue;
+            if (p > q) {
+                const int tq = p;
+                p = q;
+                q = tq;
+            }
+            any |= jacobi_pair(lds + (int64_t)p * r, lds + (int64_t)q * r, ldj + (int64_t)p * r,
+                               ldj + (int64_t)q * r, r, tol, gl, gs);
+        }
+        __syncthreads();
+    }
+    if (any && gl == 0) *sh_flag = 1;
+    __syncthreads();
+    const bool res = *sh_flag != 0;
+    // every thread has read the flag before anyone may reset it again
+    __syncthreads();
+    return res;
+}
+
+// One-sided Jacobi SVD of the r x r column-major matrix M (global), in place,
+// accumulating the rotations into J (global, identity on entry): on exit the
+// columns of M J are mutually orthogonal, M J = P S, and J = L.  Columns are
+// processed in LDS (M and J side by side), the whole matrix at once when it
+// fits, else as pairs of column blocks of width bw (block Jacobi,
+// round-robin over the blocks).
+__device__ void jacobi_svd(cplx<double> *M, cplx<double> *J, int r, cplx<double> *lds,
+                           int64_t lds_elems, int *sh_flag) {
+    const double tol = fmax(1e-14, 4.0 * r * 1.1e-16);
+    const int tid = threadIdx.x;
+    if (2 * (int64_t)r * r <= lds_elems) {
+        cplx<double> *ldj = lds + (int64_t)r * r;
+        for (int64_t q = tid; q < (int64_t)r * r; q += blockDim.x) {
+            lds[q] = M[q];
+            ldj[q] = J[q];
+        }
+        __syncthreads();
+        for (int sweep = 0; sweep < 30; ++sweep)
+            if (!lds_sweep(lds, ldj, r, r, tol, sh_flag)) break;
+        for (int64_t q = tid; q < (int64_t)r * r; q += blockDim.x) {
+            M[q] = lds[q];
+            J[q] = ldj[q];
+        }
+        __syncthreads();
+        return;
+    }
+    const int bw = (int)max<int64_t>(1, lds_elems / (4 * (int64_t)r));
+    const int nb = (r + bw - 1) / bw;
+    const int ne = (nb + 1) & ~1;
+    cplx<double> *ldj = lds + 2 * (int64_t)bw * r;
+    for (int sweep = 0; sweep < 30; ++sweep) {
+        bool any = false;
+        for (int round = 0; round < ne - 1; ++round) {
+            for (int pr = 0; pr < ne / 2; ++pr) {
+                const int bi = rr_slot(pr, round, ne), bj = rr_slot(ne - 1 - pr, round, ne);
+                if (bi >= nb || bj >= nb) continue;
+                const int c0 = bi * bw, n0 = min(bw, r - c0);
+                const int c1 = bj * bw, n1 = min(bw, r - c1);
+                const int nc = n0 + n1;
+                for (int64_t q = tid; q < (int64_t)nc * r; q += blockDim.x) {
+                    const int cc = (int)(q / r), i = (int)(q % r);
+                    const int col = cc < n0 ? c0 + cc : c1 + (cc - n0);
+                    lds[q] = M[(int64_t)col * r + i];
+                    ldj[q] = J[(int64_t)col * r + i];
+                }
+                __syncthreads();
+                any |= lds_sweep(lds, ldj, nc, r, tol, sh_flag);
+                for (int64_t q = tid; q < (int64_t)nc * r; q += blockDim.x) {
+                    const int cc = (int)(q / r), i = (int)(q % r);
+                    const int col = cc < n0 ? c0 + cc : c1 + (cc - n0);
+                    M[(int64_t)col * r + i] = lds[q];
+                    J[(int64_t)col * r + i] = ldj[q];
+                }
+                __syncthreads();
+            }
+        }
+        if (!any) break;
+    }
 }
 
 template <typename R>
 __global__ void __launch_bounds__(256) factor_kernel(const RcBlk *__restrict__ blks,
+                                                     const int32_t *__restrict__ order,
                                                      cplx<double> *__restrict__ work,
-                                                     int32_t *__restrict__ newrank, double eps) {
+                                                     int32_t *__restrict__ newrank, double eps,
+                                                     int64_t lds_elems) {
+    extern __shared__ unsigned char smem_raw[];
+    cplx<double> *lds = reinterpret_cast<cplx<double> *>(smem_raw);
     __shared__ double sh_s[1];
-    __shared__ int sh_rot[4];
-    __shared__ double sh_red[8];
-    const RcBlk b = blks[blockIdx.x];
+    __shared__ int sh_i[4];
+    const int32_t bi = order[blockIdx.x];
+    const RcBlk b = blks[bi];
     const int r = b.r;
     const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
     if (r == 0) {
-        if (tid == 0) newrank[blockIdx.x] = 0;
+        if (tid == 0) newrank[bi] = 0;
         return;
     }
     cplx<double> *W = work + b.goff;
     cplx<double> *RU = W + rc_slot(r, 0), *RV = W + rc_slot(r, 1), *M = W + rc_slot(r, 2),
                  *J = W + rc_slot(r, 3), *WU = W + rc_slot(r, 4), *WV = W + rc_slot(r, 5);
-    chol_upper(RU, r, sh_s);
-    chol_upper(RV, r, sh_s);
-    // M = R_U R_V^*, J = I
+    double *du = reinterpret_cast<double *>(W + rc_slot(r, 6));
+    double *dv = du + r;
+    double *sv = dv + r;
+    int *idx = reinterpret_cast<int *>(sv + r);
+    // Column equilibration: G~ = D^-1 G D^-1, D = sqrt(diag G).
+    for (int k = tid; k < r; k += 256) {
+        const double a = sqrt(fmax(RU[k + (int64_t)k * r].re, 0.0));
+        const double c = sqrt(fmax(RV[k + (int64_t)k * r].re, 0.0));
+        du[k] = a > 0 ? a : 1.0;
+        dv[k] = c > 0 ? c : 1.0;
+    }
+    __syncthreads();
+    for (int64_t q = tid; q < (int64_t)r * r; q += 256) {
+        const int i = (int)(q % r), j = (int)(q / r);
+        RU[q] = (1.0 / (du[i] * du[j])) * RU[q];
+        RV[q] = (1.0 / (dv[i] * dv[j])) * RV[q];
+    }
+    __syncthreads();
+    const double ctol = 4.0 * r * 1.1e-16;
+    for (int side = 0; side < 2; ++side) {
+        cplx<double> *G = side == 0 ? RU : RV;
+        if ((int64_t)r * r <= lds_elems) {
+            // factor in LDS (the dot products of the left-looking sweep are
+            // then LDS reads instead of dependent global loads)
+            for (int64_t q = tid; q < (int64_t)r * r; q += 256) lds[q] = G[q];
+            __syncthreads();
+            chol_upper(lds, r, ctol, sh_s);
+            for (int64_t q = tid; q < (int64_t)r * r; q += 256) G[q] = lds[q];
+            __syncthreads();
+        } else {
+            chol_upper(G, r, ctol, sh_s);
+        }
+    }
+    // M = R_U D R_V^*, D = du dv (the block is U~ D V~^*)
     for (int64_t q = tid; q < (int64_t)r * r; q += 256) {
         const int i = (int)(q % r), j = (int)(q / r);
         cplx<double> s = {0, 0};
         for (int k = max(i, j); k < r; ++k)
-            s = s + mulc(RU[i + (int64_t)k * r], RV[j + (int64_t)k * r]);
+            s = s + (du[k] * dv[k]) * mulc(RU[i + (int64_t)k * r], RV[j + (int64_t)k * r]);
         M[q] = s;
         J[q] = (i == j) ? cplx<double>{1, 0} : cplx<double>{0, 0};
     }
     __syncthreads();
-    // One-sided Jacobi with round-robin pairing over rr = r rounded up to even.
-    const int rr = (r + 1) & ~1;
-    for (int sweep = 0; sweep < 40; ++sweep) {
-        if (tid == 0) sh_rot[0] = 0;
-        __syncthreads();
-        for (int round = 0; round < rr - 1; ++round) {
-            for (int pr = wave; pr < rr / 2; pr += 4) {
-                // tournament pairing: position 0 fixed, others rotate
-                auto at = [&](int pos) { return pos == 0 ? 0 : 1 + (pos - 1 + round) % (rr - 1); };
-                int pcol = at(pr), qcol = at(rr - 1 - pr);
-                if (pcol >= r || qcol >= r) continue;
-                if (pcol > qcol) {
-                    const int t = pcol;
-                    pcol = qcol;
-                    qcol = t;
-                }
-                cplx<double> *mp = M + (int64_t)pcol * r, *mq = M + (int64_t)qcol * r;
-                double al = 0, be = 0, gr = 0, gi = 0;
-                for (int i = lane; i < r; i += 64) {
-                    const cplx<double> x = mp[i], y = mq[i];
-                    al += abs2(x);
-                    be += abs2(y);
-                    gr += x.re * y.re + x.im * y.im;
-                    gi += x.re * y.im - x.im * y.re;
-                }
-                al = wave_sumd(al);
-                be = wave_sumd(be);
-                gr = wave_sumd(gr);
-                gi = wave_sumd(gi);
-                const double ag = sqrt(gr * gr + gi * gi);
-                if (ag == 0.0 || ag <= 1e-15 * sqrt(al * be)) continue;
-                if (lane == 0) sh_rot[0] = 1;
-                const double tau = (be - al) / (2.0 * ag);
-                const double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-                const double c = 1.0 / sqrt(1.0 + t * t), s = t * c;
-                const cplx<double> ph = {gr / ag, -gi / ag};
-                const cplx<double> v10 = (-s) * ph, v11 = c * ph;
-                cplx<double> *jp = J + (int64_t)pcol * r, *jq = J + (int64_t)qcol * r;
-                for (int i = lane; i < r; i += 64) {
-                    const cplx<double> x = mp[i], y = mq[i];
-                    mp[i] = c * x + y * v10;
-                    mq[i] = s * x + y * v11;
-                    const cplx<double> u = jp[i], w = jq[i];
-                    jp[i] = c * u + w * v10;
-                    jq[i] = s * u + w * v11;
-                }
-            }
-            __syncthreads();
-        }
-        const int any = sh_rot[0];
-        __syncthreads();
-        if (!any) break;
-    }
-    // Singular values = column norms of M J, ranked in descending order.
-    double *sv = reinterpret_cast<double *>(W + rc_slot(r, 6));   // r doubles
-    int *idx = reinterpret_cast<int *>(sv + r);                   // r ints
+    jacobi_svd(M, J, r, lds, lds_elems, &sh_i[0]);
+    // singular values = column norms of M J, ranked in descending order
     for (int c = wave; c < r; c += 4) {
         double s = 0;
         for (int i = lane; i < r; i += 64) s += abs2(M[i + (int64_t)c * r]);
@@ -238,12 +368,12 @@ __global__ void __launch_bounds__(256) factor_kernel(const RcBlk *__restrict__ b
                 if (k > 0) tail += sv[idx[k - 1]] * sv[idx[k - 1]];
             }
         }
-        sh_rot[1] = keep;
+        sh_i[1] = keep;
     }
     __syncthreads();
-    const int keep = sh_rot[1];
-    // W_U[k][c] = sum_{j<=k} conj(R_V[j][k]) J[j][idx_c] / sqrt(s_c)
-    // W_V[k][c] = sum_{i<=k} conj(R_U[i][k]) (M J)[i][idx_c] / s_c^(3/2)
+    const int keep = sh_i[1];
+    // W_U = D_v R_V^* L_r S_r^-1/2 with L = J,  W_V = D_u R_U^* P_r S_r^-1/2 with
+    // P_r = (M J)[:, idx] / s
     for (int64_t q = tid; q < (int64_t)r * keep; q += 256) {
         const int k = (int)(q % r), c = (int)(q / r);
         const int ic = idx[c];
@@ -251,10 +381,10 @@ __global__ void __launch_bounds__(256) factor_kernel(const RcBlk *__restrict__ b
         cplx<double> a = {0, 0}, bb = {0, 0};
         for (int j = 0; j <= k; ++j) a = a + cmul(RV[j + (int64_t)k * r], J[j + (int64_t)ic * r]);
         for (int i = 0; i <= k; ++i) bb = bb + cmul(RU[i + (int64_t)k * r], M[i + (int64_t)ic * r]);
-        WU[q] = (1.0 / sqrt(s)) * a;
-        WV[q] = (1.0 / (s * sqrt(s))) * bb;
+        WU[q] = (dv[k] / sqrt(s)) * a;
+        WV[q] = (du[k] / (s * sqrt(s))) * bb;
     }
-    if (tid == 0) newrank[blockIdx.x] = keep;
+    if (tid == 0) newrank[bi] = keep;
 }
 
 // U' = U W_U (3m x keep), V' = V W_V (3n x keep) into the compact slab.
@@ -291,7 +421,12 @@ __global__ void __launch_bounds__(256) apply_kernel(const RcBlk *__restrict__ bl
             }
 #pragma unroll
             for (int k = 0; k < 8; ++k)
-                if (c0 + k < keep) Y[(int64_t)(c0 + k) * rows + row] = cvt<R>(acc[k]);
+                if (c0 + k < keep) {
+                    // U' column-major, V' row-major
+                    const int64_t o = which == 0 ? (int64_t)(c0 + k) * rows + row
+                                                 : row * keep + (c0 + k);
+                    Y[o] = cvt<R>(acc[k]);
+                }
         }
     }
 }
@@ -317,8 +452,47 @@ void run_recompress(const std::vector<RcBlk> &blk, RcBlk *d_blk, const cplx<R> *
                            d_items.as<GramItem>(), acaslab, reinterpret_cast<cplx<double> *>(work));
         HM_HIP_CHECK(hipGetLastError());
     }
-    hipLaunchKernelGGL(factor_kernel<R>, dim3((unsigned)blk.size()), dim3(256), 0, st, d_blk,
-                       reinterpret_cast<cplx<double> *>(work), d_newrank, eps);
+    // LDS for the Jacobi sweeps: per rank class, what M and J of the largest
+    // block of the class need (whole-matrix mode), capped at what the device
+    // grants one workgroup (block mode above that), so that small blocks keep
+    // several workgroups per CU.
+    static int max_lds = -1;
+    if (max_lds < 0) {
+        int dev = 0, v = 65536;
+        HM_HIP_CHECK(hipGetDevice(&dev));
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+            v = 65536;
+        max_lds = std::min(v, 160 * 1024) - 1024;
+        if (max_lds > 65536)
+            HM_HIP_CHECK(hipFuncSetAttribute((const void *)factor_kernel<R>,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, max_lds));
+    }
+    std::vector<int32_t> order(blk.size());
+    for (size_t i = 0; i < blk.size(); ++i) order[i] = (int32_t)i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int32_t a, int32_t b) { return blk[a].r > blk[b].r; });
+    DeviceBuf d_order;
+    d_order.alloc(order.size() * sizeof(int32_t));
+    HM_HIP_CHECK(hipMemcpyAsync(d_order.p, order.data(), order.size() * sizeof(int32_t),
+                                hipMemcpyHostToDevice, st));
+    const int classes[] = {16, 24, 32, 48, 64, 1 << 30};
+    size_t q0 = 0;
+    while (q0 < order.size()) {
+        const int rmax = blk[order[q0]].r;
+        int cls = 0;
+        while (classes[cls] < rmax) ++cls;
+        const int lo = cls > 0 ? classes[cls - 1] : -1;
+        size_t q1 = q0;
+        while (q1 < order.size() && blk[order[q1]].r > lo) ++q1;
+        const int64_t need = 2 * (int64_t)rmax * rmax * (int64_t)sizeof(cplx<double>);
+        const int64_t bytes = std::min<int64_t>(std::max<int64_t>(need, 1024), max_lds);
+        const int64_t lds_elems = bytes / (int64_t)sizeof(cplx<double>);
+        hipLaunchKernelGGL(factor_kernel<R>, dim3((unsigned)(q1 - q0)), dim3(256), (size_t)bytes,
+                           st, d_blk, d_order.as<int32_t>() + q0,
+                           reinterpret_cast<cplx<double> *>(work), d_newrank, eps, lds_elems);
+        HM_HIP_CHECK(hipGetLastError());
+        q0 = q1;
+    }
     HM_HIP_CHECK(hipGetLastError());
     // items (pageable) and d_items must outlive the copy and the kernels.
     HM_HIP_CHECK(hipStreamSynchronize(st));
