@@ -54,22 +54,27 @@ static void upload(DeviceBuf &buf, const std::vector<T> &v, hipStream_t st) {
     }
 }
 
-// Copies the leading r columns of ACA factors into the final slab.
+// Copies the leading r columns of ACA factors into the final slab: U to the
+// padded column-major layout, V transposed to row-major with an even stride.
 template <typename R>
 __global__ void copy_factors_kernel(const RcBlk *__restrict__ blks, const cplx<R> *__restrict__ src,
                                     const int64_t *__restrict__ outu,
-                                    const int64_t *__restrict__ outv, cplx<R> *__restrict__ dst) {
+                                    const int64_t *__restrict__ outv, cplx<R> *__restrict__ dst,
+                                    const int32_t *__restrict__ rowpad) {
     const RcBlk b = blks[blockIdx.y];
-    const int64_t nu = 3 * (int64_t)b.m * b.r, nv = 3 * (int64_t)b.n * b.r;
+    const int64_t rows_u = 3 * (int64_t)b.m, rows_v = 3 * (int64_t)b.n;
+    const int64_t nu = rows_u * b.r, nv = rows_v * b.r;
+    const int64_t ldu = padded_rows(rowpad, b.rb, b.m), ldv = even_up(b.r);
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nu + nv;
          k += (int64_t)gridDim.x * blockDim.x) {
         if (k < nu) {
-            dst[outu[blockIdx.y] + k] = src[b.uoff + k];
+            const int64_t row = k % rows_u, c = k / rows_u;
+            dst[outu[blockIdx.y] + c * ldu +
+                padded_row(rowpad, b.rb, (int32_t)(row / 3), (int)(row % 3))] = src[b.uoff + k];
         } else {
-            // V: column-major scratch -> row-major final layout
-            const int64_t q = k - nu, rows = 3 * (int64_t)b.n;
-            const int64_t row = q % rows, c = q / rows;
-            dst[outv[blockIdx.y] + row * b.r + c] = src[b.voff + q];
+            const int64_t q = k - nu;
+            const int64_t row = q % rows_v, c = q / rows_v;
+            dst[outv[blockIdx.y] + row * ldv + c] = src[b.voff + q];
         }
     }
 }
@@ -292,6 +297,19 @@ void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vect
     M->block_slot.assign(nb, -1);
     M->off_a.assign(nb, -1);
     M->off_v.assign(nb, -1);
+    // ---- padded row layout: one zero row after every odd leaf segment -------
+    M->rowpad.assign(nx + 1, 0);
+    {
+        int32_t acc = 0;
+        for (int32_t v = 0; v < tx.nodes(); ++v) {
+            if (!tx.is_leaf(v)) continue;   // pre-order visits leaves in position order
+            for (int32_t q = tx.begin[v]; q < tx.end[v]; ++q) M->rowpad[q] = acc;
+            acc += tx.size(v) & 1;
+        }
+        M->rowpad[nx] = acc;
+    }
+    upload(M->d_rowpad, M->rowpad, st);
+    const int32_t *rowpad = M->rowpad.data();
     // ---- dense near-field tiles ------------------------------------------
     int64_t dense_entries = 0;
     for (int64_t b = 0; b < nb; ++b) {
@@ -303,13 +321,17 @@ void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vect
         d.m = tx.size(B.row);
         d.cb = ty.begin[B.col];
         d.n = ty.size(B.col);
+        d.ld = padded_rows(rowpad, d.rb, d.m);
+        d.pad = 0;
         M->block_slot[b] = (int32_t)M->h_dblk.size();
         M->off_a[b] = d.off;
         M->h_dblk.push_back(d);
-        dense_entries += 9 * (int64_t)d.m * d.n;
+        dense_entries += (int64_t)d.ld * 3 * d.n;
     }
     M->n_dblk = (int32_t)M->h_dblk.size();
-    M->dense.alloc(std::max<int64_t>(dense_entries, 1) * sizeof(cplx<R>));
+    // +2 elements: paired 16-byte loads may touch one element past the last tile
+    M->dense.alloc((dense_entries + 2) * sizeof(cplx<R>));
+    HM_HIP_CHECK(hipMemsetAsync(M->dense.p, 0, (dense_entries + 2) * sizeof(cplx<R>), st));
     upload(M->d_dblk, M->h_dblk, st);
     DeviceBuf derr;
     derr.alloc(sizeof(int32_t));
@@ -441,10 +463,12 @@ void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vect
             c.uoff = aca_u[k];
             c.voff = aca_v[k];
             c.m = lm[k];
+            c.rb = tx.begin[M->blocks[lr_ids[k]].row];
             c.n = ln[k];
             c.r = aca_rank[k];
             c.goff = goff;
-            goff += 7 * (int64_t)c.r * c.r + 2 * (int64_t)c.r;
+            // slot 6 holds r^2 + 2r entries (see the recompression work layout)
+            goff += 8 * (int64_t)c.r * c.r + 2 * (int64_t)c.r;
             rc.push_back(c);
         }
         pass_drc[ps] = std::make_unique<DeviceBuf>();
@@ -470,16 +494,20 @@ void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vect
     int64_t lr_entries = 0, t_len = 0;
     std::vector<int64_t> fu(nlr), fv(nlr);
     for (int64_t k = 0; k < nlr; ++k) {
+        const Block &B = M->blocks[lr_ids[k]];
         fu[k] = lr_entries;
-        lr_entries += 3 * (int64_t)lm[k] * final_rank[k];
+        lr_entries += (int64_t)padded_rows(rowpad, tx.begin[B.row], lm[k]) * final_rank[k];
         fv[k] = lr_entries;
-        lr_entries += 3 * (int64_t)ln[k] * final_rank[k];
+        lr_entries += 3 * (int64_t)ln[k] * even_up(final_rank[k]);
     }
-    M->lowrank.alloc(std::max<int64_t>(lr_entries, 1) * sizeof(cplx<R>));
+    M->lowrank.alloc((lr_entries + 2) * sizeof(cplx<R>));
+    HM_HIP_CHECK(hipMemsetAsync(M->lowrank.p, 0, (lr_entries + 2) * sizeof(cplx<R>), st));
     for (size_t ps = 0; ps < pass_scratch.size(); ++ps) {
         auto &mem = pass_members[ps];
         if (mem.empty()) continue;
         std::vector<int64_t> ou(mem.size()), ov(mem.size());
+        std::vector<int32_t> kp(mem.size());
+        for (size_t q = 0; q < mem.size(); ++q) kp[q] = final_rank[mem[q]];
         int32_t maxrows = 0;
         for (size_t q = 0; q < mem.size(); ++q) {
             ou[q] = fu[mem[q]];
@@ -494,11 +522,12 @@ void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vect
                                     pass_scratch[ps]->as<cplx<R>>(), pass_work[ps]->as<double>(),
                                     d_ou.as<int64_t>(), d_ov.as<int64_t>(),
                                     pass_newrank[ps]->as<int32_t>(), M->lowrank.as<cplx<R>>(),
-                                    maxrows, st);
+                                    kp, M->d_rowpad.as<int32_t>(), st);
         } else {
             hipLaunchKernelGGL(copy_factors_kernel<R>, dim3(64, (unsigned)mem.size()), dim3(256), 0,
                                st, pass_drc[ps]->as<RcBlk>(), pass_scratch[ps]->as<cplx<R>>(),
-                               d_ou.as<int64_t>(), d_ov.as<int64_t>(), M->lowrank.as<cplx<R>>());
+                               d_ou.as<int64_t>(), d_ov.as<int64_t>(), M->lowrank.as<cplx<R>>(),
+                               M->d_rowpad.as<int32_t>());
             HM_HIP_CHECK(hipGetLastError());
         }
         HM_HIP_CHECK(hipStreamSynchronize(st));
@@ -522,6 +551,8 @@ void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vect
         L.cb = ty.begin[B.col];
         L.n = ln[k];
         L.r = final_rank[k];
+        L.ldu = padded_rows(rowpad, L.rb, L.m);
+        L.ldv = even_up(L.r);
         L.pad = 0;
         t_len += L.r;
         M->block_slot[b] = (int32_t)M->h_lblk.size();
@@ -556,7 +587,8 @@ void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vect
             Task tk;
             tk.kind = B.kind == BLOCK_DENSE ? 0 : 1;
             tk.idx = M->block_slot[b];
-            tk.rowoff = tx.begin[L] - tx.begin[B.row];
+            // padded row offset of leaf L inside the block's rows (even)
+            tk.rowoff = padded_row(rowpad, tx.begin[B.row], tx.begin[L] - tx.begin[B.row], 0);
             tk.pad = 0;
             per_leaf[leaf_index[L]].push_back(tk);
         }
@@ -608,7 +640,12 @@ void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vect
     S.sum_rank_aca = sr_aca;
     S.sum_rank = sr;
     S.storage_bytes = (dense_entries + lr_entries) * (int64_t)sizeof(cplx<R>);
-    S.matvec_bytes = S.storage_bytes + (3 * nx + 3 * ny) * (int64_t)sizeof(cplx<R>);
+    // algorithmic bytes: 9mn per dense tile + 3r(m+n) per low-rank block
+    // (padding excluded) + one read of x + one write of y
+    int64_t alg = 0;
+    for (const auto &d : M->h_dblk) alg += 9 * (int64_t)d.m * d.n;
+    for (const auto &L : M->h_lblk) alg += 3 * (int64_t)L.r * (L.m + L.n);
+    S.matvec_bytes = (alg + 3 * nx + 3 * ny) * (int64_t)sizeof(cplx<R>);
 }
 
 }  // namespace
@@ -668,7 +705,8 @@ extern "C" hm_status hm_profile_matvec(const hm_matrix *A, const void *x, void *
         vbytes += 3 * (int64_t)L.n * L.r * es;
         ubytes += 3 * (int64_t)L.m * L.r * es;
     }
-    const int64_t dbytes = A->stats.dense_entries * es;
+    int64_t dbytes = 0;
+    for (const auto &d : A->h_dblk) dbytes += 9 * (int64_t)d.m * d.n * es;
     if (kernel_ms)
         for (int k = 0; k < 3; ++k) kernel_ms[k] = ms[k] / reps;
     if (kernel_bytes) {
@@ -736,23 +774,35 @@ extern "C" hm_status hm_export_block(const hm_matrix *A, int64_t b, void *host_b
     const size_t es = elem_bytes(A->p.prec);
     const Block &B = A->blocks[b];
     const int64_t m = A->rowtree().size(B.row), n = A->coltree().size(B.col);
+    const int32_t rb = A->rowtree().begin[B.row];
+    const int32_t *rowpad = A->rowpad.data();
+    char *h = static_cast<char *>(host_buf);
+    auto pr = [&](int64_t row) { return padded_row(rowpad, rb, (int32_t)(row / 3), (int)(row % 3)); };
     if (B.kind == BLOCK_DENSE) {
-        HM_HIP_CHECK(hipMemcpy(host_buf, static_cast<char *>(A->dense.p) + A->off_a[b] * es,
-                               9 * m * n * es, hipMemcpyDeviceToHost));
+        const int64_t ld = padded_rows(rowpad, rb, (int32_t)m);
+        std::vector<char> tmp(ld * 3 * n * es);
+        HM_HIP_CHECK(hipMemcpy(tmp.data(), static_cast<char *>(A->dense.p) + A->off_a[b] * es,
+                               tmp.size(), hipMemcpyDeviceToHost));
+        for (int64_t c = 0; c < 3 * n; ++c)
+            for (int64_t row = 0; row < 3 * m; ++row)
+                std::memcpy(h + (c * 3 * m + row) * es, tmp.data() + (c * ld + pr(row)) * es, es);
     } else {
         const int64_t r = A->rank[b];
-        char *h = static_cast<char *>(host_buf);
         if (r > 0) {
-            HM_HIP_CHECK(hipMemcpy(h, static_cast<char *>(A->lowrank.p) + A->off_a[b] * es,
-                                   3 * m * r * es, hipMemcpyDeviceToHost));
+            const int64_t ldu = padded_rows(rowpad, rb, (int32_t)m), ldv = even_up((int32_t)r);
+            std::vector<char> tu(ldu * r * es), tv(3 * n * ldv * es);
+            HM_HIP_CHECK(hipMemcpy(tu.data(), static_cast<char *>(A->lowrank.p) + A->off_a[b] * es,
+                                   tu.size(), hipMemcpyDeviceToHost));
+            HM_HIP_CHECK(hipMemcpy(tv.data(), static_cast<char *>(A->lowrank.p) + A->off_v[b] * es,
+                                   tv.size(), hipMemcpyDeviceToHost));
+            for (int64_t c = 0; c < r; ++c)
+                for (int64_t row = 0; row < 3 * m; ++row)
+                    std::memcpy(h + (c * 3 * m + row) * es, tu.data() + (c * ldu + pr(row)) * es, es);
             // V is stored row-major; export it column-major.
-            std::vector<char> tmp(3 * n * r * es);
-            HM_HIP_CHECK(hipMemcpy(tmp.data(), static_cast<char *>(A->lowrank.p) + A->off_v[b] * es,
-                                   tmp.size(), hipMemcpyDeviceToHost));
             char *hv = h + 3 * m * r * es;
             for (int64_t row = 0; row < 3 * n; ++row)
                 for (int64_t c = 0; c < r; ++c)
-                    std::memcpy(hv + (c * 3 * n + row) * es, tmp.data() + (row * r + c) * es, es);
+                    std::memcpy(hv + (c * 3 * n + row) * es, tv.data() + (row * ldv + c) * es, es);
         }
     }
     return HM_OK;

@@ -13,16 +13,25 @@ namespace hm {
 
 // Dense near-field tile: rows rb..rb+m (row cluster order), cols cb..cb+n,
 // stored column-major (3m x 3n) at `off` complex elements into the dense slab.
+// Storage layout shared by dense tiles and U factors: the rows of a row
+// cluster are the concatenation of its leaves' row segments (3 per point),
+// each padded with one zero row when odd, so every leaf segment starts at an
+// even row (16-byte aligned complex64 pairs).  rowpad(P) below is that
+// padding count before cluster position P.
 struct DenseBlk {
     int64_t off;
     int32_t rb, m, cb, n;
+    int32_t ld, pad;     // ld = padded row count of the tile (even)
 };
 
 // Low-rank block U V^*: U (3m x r) column-major at uoff, V (3n x r) row-major
 // at voff, t-vector slot at toff (r entries per right-hand side).
 struct LowRankBlk {
     int64_t uoff, voff, toff;
-    int32_t rb, m, cb, n, r, pad;
+    int32_t rb, m, cb, n, r;
+    int32_t ldu;         // padded row count of U (even)
+    int32_t ldv;         // row stride of the row-major V: r rounded up to even
+    int32_t pad;
 };
 
 // Work item of a leaf row cluster: kind 0 = dense block index, 1 = low-rank
@@ -71,7 +80,7 @@ struct AcaOut {
 struct RcBlk {
     int64_t uoff, voff;   // ACA factors (scratch slab)
     int64_t goff;         // r x r FP64 work matrices offset (complex doubles)
-    int32_t m, n, r, pad;
+    int32_t m, n, r, rb;  // rb: first row point (cluster order) for the padded U layout
 };
 
 struct DeviceBuf {
@@ -113,6 +122,8 @@ struct hm_matrix {
     hm::DeviceBuf d_dblk, d_lblk, d_tasks, d_leaves, d_ptasks, d_preduce, tpart;
     int32_t n_dblk = 0, n_lblk = 0, n_leaves = 0, n_ptasks = 0, n_preduce = 0;
     int32_t max_leaf = 1;     // largest leaf row cluster (points)
+    hm::DeviceBuf d_rowpad;   // int32[nx + 1]: padding rows before each position
+    std::vector<int32_t> rowpad;
     int64_t t_len = 0;        // sum of ranks
     std::vector<hm::DenseBlk> h_dblk;
     std::vector<hm::LowRankBlk> h_lblk;
@@ -155,6 +166,17 @@ void run_recompress(const std::vector<RcBlk> &blk, RcBlk *d_blk, const cplx<R> *
 template <typename R>
 void run_recompress_apply(const std::vector<RcBlk> &blk, RcBlk *d_blk, const cplx<R> *acaslab,
                           const double *work, const int64_t *d_outu, const int64_t *d_outv,
-                          const int32_t *d_newrank, cplx<R> *out, int32_t rmax, hipStream_t st);
+                          const int32_t *d_newrank, cplx<R> *out, const std::vector<int32_t> &keep,
+                          const int32_t *d_rowpad, hipStream_t st);
+
+// Padded row of (local point p, component a) in a block whose row cluster
+// starts at cluster position rb.
+__host__ __device__ inline int64_t padded_row(const int32_t *rowpad, int32_t rb, int32_t p, int a) {
+    return 3 * (int64_t)p + a + (rowpad[rb + p] - rowpad[rb]);
+}
+__host__ __device__ inline int32_t padded_rows(const int32_t *rowpad, int32_t rb, int32_t m) {
+    return 3 * m + (rowpad[rb + m] - rowpad[rb]);
+}
+__host__ __device__ inline int32_t even_up(int32_t v) { return v + (v & 1); }
 
 }  // namespace hm

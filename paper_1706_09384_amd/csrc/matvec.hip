@@ -1,8 +1,9 @@
 // H-matrix-vector product (Section 3.1): y = sum over leaf blocks of the
 // dense tile times x_sigma, or U (V^* x_sigma) for low-rank blocks.
 //
-// Storage: dense tiles 3m x 3n column-major; U (3m x r) column-major; V
-// stored row-major (3n x r, the r coefficients of one row contiguous).
+// Storage: dense tiles and U column-major with the padded leaf-segment row
+// layout (even leading dimension, every leaf segment starting on an even
+// row); V stored row-major (3n x r, row stride r rounded up to even).
 // Three passes, no atomics, every output row written exactly once:
 //   gather   x (original order, one column) -> xc (column-cluster order)
 //   project  t_b = V_b^* xc[sigma_b]: one wave per (block, group of up to 64
@@ -11,8 +12,9 @@
 //            segment of the row-major V; the row groups are summed in LDS
 //   accum    one workgroup per leaf row cluster L: the sum over the dense
 //            tiles of L and over the rows of every low-rank U whose row
-//            cluster contains L; lanes own rows, waves split the task list,
-//            8-way unrolled column loops keep loads in flight, LDS combines
+//            cluster contains L; lanes own rows (complex64: row pairs read
+//            with one 16-byte load), waves split the task list, 8-way
+//            unrolled column loops keep loads in flight, LDS combines
 //            the waves, and the result is scattered to original order (or
 //            subtracted from b for the FP64 residual).
 // S is the storage real type, A the accumulation real type.
@@ -42,57 +44,95 @@ __global__ void __launch_bounds__(256) project_kernel(const LowRankBlk *__restri
                                                       const cplx<A> *__restrict__ xc,
                                                       cplx<A> *__restrict__ t,
                                                       cplx<A> *__restrict__ tpart) {
-    __shared__ cplx<A> part[256];
+    // complex64: each lane owns a column pair (one 16-byte load per row; the
+    // even row stride and zero pad column keep loads aligned and in bounds)
+    constexpr bool PAIR = sizeof(S) == 4 && sizeof(A) == 4;
+    constexpr int CPL = PAIR ? 2 : 1;   // columns per lane
+    __shared__ cplx<A> part[256 * CPL];
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int32_t ti = blockIdx.x * (blockDim.x / kWave) + wave;
     const bool live = ti < ntasks;
-    A re = 0, im = 0;
-    int width = 1, G = 1;
+    cplx<A> acc[CPL];
+#pragma unroll
+    for (int h = 0; h < CPL; ++h) acc[h] = {A(0), A(0)};
+    int width = 1, G = 1, lw = 1;
     LowRankBlk b;
     ProjTask pt = {0, 0, 0, 0, -1, 0};
     if (live) {
         pt = ptasks[ti];
         b = blk[pt.blk];
-        const int r = b.r;
-        width = min(64, r - pt.col0);
-        // G row groups of `width` lanes: for a fixed iteration the wave reads
-        // G consecutive rows of the row-major V, i.e. one contiguous segment.
-        G = kWave / width;
-        const int g = lane / width, c = lane - g * width;
+        width = min(64, b.r - pt.col0);
+        lw = (width + CPL - 1) / CPL;   // lanes per row
+        // G row groups of lw lanes: for a fixed iteration the wave reads G
+        // consecutive rows of the row-major V, i.e. one contiguous segment.
+        G = kWave / lw;
+        const int g = lane / lw, c = lane - g * lw;
         if (g < G) {
             const int32_t rows = pt.nrows;
-            const cplx<S> *v = fac + b.voff + (int64_t)pt.row0 * r + pt.col0 + c;
+            const int64_t ldv = b.ldv;
+            const cplx<S> *v = fac + b.voff + (int64_t)pt.row0 * ldv + pt.col0 + CPL * c;
             const cplx<A> *xs = xc + 3 * (int64_t)b.cb + pt.row0;
             int32_t i = g;
-            for (; i + 7 * G < rows; i += 8 * G) {
-                cplx<S> vv[8];
-                cplx<A> xv[8];
+            if constexpr (PAIR) {
+                for (; i + 7 * G < rows; i += 8 * G) {
+                    float4 vv[8];
+                    cplx<A> xv[8];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    vv[u] = v[(int64_t)(i + u * G) * r];
-                    xv[u] = xs[i + u * G];
-                }
+                    for (int u = 0; u < 8; ++u) {
+                        vv[u] = *reinterpret_cast<const float4 *>(v + (int64_t)(i + u * G) * ldv);
+                        xv[u] = xs[i + u * G];
+                    }
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const cplx<A> a = cvt<A>(vv[u]);
-                    re += a.re * xv[u].re + a.im * xv[u].im;
-                    im += a.re * xv[u].im - a.im * xv[u].re;
+                    for (int u = 0; u < 8; ++u) {
+                        // conj(v) * x for both columns
+                        acc[0].re += vv[u].x * xv[u].re + vv[u].y * xv[u].im;
+                        acc[0].im += vv[u].x * xv[u].im - vv[u].y * xv[u].re;
+                        acc[1].re += vv[u].z * xv[u].re + vv[u].w * xv[u].im;
+                        acc[1].im += vv[u].z * xv[u].im - vv[u].w * xv[u].re;
+                    }
                 }
-            }
-            for (; i < rows; i += G) {
-                const cplx<A> a = cvt<A>(v[(int64_t)i * r]);
-                const cplx<A> xv = xs[i];
-                re += a.re * xv.re + a.im * xv.im;
-                im += a.re * xv.im - a.im * xv.re;
+                for (; i < rows; i += G) {
+                    const float4 vv = *reinterpret_cast<const float4 *>(v + (int64_t)i * ldv);
+                    const cplx<A> xv = xs[i];
+                    acc[0].re += vv.x * xv.re + vv.y * xv.im;
+                    acc[0].im += vv.x * xv.im - vv.y * xv.re;
+                    acc[1].re += vv.z * xv.re + vv.w * xv.im;
+                    acc[1].im += vv.z * xv.im - vv.w * xv.re;
+                }
+            } else {
+                for (; i + 7 * G < rows; i += 8 * G) {
+                    cplx<S> vv[8];
+                    cplx<A> xv[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        vv[u] = v[(int64_t)(i + u * G) * ldv];
+                        xv[u] = xs[i + u * G];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const cplx<A> a = cvt<A>(vv[u]);
+                        acc[0].re += a.re * xv[u].re + a.im * xv[u].im;
+                        acc[0].im += a.re * xv[u].im - a.im * xv[u].re;
+                    }
+                }
+                for (; i < rows; i += G) {
+                    const cplx<A> a = cvt<A>(v[(int64_t)i * ldv]);
+                    const cplx<A> xv = xs[i];
+                    acc[0].re += a.re * xv.re + a.im * xv.im;
+                    acc[0].im += a.re * xv.im - a.im * xv.re;
+                }
             }
         }
     }
-    // sum the G row groups of each column through LDS (per-wave region)
-    part[threadIdx.x] = {re, im};
+    // sum the G row groups of each column through LDS (per-wave region);
+    // part index (wave, lane) * CPL + h holds column CPL * (lane % lw) + h of row group lane / lw
+#pragma unroll
+    for (int h = 0; h < CPL; ++h) part[threadIdx.x * CPL + h] = acc[h];
     __syncthreads();
     if (live && lane < width) {
+        const int cl = lane / CPL, h = lane % CPL;   // column `lane` lives in lane cl, slot h
         cplx<A> s = {A(0), A(0)};
-        for (int q = 0; q < G; ++q) s = s + part[wave * kWave + q * width + lane];
+        for (int q = 0; q < G; ++q) s = s + part[(wave * kWave + q * lw + cl) * CPL + h];
         if (pt.slot < 0)
             t[b.toff + pt.col0 + lane] = s;
         else
@@ -149,10 +189,55 @@ __device__ inline void panel_accum(cplx<A> (&acc)[RPL], const cplx<S> *__restric
     }
 }
 
+// Complex64 variant: each lane owns row pairs (2q, 2q+1) and reads both with
+// one 16-byte load; panels start on even rows and have even leading
+// dimensions (padded layout), so every load is aligned.
+template <int RPL>
+__device__ inline void panel_accum_pair(cplx<float> (&acc)[2 * RPL],
+                                        const cplx<float> *__restrict__ base, int64_t ld,
+                                        const cplx<float> *__restrict__ wv, int32_t ncol,
+                                        int32_t p0, int32_t npairs, int lane) {
+    const float4 *b4 = reinterpret_cast<const float4 *>(base);
+    const int64_t ld4 = ld >> 1;
+    int32_t j = 0;
+    for (; j + 8 <= ncol; j += 8) {
+        cplx<float> w[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) w[u] = wv[j + u];
+#pragma unroll
+        for (int k = 0; k < RPL; ++k) {
+            const int32_t q = p0 + lane + k * kWave;
+            if (q < npairs) {
+                float4 c[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) c[u] = b4[(j + u) * ld4 + q];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    fma_(acc[2 * k], cplx<float>{c[u].x, c[u].y}, w[u]);
+                    fma_(acc[2 * k + 1], cplx<float>{c[u].z, c[u].w}, w[u]);
+                }
+            }
+        }
+    }
+    for (; j < ncol; ++j) {
+        const cplx<float> w = wv[j];
+#pragma unroll
+        for (int k = 0; k < RPL; ++k) {
+            const int32_t q = p0 + lane + k * kWave;
+            if (q < npairs) {
+                const float4 c = b4[j * ld4 + q];
+                fma_(acc[2 * k], cplx<float>{c.x, c.y}, w);
+                fma_(acc[2 * k + 1], cplx<float>{c.z, c.w}, w);
+            }
+        }
+    }
+}
+
 constexpr int kAccWaves = 8;
 
 // OUT = 0: y (type S) = A x; OUT = 1: r (double) = b - A x.
-// RPL rows per lane per chunk (64 * RPL rows), kAccWaves waves per leaf.
+// RPL rows (row pairs for complex64 storage with complex64 accumulation) per
+// lane per chunk, kAccWaves waves per leaf.
 template <typename S, typename A, int OUT, int RPL>
 __global__ void __launch_bounds__(64 * kAccWaves) accum_kernel(
     const LeafRow *__restrict__ leaves, const Task *__restrict__ tasks,
@@ -161,32 +246,52 @@ __global__ void __launch_bounds__(64 * kAccWaves) accum_kernel(
     const cplx<A> *__restrict__ xc, const cplx<A> *__restrict__ t,
     const int32_t *__restrict__ perm, void *__restrict__ yout, int64_t ldy, int32_t col,
     const double *__restrict__ bvec) {
-    __shared__ cplx<A> red[kAccWaves][kWave * RPL];
+    constexpr bool PAIR = sizeof(S) == 4 && sizeof(A) == 4;
+    constexpr int RPC = PAIR ? 2 : 1;   // rows per accumulator slot group
+    __shared__ cplx<A> red[kAccWaves][kWave * RPL * RPC];
     const LeafRow L = leaves[blockIdx.x];
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int nw = blockDim.x / kWave;
     const int32_t rows = 3 * L.m;
-    for (int32_t r0 = 0; r0 < rows; r0 += kWave * RPL) {
-        cplx<A> acc[RPL];
+    constexpr int32_t chunk = kWave * RPL * RPC;
+    for (int32_t r0 = 0; r0 < rows; r0 += chunk) {
+        cplx<A> acc[RPL * RPC];
 #pragma unroll
-        for (int k = 0; k < RPL; ++k) acc[k] = {A(0), A(0)};
+        for (int k = 0; k < RPL * RPC; ++k) acc[k] = {A(0), A(0)};
         for (int32_t ti = L.tbeg + wave; ti < L.tend; ti += nw) {
             const Task tk = tasks[ti];
+            const cplx<S> *base;
+            int64_t ld;
+            const cplx<A> *wv;
+            int32_t ncol;
             if (tk.kind == 0) {
                 const DenseBlk d = dblk[tk.idx];
-                panel_accum<S, A, RPL>(acc, dense + d.off + 3 * (int64_t)tk.rowoff,
-                                       3 * (int64_t)d.m, xc + 3 * (int64_t)d.cb, 3 * d.n, r0,
-                                       rows, lane);
+                base = dense + d.off + tk.rowoff;
+                ld = d.ld;
+                wv = xc + 3 * (int64_t)d.cb;
+                ncol = 3 * d.n;
             } else {
                 const LowRankBlk b = lblk[tk.idx];
-                panel_accum<S, A, RPL>(acc, fac + b.uoff + 3 * (int64_t)tk.rowoff,
-                                       3 * (int64_t)b.m, t + b.toff, b.r, r0, rows, lane);
+                base = fac + b.uoff + tk.rowoff;
+                ld = b.ldu;
+                wv = t + b.toff;
+                ncol = b.r;
+            }
+            if constexpr (PAIR) {
+                panel_accum_pair<RPL>(acc, reinterpret_cast<const cplx<float> *>(base), ld,
+                                      reinterpret_cast<const cplx<float> *>(wv), ncol, r0 / 2,
+                                      (rows + 1) / 2, lane);
+            } else {
+                panel_accum<S, A, RPL>(acc, base, ld, wv, ncol, r0, rows, lane);
             }
         }
+        // slot (k, h) holds row r0 + RPC * (lane + 64 k) + h
 #pragma unroll
-        for (int k = 0; k < RPL; ++k) red[wave][lane + k * kWave] = acc[k];
+        for (int k = 0; k < RPL; ++k)
+#pragma unroll
+            for (int h = 0; h < RPC; ++h) red[wave][RPC * (lane + k * kWave) + h] = acc[RPC * k + h];
         __syncthreads();
-        for (int32_t q = threadIdx.x; q < kWave * RPL; q += blockDim.x) {
+        for (int32_t q = threadIdx.x; q < chunk; q += blockDim.x) {
             const int32_t row = r0 + q;
             if (row < rows) {
                 cplx<A> s = red[0][q];
@@ -236,7 +341,9 @@ static void launch_accum_rpl(const hm_matrix *M, const cplx<A> *xc, const cplx<A
 template <typename S, typename A, int OUT>
 static void launch_accum(const hm_matrix *M, const cplx<A> *xc, const cplx<A> *tb, void *y,
                          int64_t ldy, int32_t col, const double *b, hipStream_t st) {
-    const int rpl = (int)std::min<int64_t>(4, std::max<int64_t>(1, ceil_div(3 * M->max_leaf, 64)));
+    const int per_lane = (sizeof(S) == 4 && sizeof(A) == 4) ? 128 : 64;   // rows per RPL unit
+    const int rpl =
+        (int)std::min<int64_t>(4, std::max<int64_t>(1, ceil_div(3 * M->max_leaf, per_lane)));
     switch (rpl) {
         case 1: launch_accum_rpl<S, A, OUT, 1>(M, xc, tb, y, ldy, col, b, st); break;
         case 2: launch_accum_rpl<S, A, OUT, 2>(M, xc, tb, y, ldy, col, b, st); break;

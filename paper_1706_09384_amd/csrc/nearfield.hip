@@ -16,7 +16,7 @@ __global__ void __launch_bounds__(256) nearfield_kernel(Geometry g, GreenParams<
                                                         cplx<R> *__restrict__ slab, R self_re,
                                                         R self_im, int32_t *__restrict__ err) {
     const DenseBlk b = blk[blockIdx.x];
-    const int64_t ld = 3 * (int64_t)b.m;
+    const int64_t ld = b.ld;   // padded (even) row count of the tile
     cplx<R> *tile = slab + b.off;
     const int32_t pairs = b.m * b.n;
     for (int32_t k = threadIdx.x; k < pairs; k += blockDim.x) {

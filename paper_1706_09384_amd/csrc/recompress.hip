@@ -23,10 +23,11 @@
 
 namespace hm {
 
-// Per-block FP64 work area (complex doubles): 7 r x r column-major slots
-// 0 R_U (from G_U), 1 R_V (from G_V), 2 M (then M J), 3 J, 4 W_U, 5 W_V,
-// 6 column scales, singular values and their ranking (6 holds r^2 + 2r
-// complex doubles, enough for 3r doubles and r ints for every r >= 1).
+// Per-block FP64 work area (complex doubles): r x r column-major slots
+// 0 R_U (from G_U), 1 R_V (from G_V), 2 M (then M J), 3 J or the unrotated
+// core, 4 W_U, 5 W_V, 6 right singular vectors L (r x keep), 7 (last, with
+// r^2 + 2r complex doubles: enough for 3r doubles and r ints for every
+// r >= 1) column scales, singular values and their ranking.
 __host__ __device__ inline int64_t rc_slot(int32_t r, int s) { return (int64_t)s * r * r; }
 
 struct GramItem {
@@ -131,6 +132,7 @@ __device__ void chol_upper(cplx<double> *G, int r, double tol, double *sh) {
 // with the matching columns jx, jy of J, executed by a group of gs lanes
 // (gs a power of two dividing 64; gl = lane index inside the group).
 // Returns true if a rotation was applied.
+template <bool WITHJ>
 __device__ inline bool jacobi_pair(cplx<double> *x, cplx<double> *y, cplx<double> *jx,
                                    cplx<double> *jy, int r, double tol, int gl, int gs) {
     double al = 0, be = 0, gr = 0, gi = 0;
@@ -159,9 +161,11 @@ __device__ inline bool jacobi_pair(cplx<double> *x, cplx<double> *y, cplx<double
         const cplx<double> a = x[i], b = y[i];
         x[i] = c * a + b * v10;
         y[i] = s * a + b * v11;
-        const cplx<double> ja = jx[i], jb = jy[i];
-        jx[i] = c * ja + jb * v10;
-        jy[i] = s * ja + jb * v11;
+        if constexpr (WITHJ) {
+            const cplx<double> ja = jx[i], jb = jy[i];
+            jx[i] = c * ja + jb * v10;
+            jy[i] = s * ja + jb * v11;
+        }
     }
     return true;
 }
@@ -176,6 +180,7 @@ __device__ inline int rr_slot(int pos, int round, int n) {
 // ldj; the pairs of one round are disjoint and run concurrently, each on a
 // group of gs lanes sized so that a round fills the workgroup.  Returns
 // whether anything rotated.
+template <bool WITHJ>
 __device__ bool lds_sweep(cplx<double> *lds, cplx<double> *ldj, int nc, int r, double tol,
                           int *sh_flag) {
     const int ne = (nc + 1) & ~1;
@@ -196,8 +201,9 @@ __device__ bool lds_sweep(cplx<double> *lds, cplx<double> *ldj, int nc, int r, d
                 p = q;
                 q = tq;
             }
-            any |= jacobi_pair(lds + (int64_t)p * r, lds + (int64_t)q * r, ldj + (int64_t)p * r,
-                               ldj + (int64_t)q * r, r, tol, gl, gs);
+            any |= jacobi_pair<WITHJ>(lds + (int64_t)p * r, lds + (int64_t)q * r,
+                                      WITHJ ? ldj + (int64_t)p * r : nullptr,
+                                      WITHJ ? ldj + (int64_t)q * r : nullptr, r, tol, gl, gs);
         }
         __syncthreads();
     }
@@ -209,33 +215,35 @@ __device__ bool lds_sweep(cplx<double> *lds, cplx<double> *ldj, int nc, int r, d
     return res;
 }
 
-// One-sided Jacobi SVD of the r x r column-major matrix M (global), in place,
-// accumulating the rotations into J (global, identity on entry): on exit the
-// columns of M J are mutually orthogonal, M J = P S, and J = L.  Columns are
-// processed in LDS (M and J side by side), the whole matrix at once when it
-// fits, else as pairs of column blocks of width bw (block Jacobi,
-// round-robin over the blocks).
+// One-sided Jacobi SVD of the r x r column-major matrix M (global), in place:
+// on exit the columns of M J are mutually orthogonal, M J = P S.  With WITHJ
+// the rotations are also applied to J (global, identity on entry), giving
+// J = L.  Columns are processed in LDS (with J side by side), the whole
+// matrix at once when it fits, else as pairs of column blocks of width bw
+// (block Jacobi, round-robin over the blocks).
+template <bool WITHJ>
 __device__ void jacobi_svd(cplx<double> *M, cplx<double> *J, int r, cplx<double> *lds,
                            int64_t lds_elems, int *sh_flag) {
     const double tol = fmax(1e-14, 4.0 * r * 1.1e-16);
     const int tid = threadIdx.x;
-    if (2 * (int64_t)r * r <= lds_elems) {
+    constexpr int NJ = WITHJ ? 2 : 1;
+    if (NJ * (int64_t)r * r <= lds_elems) {
         cplx<double> *ldj = lds + (int64_t)r * r;
         for (int64_t q = tid; q < (int64_t)r * r; q += blockDim.x) {
             lds[q] = M[q];
-            ldj[q] = J[q];
+            if constexpr (WITHJ) ldj[q] = J[q];
         }
         __syncthreads();
         for (int sweep = 0; sweep < 30; ++sweep)
-            if (!lds_sweep(lds, ldj, r, r, tol, sh_flag)) break;
+            if (!lds_sweep<WITHJ>(lds, ldj, r, r, tol, sh_flag)) break;
         for (int64_t q = tid; q < (int64_t)r * r; q += blockDim.x) {
             M[q] = lds[q];
-            J[q] = ldj[q];
+            if constexpr (WITHJ) J[q] = ldj[q];
         }
         __syncthreads();
         return;
     }
-    const int bw = (int)max<int64_t>(1, lds_elems / (4 * (int64_t)r));
+    const int bw = (int)max<int64_t>(1, lds_elems / (2 * NJ * (int64_t)r));
     const int nb = (r + bw - 1) / bw;
     const int ne = (nb + 1) & ~1;
     cplx<double> *ldj = lds + 2 * (int64_t)bw * r;
@@ -252,21 +260,60 @@ __device__ void jacobi_svd(cplx<double> *M, cplx<double> *J, int r, cplx<double>
                     const int cc = (int)(q / r), i = (int)(q % r);
                     const int col = cc < n0 ? c0 + cc : c1 + (cc - n0);
                     lds[q] = M[(int64_t)col * r + i];
-                    ldj[q] = J[(int64_t)col * r + i];
+                    if constexpr (WITHJ) ldj[q] = J[(int64_t)col * r + i];
                 }
                 __syncthreads();
-                any |= lds_sweep(lds, ldj, nc, r, tol, sh_flag);
+                any |= lds_sweep<WITHJ>(lds, ldj, nc, r, tol, sh_flag);
                 for (int64_t q = tid; q < (int64_t)nc * r; q += blockDim.x) {
                     const int cc = (int)(q / r), i = (int)(q % r);
                     const int col = cc < n0 ? c0 + cc : c1 + (cc - n0);
                     M[(int64_t)col * r + i] = lds[q];
-                    J[(int64_t)col * r + i] = ldj[q];
+                    if constexpr (WITHJ) J[(int64_t)col * r + i] = ldj[q];
                 }
                 __syncthreads();
             }
         }
         if (!any) break;
     }
+}
+
+// C(i, j) = sum_k A(i, k) B(k, j) for 0 <= i < mC, 0 <= j < nC, 0 <= k < K,
+// with element accessors fa(i, k), fb(k, j) and a sink fc(i, j, value);
+// 32 x 32 output tiles, 32-deep k slabs staged in LDS (sh: 2 * 32 * 33
+// complex doubles), 4 outputs per thread of a 256-thread workgroup.
+template <typename FA, typename FB, typename FC>
+__device__ void small_gemm(int mC, int nC, int K, FA fa, FB fb, FC fc, cplx<double> *sh) {
+    constexpr int T = 32, P = T + 1;
+    cplx<double> *As = sh, *Bs = sh + T * P;
+    const int tid = threadIdx.x;
+    const int tx = tid % T, ty = tid / T;   // ty in 0..7
+    for (int i0 = 0; i0 < mC; i0 += T)
+        for (int j0 = 0; j0 < nC; j0 += T) {
+            cplx<double> acc[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+            for (int k0 = 0; k0 < K; k0 += T) {
+                for (int q = tid; q < T * T; q += 256) {
+                    const int a = q % T, c = q / T;   // a fastest: contiguous rows
+                    As[c * P + a] = (i0 + a < mC && k0 + c < K) ? fa(i0 + a, k0 + c)
+                                                                  : cplx<double>{0, 0};
+                    Bs[a * P + c] = (k0 + a < K && j0 + c < nC) ? fb(k0 + a, j0 + c)
+                                                                  : cplx<double>{0, 0};
+                }
+                __syncthreads();
+#pragma unroll 8
+                for (int kk = 0; kk < T; ++kk) {
+                    const cplx<double> bv = Bs[kk * P + tx];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) acc[u] = acc[u] + As[kk * P + ty * 4 + u] * bv;
+                }
+                __syncthreads();
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int i = i0 + ty * 4 + u, j = j0 + tx;
+                if (i < mC && j < nC) fc(i, j, acc[u]);
+            }
+        }
+    __syncthreads();
 }
 
 template <typename R>
@@ -290,7 +337,8 @@ __global__ void __launch_bounds__(256) factor_kernel(const RcBlk *__restrict__ b
     cplx<double> *W = work + b.goff;
     cplx<double> *RU = W + rc_slot(r, 0), *RV = W + rc_slot(r, 1), *M = W + rc_slot(r, 2),
                  *J = W + rc_slot(r, 3), *WU = W + rc_slot(r, 4), *WV = W + rc_slot(r, 5);
-    double *du = reinterpret_cast<double *>(W + rc_slot(r, 6));
+    cplx<double> *Lw = W + rc_slot(r, 6);
+    double *du = reinterpret_cast<double *>(W + rc_slot(r, 7));
     double *dv = du + r;
     double *sv = dv + r;
     int *idx = reinterpret_cast<int *>(sv + r);
@@ -323,112 +371,149 @@ __global__ void __launch_bounds__(256) factor_kernel(const RcBlk *__restrict__ b
             chol_upper(G, r, ctol, sh_s);
         }
     }
-    // M = R_U D R_V^*, D = du dv (the block is U~ D V~^*)
-    for (int64_t q = tid; q < (int64_t)r * r; q += 256) {
-        const int i = (int)(q % r), j = (int)(q / r);
-        cplx<double> s = {0, 0};
-        for (int k = max(i, j); k < r; ++k)
-            s = s + (du[k] * dv[k]) * mulc(RU[i + (int64_t)k * r], RV[j + (int64_t)k * r]);
-        M[q] = s;
-        J[q] = (i == j) ? cplx<double>{1, 0} : cplx<double>{0, 0};
-    }
-    __syncthreads();
-    jacobi_svd(M, J, r, lds, lds_elems, &sh_i[0]);
-    // singular values = column norms of M J, ranked in descending order
-    for (int c = wave; c < r; c += 4) {
-        double s = 0;
-        for (int i = lane; i < r; i += 64) s += abs2(M[i + (int64_t)c * r]);
-        s = wave_sumd(s);
-        if (lane == 0) sv[c] = sqrt(s);
-    }
-    __syncthreads();
-    for (int c = tid; c < r; c += 256) {
-        const double v = sv[c];
-        int pos = 0;
-        for (int k = 0; k < r; ++k) {
-            const double w = sv[k];
-            if (w > v || (w == v && k < c)) ++pos;
+    // core M = R_U D R_V^*, D = du dv (the block is U~ D V~^*), written to dst
+    auto form_core = [&](cplx<double> *dst) {
+        small_gemm(
+            r, r, r,
+            [&](int i, int k) {
+                return (du[k] * dv[k]) * (i <= k ? RU[i + (int64_t)k * r] : cplx<double>{0, 0});
+            },
+            [&](int k, int j) { return j <= k ? conj(RV[j + (int64_t)k * r]) : cplx<double>{0, 0}; },
+            [&](int i, int j, cplx<double> v) { dst[i + (int64_t)j * r] = v; }, lds);
+    };
+    // singular values = column norms of M J, ranked in descending order; keep =
+    // smallest k with sum_{i >= k} s_i^2 <= eps^2 sum s_i^2 (Frobenius tail)
+    auto rank_and_keep = [&]() -> int {
+        for (int c = wave; c < r; c += 4) {
+            double s = 0;
+            for (int i = lane; i < r; i += 64) s += abs2(M[i + (int64_t)c * r]);
+            s = wave_sumd(s);
+            if (lane == 0) sv[c] = sqrt(s);
         }
-        idx[pos] = c;
-    }
-    __syncthreads();
-    if (tid == 0) {
-        // keep = smallest k with sum_{i >= k} s_i^2 <= eps^2 sum s_i^2 (Frobenius tail)
-        double tot = 0;
-        for (int k = 0; k < r; ++k) tot += sv[idx[k]] * sv[idx[k]];
-        int keep = 0;
-        if (tot > 0.0) {
-            double tail = 0;
-            keep = r;
-            for (int k = r; k >= 0; --k) {
-                if (tail <= eps * eps * tot)
-                    keep = k;
-                else
-                    break;
-                if (k > 0) tail += sv[idx[k - 1]] * sv[idx[k - 1]];
+        __syncthreads();
+        for (int c = tid; c < r; c += 256) {
+            const double v = sv[c];
+            int pos = 0;
+            for (int k = 0; k < r; ++k) {
+                const double w = sv[k];
+                if (w > v || (w == v && k < c)) ++pos;
             }
+            idx[pos] = c;
         }
-        sh_i[1] = keep;
+        __syncthreads();
+        if (tid == 0) {
+            double tot = 0;
+            for (int k = 0; k < r; ++k) tot += sv[idx[k]] * sv[idx[k]];
+            int kp = 0;
+            if (tot > 0.0) {
+                double tail = 0;
+                kp = r;
+                for (int k = r; k >= 0; --k) {
+                    if (tail <= eps * eps * tot)
+                        kp = k;
+                    else
+                        break;
+                    if (k > 0) tail += sv[idx[k - 1]] * sv[idx[k - 1]];
+                }
+            }
+            sh_i[1] = kp;
+        }
+        __syncthreads();
+        return sh_i[1];
+    };
+    form_core(M);
+    jacobi_svd<false>(M, nullptr, r, lds, lds_elems, &sh_i[0]);
+    int keep = rank_and_keep();
+    // Right singular vectors: L = M0^* P S^-1 from the unrotated core M0 has an
+    // error of order u s_1 / s_c, harmless unless a kept singular value is far
+    // below s_1; then the sweeps are redone accumulating the rotations in J.
+    const bool useJ = keep > 0 && sv[idx[keep - 1]] < 1e-6 * sv[idx[0]];
+    if (useJ) {
+        form_core(M);
+        for (int64_t q = tid; q < (int64_t)r * r; q += 256)
+            J[q] = (q % r == q / r) ? cplx<double>{1, 0} : cplx<double>{0, 0};
+        __syncthreads();
+        jacobi_svd<true>(M, J, r, lds, lds_elems, &sh_i[0]);
+        keep = rank_and_keep();
+    } else {
+        form_core(J);   // J slot holds M0
+        // L[:, c] = M0^* (M J)[:, idx_c] / s_c^2
+        small_gemm(
+            r, keep, r, [&](int j, int i) { return conj(J[i + (int64_t)j * r]); },
+            [&](int i, int c) { return M[i + (int64_t)idx[c] * r]; },
+            [&](int j, int c, cplx<double> v) {
+                const double sc = sv[idx[c]];
+                Lw[j + (int64_t)c * r] = (1.0 / (sc * sc)) * v;
+            },
+            lds);
     }
-    __syncthreads();
-    const int keep = sh_i[1];
-    // W_U = D_v R_V^* L_r S_r^-1/2 with L = J,  W_V = D_u R_U^* P_r S_r^-1/2 with
+    // W_U = D_v R_V^* L_r S_r^-1/2,  W_V = D_u R_U^* P_r S_r^-1/2 with
     // P_r = (M J)[:, idx] / s
-    for (int64_t q = tid; q < (int64_t)r * keep; q += 256) {
-        const int k = (int)(q % r), c = (int)(q / r);
-        const int ic = idx[c];
-        const double s = sv[ic];
-        cplx<double> a = {0, 0}, bb = {0, 0};
-        for (int j = 0; j <= k; ++j) a = a + cmul(RV[j + (int64_t)k * r], J[j + (int64_t)ic * r]);
-        for (int i = 0; i <= k; ++i) bb = bb + cmul(RU[i + (int64_t)k * r], M[i + (int64_t)ic * r]);
-        WU[q] = (dv[k] / sqrt(s)) * a;
-        WV[q] = (du[k] / (s * sqrt(s))) * bb;
-    }
+    small_gemm(
+        r, keep, r,
+        [&](int k, int j) { return j <= k ? conj(RV[j + (int64_t)k * r]) : cplx<double>{0, 0}; },
+        [&](int j, int c) { return useJ ? J[j + (int64_t)idx[c] * r] : Lw[j + (int64_t)c * r]; },
+        [&](int k, int c, cplx<double> v) {
+            WU[k + (int64_t)c * r] = (dv[k] / sqrt(sv[idx[c]])) * v;
+        },
+        lds);
+    small_gemm(
+        r, keep, r,
+        [&](int k, int i) { return i <= k ? conj(RU[i + (int64_t)k * r]) : cplx<double>{0, 0}; },
+        [&](int i, int c) { return M[i + (int64_t)idx[c] * r]; },
+        [&](int k, int c, cplx<double> v) {
+            const double sc = sv[idx[c]];
+            WV[k + (int64_t)c * r] = (du[k] / (sc * sqrt(sc))) * v;
+        },
+        lds);
     if (tid == 0) newrank[bi] = keep;
 }
 
-// U' = U W_U (3m x keep), V' = V W_V (3n x keep) into the compact slab.
+// U' = U W_U (3m x keep), V' = V W_V (3n x keep) into the compact slab, one
+// workgroup per (block, factor, 128-row chunk): a tiled product with the
+// factor rows converted to FP64 and the result rounded to the storage type.
+struct ApplyTask {
+    int32_t blk, which, row0, pad;
+};
+
 template <typename R>
 __global__ void __launch_bounds__(256) apply_kernel(const RcBlk *__restrict__ blks,
+                                                    const ApplyTask *__restrict__ tasks,
                                                     const cplx<R> *__restrict__ fac,
                                                     const cplx<double> *__restrict__ work,
                                                     const int32_t *__restrict__ newrank,
                                                     const int64_t *__restrict__ outu,
                                                     const int64_t *__restrict__ outv,
-                                                    cplx<R> *__restrict__ out) {
-    const int bi = blockIdx.y;
+                                                    cplx<R> *__restrict__ out,
+                                                    const int32_t *__restrict__ rowpad) {
+    __shared__ cplx<double> sh[2 * 32 * 33];
+    const ApplyTask tk = tasks[blockIdx.x];
+    const int bi = tk.blk;
     const RcBlk b = blks[bi];
     const int r = b.r, keep = newrank[bi];
-    if (keep == 0) return;
     const cplx<double> *W = work + b.goff;
-    for (int which = 0; which < 2; ++which) {
-        const int64_t rows = 3 * (int64_t)(which == 0 ? b.m : b.n);
-        const int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x;
-        if (blockIdx.x * 256 >= rows) continue;
-        const cplx<R> *X = fac + (which == 0 ? b.uoff : b.voff);
-        const cplx<double> *T = W + rc_slot(r, which == 0 ? 4 : 5);
-        cplx<R> *Y = out + (which == 0 ? outu[bi] : outv[bi]);
-        if (row >= rows) continue;
-        for (int c0 = 0; c0 < keep; c0 += 8) {
-            cplx<double> acc[8];
-#pragma unroll
-            for (int k = 0; k < 8; ++k) acc[k] = {0, 0};
-            for (int l = 0; l < r; ++l) {
-                const cplx<double> x = cvt<double>(X[(int64_t)l * rows + row]);
-#pragma unroll
-                for (int k = 0; k < 8; ++k)
-                    if (c0 + k < keep) acc[k] = acc[k] + x * T[l + (int64_t)(c0 + k) * r];
-            }
-#pragma unroll
-            for (int k = 0; k < 8; ++k)
-                if (c0 + k < keep) {
-                    // U' column-major, V' row-major
-                    const int64_t o = which == 0 ? (int64_t)(c0 + k) * rows + row
-                                                 : row * keep + (c0 + k);
-                    Y[o] = cvt<R>(acc[k]);
-                }
-        }
-    }
+    const int which = tk.which;
+    const int64_t rows = 3 * (int64_t)(which == 0 ? b.m : b.n);
+    const int nrow = (int)min<int64_t>(128, rows - tk.row0);
+    const cplx<R> *X = fac + (which == 0 ? b.uoff : b.voff);
+    const cplx<double> *T = W + rc_slot(r, which == 0 ? 4 : 5);
+    cplx<R> *Y = out + (which == 0 ? outu[bi] : outv[bi]);
+    // U' column-major with the padded leaf-segment rows; V' row-major with an
+    // even row stride.
+    const int64_t ldu = padded_rows(rowpad, b.rb, b.m);
+    const int64_t ldv = even_up(keep);
+    const int64_t row0 = tk.row0;
+    small_gemm(
+        nrow, keep, r, [&](int i, int k) { return cvt<double>(X[(int64_t)k * rows + row0 + i]); },
+        [&](int k, int c) { return T[k + (int64_t)c * r]; },
+        [&](int i, int c, cplx<double> v) {
+            const int64_t row = row0 + i;
+            const int64_t o =
+                which == 0 ? (int64_t)c * ldu + padded_row(rowpad, b.rb, (int32_t)(row / 3), (int)(row % 3))
+                           : row * ldv + c;
+            Y[o] = cvt<R>(v);
+        },
+        sh);
 }
 
 template <typename R>
@@ -484,8 +569,10 @@ void run_recompress(const std::vector<RcBlk> &blk, RcBlk *d_blk, const cplx<R> *
         const int lo = cls > 0 ? classes[cls - 1] : -1;
         size_t q1 = q0;
         while (q1 < order.size() && blk[order[q1]].r > lo) ++q1;
-        const int64_t need = 2 * (int64_t)rmax * rmax * (int64_t)sizeof(cplx<double>);
-        const int64_t bytes = std::min<int64_t>(std::max<int64_t>(need, 1024), max_lds);
+        const int64_t need = (int64_t)rmax * rmax * (int64_t)sizeof(cplx<double>);
+        // at least what small_gemm stages (2 x 32 x 33 complex doubles)
+        const int64_t bytes = std::min<int64_t>(
+            std::max<int64_t>(need, 2 * 32 * 33 * (int64_t)sizeof(cplx<double>)), max_lds);
         const int64_t lds_elems = bytes / (int64_t)sizeof(cplx<double>);
         hipLaunchKernelGGL(factor_kernel<R>, dim3((unsigned)(q1 - q0)), dim3(256), (size_t)bytes,
                            st, d_blk, d_order.as<int32_t>() + q0,
@@ -501,14 +588,29 @@ void run_recompress(const std::vector<RcBlk> &blk, RcBlk *d_blk, const cplx<R> *
 template <typename R>
 void run_recompress_apply(const std::vector<RcBlk> &blk, RcBlk *d_blk, const cplx<R> *acaslab,
                           const double *work, const int64_t *d_outu, const int64_t *d_outv,
-                          const int32_t *d_newrank, cplx<R> *out, int32_t maxrows,
-                          hipStream_t st) {
+                          const int32_t *d_newrank, cplx<R> *out, const std::vector<int32_t> &keep,
+                          const int32_t *d_rowpad, hipStream_t st) {
     if (blk.empty()) return;
-    hipLaunchKernelGGL(apply_kernel<R>, dim3((unsigned)ceil_div(maxrows, 256), (unsigned)blk.size()),
-                       dim3(256), 0, st, d_blk, acaslab,
+    std::vector<ApplyTask> tasks;
+    for (int32_t i = 0; i < (int32_t)blk.size(); ++i) {
+        if (keep[i] == 0) continue;
+        for (int w = 0; w < 2; ++w) {
+            const int32_t rows = 3 * (w == 0 ? blk[i].m : blk[i].n);
+            for (int32_t r0 = 0; r0 < rows; r0 += 128) tasks.push_back({i, w, r0, 0});
+        }
+    }
+    if (tasks.empty()) return;
+    DeviceBuf d_tasks;
+    d_tasks.alloc(tasks.size() * sizeof(ApplyTask));
+    HM_HIP_CHECK(hipMemcpyAsync(d_tasks.p, tasks.data(), tasks.size() * sizeof(ApplyTask),
+                                hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(apply_kernel<R>, dim3((unsigned)tasks.size()), dim3(256), 0, st, d_blk,
+                       d_tasks.as<ApplyTask>(), acaslab,
                        reinterpret_cast<const cplx<double> *>(work), d_newrank, d_outu, d_outv,
-                       out);
+                       out, d_rowpad);
     HM_HIP_CHECK(hipGetLastError());
+    // tasks (pageable) and d_tasks must outlive the copy and the kernel
+    HM_HIP_CHECK(hipStreamSynchronize(st));
 }
 
 template void run_recompress<float>(const std::vector<RcBlk> &, RcBlk *, const cplx<float> *,
@@ -517,11 +619,13 @@ template void run_recompress<double>(const std::vector<RcBlk> &, RcBlk *, const 
                                      double *, int32_t *, double, int32_t, hipStream_t);
 template void run_recompress_apply<float>(const std::vector<RcBlk> &, RcBlk *,
                                           const cplx<float> *, const double *, const int64_t *,
-                                          const int64_t *, const int32_t *, cplx<float> *, int32_t,
+                                          const int64_t *, const int32_t *, cplx<float> *,
+                                          const std::vector<int32_t> &, const int32_t *,
                                           hipStream_t);
 template void run_recompress_apply<double>(const std::vector<RcBlk> &, RcBlk *,
                                            const cplx<double> *, const double *, const int64_t *,
                                            const int64_t *, const int32_t *, cplx<double> *,
-                                           int32_t, hipStream_t);
+                                           const std::vector<int32_t> &, const int32_t *,
+                                           hipStream_t);
 
 }  // namespace hm
