@@ -50,6 +50,30 @@ def timed_matvecs(H, x, reps=50, warm=5):
     return float(np.median(ts)), y
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_matvec_sphere20k_c64.md")
+TRAFFIC_SOURCES = ["paper_1706_09384_amd/csrc/matvec.hip", "paper_1706_09384_amd/csrc/internal.hpp",
+                   "paper_1706_09384_amd/csrc/api.hip"]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE/WRITE_SIZE summary
+    (copy-calibrated), or None when that summary was taken on other sources."""
+    import hashlib
+    try:
+        lines = open(TRAFFIC_FILE).read().splitlines()
+    except OSError:
+        return None
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    for ln in lines:
+        if ln.startswith("traffic-per-launch "):
+            kv = dict(t.split("=", 1) for t in ln.split()[1:])
+            if kv.get("kernel") == kernel and kv.get("sources-sha256") == h.hexdigest():
+                return int(kv["bytes"])
+    return None
+
+
 def sampled_error(orc, w, X, y, b, rows):
     pb = orc.Problem.from_workload(w, X)
     ref = orc.matvec_rows(pb, b, rows)
@@ -135,7 +159,8 @@ def main():
     roof = {"bound": "hbm", "kernel": names[dom], "achieved": kbytes[dom] / (kms[dom] * 1e-3) / 1e9,
             "peak": HBM_PEAK_GBPS, "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
+    roof["traffic"] = measured_traffic(names[dom])
+    roof["traffic_unit"] = "B/launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
     log(f"[bench] matvec {mv_ms:.3f} ms, {gbps:.1f} GB/s; kernels ms {kms} bytes {kbytes}")
 
     import oracle as orc
