@@ -108,6 +108,11 @@ hm_status hm_build(const double *x, int64_t nx, const double *y, int64_t ny, con
  * y = A_H x, Section 3.1 (leaf blocks: dense O(mn), low-rank O(r(m+n))).
  *   x  device, (3 ny, nrhs), complex64 for HM_C64 or complex128 for HM_C128
  *   y  device, (3 nx, nrhs), same type; overwritten.  x and y must not overlap.
+ * Both are row-major: entry (3i + a, c) is at index (3i + a) * nrhs + c.
+ * Complex64 operators with nrhs >= 8 run on panels of 64 right-hand sides
+ * with FP32 matrix-core products (the first such call allocates the panel
+ * workspaces: 3 ny x 64 and sum(rank) x 64 complex64); other cases apply one
+ * column at a time.  Calls that overlap on one matrix race on its workspaces.
  * Asynchronous on stream.  HM_ERR_ARG for nrhs < 1 or NULL pointers.
  */
 hm_status hm_matvec(const hm_matrix *A, const void *x, void *y, int32_t nrhs, void *stream);
@@ -177,6 +182,20 @@ hm_status hm_info(const hm_matrix *A, hm_stats *s);
  */
 hm_status hm_profile_matvec(const hm_matrix *A, const void *x, void *y, int32_t reps, void *stream,
                             double *kernel_ms, int64_t *kernel_bytes);
+
+/*
+ * Measurement helper for the multi-RHS panels (complex64 operators only):
+ * runs one 64-column panel product `reps` times on `stream` with HIP events
+ * between the gather, project (+ reduction) and accumulate passes.
+ *   x, y          device complex64, (3 ny, 64) and (3 nx, 64), row-major
+ *   kernel_ms     host double[3]: mean duration of each pass (ms)
+ *   kernel_flops  host double[3]: algorithmic flops of each pass (8 per
+ *                 complex multiply-add: 0; 64 * 8 * sum 3 n r; 64 * 8 *
+ *                 (sum 9 m n + sum 3 m r))
+ * Synchronous.  HM_ERR_STATE for complex128 operators.
+ */
+hm_status hm_profile_matvec_multi(const hm_matrix *A, const void *x, void *y, int32_t reps,
+                                  void *stream, double *kernel_ms, double *kernel_flops);
 
 /*
  * Copy a cluster tree to host buffers (which = 0: row tree, 1: column tree).

@@ -630,6 +630,48 @@ void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vect
     upload(M->d_lblk, M->h_lblk, st);
     upload(M->d_tasks, tasks, st);
     upload(M->d_leaves, leaves, st);
+    if (M->p.prec == HM_C64) {
+        // multi-RHS plan: accumulation waves ordered by the contraction length
+        // of their leaf (longest first), projection items by chunk length
+        std::vector<int64_t> leaf_cost(leaves.size(), 0);
+        for (size_t l = 0; l < leaves.size(); ++l)
+            for (int32_t q = leaves[l].tbeg; q < leaves[l].tend; ++q)
+                leaf_cost[l] += tasks[q].kind == 0 ? 3 * (int64_t)M->h_dblk[tasks[q].idx].n
+                                                   : (int64_t)M->h_lblk[tasks[q].idx].r;
+        std::vector<MrAccItem> mracc;
+        for (size_t l = 0; l < leaves.size(); ++l)
+            for (int32_t r0 = 0; r0 < 3 * leaves[l].m; r0 += 16)
+                mracc.push_back({(int32_t)l, r0, 0, 0});
+        std::stable_sort(mracc.begin(), mracc.end(), [&](const MrAccItem &a, const MrAccItem &b) {
+            return leaf_cost[a.leaf] > leaf_cost[b.leaf];
+        });
+        std::vector<MrProjItem> mrproj;
+        std::vector<MrProjReduce> mrred;
+        int32_t mslots = 0;
+        for (int32_t i = 0; i < M->n_lblk; ++i) {
+            const int32_t rows = 3 * M->h_lblk[i].n;
+            const int32_t nch = (int32_t)ceil_div(rows, kMrChunk);
+            for (int32_t j0 = 0; j0 < M->h_lblk[i].r; j0 += 16) {
+                if (nch == 1) {
+                    mrproj.push_back({i, j0, 0, rows, -1, 0});
+                    continue;
+                }
+                mrred.push_back({i, j0, mslots, nch});
+                for (int32_t ch = 0; ch < nch; ++ch)
+                    mrproj.push_back({i, j0, ch * kMrChunk,
+                                      std::min(kMrChunk, rows - ch * kMrChunk), mslots++, 0});
+            }
+        }
+        std::stable_sort(mrproj.begin(), mrproj.end(),
+                         [](const MrProjItem &a, const MrProjItem &b) { return a.klen > b.klen; });
+        M->n_mracc = (int32_t)mracc.size();
+        M->n_mrproj = (int32_t)mrproj.size();
+        M->n_mrred = (int32_t)mrred.size();
+        M->mr_nslots = mslots;
+        upload(M->d_mracc, mracc, st);
+        upload(M->d_mrproj, mrproj, st);
+        upload(M->d_mrred, mrred, st);
+    }
     M->ws_xc.alloc(3 * std::max(nx, ny) * sizeof(cplx<double>));
     M->ws_t.alloc(std::max<int64_t>(t_len, 1) * sizeof(cplx<double>));
     HM_HIP_CHECK(hipStreamSynchronize(st));
@@ -657,6 +699,11 @@ extern "C" hm_status hm_matvec(const hm_matrix *A, const void *x, void *y, int32
     require(nrhs >= 1, "nrhs must be >= 1");
     if (A->plan_only) throw StatusError(HM_ERR_STATE, "matrix was built with plan_only");
     hipStream_t st = static_cast<hipStream_t>(stream);
+    if (A->p.prec == HM_C64 && nrhs >= kMrMinCols) {
+        for (int32_t c0 = 0; c0 < nrhs; c0 += kMrPanel)
+            launch_matvec_mrhs(A, x, nrhs, c0, std::min(kMrPanel, nrhs - c0), y, nrhs, st, nullptr);
+        return HM_OK;
+    }
     for (int32_t c = 0; c < nrhs; ++c) {
         if (A->p.prec == HM_C64)
             launch_matvec_col<float, float>(A, x, nrhs, c, y, nrhs, nullptr, st);
@@ -713,6 +760,51 @@ extern "C" hm_status hm_profile_matvec(const hm_matrix *A, const void *x, void *
         kernel_bytes[0] = 3 * A->ny * es;               // x read
         kernel_bytes[1] = vbytes;                       // V factors
         kernel_bytes[2] = dbytes + ubytes + 3 * A->nx * es;  // tiles + U factors + y write
+    }
+    return HM_OK;
+    HM_API_END
+}
+
+extern "C" hm_status hm_profile_matvec_multi(const hm_matrix *A, const void *x, void *y,
+                                             int32_t reps, void *stream, double *kernel_ms,
+                                             double *kernel_flops) {
+    HM_API_BEGIN
+    require(A != nullptr && x != nullptr && y != nullptr && reps >= 1, "bad arguments");
+    if (A->plan_only) throw StatusError(HM_ERR_STATE, "matrix was built with plan_only");
+    if (A->p.prec != HM_C64)
+        throw StatusError(HM_ERR_STATE, "the multi-RHS panels need a complex64 operator");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipEvent_t ev[4];
+    for (auto &e : ev) HM_HIP_CHECK(hipEventCreate(&e));
+    double ms[3] = {0, 0, 0};
+    try {
+        for (int32_t k = 0; k < reps; ++k) {
+            launch_matvec_mrhs(A, x, kMrPanel, 0, kMrPanel, y, kMrPanel, st, ev);
+            HM_HIP_CHECK(hipEventSynchronize(ev[3]));
+            for (int q = 0; q < 3; ++q) {
+                float t = 0;
+                HM_HIP_CHECK(hipEventElapsedTime(&t, ev[q], ev[q + 1]));
+                ms[q] += t;
+            }
+        }
+    } catch (...) {
+        for (auto &e : ev) (void)hipEventDestroy(e);
+        throw;
+    }
+    for (auto &e : ev) HM_HIP_CHECK(hipEventDestroy(e));
+    // algorithmic flops: 8 per complex multiply-add, 64 right-hand sides
+    double vfl = 0, afl = 0;
+    for (const auto &L : A->h_lblk) {
+        vfl += 3.0 * L.n * L.r;
+        afl += 3.0 * L.m * L.r;
+    }
+    for (const auto &d : A->h_dblk) afl += 9.0 * d.m * d.n;
+    if (kernel_ms)
+        for (int k = 0; k < 3; ++k) kernel_ms[k] = ms[k] / reps;
+    if (kernel_flops) {
+        kernel_flops[0] = 0;
+        kernel_flops[1] = 8.0 * kMrPanel * vfl;
+        kernel_flops[2] = 8.0 * kMrPanel * afl;
     }
     return HM_OK;
     HM_API_END

@@ -55,6 +55,23 @@ struct ProjReduce {
 
 constexpr int32_t kProjRows = 512;
 
+// Multi-RHS (matrix-core) plan.  Accumulation: one wave per 16 rows of a
+// leaf row cluster's segment.  Projection: one wave per (low-rank block, 16
+// rows of T = V^* X, chunk k0..k0+klen of the contraction over 3n); slot < 0
+// writes T directly, otherwise a partial summed by an MrProjReduce.
+struct MrAccItem {
+    int32_t leaf, row0, pad0, pad1;
+};
+struct MrProjItem {
+    int32_t blk, j0, k0, klen, slot, pad;
+};
+struct MrProjReduce {
+    int32_t blk, j0, slot0, nslots;
+};
+constexpr int32_t kMrPanel = 64;    // right-hand sides per panel
+constexpr int32_t kMrChunk = 768;   // contraction chunk of a projection item
+constexpr int32_t kMrMinCols = 8;   // panels are used from this many right-hand sides on
+
 struct LeafRow {
     int32_t rb, m, tbeg, tend;
 };
@@ -132,6 +149,12 @@ struct hm_matrix {
     // lazily sized work buffers for matvec
     hm::DeviceBuf ws_xc, ws_t, ws_y;
 
+    // multi-RHS plan (complex64 operators) and its workspaces, allocated on
+    // first use
+    hm::DeviceBuf d_mracc, d_mrproj, d_mrred;
+    int32_t n_mracc = 0, n_mrproj = 0, n_mrred = 0, mr_nslots = 0;
+    mutable hm::DeviceBuf ws_x64, ws_t64, ws_tp64;
+
     const hm::ClusterTree &rowtree() const { return tx; }
     const hm::ClusterTree &coltree() const { return p.same ? tx : ty; }
     hm::Geometry geometry() const;
@@ -149,6 +172,11 @@ void launch_nearfield(const Geometry &g, const GreenParams<R> &gp, const DenseBl
 template <typename S, typename A>
 void launch_matvec_col(const hm_matrix *M, const void *x, int64_t ldx, int32_t col, void *y,
                        int64_t ldy, const double *b, hipStream_t st);
+
+// Y[:, col0 .. col0+ncols) = A X[:, col0 .. col0+ncols), ncols <= 64,
+// complex64 operators only; ev (optional) receives 4 event records.
+void launch_matvec_mrhs(const hm_matrix *M, const void *x, int64_t ldx, int32_t col0,
+                        int32_t ncols, void *y, int64_t ldy, hipStream_t st, hipEvent_t *ev);
 
 template <typename S>
 void profile_matvec_col(const hm_matrix *M, const void *x, void *y, hipStream_t st, double *ms3);

@@ -98,6 +98,7 @@ def _load():
         "hm_gmres": ([P, P, P, i32, d, i32, i32, P, P], i32),
         "hm_info": ([P, P], i32),
         "hm_profile_matvec": ([P, P, P, i32, P, P, P], i32),
+        "hm_profile_matvec_multi": ([P, P, P, i32, P, P, P], i32),
         "hm_export_tree": ([P, i32, P, P, P], i32),
         "hm_export_blocklist": ([P, P, P, P], i32),
         "hm_export_block": ([P, i64, P], i32),
@@ -117,7 +118,7 @@ def _load():
 
 LIB = _load()
 EXPORTED = ["hm_params_default", "hm_build", "hm_matvec", "hm_residual", "hm_gmres", "hm_info",
-            "hm_profile_matvec",
+            "hm_profile_matvec", "hm_profile_matvec_multi",
             "hm_export_tree", "hm_export_blocklist", "hm_export_block", "hm_destroy",
             "hm_last_error", "hm_rank_samples", "hm_rank_model_train", "hm_rank_model_predict",
             "hm_rank_model_grad"]
@@ -229,6 +230,18 @@ class HMatrix:
         out = inf.as_dict()
         out["status"] = rc
         return (x.reshape(-1) if vec else x), out
+
+    def profile_matvec_multi(self, x, reps=10, stream=None):
+        """Mean duration (ms) and algorithmic flops of the gather/project/accum passes of one
+        64-column multi-RHS panel (complex64 operators)."""
+        import torch
+        assert x.shape == (3 * self.ny, 64) and x.dtype == torch.complex64
+        y = torch.empty(3 * self.nx, 64, dtype=x.dtype, device=x.device)
+        ms = (ctypes.c_double * 3)()
+        fl = (ctypes.c_double * 3)()
+        _check(LIB.hm_profile_matvec_multi(self._h, _ptr(x.contiguous()), _ptr(y), int(reps),
+                                           _stream(stream), ms, fl))
+        return list(ms), list(fl), y
 
     def profile_matvec(self, x, reps=20, stream=None):
         """Mean duration (ms) and algorithmic bytes of the gather/project/accum kernels."""

@@ -1,0 +1,152 @@
+"""Multi-RHS panels (complex64 operators, FP32 matrix-core products) against the
+oracle and against the one-column path, through the C ABI.
+
+Gates, per right-hand side column c (relative 2-norm):
+* panel product vs the one-column product of the same operator: <= 2e-6
+  (both FP32 accumulations of the same stored factors, different order);
+* panel product vs the oracle's re-application of the exported operator to
+  the complex64-rounded input: <= 1e-5;
+* panel product vs the dense oracle product: <= 5 eps.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1706_09384_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def hm():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1706_09384_amd import hmat
+    return hmat
+
+
+def to_dev(a, dtype=None):
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    return t if dtype is None else t.to(dtype)
+
+
+def colrel(a, b):
+    return np.linalg.norm(a - b, axis=0) / np.linalg.norm(b, axis=0)
+
+
+def export_all(A):
+    blocks, rank, _ = A.export_blocklist()
+    _, nx, _ = A.export_tree(0)
+    _, ny, _ = A.export_tree(1)
+    out = []
+    for b in range(blocks.shape[0]):
+        t, s, k = blocks[b]
+        data = A.export_block(b, blocks, rank, nx, ny)
+        if k == 0:
+            data = data.astype(np.complex128)
+        else:
+            data = (data[0].astype(np.complex128), data[1].astype(np.complex128))
+        out.append((int(t), int(s), int(k), data))
+    return out
+
+
+class _T:
+    def __init__(self, perm, nodes):
+        self.perm = perm.astype(np.int64)
+        self.begin = nodes[:, 0]
+        self.end = nodes[:, 1]
+
+
+def check_panels(hm, orc, H, A, B, eps, tol_dense):
+    import torch
+    Y = H.matvec(to_dev(B, torch.complex64)).cpu().numpy().astype(np.complex128)
+    cols = np.stack([H.matvec(to_dev(np.ascontiguousarray(B[:, c]), torch.complex64)).cpu().numpy()
+                     for c in range(B.shape[1])], axis=1).astype(np.complex128)
+    d1 = colrel(Y, cols).max()
+    p0, n0, _ = H.export_tree(0)
+    p1, n1, _ = H.export_tree(1)
+    Bq = B.astype(np.complex64).astype(np.complex128)
+    Yo = orc.hmatvec(export_all(H), _T(p0, n0), _T(p1, n1), Bq)
+    d2 = colrel(Y, Yo).max()
+    d3 = colrel(Y, A @ B).max()
+    say(f"panel vs columns {d1:.2e}, vs oracle re-apply {d2:.2e}, vs dense {d3:.2e}")
+    assert d1 <= 2e-6
+    assert d2 <= 1e-5
+    assert d3 <= tol_dense
+    return Y
+
+
+@pytest.fixture(scope="module")
+def sphere1k(orc):
+    w = W.plain_sphere_1k()
+    X, _ = w.points()
+    pb = orc.Problem.from_workload(w, X)
+    return w, X, orc.dense(pb)
+
+
+@pytest.mark.parametrize("nrhs", [8, 64, 70, 130])
+def test_panels_sphere1k(hm, orc, sphere1k, nrhs):
+    """One full panel, a panel plus a ragged one, three panels."""
+    w, X, A = sphere1k
+    say(f"case multirhs sphere1k nrhs={nrhs}")
+    H = hm.build_workload(w, X=X, prec=1)
+    B = W.complex_normal(3 * w.n_points, nrhs, seed=7)
+    check_panels(hm, orc, H, A, B, w.eps, 5 * w.eps)
+
+
+@pytest.mark.parametrize("kernel,n,leaf,omega", [(1, 513, 5, 9.0), (0, 97, 7, 0.5), (1, 300, 40, 3.0)])
+def test_panels_small_ragged(hm, orc, kernel, n, leaf, omega):
+    """Tiles of 15..120 rows (partial 16-row groups), both kernels."""
+    say(f"case multirhs small kernel={kernel} n={n} leaf={leaf}")
+    w = W.small_sphere(n, kernel=kernel, omega=omega, leaf=leaf, eps=1e-5)
+    X, N = w.points()
+    pb = orc.Problem.from_workload(w, X, N)
+    A = orc.dense(pb)
+    H = hm.build_workload(w, X=X, N=N, prec=1)
+    B = W.complex_normal(3 * n, 24, seed=8)
+    check_panels(hm, orc, H, A, B, w.eps, 6e-5)
+
+
+def test_panels_two_clouds(hm, orc):
+    say("case multirhs two clouds")
+    X = W.fibonacci_sphere(400)
+    Y = W.uniform_ball(300, seed=2) * 0.6 + np.array([2.2, 0.0, 0.1])
+    pb = orc.Problem(0, X, Y, None, 4.0, same=False)
+    A = orc.dense(pb)
+    H = hm.build(to_dev(X), to_dev(Y), kernel=0, omega=4.0, leaf=16, eps=1e-5, prec=1)
+    B = W.complex_normal(900, 16, seed=9)
+    check_panels(hm, orc, H, A, B, 1e-5, 5e-5)
+
+
+def test_panels_single_point(hm, orc):
+    say("case multirhs n=1")
+    w = W.small_sphere(1, leaf=3)
+    X, _ = w.points()
+    pb = orc.Problem.from_workload(w, X)
+    A = orc.dense(pb)
+    H = hm.build_workload(w, X=X, prec=1)
+    B = W.complex_normal(3, 9, seed=10)
+    check_panels(hm, orc, H, A, B, 1e-4, 1e-6)
+
+
+def test_lockstep_gmres_on_panels(hm, orc, sphere1k):
+    """Twelve right-hand sides share each panel product of the inner complex64 GMRES."""
+    w, X, A = sphere1k
+    say("case multirhs gmres 12 rhs")
+    H = hm.build_workload(w, X=X, prec=1)
+    B = W.complex_normal(3 * w.n_points, 12, seed=11)
+    x, info = H.gmres(to_dev(B), tol=1e-8, restart=50, maxit=6000)
+    say("gmres", info)
+    assert info["converged"] == 12
+    x = x.cpu().numpy()
+    p0, n0, _ = H.export_tree(0)
+    p1, n1, _ = H.export_tree(1)
+    R = B - orc.hmatvec(export_all(H), _T(p0, n0), _T(p1, n1), x)
+    assert (np.linalg.norm(R, axis=0) / np.linalg.norm(B, axis=0)).max() <= 1.5e-8
