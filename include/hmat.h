@@ -241,8 +241,11 @@ const char *hm_last_error(void);
  * --------------------------------------------------------------------- */
 #define HM_RANK_MODEL_PARAMS (64 * 6 + 64 + 64 * 64 + 64 + 64 + 1)
 
-/* Features and ACA ranks of every admissible block of a built matrix:
- * feats float32[n_lowrank * 6], ranks int32[n_lowrank] (host buffers). */
+/* Features and ACA ranks of every admissible block of a built matrix, in
+ * block-list order: feats float32[n_lowrank * 6], ranks int32[n_lowrank]
+ * (host buffers).  ln is the natural logarithm; diam and dist are the
+ * bounding-box diameter and box distance of the admissibility test
+ * (Section 7.1).  For a plan_only matrix the ranks are -1. */
 hm_status hm_rank_samples(const hm_matrix *A, float *feats, int32_t *ranks);
 
 /*

@@ -582,6 +582,31 @@ def storage_entries(blocks_kind_sizes_ranks) -> int:
 # Rank-predictor MLP reference (FP64): 6 -> 64 -> 64 -> 1, ReLU, MSE, Adam
 # --------------------------------------------------------------------------
 
+def rank_features(tx: ClusterTree, ty: ClusterTree, blocks, kappa_s: float, eps: float):
+    """Rank-model features of every admissible block, in block-list order:
+    (ln |X|, ln |Y|, kappa_s diam X, kappa_s diam Y, kappa_s dist(X, Y), log10 eps),
+    with the bounding-box diameter and the box distance (positive parts) used by
+    the admissibility test of Section 7.1.  Returns an (n_lowrank, 6) float64 array.
+    """
+    rows = []
+    for t, s, kind in blocks:
+        if kind != LOWRANK:
+            continue
+        ex = tx.hi[t] - tx.lo[t]
+        ey = ty.hi[s] - ty.lo[s]
+        gap = np.maximum(0.0, ty.lo[s] - tx.hi[t]) ** 2 + np.maximum(0.0, tx.lo[t] - ty.hi[s]) ** 2
+        rows.append([math.log(tx.end[t] - tx.begin[t]), math.log(ty.end[s] - ty.begin[s]),
+                     kappa_s * math.sqrt(float(np.sum(ex * ex))),
+                     kappa_s * math.sqrt(float(np.sum(ey * ey))),
+                     kappa_s * math.sqrt(float(np.sum(gap))), math.log10(eps)])
+    return np.array(rows, dtype=np.float64).reshape(-1, 6)
+
+
+def rank_target(r):
+    """Regression target of the rank model: log2(1 + r/3)."""
+    return np.log2(1.0 + np.asarray(r, dtype=np.float64) / 3.0)
+
+
 def mlp_init(seed: int = 0, sizes=(6, 64, 64, 1)):
     rng = np.random.default_rng(seed)
     params = []

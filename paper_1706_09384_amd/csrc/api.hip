@@ -98,27 +98,6 @@ hm::Geometry hm_matrix::geometry() const {
     return g;
 }
 
-#define HM_API_BEGIN try {
-#define HM_API_END                                               \
-    }                                                            \
-    catch (const hm::StatusError &e) {                           \
-        hm::set_error(e.msg);                                    \
-        return e.status;                                         \
-    }                                                            \
-    catch (const hm::HipError &e) {                              \
-        hm::set_error(e.msg);                                    \
-        (void)hipGetLastError();                                 \
-        return HM_ERR_HIP;                                       \
-    }                                                            \
-    catch (const std::bad_alloc &) {                             \
-        hm::set_error("host allocation failed");                 \
-        return HM_ERR_ALLOC;                                     \
-    }                                                            \
-    catch (const std::exception &e) {                            \
-        hm::set_error(e.what());                                 \
-        return HM_ERR_ARG;                                       \
-    }
-
 static void require(bool ok, const std::string &msg) {
     if (!ok) throw StatusError(HM_ERR_ARG, msg);
 }
@@ -366,6 +345,22 @@ void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vect
         budget[k] = std::min(full, std::max(b0, 3));
         budget[k] = std::max(3, budget[k] - budget[k] % 3);
     }
+    // A rank model replaces the size rule: first budget = predicted rank
+    // * 1.25 + 6, rounded up to a multiple of 3.
+    std::vector<uint8_t> from_model(nlr, 0);
+    if (p.rank_model != nullptr && nlr > 0) {
+        std::vector<float> feats, pred;
+        std::vector<int64_t> ids;
+        rank_features(M, feats, ids);
+        rank_predict(p.rank_model, feats, pred, st);
+        for (int64_t k = 0; k < nlr; ++k) {
+            const double rh = 3.0 * (std::exp2(std::min(20.0, (double)pred[k])) - 1.0);
+            int32_t b0 = (int32_t)std::ceil(1.25 * std::max(0.0, rh) + 6.0);
+            b0 += (3 - b0 % 3) % 3;
+            budget[k] = std::max(3, std::min(b0, 3 * std::min(lm[k], ln[k])));
+            from_model[k] = 1;
+        }
+    }
     // Per low-rank block: which pass holds its factors, and where.
     std::vector<int32_t> pass_of(nlr, -1), aca_rank(nlr, 0);
     std::vector<int64_t> aca_u(nlr), aca_v(nlr);
@@ -373,7 +368,7 @@ void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vect
     std::vector<std::vector<int64_t>> pass_members;
     std::vector<int64_t> todo(nlr);
     std::iota(todo.begin(), todo.end(), 0);
-    int32_t overflow = 0, fallbacks = 0, capped = 0;
+    int32_t overflow = 0, fallbacks = 0, capped = 0, hits = 0;
     // The ACA kernel keeps the pivot row (3 x budget, compute type) and the V
     // Gram column (budget x 3, complex FP64) in LDS: cap the budget so that
     // both fit in 64 KiB.  A block still unconverged at the cap keeps its
@@ -430,6 +425,7 @@ void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vect
                 continue;
             }
             if (res[q].status == 1) ++capped;
+            if (pass == 0 && from_model[k]) ++hits;
             pass_of[k] = pass;
             aca_rank[k] = res[q].rank;
             aca_u[k] = ab[q].uoff;
@@ -445,6 +441,7 @@ void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vect
         std::fprintf(stderr, "hmat: %d admissible blocks reached the ACA rank cap %d\n", capped,
                      budget_cap);
     S.n_fallback = fallbacks;
+    S.n_model_hits = hits;
     HM_HIP_CHECK(hipStreamSynchronize(st));
     S.t_aca = now_s() - t;
     t = now_s();

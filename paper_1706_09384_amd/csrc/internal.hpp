@@ -178,6 +178,12 @@ void launch_matvec_col(const hm_matrix *M, const void *x, int64_t ldx, int32_t c
 void launch_matvec_mrhs(const hm_matrix *M, const void *x, int64_t ldx, int32_t col0,
                         int32_t ncols, void *y, int64_t ldy, hipStream_t st, hipEvent_t *ev);
 
+// Rank-model features of the admissible blocks (block-list order) and a
+// forward pass of the model on them.
+void rank_features(const hm_matrix *M, std::vector<float> &feats, std::vector<int64_t> &ids);
+void rank_predict(const float *w_host, const std::vector<float> &feats, std::vector<float> &pred,
+                  hipStream_t st);
+
 template <typename S>
 void profile_matvec_col(const hm_matrix *M, const void *x, void *y, hipStream_t st, double *ms3);
 
@@ -208,3 +214,25 @@ __host__ __device__ inline int32_t padded_rows(const int32_t *rowpad, int32_t rb
 __host__ __device__ inline int32_t even_up(int32_t v) { return v + (v & 1); }
 
 }  // namespace hm
+
+// Exception-to-status translation around every C entry point.
+#define HM_API_BEGIN try {
+#define HM_API_END                                               \
+    }                                                            \
+    catch (const hm::StatusError &e) {                           \
+        hm::set_error(e.msg);                                    \
+        return e.status;                                         \
+    }                                                            \
+    catch (const hm::HipError &e) {                              \
+        hm::set_error(e.msg);                                    \
+        (void)hipGetLastError();                                 \
+        return HM_ERR_HIP;                                       \
+    }                                                            \
+    catch (const std::bad_alloc &) {                             \
+        hm::set_error("host allocation failed");                 \
+        return HM_ERR_ALLOC;                                     \
+    }                                                            \
+    catch (const std::exception &e) {                            \
+        hm::set_error(e.what());                                 \
+        return HM_ERR_ARG;                                       \
+    }

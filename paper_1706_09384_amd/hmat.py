@@ -253,6 +253,15 @@ class HMatrix:
                                      _stream(stream), ms, by))
         return list(ms), list(by)
 
+    def rank_samples(self):
+        """(features float32 (n_lowrank, 6), ACA ranks int32 (n_lowrank,)) of every admissible
+        block, in block-list order."""
+        n = self.info()["n_lowrank"]
+        f = np.zeros((n, 6), np.float32)
+        r = np.zeros(n, np.int32)
+        _check(LIB.hm_rank_samples(self._h, _ptr(f), _ptr(r)))
+        return f, r
+
     def export_tree(self, which=0):
         s = self.info()
         n = s["nx"] if which == 0 else s["ny"]
@@ -292,6 +301,52 @@ class HMatrix:
         U = buf[:3 * m * r].reshape(r, 3 * m).T.copy()
         V = buf[3 * m * r:].reshape(r, 3 * n).T.copy()
         return U, V
+
+
+def rank_model_init(seed=0):
+    """Initial rank-model weights: uniform(-sqrt(6/fan_in), +sqrt(6/fan_in)) weights and zero
+    biases, packed W1 b1 W2 b2 W3 b3 (float32)."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for fi, fo in ((6, 64), (64, 64), (64, 1)):
+        lim = np.sqrt(6.0 / fi)
+        parts.append(rng.uniform(-lim, lim, size=fo * fi))
+        parts.append(np.zeros(fo))
+    w = np.concatenate(parts).astype(np.float32)
+    assert w.size == RANK_MODEL_PARAMS
+    return w
+
+
+def rank_model_train(feats, ranks, weights, epochs=100, batch=256, lr=1e-3, seed=0, stream=None):
+    """Train with the library's FP32 kernels; returns (weights, mean loss per epoch)."""
+    f = np.ascontiguousarray(feats, np.float32)
+    r = np.ascontiguousarray(ranks, np.int32)
+    w = np.array(weights, dtype=np.float32, copy=True)
+    loss = np.zeros(int(epochs), np.float32)
+    _check(LIB.hm_rank_model_train(_ptr(f), _ptr(r), int(r.size), _ptr(w), int(epochs), int(batch),
+                                   float(lr), int(seed), _ptr(loss), _stream(stream)))
+    return w, loss
+
+
+def rank_model_predict(weights, feats, stream=None):
+    """Forward pass on the device: feats float32 cuda tensor (n, 6) -> (n,)."""
+    import torch
+    w = np.ascontiguousarray(weights, np.float32)
+    X = feats.contiguous()
+    out = torch.empty(X.shape[0], dtype=torch.float32, device=X.device)
+    _check(LIB.hm_rank_model_predict(_ptr(w), _ptr(X), _ptr(out), int(X.shape[0]), _stream(stream)))
+    return out
+
+
+def rank_model_grad(weights, feats, targets, stream=None):
+    """(loss, gradient) of the mean squared error on the device (float32 cuda tensors)."""
+    w = np.ascontiguousarray(weights, np.float32)
+    g = np.zeros(RANK_MODEL_PARAMS, np.float32)
+    loss = np.zeros(1, np.float32)
+    X, t = feats.contiguous(), targets.contiguous()
+    _check(LIB.hm_rank_model_grad(_ptr(w), _ptr(X), _ptr(t), int(X.shape[0]), _ptr(loss), _ptr(g),
+                                  _stream(stream)))
+    return float(loss[0]), g
 
 
 def build(x, y=None, normals=None, stream=None, **kw) -> HMatrix:
