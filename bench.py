@@ -27,6 +27,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "H-assembly s + H-matvec GB/s (3N_c unknowns) vs plain FP64 GPU at 5eps rel err"
 HBM_PEAK_GBPS = 8000.0
+FP32_MFMA_PEAK_TFLOPS = 157.3
 
 
 def log(*a):
@@ -82,6 +83,123 @@ def sampled_error(orc, w, X, y, b, rows):
     return float(np.linalg.norm(yy - ref) / np.linalg.norm(ref)), ref
 
 
+def multirhs_leg(hmat, W, orc):
+    """Multi-RHS panels on the 200k-point T workload: 64 right-hand sides on FP32 matrix cores."""
+    import torch
+    w = W.multirhs_sphere_200k()
+    X, N = w.points()
+    tb = time.perf_counter()
+    H = hmat.build_workload(w, X=X, N=N, prec=hmat.C64)
+    torch.cuda.synchronize()
+    t_build = time.perf_counter() - tb
+    s = H.info()
+    B = w.rhs()
+    Bd = torch.from_numpy(B).cuda().to(torch.complex64)
+    Y = torch.empty_like(Bd)
+    for _ in range(2):
+        H.matvec(Bd, Y)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(10):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        H.matvec(Bd, Y)
+        e1.record()
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    ms = float(np.median(ts))
+    kms, kfl, _ = H.profile_matvec_multi(Bd, reps=5)
+    flops = sum(kfl)
+    dom = int(np.argmax(kms))
+    names = ["gather", "project", "accum"]
+    roof = {"bound": "mfma", "kernel": names[dom], "achieved": kfl[dom] / (kms[dom] * 1e-3) / 1e12,
+            "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s", "traffic": None}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    rows = np.random.default_rng(0).choice(w.n_points, 64, replace=False)
+    pb = orc.Problem.from_workload(w, X, N)
+    ref = orc.matvec_rows(pb, B, rows)
+    idx = (3 * rows[:, None] + np.arange(3)).ravel()
+    y = Y.cpu().numpy().astype(np.complex128)[idx]
+    err = float((np.linalg.norm(y - ref, axis=0) / np.linalg.norm(ref, axis=0)).max())
+    out = {"workload": w.name, "N_c": w.n_points, "nrhs": 64, "kernel": "T", "kappa_s": w.omega,
+           "leaf": w.leaf, "eps": w.eps, "assembly_s": round(t_build, 3),
+           "storage_bytes": s["storage_bytes"], "max_rank": s["max_rank"],
+           "panel_ms": round(ms, 3), "TFLOPs": round(flops / (ms * 1e-3) / 1e12, 2),
+           "kernel_ms": [round(k, 4) for k in kms], "roofline": roof,
+           "err_vs_oracle_sampled_max_over_rhs": err}
+    log(f"[bench] multirhs {out}")
+    H.close()
+    return out
+
+
+def collect_rank_samples(hmat, W):
+    """(features, ACA ranks) from the 1k complex128 sphere and the 20k sphere at three eps."""
+    fs, rs = [], []
+    w = W.plain_sphere_1k()
+    H = hmat.build_workload(w, prec=hmat.C128)
+    f, r = H.rank_samples()
+    fs.append(f); rs.append(r)
+    H.close()
+    for eps in (1e-3, 1e-4, 1e-5):
+        w = W.precision_sphere_20k(eps)
+        H = hmat.build_workload(w, prec=hmat.C64)
+        f, r = H.rank_samples()
+        fs.append(f); rs.append(r)
+        H.close()
+    return np.concatenate(fs), np.concatenate(rs)
+
+
+def learned_leg(hmat, W, orc):
+    """Rank model trained on the 1k and 20k spheres, used on the 50k prolate spheroid."""
+    import torch
+    t0 = time.perf_counter()
+    f, r = collect_rank_samples(hmat, W)
+    t1 = time.perf_counter()
+    wts, loss = hmat.rank_model_train(f, r, hmat.rank_model_init(0), epochs=150, batch=256,
+                                      lr=1e-3, seed=0)
+    t_train = time.perf_counter() - t1
+    w = W.learned_spheroid_50k()
+    X, _ = w.points()
+    Xd = torch.from_numpy(X).cuda()
+    res = {}
+    for tag, model in (("size_rule", None), ("model", wts)):
+        times, st = [], None
+        for k in range(3):
+            tb = time.perf_counter()
+            H = hmat.build(Xd, kernel=w.kernel, prec=hmat.C64, omega=w.omega, lam=w.lam, mu=w.mu,
+                           rho=w.rho, eta=w.eta, eps=w.eps, leaf=w.leaf, self_re=w.self_re,
+                           self_im=w.self_im, rank_model=model)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - tb)
+            st = H.info()
+            if k < 2:
+                H.close()
+        res[tag] = {"assembly_s": round(float(np.median(times)), 4), "t_aca": round(st["t_aca"], 4),
+                    "n_overflow": st["n_overflow"], "n_model_hits": st["n_model_hits"],
+                    "aca_scratch_bytes": st["aca_scratch_bytes"]}
+        if tag == "model":
+            fe, ra = H.rank_samples()
+            pred = hmat.rank_model_predict(wts, torch.from_numpy(fe).cuda()).cpu().numpy()
+            tgt = np.log2(1.0 + ra / 3.0)
+            res[tag]["pred_err_median_log2"] = round(float(np.median(np.abs(pred - tgt))), 4)
+            res[tag]["underpredicted_frac"] = round(float(np.mean(pred < tgt)), 4)
+            b = w.rhs()
+            y = H.matvec(torch.from_numpy(b).cuda().to(torch.complex64)).cpu().numpy()
+            rows = np.random.default_rng(0).choice(w.n_points, 128, replace=False)
+            pb = orc.Problem.from_workload(w, X)
+            ref = orc.matvec_rows(pb, b, rows)
+            idx = (3 * rows[:, None] + np.arange(3)).ravel()
+            res[tag]["err_vs_oracle_sampled"] = float(
+                np.linalg.norm(y.astype(np.complex128)[idx] - ref) / np.linalg.norm(ref))
+        H.close()
+    out = {"workload": w.name, "N_c": w.n_points, "train_samples": int(r.size),
+           "sampling_s": round(t1 - t0, 3), "train_s": round(t_train, 3),
+           "train_loss_first_last": [float(loss[0]), float(loss[-1])], **res,
+           "speedup_assembly": round(res["size_rule"]["assembly_s"] / res["model"]["assembly_s"], 3)}
+    log(f"[bench] learned {out}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -92,6 +210,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-gmres", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=256)
+    ap.add_argument("--no-multirhs", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--counters", action="store_true",
                     help="profiling mode: one build, 10 matvecs, then a 256 MiB device copy "
                          "(x3) whose known byte count calibrates FETCH_SIZE / WRITE_SIZE")
@@ -228,6 +348,10 @@ def main():
                                "sample": f"{nrows} of {w.n_points} row points of the streamed FP64 "
                                          f"dense product ({dt:.2f} s), extrapolated to {t_full:.1f} s "
                                          "per full product"}
+    if not args.no_multirhs:
+        out["multirhs"] = multirhs_leg(hmat, W, orc)
+    if not args.no_learned:
+        out["learned"] = learned_leg(hmat, W, orc)
     print(json.dumps(out), flush=True)
 
 

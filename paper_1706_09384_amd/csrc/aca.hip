@@ -297,7 +297,7 @@ __global__ void __launch_bounds__(kAcaThreads)
                 ny = R(g.n[1][pj]);
                 nz = R(g.n[2][pj]);
             }
-            green_block<R>(gp, R(xi0 - g.y[0][pj]), R(xi1 - g.y[1][pj]), R(xi2 - g.y[2][pj]), nx,
+            green_block<R>(gp, xi0 - g.y[0][pj], xi1 - g.y[1][pj], xi2 - g.y[2][pj], nx,
                            ny, nz, K);
             const cplx<R> *vrow = V + 3 * j;
             int l = 0;
@@ -496,7 +496,7 @@ __global__ void __launch_bounds__(kAcaThreads)
         for (int i = tid; i < m; i += kAcaThreads) {
             const int pii = b.rb + i;
             cplx<R> K[9];
-            green_block<R>(gp, R(g.x[0][pii] - yj0), R(g.x[1][pii] - yj1), R(g.x[2][pii] - yj2),
+            green_block<R>(gp, g.x[0][pii] - yj0, g.x[1][pii] - yj1, g.x[2][pii] - yj2,
                            njx, njy, njz, K);
             const cplx<R> *urow = U + 3 * i;
             int l = 0;

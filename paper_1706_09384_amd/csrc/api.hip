@@ -379,7 +379,9 @@ void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vect
     while (!todo.empty()) {
         // longest first (cost ~ budget * (m + n))
         std::stable_sort(todo.begin(), todo.end(), [&](int64_t a, int64_t b) {
-            return (int64_t)(lm[a] + ln[a]) * budget[a] > (int64_t)(lm[b] + ln[b]) * budget[b];
+            // ACA step k costs O(k (m + n)): a block costs about budget^2 (m + n)
+            return (int64_t)(lm[a] + ln[a]) * budget[a] * budget[a] >
+                   (int64_t)(lm[b] + ln[b]) * budget[b] * budget[b];
         });
         std::vector<AcaBlk> ab(todo.size());
         int64_t fac = 0, flg = 0;
@@ -401,6 +403,7 @@ void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vect
             flg += a.m + a.n;
             maxb = std::max(maxb, a.budget);
         }
+        if (pass_scratch.empty()) S.aca_scratch_bytes = fac * (int64_t)sizeof(cplx<R>);
         auto scratch = std::make_unique<DeviceBuf>();
         scratch->alloc(std::max<int64_t>(fac, 1) * sizeof(cplx<R>));
         DeviceBuf flags, d_ab, d_out;

@@ -14,6 +14,10 @@
 // functions is summed instead; every series term carries a factor (1 - q^m)
 // and there is no cancellation.  Threshold / number of terms: 1.0 / 14 in
 // float32, 0.5 / 17 in float64 (truncation below the type's rounding).
+// The distance and the phases a, q a are formed in FP64 and reduced modulo
+// 2 pi before the sine and cosine, so a float32 evaluation keeps its
+// relative accuracy for large a (a float32 phase a = ks r would carry an
+// absolute error of about 1e-7 a).
 #pragma once
 
 #include "common.hpp"
@@ -22,6 +26,7 @@ namespace hm {
 
 template <typename R>
 struct GreenParams {
+    double ks_d, q_d;   // S wavenumber and kp / ks in FP64 (phases)
     R ks;        // S wavenumber
     R q;         // kp / ks
     R q2, q3;
@@ -47,12 +52,17 @@ struct SeriesCfg<double> {
 __device__ inline void sincos_(float a, float *s, float *c) { sincosf(a, s, c); }
 __device__ inline void sincos_(double a, double *s, double *c) { sincos(a, s, c); }
 
-// Radial coefficient functions A, B, aA', aB' of the closed forms.
+// v - 2 pi k with k the nearest integer to v / (2 pi), in FP64.
+__device__ inline double reduce_2pi(double v) {
+    const double k = rint(v * 0.15915494309189535);
+    return fma(-k, 6.283185307179586, v);
+}
+
+// Radial coefficient functions A, B, aA', aB' of the closed forms, given
+// a, q a and the sines and cosines of both.
 template <typename R>
-__device__ inline void radial_coeffs(R a, const GreenParams<R> &g, cplx<R> &A, cplx<R> &B,
-                                     cplx<R> &aAp, cplx<R> &aBp) {
-    R sa, ca;
-    sincos_(a, &sa, &ca);
+__device__ inline void radial_coeffs(R a, R qa, R sa, R ca, R sq, R cq, const GreenParams<R> &g,
+                                     cplx<R> &A, cplx<R> &B, cplx<R> &aAp, cplx<R> &aBp) {
     if (a < SeriesCfg<R>::below) {
         // t_m = i^m (1 - q^m) a^{m-2}/m!, summed with weights (m-1), (m-1)(m-3),
         // (m-1)(m-2), (m-1)(m-2)(m-3).
@@ -79,9 +89,6 @@ __device__ inline void radial_coeffs(R a, const GreenParams<R> &g, cplx<R> &A, c
         aBp = {sQr, sQi};
         return;
     }
-    const R qa = g.q * a;
-    R sq, cq;
-    sincos_(qa, &sq, &cq);
     const R ia2 = R(1) / (a * a);
     // E(z) = e^{iz}(iz - 1)
     const R Ear = -ca - a * sa, Eai = a * ca - sa;
@@ -100,16 +107,26 @@ __device__ inline void radial_coeffs(R a, const GreenParams<R> &g, cplx<R> &A, c
            (sa - a * ca) - g.q2 * (sq - qa * cq) - R(2) * B.im};
 }
 
-// 3x3 block, row-major out[3a + b].  d = x - y (nonzero), n = unit normal at y.
+// 3x3 block, row-major out[3a + b].  d = x - y (nonzero, FP64), n = unit
+// normal at y.
 template <typename R>
-__device__ inline void green_block(const GreenParams<R> &g, R dx, R dy, R dz, R nx, R ny, R nz,
-                                   cplx<R> out[9]) {
-    const R r2 = dx * dx + dy * dy + dz * dz;
-    const R r = sqrt(r2);
-    const R ir = R(1) / r;
-    const R d[3] = {dx * ir, dy * ir, dz * ir};
+__device__ inline void green_block(const GreenParams<R> &g, double dx, double dy, double dz, R nx,
+                                   R ny, R nz, cplx<R> out[9]) {
+    const double rd = sqrt(dx * dx + dy * dy + dz * dz);
+    const double ird = 1.0 / rd;
+    const R ir = R(ird);
+    const R d[3] = {R(dx * ird), R(dy * ird), R(dz * ird)};
+    const double ad = g.ks_d * rd, qad = g.q_d * ad;
+    R sa, ca, sq, cq;
+    if constexpr (sizeof(R) == 4) {
+        sincos_(R(reduce_2pi(ad)), &sa, &ca);
+        sincos_(R(reduce_2pi(qad)), &sq, &cq);
+    } else {
+        sincos_(R(ad), &sa, &ca);
+        sincos_(R(qad), &sq, &cq);
+    }
     cplx<R> A, B, aAp, aBp;
-    radial_coeffs<R>(g.ks * r, g, A, B, aAp, aBp);
+    radial_coeffs<R>(R(ad), R(qad), sa, ca, sq, cq, g, A, B, aAp, aBp);
     if (g.kind == 0) {
         const R s = g.inv4pimu * ir;
         const cplx<R> sA = s * A, sB = s * B;
@@ -149,6 +166,8 @@ inline GreenParams<R> make_green_params(int kind, double omega, double lambda, d
     const double kp = omega * std::sqrt(rho / (lambda + 2.0 * mu));
     const double q = ks > 0 ? kp / ks : std::sqrt(mu / (lambda + 2.0 * mu));
     GreenParams<R> g;
+    g.ks_d = ks;
+    g.q_d = q;
     g.ks = R(ks);
     g.q = R(q);
     g.q2 = R(q * q);

@@ -4,8 +4,8 @@
 // One workgroup per tile; threads walk the m*n point pairs with the row
 // point fastest, so that each column of the column-major tile is written by
 // consecutive lanes (three contiguous entries per lane).  Geometry is read
-// from cluster-ordered float64 SoA arrays; the difference x - y is formed in
-// float64 and only then rounded to the compute type.
+// from cluster-ordered float64 SoA arrays; the difference x - y, the distance
+// and the phases are formed in float64.
 #include "internal.hpp"
 
 namespace hm {
@@ -42,7 +42,7 @@ __global__ void __launch_bounds__(256) nearfield_kernel(Geometry g, GreenParams<
                     ny = R(g.n[1][pj]);
                     nz = R(g.n[2][pj]);
                 }
-                green_block<R>(gp, R(dx), R(dy), R(dz), nx, ny, nz, K);
+                green_block<R>(gp, dx, dy, dz, nx, ny, nz, K);
             }
         }
 #pragma unroll

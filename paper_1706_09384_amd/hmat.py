@@ -69,6 +69,7 @@ class Stats(ctypes.Structure):
         ("t_recompress", ctypes.c_double), ("t_plan", ctypes.c_double),
         ("t_total", ctypes.c_double),
         ("matvec_bytes", ctypes.c_int64),
+        ("aca_scratch_bytes", ctypes.c_int64),
     ]
 
     def as_dict(self):

@@ -150,3 +150,26 @@ def test_lockstep_gmres_on_panels(hm, orc, sphere1k):
     p1, n1, _ = H.export_tree(1)
     R = B - orc.hmatvec(export_all(H), _T(p0, n0), _T(p1, n1), x)
     assert (np.linalg.norm(R, axis=0) / np.linalg.norm(B, axis=0)).max() <= 1.5e-8
+
+
+def test_sphere200k_T_64rhs_sampled_rows(hm, orc):
+    """The full multi-RHS workload: 200,000 points, T kernel, 64 right-hand sides,
+    checked on 64 sampled rows for every right-hand side."""
+    import torch
+    w = W.multirhs_sphere_200k()
+    say(f"case {w.name}")
+    X, N = w.points()
+    H = hm.build_workload(w, X=X, N=N, prec=1)
+    s = H.info()
+    say({k: s[k] for k in ("n_lowrank", "max_rank", "n_overflow", "n_fallback", "storage_bytes",
+                           "t_total")})
+    B = w.rhs()
+    assert B.shape == (3 * w.n_points, 64)
+    Y = H.matvec(to_dev(B, torch.complex64)).cpu().numpy().astype(np.complex128)
+    rows = np.random.default_rng(0).choice(w.n_points, 64, replace=False)
+    pb = orc.Problem.from_workload(w, X, N)
+    ref = orc.matvec_rows(pb, B, rows)
+    idx = (3 * rows[:, None] + np.arange(3)).ravel()
+    e = colrel(Y[idx], ref)
+    say("sampled e max", e.max())
+    assert e.max() <= 5 * w.eps

@@ -171,3 +171,28 @@ def test_model_changes_budgets_not_factors(hm, samples):
             assert all(np.array_equal(u, v) for u, v in zip(d0, d1)), k
         else:
             assert np.array_equal(d0, d1), k
+
+
+def test_spheroid50k_with_model_sampled_rows(hm, samples):
+    """The rank model's evaluation workload (50,000-point prolate spheroid) built with
+    predicted budgets stays within 5 eps of the oracle on sampled rows."""
+    import torch
+    f, r = samples
+    w = W.learned_spheroid_50k()
+    say(f"case {w.name} with rank model")
+    wts, _ = hm.rank_model_train(f, r, hm.rank_model_init(seed=0), epochs=100, batch=256, seed=0)
+    X, _ = w.points()
+    H = hm.build_workload(w, X=X, prec=1, rank_model=wts)
+    s = H.info()
+    say({k: s[k] for k in ("n_lowrank", "n_model_hits", "n_overflow", "aca_scratch_bytes", "t_aca",
+                           "t_total")})
+    assert s["n_model_hits"] > 0.9 * s["n_lowrank"]
+    b = w.rhs()
+    y = H.matvec(torch.from_numpy(b).cuda().to(torch.complex64)).cpu().numpy().astype(np.complex128)
+    rows = np.random.default_rng(0).choice(w.n_points, 256, replace=False)
+    pb = orc.Problem.from_workload(w, X)
+    ref = orc.matvec_rows(pb, b, rows)
+    idx = (3 * rows[:, None] + np.arange(3)).ravel()
+    e = float(np.linalg.norm(y[idx] - ref) / np.linalg.norm(ref))
+    say("sampled e", e)
+    assert e <= 5 * w.eps
