@@ -21,6 +21,11 @@
 // Rows/columns whose every candidate 3x3 block is numerically singular
 // (sigma_3 <= tau_piv |block|_F, e.g. T between coplanar points) fall back
 // to the largest-Frobenius candidate and a rank-p pseudo-inverse update.
+// A sigma_3 at or below the rounding-noise floor nu |A(i, j)|_F of the
+// unreduced block counts as zero, and the pseudo-inverse drops singular
+// values below that floor: near convergence the residual of an exactly
+// singular pattern (the planar T blocks) is rounding noise, whose inverse
+// would otherwise blow the update up.
 // A residual row that vanishes on all unused columns marks the row used and
 // moves to the next unused row without adding a term.
 #include <climits>
@@ -236,7 +241,8 @@ template <typename R>
 __global__ void __launch_bounds__(kAcaThreads)
     aca_kernel(Geometry g, GreenParams<R> gp, const AcaBlk *__restrict__ blks,
                cplx<R> *__restrict__ fac, uint8_t *__restrict__ flags,
-               AcaOut *__restrict__ outs, double eps, double tau_piv, int32_t max_budget) {
+               AcaOut *__restrict__ outs, double eps, double tau_piv, double nu2,
+               int32_t max_budget) {
     extern __shared__ unsigned char smem_raw[];
     // dynamic LDS: pivot row (3 x budget, type R) then cv (budget x 3 complex doubles)
     cplx<double> *cv = reinterpret_cast<cplx<double> *>(smem_raw);
@@ -247,7 +253,7 @@ __global__ void __launch_bounds__(kAcaThreads)
     __shared__ cplx<double> sh_T[9];   // M^-1 (mode 0) or Z_p Sigma_p^-1 (mode 1)
     __shared__ cplx<double> sh_W[9];   // W_p (mode 1)
     __shared__ int sh_ctl[8];          // 0 ihat, 2 mode, 3 p, 5 stop
-    __shared__ double sh_norm2, sh_cross, sh_new;
+    __shared__ double sh_norm2, sh_cross, sh_new, sh_anorm;
 
     const AcaBlk b = blks[blockIdx.x];
     const int tid = threadIdx.x;
@@ -299,6 +305,9 @@ __global__ void __launch_bounds__(kAcaThreads)
             }
             green_block<R>(gp, xi0 - g.y[0][pj], xi1 - g.y[1][pj], xi2 - g.y[2][pj], nx,
                            ny, nz, K);
+            double a2 = 0.0;   // |A(i, j)|_F^2 before the update: scale of the rounding noise
+#pragma unroll
+            for (int e = 0; e < 9; ++e) a2 += (double)abs2(K[e]);
             const cplx<R> *vrow = V + 3 * j;
             int l = 0;
             for (; l + 4 <= r; l += 4) {
@@ -335,7 +344,7 @@ __global__ void __launch_bounds__(kAcaThreads)
 #pragma unroll
                 for (int e = 0; e < 9; ++e) Md[e] = cvt<double>(K[e]);
                 const Inv3 iv = invariants3(Md);
-                cand_better(best.s3, best.i3, iv.s3sq, j);
+                cand_better(best.s3, best.i3, iv.s3sq > nu2 * a2 ? iv.s3sq : 0.0, j);
                 cand_better(best.fro, best.ifro, iv.fro2, j);
             }
         }
@@ -384,6 +393,19 @@ __global__ void __launch_bounds__(kAcaThreads)
                 for (int be = 0; be < 3; ++be)
                     sh_W[3 * a + be] = cvt<double>(conj(V[(r + a) * ldv + 3 * jh + be]));
             used_j[jh] = 1;
+            const int pjh = b.cb + jh;
+            cplx<R> K[9];
+            R nx = 0, ny = 0, nz = 0;
+            if (isT) {
+                nx = R(g.n[0][pjh]);
+                ny = R(g.n[1][pjh]);
+                nz = R(g.n[2][pjh]);
+            }
+            green_block<R>(gp, xi0 - g.y[0][pjh], xi1 - g.y[1][pjh], xi2 - g.y[2][pjh], nx, ny,
+                           nz, K);
+            double a2 = 0.0;
+            for (int e = 0; e < 9; ++e) a2 += (double)abs2(K[e]);
+            sh_anorm = sqrt(a2);
         }
         __syncthreads();
         if (tid == 0) {
@@ -398,11 +420,14 @@ __global__ void __launch_bounds__(kAcaThreads)
             double lam[3];
             herm3_eig(G, lam, Z);
             const double s1 = sqrt(fmax(lam[0], 0.0));
+            // singular values at or below the rounding-noise floor of the
+            // entries (nu |A(i, j)|_F) do not count as pivot directions
+            const double floor_s = fmax(tau_piv * s1, sqrt(nu2) * sh_anorm);
             double sv[3];
             int p = 0;
             for (int k = 0; k < 3; ++k) {
                 sv[k] = sqrt(fmax(lam[k], 0.0));
-                if (sv[k] > tau_piv * s1) ++p;
+                if (sv[k] > floor_s) ++p;
             }
             if (p == 3) {
                 // M^-1 = adj(M) / det(M)
@@ -498,6 +523,9 @@ __global__ void __launch_bounds__(kAcaThreads)
             cplx<R> K[9];
             green_block<R>(gp, g.x[0][pii] - yj0, g.x[1][pii] - yj1, g.x[2][pii] - yj2,
                            njx, njy, njz, K);
+            double a2 = 0.0;
+#pragma unroll
+            for (int e = 0; e < 9; ++e) a2 += (double)abs2(K[e]);
             const cplx<R> *urow = U + 3 * i;
             int l = 0;
             for (; l + 4 <= r; l += 4) {
@@ -528,7 +556,7 @@ __global__ void __launch_bounds__(kAcaThreads)
 #pragma unroll
                 for (int e = 0; e < 9; ++e) Md[e] = cvt<double>(K[e]);
                 const Inv3 iv = invariants3(Md);
-                cand_better(best.s3, best.i3, iv.s3sq, i);
+                cand_better(best.s3, best.i3, iv.s3sq > nu2 * a2 ? iv.s3sq : 0.0, i);
                 cand_better(best.fro, best.ifro, iv.fro2, i);
             }
 #pragma unroll
@@ -607,8 +635,12 @@ void run_aca(const Geometry &g, const GreenParams<R> &gp, const std::vector<AcaB
              double tau_piv, int32_t max_budget, hipStream_t st) {
     if (blk.empty()) return;
     const size_t smem = 3 * (size_t)max_budget * (sizeof(cplx<R>) + sizeof(cplx<double>));
+    // Rounding-noise floor of a residual 3x3 block relative to the Frobenius
+    // norm of the same block of A: float32 kernel evaluation and updates
+    // leave about 1e-6 relative noise (3e-5 keeps a margin), float64 1e-15.
+    const double nu = sizeof(R) == 4 ? 3e-5 : 1e-12;
     hipLaunchKernelGGL(aca_kernel<R>, dim3((unsigned)blk.size()), dim3(kAcaThreads), smem, st, g,
-                       gp, d_blk, scratch, flags, d_out, eps, tau_piv, max_budget);
+                       gp, d_blk, scratch, flags, d_out, eps, tau_piv, nu * nu, max_budget);
     HM_HIP_CHECK(hipGetLastError());
 }
 
