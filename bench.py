@@ -132,6 +132,89 @@ def multirhs_leg(hmat, W, orc):
     return out
 
 
+def batching_leg(hmat, W, orc):
+    """Batched assembly on the 100k cube (leaf 32 and 64) with autotuned and graph-captured
+    matvecs; the per-block (unbatched) baseline on a 10k cube of the same recipe."""
+    import torch
+
+    def mv_time(H, x, reps=50):
+        y = torch.empty_like(x)
+        for _ in range(5):
+            H.matvec(x, y)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            H.matvec(x, y)
+        e1.record()
+        e1.synchronize()
+        return e0.elapsed_time(e1) / reps, y
+
+    out = {}
+    for leaf in (32, 64):
+        w = W.batching_cube_100k(leaf)
+        X, N = w.points()
+        Xd, Nd = torch.from_numpy(X).cuda(), torch.from_numpy(N).cuda()
+        times = []
+        for k in range(3):
+            tb = time.perf_counter()
+            H = hmat.build(Xd, normals=Nd, kernel=w.kernel, prec=hmat.C64, omega=w.omega,
+                           lam=w.lam, mu=w.mu, rho=w.rho, eta=w.eta, eps=w.eps, leaf=w.leaf,
+                           self_re=w.self_re, self_im=w.self_im)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - tb)
+            if k < 2:
+                H.close()
+        s = H.info()
+        b = w.rhs()
+        x = torch.from_numpy(b[:, 0]).cuda().to(torch.complex64)
+        ms0, _ = mv_time(H, x)
+        H.autotune(reps=5)
+        ms1, y = mv_time(H, x)
+        s1 = H.info()
+        rows = np.random.default_rng(0).choice(w.n_points, 256, replace=False)
+        ref = orc.matvec_rows(orc.Problem.from_workload(w, X, N), b[:, :1], rows)[:, 0]
+        idx = (3 * rows[:, None] + np.arange(3)).ravel()
+        yy = y.cpu().numpy().astype(np.complex128)[idx]
+        H.close()
+        Hg = hmat.build(Xd, normals=Nd, kernel=w.kernel, prec=hmat.C64, omega=w.omega, lam=w.lam,
+                        mu=w.mu, rho=w.rho, eta=w.eta, eps=w.eps, leaf=w.leaf, self_re=w.self_re,
+                        self_im=w.self_im, matvec_graph=True)
+        msg, _ = mv_time(Hg, x)
+        Hg.close()
+        out[f"leaf{leaf}"] = {
+            "assembly_s": round(float(np.median(times[1:])), 4),
+            "phases_s": {k: round(s[k], 4) for k in ("t_tree", "t_nearfield", "t_aca",
+                                                     "t_recompress", "t_plan")},
+            "n_dense": s["n_dense"], "n_lowrank": s["n_lowrank"], "max_rank": s["max_rank"],
+            "n_fallback": s["n_fallback"], "storage_bytes": s["storage_bytes"],
+            "matvec_ms_default": round(ms0, 4), "matvec_ms_autotuned": round(ms1, 4),
+            "matvec_ms_graph_default_shape": round(msg, 4),
+            "autotuned": {"acc_waves": s1["acc_waves"], "proj_rows": s1["proj_rows"]},
+            "matvec_GBps_autotuned": round(s["matvec_bytes"] / (ms1 * 1e-3) / 1e9, 1),
+            "err_vs_oracle_sampled": float(np.linalg.norm(yy - ref) / np.linalg.norm(ref))}
+        log(f"[bench] batching leaf {leaf}: {out[f'leaf{leaf}']}")
+    n = 10000
+    P, Nrm = W.cube_surface(n, seed=0)
+    Pd, Nd = torch.from_numpy(P).cuda(), torch.from_numpy(Nrm).cuda()
+    kw = dict(normals=Nd, kernel=1, prec=hmat.C64, omega=4.0 / (2.0 * np.sqrt(3.0)), eps=1e-4,
+              leaf=32, self_re=W._t_self(W.CUBE_AREA, n))
+    hmat.build(Pd, **kw).close()
+    tb = time.perf_counter()
+    hmat.build(Pd, **kw).close()
+    torch.cuda.synchronize()
+    t_b = time.perf_counter() - tb
+    tb = time.perf_counter()
+    hmat.build(Pd, unbatched=True, **kw).close()
+    torch.cuda.synchronize()
+    t_u = time.perf_counter() - tb
+    out["unbatched_baseline"] = {"workload": "cube10k_T_leaf32 (same recipe as the 100k cube)",
+                                 "batched_s": round(t_b, 4), "unbatched_s": round(t_u, 3),
+                                 "speedup": round(t_u / t_b, 1)}
+    log(f"[bench] batching baseline {out['unbatched_baseline']}")
+    return out
+
+
 def collect_rank_samples(hmat, W):
     """(features, ACA ranks) from the 1k complex128 sphere and the 20k sphere at three eps."""
     fs, rs = [], []
@@ -212,6 +295,7 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=256)
     ap.add_argument("--no-multirhs", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-batching", action="store_true")
     ap.add_argument("--counters", action="store_true",
                     help="profiling mode: one build, 10 matvecs, then a 256 MiB device copy "
                          "(x3) whose known byte count calibrates FETCH_SIZE / WRITE_SIZE")
@@ -352,6 +436,8 @@ def main():
         out["multirhs"] = multirhs_leg(hmat, W, orc)
     if not args.no_learned:
         out["learned"] = learned_leg(hmat, W, orc)
+    if not args.no_batching:
+        out["batching"] = batching_leg(hmat, W, orc)
     print(json.dumps(out), flush=True)
 
 

@@ -78,7 +78,11 @@ typedef struct {
     double tau_piv;        /* singular-pivot threshold on sigma_3/|M|_F, 0 = default per precision */
     const float *rank_model;   /* optional host pointer to rank-model weights
                                   (HM_RANK_MODEL_PARAMS floats), NULL = none */
-    int32_t reserved[8];
+    int32_t matvec_graph;  /* 1: hm_matvec replays a captured HIP graph of its launches
+                              (re-captured when x, y or nrhs change) */
+    int32_t unbatched;     /* 1: assembly launches its kernels once per block (the
+                              comparison baseline of the batched default) */
+    int32_t reserved[6];
 } hm_params;
 
 /* Fill p with the defaults: U kernel, complex128, w = 1, lambda = 2, mu = rho = 1,
@@ -167,6 +171,8 @@ typedef struct {
     int32_t n_model_hits;              /* blocks whose predicted budget sufficed */
     double t_tree, t_upload, t_nearfield, t_aca, t_recompress, t_plan, t_total; /* seconds */
     int64_t matvec_bytes;              /* algorithmic bytes of one 1-RHS matvec */
+    int64_t aca_scratch_bytes;         /* factor scratch of the first ACA pass (first budgets) */
+    int32_t acc_waves, proj_rows;      /* 1-RHS matvec launch shape (hm_autotune may change it) */
 } hm_stats;
 
 hm_status hm_info(const hm_matrix *A, hm_stats *s);
@@ -196,6 +202,17 @@ hm_status hm_profile_matvec(const hm_matrix *A, const void *x, void *y, int32_t 
  */
 hm_status hm_profile_matvec_multi(const hm_matrix *A, const void *x, void *y, int32_t reps,
                                   void *stream, double *kernel_ms, double *kernel_flops);
+
+/*
+ * Autotuner of the 1-RHS matvec launch shape: times every combination of
+ * waves per accumulation workgroup {4, 8, 16} and projection row chunk
+ * {256, 512, 1024} (`reps` timed products each, HIP events on `stream`) and
+ * keeps the fastest for later hm_matvec calls.
+ *   ms_table  host double[9] (may be NULL): mean ms, index 3 * chunk + waves
+ * Synchronous; allocates two temporary vectors.  The products change only in
+ * their floating-point summation order.
+ */
+hm_status hm_autotune(hm_matrix *A, int32_t reps, void *stream, double *ms_table);
 
 /*
  * Copy a cluster tree to host buffers (which = 0: row tree, 1: column tree).

@@ -632,13 +632,24 @@ __global__ void __launch_bounds__(kAcaThreads)
 template <typename R>
 void run_aca(const Geometry &g, const GreenParams<R> &gp, const std::vector<AcaBlk> &blk,
              AcaBlk *d_blk, cplx<R> *scratch, uint8_t *flags, AcaOut *d_out, double eps,
-             double tau_piv, int32_t max_budget, hipStream_t st) {
+             double tau_piv, int32_t max_budget, hipStream_t st, bool unbatched) {
     if (blk.empty()) return;
     const size_t smem = 3 * (size_t)max_budget * (sizeof(cplx<R>) + sizeof(cplx<double>));
     // Rounding-noise floor of a residual 3x3 block relative to the Frobenius
     // norm of the same block of A: float32 kernel evaluation and updates
     // leave about 1e-6 relative noise (3e-5 keeps a margin), float64 1e-15.
     const double nu = sizeof(R) == 4 ? 3e-5 : 1e-12;
+    if (unbatched) {
+        // comparison baseline: one launch per block, each with the LDS its own budget needs
+        for (size_t q = 0; q < blk.size(); ++q) {
+            const size_t sm = 3 * (size_t)blk[q].budget * (sizeof(cplx<R>) + sizeof(cplx<double>));
+            hipLaunchKernelGGL(aca_kernel<R>, dim3(1), dim3(kAcaThreads), sm, st, g, gp,
+                               d_blk + q, scratch, flags, d_out + q, eps, tau_piv, nu * nu,
+                               blk[q].budget);
+        }
+        HM_HIP_CHECK(hipGetLastError());
+        return;
+    }
     hipLaunchKernelGGL(aca_kernel<R>, dim3((unsigned)blk.size()), dim3(kAcaThreads), smem, st, g,
                        gp, d_blk, scratch, flags, d_out, eps, tau_piv, nu * nu, max_budget);
     HM_HIP_CHECK(hipGetLastError());
@@ -646,9 +657,9 @@ void run_aca(const Geometry &g, const GreenParams<R> &gp, const std::vector<AcaB
 
 template void run_aca<float>(const Geometry &, const GreenParams<float> &,
                              const std::vector<AcaBlk> &, AcaBlk *, cplx<float> *, uint8_t *,
-                             AcaOut *, double, double, int32_t, hipStream_t);
+                             AcaOut *, double, double, int32_t, hipStream_t, bool);
 template void run_aca<double>(const Geometry &, const GreenParams<double> &,
                               const std::vector<AcaBlk> &, AcaBlk *, cplx<double> *, uint8_t *,
-                              AcaOut *, double, double, int32_t, hipStream_t);
+                              AcaOut *, double, double, int32_t, hipStream_t, bool);
 
 }  // namespace hm

@@ -102,6 +102,38 @@ static void require(bool ok, const std::string &msg) {
     if (!ok) throw StatusError(HM_ERR_ARG, msg);
 }
 
+// 1-RHS projection items: every (block, 64 columns of V) split into row
+// chunks of `chunk` rows; multi-chunk groups get a reduction item.  Largest
+// items first.
+static void build_project_plan(hm_matrix *M, int32_t chunk, hipStream_t st) {
+    std::vector<ProjTask> ptasks;
+    std::vector<ProjReduce> preduce;
+    int32_t nslots = 0;
+    for (int32_t i = 0; i < M->n_lblk; ++i) {
+        const int32_t rows = 3 * M->h_lblk[i].n;
+        const int32_t nch = (int32_t)ceil_div(rows, chunk);
+        for (int32_t c0 = 0; c0 < M->h_lblk[i].r; c0 += 64) {
+            if (nch == 1) {
+                ptasks.push_back({i, c0, 0, rows, -1, 0});
+                continue;
+            }
+            preduce.push_back({i, c0, nslots, nch});
+            for (int32_t ch = 0; ch < nch; ++ch)
+                ptasks.push_back({i, c0, ch * chunk, std::min(chunk, rows - ch * chunk), nslots++, 0});
+        }
+    }
+    std::stable_sort(ptasks.begin(), ptasks.end(), [&](const ProjTask &a, const ProjTask &b) {
+        return (int64_t)a.nrows * std::min(64, M->h_lblk[a.blk].r - a.col0) >
+               (int64_t)b.nrows * std::min(64, M->h_lblk[b.blk].r - b.col0);
+    });
+    M->n_ptasks = (int32_t)ptasks.size();
+    M->n_preduce = (int32_t)preduce.size();
+    M->proj_rows = chunk;
+    upload(M->d_ptasks, ptasks, st);
+    upload(M->d_preduce, preduce, st);
+    M->tpart.alloc(std::max<int64_t>(nslots, 1) * 64 * sizeof(cplx<double>));
+}
+
 extern "C" hm_status hm_params_default(hm_params *p) {
     if (!p) return HM_ERR_ARG;
     std::memset(p, 0, sizeof(*p));
@@ -316,7 +348,7 @@ void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vect
     derr.alloc(sizeof(int32_t));
     HM_HIP_CHECK(hipMemsetAsync(derr.p, 0, sizeof(int32_t), st));
     launch_nearfield<R>(g, gp, M->d_dblk.as<DenseBlk>(), M->n_dblk, M->dense.as<cplx<R>>(),
-                        R(p.self_re), R(p.self_im), derr.as<int32_t>(), st);
+                        R(p.self_re), R(p.self_im), derr.as<int32_t>(), st, p.unbatched != 0);
     int32_t nerr = 0;
     HM_HIP_CHECK(hipMemcpyAsync(&nerr, derr.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     HM_HIP_CHECK(hipStreamSynchronize(st));
@@ -411,7 +443,7 @@ void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vect
         upload(d_ab, ab, st);
         d_out.alloc(ab.size() * sizeof(AcaOut));
         run_aca<R>(g, gp, ab, d_ab.as<AcaBlk>(), scratch->as<cplx<R>>(), flags.as<uint8_t>(),
-                   d_out.as<AcaOut>(), p.eps, tau_piv, maxb, st);
+                   d_out.as<AcaOut>(), p.eps, tau_piv, maxb, st, p.unbatched != 0);
         std::vector<AcaOut> res(ab.size());
         HM_HIP_CHECK(hipMemcpyAsync(res.data(), d_out.p, res.size() * sizeof(AcaOut),
                                     hipMemcpyDeviceToHost, st));
@@ -480,7 +512,7 @@ void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vect
             pass_work[ps]->alloc(std::max<int64_t>(goff, 1) * sizeof(cplx<double>));
             run_recompress<R>(rc, pass_drc[ps]->as<RcBlk>(), pass_scratch[ps]->as<cplx<R>>(),
                               pass_work[ps]->as<double>(), pass_newrank[ps]->as<int32_t>(), p.eps,
-                              0, st);
+                              0, st, p.unbatched != 0);
             std::vector<int32_t> nr(rc.size());
             HM_HIP_CHECK(hipMemcpyAsync(nr.data(), pass_newrank[ps]->p, nr.size() * sizeof(int32_t),
                                         hipMemcpyDeviceToHost, st));
@@ -522,7 +554,7 @@ void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vect
                                     pass_scratch[ps]->as<cplx<R>>(), pass_work[ps]->as<double>(),
                                     d_ou.as<int64_t>(), d_ov.as<int64_t>(),
                                     pass_newrank[ps]->as<int32_t>(), M->lowrank.as<cplx<R>>(),
-                                    kp, M->d_rowpad.as<int32_t>(), st);
+                                    kp, M->d_rowpad.as<int32_t>(), st, p.unbatched != 0);
         } else {
             hipLaunchKernelGGL(copy_factors_kernel<R>, dim3(64, (unsigned)mem.size()), dim3(256), 0,
                                st, pass_drc[ps]->as<RcBlk>(), pass_scratch[ps]->as<cplx<R>>(),
@@ -600,33 +632,7 @@ void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vect
         leaves[l].tend = (int32_t)tasks.size();
     }
     M->n_leaves = (int32_t)leaves.size();
-    std::vector<ProjTask> ptasks;
-    std::vector<ProjReduce> preduce;
-    int32_t nslots = 0;
-    for (int32_t i = 0; i < M->n_lblk; ++i) {
-        const int32_t rows = 3 * M->h_lblk[i].n;
-        const int32_t nch = (int32_t)ceil_div(rows, kProjRows);
-        for (int32_t c0 = 0; c0 < M->h_lblk[i].r; c0 += 64) {
-            if (nch == 1) {
-                ptasks.push_back({i, c0, 0, rows, -1, 0});
-                continue;
-            }
-            preduce.push_back({i, c0, nslots, nch});
-            for (int32_t ch = 0; ch < nch; ++ch)
-                ptasks.push_back({i, c0, ch * kProjRows, std::min(kProjRows, rows - ch * kProjRows),
-                                  nslots++, 0});
-        }
-    }
-    // biggest chunks first
-    std::stable_sort(ptasks.begin(), ptasks.end(), [&](const ProjTask &a, const ProjTask &b) {
-        return (int64_t)a.nrows * std::min(64, M->h_lblk[a.blk].r - a.col0) >
-               (int64_t)b.nrows * std::min(64, M->h_lblk[b.blk].r - b.col0);
-    });
-    M->n_ptasks = (int32_t)ptasks.size();
-    M->n_preduce = (int32_t)preduce.size();
-    upload(M->d_ptasks, ptasks, st);
-    upload(M->d_preduce, preduce, st);
-    M->tpart.alloc(std::max<int64_t>(nslots, 1) * 64 * sizeof(cplx<double>));
+    build_project_plan(M, kProjRows, st);
     upload(M->d_lblk, M->h_lblk, st);
     upload(M->d_tasks, tasks, st);
     upload(M->d_leaves, leaves, st);
@@ -688,9 +694,58 @@ void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vect
     for (const auto &d : M->h_dblk) alg += 9 * (int64_t)d.m * d.n;
     for (const auto &L : M->h_lblk) alg += 3 * (int64_t)L.r * (L.m + L.n);
     S.matvec_bytes = (alg + 3 * nx + 3 * ny) * (int64_t)sizeof(cplx<R>);
+    S.acc_waves = M->acc_waves;
+    S.proj_rows = M->proj_rows;
 }
 
 }  // namespace
+
+// The launches of y = A x on stream st (no allocation once the workspaces
+// exist, no memset: safe to capture).
+static void matvec_launches(const hm_matrix *A, const void *x, void *y, int32_t nrhs,
+                            hipStream_t st) {
+    if (A->p.prec == HM_C64 && nrhs >= kMrMinCols) {
+        for (int32_t c0 = 0; c0 < nrhs; c0 += kMrPanel)
+            launch_matvec_mrhs(A, x, nrhs, c0, std::min(kMrPanel, nrhs - c0), y, nrhs, st, nullptr);
+        return;
+    }
+    for (int32_t c = 0; c < nrhs; ++c) {
+        if (A->p.prec == HM_C64)
+            launch_matvec_col<float, float>(A, x, nrhs, c, y, nrhs, nullptr, st);
+        else
+            launch_matvec_col<double, double>(A, x, nrhs, c, y, nrhs, nullptr, st);
+    }
+}
+
+// Replays the captured launches of matvec_launches for (x, y, nrhs); a new
+// key re-captures them on the matrix's private stream.
+static void matvec_graph(const hm_matrix *A, const void *x, void *y, int32_t nrhs, hipStream_t st) {
+    if (!A->g_exec || A->g_x != x || A->g_y != y || A->g_nrhs != nrhs) {
+        if (A->g_exec) {
+            HM_HIP_CHECK(hipGraphExecDestroy(A->g_exec));
+            A->g_exec = nullptr;
+        }
+        if (!A->g_stream) HM_HIP_CHECK(hipStreamCreateWithFlags(&A->g_stream, hipStreamNonBlocking));
+        if (A->p.prec == HM_C64 && nrhs >= kMrMinCols) ensure_mrhs_workspace(A);
+        hipGraph_t graph = nullptr;
+        HM_HIP_CHECK(hipStreamBeginCapture(A->g_stream, hipStreamCaptureModeThreadLocal));
+        try {
+            matvec_launches(A, x, y, nrhs, A->g_stream);
+        } catch (...) {
+            (void)hipStreamEndCapture(A->g_stream, &graph);
+            if (graph) (void)hipGraphDestroy(graph);
+            throw;
+        }
+        HM_HIP_CHECK(hipStreamEndCapture(A->g_stream, &graph));
+        const hipError_t e = hipGraphInstantiate(&A->g_exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        HM_HIP_CHECK(e);
+        A->g_x = x;
+        A->g_y = y;
+        A->g_nrhs = nrhs;
+    }
+    HM_HIP_CHECK(hipGraphLaunch(A->g_exec, st));
+}
 
 extern "C" hm_status hm_matvec(const hm_matrix *A, const void *x, void *y, int32_t nrhs,
                                void *stream) {
@@ -699,17 +754,11 @@ extern "C" hm_status hm_matvec(const hm_matrix *A, const void *x, void *y, int32
     require(nrhs >= 1, "nrhs must be >= 1");
     if (A->plan_only) throw StatusError(HM_ERR_STATE, "matrix was built with plan_only");
     hipStream_t st = static_cast<hipStream_t>(stream);
-    if (A->p.prec == HM_C64 && nrhs >= kMrMinCols) {
-        for (int32_t c0 = 0; c0 < nrhs; c0 += kMrPanel)
-            launch_matvec_mrhs(A, x, nrhs, c0, std::min(kMrPanel, nrhs - c0), y, nrhs, st, nullptr);
+    if (A->p.matvec_graph) {
+        matvec_graph(A, x, y, nrhs, st);
         return HM_OK;
     }
-    for (int32_t c = 0; c < nrhs; ++c) {
-        if (A->p.prec == HM_C64)
-            launch_matvec_col<float, float>(A, x, nrhs, c, y, nrhs, nullptr, st);
-        else
-            launch_matvec_col<double, double>(A, x, nrhs, c, y, nrhs, nullptr, st);
-    }
+    matvec_launches(A, x, y, nrhs, st);
     return HM_OK;
     HM_API_END
 }
@@ -806,6 +855,64 @@ extern "C" hm_status hm_profile_matvec_multi(const hm_matrix *A, const void *x, 
         kernel_flops[1] = 8.0 * kMrPanel * vfl;
         kernel_flops[2] = 8.0 * kMrPanel * afl;
     }
+    return HM_OK;
+    HM_API_END
+}
+
+extern "C" hm_status hm_autotune(hm_matrix *A, int32_t reps, void *stream, double *ms_table) {
+    HM_API_BEGIN
+    require(A != nullptr && reps >= 1, "bad arguments");
+    if (A->plan_only) throw StatusError(HM_ERR_STATE, "matrix was built with plan_only");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const size_t es = elem_bytes(A->p.prec);
+    DeviceBuf xb, yb;
+    xb.alloc(3 * std::max<int64_t>(A->ny, 1) * es);
+    yb.alloc(3 * std::max<int64_t>(A->nx, 1) * es);
+    HM_HIP_CHECK(hipMemsetAsync(xb.p, 0, 3 * std::max<int64_t>(A->ny, 1) * es, st));
+    const int32_t waves[3] = {4, 8, 16}, chunks[3] = {256, 512, 1024};
+    hipEvent_t e0, e1;
+    HM_HIP_CHECK(hipEventCreate(&e0));
+    HM_HIP_CHECK(hipEventCreate(&e1));
+    double best = 1e300;
+    int bw = 1, bc = 1;
+    double table[9];
+    try {
+        for (int c = 0; c < 3; ++c) {
+            build_project_plan(A, chunks[c], st);
+            for (int w = 0; w < 3; ++w) {
+                A->acc_waves = waves[w];
+                for (int k = 0; k < 2; ++k) matvec_launches(A, xb.p, yb.p, 1, st);
+                HM_HIP_CHECK(hipEventRecord(e0, st));
+                for (int k = 0; k < reps; ++k) matvec_launches(A, xb.p, yb.p, 1, st);
+                HM_HIP_CHECK(hipEventRecord(e1, st));
+                HM_HIP_CHECK(hipEventSynchronize(e1));
+                float ms = 0;
+                HM_HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+                table[3 * c + w] = ms / reps;
+                if (table[3 * c + w] < best) {
+                    best = table[3 * c + w];
+                    bw = w;
+                    bc = c;
+                }
+            }
+        }
+    } catch (...) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        throw;
+    }
+    HM_HIP_CHECK(hipEventDestroy(e0));
+    HM_HIP_CHECK(hipEventDestroy(e1));
+    build_project_plan(A, chunks[bc], st);
+    A->acc_waves = waves[bw];
+    HM_HIP_CHECK(hipStreamSynchronize(st));
+    if (A->g_exec) {   // a captured graph holds the old launch shape
+        HM_HIP_CHECK(hipGraphExecDestroy(A->g_exec));
+        A->g_exec = nullptr;
+    }
+    A->stats.acc_waves = A->acc_waves;
+    A->stats.proj_rows = A->proj_rows;
+    if (ms_table) std::memcpy(ms_table, table, sizeof(table));
     return HM_OK;
     HM_API_END
 }

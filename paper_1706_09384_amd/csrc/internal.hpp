@@ -139,6 +139,8 @@ struct hm_matrix {
     hm::DeviceBuf d_dblk, d_lblk, d_tasks, d_leaves, d_ptasks, d_preduce, tpart;
     int32_t n_dblk = 0, n_lblk = 0, n_leaves = 0, n_ptasks = 0, n_preduce = 0;
     int32_t max_leaf = 1;     // largest leaf row cluster (points)
+    int32_t acc_waves = 8;    // waves per workgroup of the 1-RHS accumulation (4, 8, 16)
+    int32_t proj_rows = hm::kProjRows;   // row chunk of the 1-RHS projection items
     hm::DeviceBuf d_rowpad;   // int32[nx + 1]: padding rows before each position
     std::vector<int32_t> rowpad;
     int64_t t_len = 0;        // sum of ranks
@@ -155,6 +157,22 @@ struct hm_matrix {
     int32_t n_mracc = 0, n_mrproj = 0, n_mrred = 0, mr_nslots = 0;
     mutable hm::DeviceBuf ws_x64, ws_t64, ws_tp64;
 
+    // captured matvec (p.matvec_graph): the executable graph, the key it was
+    // captured for, and the private stream used for capturing
+    mutable hipGraphExec_t g_exec = nullptr;
+    mutable const void *g_x = nullptr;
+    mutable void *g_y = nullptr;
+    mutable int32_t g_nrhs = 0;
+    mutable hipStream_t g_stream = nullptr;
+
+    hm_matrix() = default;
+    hm_matrix(const hm_matrix &) = delete;
+    hm_matrix &operator=(const hm_matrix &) = delete;
+    ~hm_matrix() {
+        if (g_exec) (void)hipGraphExecDestroy(g_exec);
+        if (g_stream) (void)hipStreamDestroy(g_stream);
+    }
+
     const hm::ClusterTree &rowtree() const { return tx; }
     const hm::ClusterTree &coltree() const { return p.same ? tx : ty; }
     hm::Geometry geometry() const;
@@ -166,12 +184,15 @@ namespace hm {
 template <typename R>
 void launch_nearfield(const Geometry &g, const GreenParams<R> &gp, const DenseBlk *d_blk,
                       int32_t nblk, cplx<R> *slab, R self_re, R self_im, int32_t *d_err,
-                      hipStream_t st);
+                      hipStream_t st, bool unbatched);
 
 // y = A x for one right-hand side column (c of nrhs), S = storage real, A = accumulation
 template <typename S, typename A>
 void launch_matvec_col(const hm_matrix *M, const void *x, int64_t ldx, int32_t col, void *y,
                        int64_t ldy, const double *b, hipStream_t st);
+
+// Allocates the multi-RHS panel workspaces on first use.
+void ensure_mrhs_workspace(const hm_matrix *M);
 
 // Y[:, col0 .. col0+ncols) = A X[:, col0 .. col0+ncols), ncols <= 64,
 // complex64 operators only; ev (optional) receives 4 event records.
@@ -190,18 +211,19 @@ void profile_matvec_col(const hm_matrix *M, const void *x, void *y, hipStream_t 
 template <typename R>
 void run_aca(const Geometry &g, const GreenParams<R> &gp, const std::vector<AcaBlk> &blk,
              AcaBlk *d_blk, cplx<R> *scratchU, uint8_t *flags, AcaOut *d_out, double eps,
-             double tau_piv, int32_t max_budget, hipStream_t st);
+             double tau_piv, int32_t max_budget, hipStream_t st, bool unbatched);
 
 // Recompression of ACA factors in place into compact output.
 template <typename R>
 void run_recompress(const std::vector<RcBlk> &blk, RcBlk *d_blk, const cplx<R> *acaslab,
-                    double *work, int32_t *d_newrank, double eps, int32_t rmax, hipStream_t st);
+                    double *work, int32_t *d_newrank, double eps, int32_t rmax, hipStream_t st,
+                    bool unbatched);
 
 template <typename R>
 void run_recompress_apply(const std::vector<RcBlk> &blk, RcBlk *d_blk, const cplx<R> *acaslab,
                           const double *work, const int64_t *d_outu, const int64_t *d_outv,
                           const int32_t *d_newrank, cplx<R> *out, const std::vector<int32_t> &keep,
-                          const int32_t *d_rowpad, hipStream_t st);
+                          const int32_t *d_rowpad, hipStream_t st, bool unbatched);
 
 // Padded row of (local point p, component a) in a block whose row cluster
 // starts at cluster position rb.

@@ -233,13 +233,11 @@ __device__ inline void panel_accum_pair(cplx<float> (&acc)[2 * RPL],
     }
 }
 
-constexpr int kAccWaves = 8;
-
 // OUT = 0: y (type S) = A x; OUT = 1: r (double) = b - A x.
 // RPL rows (row pairs for complex64 storage with complex64 accumulation) per
-// lane per chunk, kAccWaves waves per leaf.
-template <typename S, typename A, int OUT, int RPL>
-__global__ void __launch_bounds__(64 * kAccWaves) accum_kernel(
+// lane per chunk, NW waves per leaf (autotuned: 4, 8 or 16).
+template <typename S, typename A, int OUT, int RPL, int NW>
+__global__ void __launch_bounds__(64 * NW) accum_kernel(
     const LeafRow *__restrict__ leaves, const Task *__restrict__ tasks,
     const DenseBlk *__restrict__ dblk, const LowRankBlk *__restrict__ lblk,
     const cplx<S> *__restrict__ dense, const cplx<S> *__restrict__ fac,
@@ -248,7 +246,7 @@ __global__ void __launch_bounds__(64 * kAccWaves) accum_kernel(
     const double *__restrict__ bvec) {
     constexpr bool PAIR = sizeof(S) == 4 && sizeof(A) == 4;
     constexpr int RPC = PAIR ? 2 : 1;   // rows per accumulator slot group
-    __shared__ cplx<A> red[kAccWaves][kWave * RPL * RPC];
+    __shared__ cplx<A> red[NW][kWave * RPL * RPC];
     const LeafRow L = leaves[blockIdx.x];
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int nw = blockDim.x / kWave;
@@ -326,15 +324,25 @@ static void launch_project(const hm_matrix *M, const cplx<A> *xc, cplx<A> *tb, h
     }
 }
 
-template <typename S, typename A, int OUT, int RPL>
-static void launch_accum_rpl(const hm_matrix *M, const cplx<A> *xc, const cplx<A> *tb, void *y,
-                             int64_t ldy, int32_t col, const double *b, hipStream_t st) {
-    hipLaunchKernelGGL((accum_kernel<S, A, OUT, RPL>), dim3(M->n_leaves), dim3(64 * kAccWaves), 0,
-                       st, M->d_leaves.as<LeafRow>(), M->d_tasks.as<Task>(),
+template <typename S, typename A, int OUT, int RPL, int NW>
+static void launch_accum_nw(const hm_matrix *M, const cplx<A> *xc, const cplx<A> *tb, void *y,
+                            int64_t ldy, int32_t col, const double *b, hipStream_t st) {
+    hipLaunchKernelGGL((accum_kernel<S, A, OUT, RPL, NW>), dim3(M->n_leaves), dim3(64 * NW), 0, st,
+                       M->d_leaves.as<LeafRow>(), M->d_tasks.as<Task>(),
                        M->d_dblk.as<DenseBlk>(), M->d_lblk.as<LowRankBlk>(),
                        M->dense.as<cplx<S>>(), M->lowrank.as<cplx<S>>(), xc, tb,
                        M->perm_x.as<int32_t>(), y, ldy, col, b);
     HM_HIP_CHECK(hipGetLastError());
+}
+
+template <typename S, typename A, int OUT, int RPL>
+static void launch_accum_rpl(const hm_matrix *M, const cplx<A> *xc, const cplx<A> *tb, void *y,
+                             int64_t ldy, int32_t col, const double *b, hipStream_t st) {
+    switch (M->acc_waves) {
+        case 4: launch_accum_nw<S, A, OUT, RPL, 4>(M, xc, tb, y, ldy, col, b, st); break;
+        case 16: launch_accum_nw<S, A, OUT, RPL, 16>(M, xc, tb, y, ldy, col, b, st); break;
+        default: launch_accum_nw<S, A, OUT, RPL, 8>(M, xc, tb, y, ldy, col, b, st); break;
+    }
 }
 
 // Rows per lane chosen so that the largest leaf is covered in one chunk.

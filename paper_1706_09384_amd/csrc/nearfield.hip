@@ -57,8 +57,16 @@ __global__ void __launch_bounds__(256) nearfield_kernel(Geometry g, GreenParams<
 template <typename R>
 void launch_nearfield(const Geometry &g, const GreenParams<R> &gp, const DenseBlk *d_blk,
                       int32_t nblk, cplx<R> *slab, R self_re, R self_im, int32_t *d_err,
-                      hipStream_t st) {
+                      hipStream_t st, bool unbatched) {
     if (nblk == 0) return;
+    if (unbatched) {
+        // comparison baseline: one launch per tile
+        for (int32_t i = 0; i < nblk; ++i)
+            hipLaunchKernelGGL(nearfield_kernel<R>, dim3(1), dim3(256), 0, st, g, gp, d_blk + i,
+                               slab, self_re, self_im, d_err);
+        HM_HIP_CHECK(hipGetLastError());
+        return;
+    }
     hipLaunchKernelGGL(nearfield_kernel<R>, dim3(nblk), dim3(256), 0, st, g, gp, d_blk, slab,
                        self_re, self_im, d_err);
     HM_HIP_CHECK(hipGetLastError());
@@ -66,9 +74,9 @@ void launch_nearfield(const Geometry &g, const GreenParams<R> &gp, const DenseBl
 
 template void launch_nearfield<float>(const Geometry &, const GreenParams<float> &,
                                       const DenseBlk *, int32_t, cplx<float> *, float, float,
-                                      int32_t *, hipStream_t);
+                                      int32_t *, hipStream_t, bool);
 template void launch_nearfield<double>(const Geometry &, const GreenParams<double> &,
                                        const DenseBlk *, int32_t, cplx<double> *, double, double,
-                                       int32_t *, hipStream_t);
+                                       int32_t *, hipStream_t, bool);
 
 }  // namespace hm

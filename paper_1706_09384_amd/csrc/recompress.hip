@@ -518,14 +518,17 @@ __global__ void __launch_bounds__(256) apply_kernel(const RcBlk *__restrict__ bl
 
 template <typename R>
 void run_recompress(const std::vector<RcBlk> &blk, RcBlk *d_blk, const cplx<R> *acaslab,
-                    double *work, int32_t *d_newrank, double eps, int32_t rmax, hipStream_t st) {
+                    double *work, int32_t *d_newrank, double eps, int32_t rmax, hipStream_t st,
+                    bool unbatched) {
     if (blk.empty()) return;
     std::vector<GramItem> items;
+    std::vector<int64_t> item0(blk.size() + 1, 0);   // items of block i: item0[i] .. item0[i+1]
     for (int32_t i = 0; i < (int32_t)blk.size(); ++i) {
         const int T = (int)ceil_div(blk[i].r, kGT);
         for (int w = 0; w < 2; ++w)
             for (int a = 0; a < T; ++a)
                 for (int c = a; c < T; ++c) items.push_back({i, w, a, c});
+        item0[i + 1] = (int64_t)items.size();
     }
     (void)rmax;
     DeviceBuf d_items;
@@ -533,8 +536,17 @@ void run_recompress(const std::vector<RcBlk> &blk, RcBlk *d_blk, const cplx<R> *
         d_items.alloc(items.size() * sizeof(GramItem));
         HM_HIP_CHECK(hipMemcpyAsync(d_items.p, items.data(), items.size() * sizeof(GramItem),
                                     hipMemcpyHostToDevice, st));
-        hipLaunchKernelGGL(gram_kernel<R>, dim3((unsigned)items.size()), dim3(256), 0, st, d_blk,
-                           d_items.as<GramItem>(), acaslab, reinterpret_cast<cplx<double> *>(work));
+        if (unbatched) {
+            for (size_t i = 0; i < blk.size(); ++i)
+                if (item0[i + 1] > item0[i])
+                    hipLaunchKernelGGL(gram_kernel<R>, dim3((unsigned)(item0[i + 1] - item0[i])),
+                                       dim3(256), 0, st, d_blk, d_items.as<GramItem>() + item0[i],
+                                       acaslab, reinterpret_cast<cplx<double> *>(work));
+        } else {
+            hipLaunchKernelGGL(gram_kernel<R>, dim3((unsigned)items.size()), dim3(256), 0, st,
+                               d_blk, d_items.as<GramItem>(), acaslab,
+                               reinterpret_cast<cplx<double> *>(work));
+        }
         HM_HIP_CHECK(hipGetLastError());
     }
     // LDS for the Jacobi sweeps: per rank class, what M and J of the largest
@@ -574,9 +586,17 @@ void run_recompress(const std::vector<RcBlk> &blk, RcBlk *d_blk, const cplx<R> *
         const int64_t bytes = std::min<int64_t>(
             std::max<int64_t>(need, 2 * 32 * 33 * (int64_t)sizeof(cplx<double>)), max_lds);
         const int64_t lds_elems = bytes / (int64_t)sizeof(cplx<double>);
-        hipLaunchKernelGGL(factor_kernel<R>, dim3((unsigned)(q1 - q0)), dim3(256), (size_t)bytes,
-                           st, d_blk, d_order.as<int32_t>() + q0,
-                           reinterpret_cast<cplx<double> *>(work), d_newrank, eps, lds_elems);
+        if (unbatched) {
+            for (size_t q = q0; q < q1; ++q)
+                hipLaunchKernelGGL(factor_kernel<R>, dim3(1), dim3(256), (size_t)bytes, st, d_blk,
+                                   d_order.as<int32_t>() + q,
+                                   reinterpret_cast<cplx<double> *>(work), d_newrank, eps,
+                                   lds_elems);
+        } else {
+            hipLaunchKernelGGL(factor_kernel<R>, dim3((unsigned)(q1 - q0)), dim3(256),
+                               (size_t)bytes, st, d_blk, d_order.as<int32_t>() + q0,
+                               reinterpret_cast<cplx<double> *>(work), d_newrank, eps, lds_elems);
+        }
         HM_HIP_CHECK(hipGetLastError());
         q0 = q1;
     }
@@ -589,43 +609,54 @@ template <typename R>
 void run_recompress_apply(const std::vector<RcBlk> &blk, RcBlk *d_blk, const cplx<R> *acaslab,
                           const double *work, const int64_t *d_outu, const int64_t *d_outv,
                           const int32_t *d_newrank, cplx<R> *out, const std::vector<int32_t> &keep,
-                          const int32_t *d_rowpad, hipStream_t st) {
+                          const int32_t *d_rowpad, hipStream_t st, bool unbatched) {
     if (blk.empty()) return;
     std::vector<ApplyTask> tasks;
+    std::vector<int64_t> task0(blk.size() + 1, 0);
     for (int32_t i = 0; i < (int32_t)blk.size(); ++i) {
-        if (keep[i] == 0) continue;
-        for (int w = 0; w < 2; ++w) {
-            const int32_t rows = 3 * (w == 0 ? blk[i].m : blk[i].n);
-            for (int32_t r0 = 0; r0 < rows; r0 += 128) tasks.push_back({i, w, r0, 0});
-        }
+        if (keep[i] != 0)
+            for (int w = 0; w < 2; ++w) {
+                const int32_t rows = 3 * (w == 0 ? blk[i].m : blk[i].n);
+                for (int32_t r0 = 0; r0 < rows; r0 += 128) tasks.push_back({i, w, r0, 0});
+            }
+        task0[i + 1] = (int64_t)tasks.size();
     }
     if (tasks.empty()) return;
     DeviceBuf d_tasks;
     d_tasks.alloc(tasks.size() * sizeof(ApplyTask));
     HM_HIP_CHECK(hipMemcpyAsync(d_tasks.p, tasks.data(), tasks.size() * sizeof(ApplyTask),
                                 hipMemcpyHostToDevice, st));
-    hipLaunchKernelGGL(apply_kernel<R>, dim3((unsigned)tasks.size()), dim3(256), 0, st, d_blk,
-                       d_tasks.as<ApplyTask>(), acaslab,
-                       reinterpret_cast<const cplx<double> *>(work), d_newrank, d_outu, d_outv,
-                       out, d_rowpad);
+    if (unbatched) {
+        for (size_t i = 0; i < blk.size(); ++i)
+            if (task0[i + 1] > task0[i])
+                hipLaunchKernelGGL(apply_kernel<R>, dim3((unsigned)(task0[i + 1] - task0[i])),
+                                   dim3(256), 0, st, d_blk, d_tasks.as<ApplyTask>() + task0[i],
+                                   acaslab, reinterpret_cast<const cplx<double> *>(work),
+                                   d_newrank, d_outu, d_outv, out, d_rowpad);
+    } else {
+        hipLaunchKernelGGL(apply_kernel<R>, dim3((unsigned)tasks.size()), dim3(256), 0, st, d_blk,
+                           d_tasks.as<ApplyTask>(), acaslab,
+                           reinterpret_cast<const cplx<double> *>(work), d_newrank, d_outu,
+                           d_outv, out, d_rowpad);
+    }
     HM_HIP_CHECK(hipGetLastError());
     // tasks (pageable) and d_tasks must outlive the copy and the kernel
     HM_HIP_CHECK(hipStreamSynchronize(st));
 }
 
 template void run_recompress<float>(const std::vector<RcBlk> &, RcBlk *, const cplx<float> *,
-                                    double *, int32_t *, double, int32_t, hipStream_t);
+                                    double *, int32_t *, double, int32_t, hipStream_t, bool);
 template void run_recompress<double>(const std::vector<RcBlk> &, RcBlk *, const cplx<double> *,
-                                     double *, int32_t *, double, int32_t, hipStream_t);
+                                     double *, int32_t *, double, int32_t, hipStream_t, bool);
 template void run_recompress_apply<float>(const std::vector<RcBlk> &, RcBlk *,
                                           const cplx<float> *, const double *, const int64_t *,
                                           const int64_t *, const int32_t *, cplx<float> *,
                                           const std::vector<int32_t> &, const int32_t *,
-                                          hipStream_t);
+                                          hipStream_t, bool);
 template void run_recompress_apply<double>(const std::vector<RcBlk> &, RcBlk *,
                                            const cplx<double> *, const double *, const int64_t *,
                                            const int64_t *, const int32_t *, cplx<double> *,
                                            const std::vector<int32_t> &, const int32_t *,
-                                           hipStream_t);
+                                           hipStream_t, bool);
 
 }  // namespace hm

@@ -46,7 +46,8 @@ class Params(ctypes.Structure):
         ("rank_budget", ctypes.c_int32), ("recompress", ctypes.c_int32),
         ("tau_piv", ctypes.c_double),
         ("rank_model", ctypes.c_void_p),
-        ("reserved", ctypes.c_int32 * 8),
+        ("matvec_graph", ctypes.c_int32), ("unbatched", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 6),
     ]
 
 
@@ -70,6 +71,7 @@ class Stats(ctypes.Structure):
         ("t_total", ctypes.c_double),
         ("matvec_bytes", ctypes.c_int64),
         ("aca_scratch_bytes", ctypes.c_int64),
+        ("acc_waves", ctypes.c_int32), ("proj_rows", ctypes.c_int32),
     ]
 
     def as_dict(self):
@@ -100,6 +102,7 @@ def _load():
         "hm_info": ([P, P], i32),
         "hm_profile_matvec": ([P, P, P, i32, P, P, P], i32),
         "hm_profile_matvec_multi": ([P, P, P, i32, P, P, P], i32),
+        "hm_autotune": ([P, i32, P, P], i32),
         "hm_export_tree": ([P, i32, P, P, P], i32),
         "hm_export_blocklist": ([P, P, P, P], i32),
         "hm_export_block": ([P, i64, P], i32),
@@ -119,7 +122,7 @@ def _load():
 
 LIB = _load()
 EXPORTED = ["hm_params_default", "hm_build", "hm_matvec", "hm_residual", "hm_gmres", "hm_info",
-            "hm_profile_matvec", "hm_profile_matvec_multi",
+            "hm_profile_matvec", "hm_profile_matvec_multi", "hm_autotune",
             "hm_export_tree", "hm_export_blocklist", "hm_export_block", "hm_destroy",
             "hm_last_error", "hm_rank_samples", "hm_rank_model_train", "hm_rank_model_predict",
             "hm_rank_model_grad"]
@@ -147,7 +150,8 @@ def _ptr(t):
 
 def make_params(kernel=KERNEL_U, prec=C128, omega=1.0, lam=2.0, mu=1.0, rho=1.0, eta=3.0,
                 eps=1e-4, leaf=32, same=True, self_re=0.0, self_im=0.0, points_on_host=False,
-                plan_only=False, rank_budget=0, recompress=True, tau_piv=0.0, rank_model=None):
+                plan_only=False, rank_budget=0, recompress=True, tau_piv=0.0, rank_model=None,
+                matvec_graph=False, unbatched=False):
     p = Params()
     _check(LIB.hm_params_default(ctypes.byref(p)))
     p.kernel, p.prec = int(kernel), int(prec)
@@ -156,6 +160,7 @@ def make_params(kernel=KERNEL_U, prec=C128, omega=1.0, lam=2.0, mu=1.0, rho=1.0,
     p.self_re, p.self_im = float(self_re), float(self_im)
     p.points_on_host, p.plan_only = int(bool(points_on_host)), int(bool(plan_only))
     p.rank_budget, p.recompress, p.tau_piv = int(rank_budget), int(bool(recompress)), float(tau_piv)
+    p.matvec_graph, p.unbatched = int(bool(matvec_graph)), int(bool(unbatched))
     p._model_keepalive = None
     if rank_model is not None:
         w = np.ascontiguousarray(rank_model, dtype=np.float32)
@@ -253,6 +258,13 @@ class HMatrix:
         _check(LIB.hm_profile_matvec(self._h, _ptr(x.contiguous()), _ptr(y), int(reps),
                                      _stream(stream), ms, by))
         return list(ms), list(by)
+
+    def autotune(self, reps=10, stream=None):
+        """Pick the fastest 1-RHS matvec launch shape; returns the 3 x 3 table of mean ms
+        (rows: projection chunk 256/512/1024, columns: waves 4/8/16)."""
+        t = (ctypes.c_double * 9)()
+        _check(LIB.hm_autotune(self._h, int(reps), _stream(stream), t))
+        return np.array(list(t)).reshape(3, 3)
 
     def rank_samples(self):
         """(features float32 (n_lowrank, 6), ACA ranks int32 (n_lowrank,)) of every admissible

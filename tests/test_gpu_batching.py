@@ -1,0 +1,125 @@
+"""Batching pattern: graph-captured matvec, per-block (unbatched) assembly as the
+baseline of the batched default, the matvec autotuner, and the 100k cube workload."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1706_09384_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def hm():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1706_09384_amd import hmat
+    return hmat
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def same_blocks(H0, H1):
+    b0, r0, a0 = H0.export_blocklist()
+    b1, r1, a1 = H1.export_blocklist()
+    assert np.array_equal(b0, b1) and np.array_equal(r0, r1) and np.array_equal(a0, a1)
+    n0, n1 = H0.export_tree(0)[1], H1.export_tree(0)[1]
+    for k in range(b0.shape[0]):
+        d0, d1 = H0.export_block(k, b0, r0, n0, n0), H1.export_block(k, b1, r1, n1, n1)
+        if isinstance(d0, tuple):
+            assert all(np.array_equal(u, v) for u, v in zip(d0, d1)), k
+        else:
+            assert np.array_equal(d0, d1), k
+
+
+@pytest.mark.parametrize("prec,nrhs", [(0, 1), (1, 1), (1, 64), (1, 3)])
+def test_graph_replays_match_eager(hm, prec, nrhs):
+    """Every replay of the captured matvec equals the eager product on the same input,
+    with eager work (new inputs written into the captured buffer) between replays."""
+    import torch
+    say(f"case graph prec={prec} nrhs={nrhs}")
+    w = W.plain_sphere_1k()
+    X, _ = w.points()
+    He = hm.build_workload(w, X=X, prec=prec)
+    Hg = hm.build_workload(w, X=X, prec=prec, matvec_graph=True)
+    dt = He.complex_dtype
+    xg = torch.zeros((3 * w.n_points, nrhs), dtype=dt, device="cuda")
+    yg = torch.empty_like(xg)
+    for k in range(4):
+        xn = torch.from_numpy(W.complex_normal(3 * w.n_points, nrhs, seed=20 + k)).cuda().to(dt)
+        xg.copy_(xn)                       # eager work between replays
+        Hg.matvec(xg, yg)                  # first call captures, the rest replay
+        ye = He.matvec(xn)
+        torch.cuda.synchronize()
+        assert torch.equal(yg, ye), k
+    # a new output buffer re-captures
+    y2 = torch.empty_like(yg)
+    Hg.matvec(xg, y2)
+    torch.cuda.synchronize()
+    assert torch.equal(y2, yg)
+
+
+@pytest.mark.parametrize("which", ["sphere_c64", "cube_T_c64", "sphere_c128"])
+def test_unbatched_assembly_is_bit_identical(hm, which):
+    """Per-block launches run the same kernels on the same blocks: identical factors."""
+    say(f"case unbatched {which}")
+    if which == "cube_T_c64":
+        P, Nrm = W.cube_surface(2000, seed=3)
+        w = W.Workload("cube2k", 2000, 1, omega=1.1547, eps=1e-4, leaf=32,
+                       self_re=W._t_self(W.CUBE_AREA, 2000), geometry="cube")
+        X, N, prec = P, Nrm, 1
+    else:
+        w = W.small_sphere(1500, omega=7.0, leaf=24, eps=1e-5)
+        X, _ = w.points()
+        N, prec = None, (1 if which == "sphere_c64" else 0)
+    H0 = hm.build_workload(w, X=X, N=N, prec=prec)
+    H1 = hm.build_workload(w, X=X, N=N, prec=prec, unbatched=True)
+    same_blocks(H0, H1)
+
+
+def test_autotune_changes_shape_not_result(hm, orc):
+    import torch
+    say("case autotune sphere20k")
+    w = W.precision_sphere_20k(1e-4)
+    X, _ = w.points()
+    H = hm.build_workload(w, X=X, prec=1)
+    b = torch.from_numpy(w.rhs()[:, 0]).cuda().to(torch.complex64)
+    y0 = H.matvec(b).cpu().numpy()
+    table = H.autotune(reps=5)
+    s = H.info()
+    say("table ms\n", table, "chosen", s["acc_waves"], s["proj_rows"])
+    assert np.all(table > 0)
+    assert s["acc_waves"] in (4, 8, 16) and s["proj_rows"] in (256, 512, 1024)
+    y1 = H.matvec(b).cpu().numpy()
+    assert rel(y1, y0) <= 2e-6
+
+
+@pytest.mark.parametrize("leaf", [32, 64])
+def test_cube100k_T_sampled_rows(hm, orc, leaf):
+    """The batching workload: 100,000 points on the cube surface, T kernel, complex64,
+    autotuned graph matvec, checked on sampled rows."""
+    import torch
+    w = W.batching_cube_100k(leaf)
+    say(f"case {w.name}")
+    X, N = w.points()
+    H = hm.build_workload(w, X=X, N=N, prec=1, matvec_graph=True)
+    H.autotune(reps=3)
+    s = H.info()
+    say({k: s[k] for k in ("n_lowrank", "max_rank_aca", "max_rank", "n_fallback", "n_overflow",
+                           "t_total", "acc_waves", "proj_rows")})
+    b = w.rhs()
+    y = H.matvec(torch.from_numpy(b[:, 0]).cuda().to(torch.complex64)).cpu().numpy()
+    rows = np.random.default_rng(0).choice(w.n_points, 256, replace=False)
+    ref = orc.matvec_rows(orc.Problem.from_workload(w, X, N), b[:, :1], rows)[:, 0]
+    idx = (3 * rows[:, None] + np.arange(3)).ravel()
+    e = rel(y.astype(np.complex128)[idx], ref)
+    say("sampled e", e)
+    assert e <= 5 * w.eps
