@@ -191,7 +191,10 @@ __device__ inline void panel_accum(cplx<A> (&acc)[RPL], const cplx<S> *__restric
 
 // Complex64 variant: each lane owns row pairs (2q, 2q+1) and reads both with
 // one 16-byte load; panels start on even rows and have even leading
-// dimensions (padded layout), so every load is aligned.
+// dimensions (padded layout), so every load is aligned.  When a leaf has at
+// most 32 row pairs (RPL = 1), the wave splits into G = 64 / npairs groups of
+// npairs lanes and group g takes the columns g, g + G, ...: every load
+// instruction then moves about a full wave's worth of bytes.
 template <int RPL>
 __device__ inline void panel_accum_pair(cplx<float> (&acc)[2 * RPL],
                                         const cplx<float> *__restrict__ base, int64_t ld,
@@ -199,6 +202,32 @@ __device__ inline void panel_accum_pair(cplx<float> (&acc)[2 * RPL],
                                         int32_t p0, int32_t npairs, int lane) {
     const float4 *b4 = reinterpret_cast<const float4 *>(base);
     const int64_t ld4 = ld >> 1;
+    if (RPL == 1 && npairs <= kWave / 2) {
+        const int G = kWave / npairs, g = lane / npairs, q = lane - g * npairs;
+        if (g >= G) return;
+        int32_t j = g;
+        for (; j + 7 * G < ncol; j += 8 * G) {
+            cplx<float> w[8];
+            float4 c[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                w[u] = wv[j + u * G];
+                c[u] = b4[(int64_t)(j + u * G) * ld4 + q];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                fma_(acc[0], cplx<float>{c[u].x, c[u].y}, w[u]);
+                fma_(acc[1], cplx<float>{c[u].z, c[u].w}, w[u]);
+            }
+        }
+        for (; j < ncol; j += G) {
+            const cplx<float> w = wv[j];
+            const float4 c = b4[(int64_t)j * ld4 + q];
+            fma_(acc[0], cplx<float>{c.x, c.y}, w);
+            fma_(acc[1], cplx<float>{c.z, c.w}, w);
+        }
+        return;
+    }
     int32_t j = 0;
     for (; j + 8 <= ncol; j += 8) {
         cplx<float> w[8];
@@ -289,11 +318,16 @@ __global__ void __launch_bounds__(64 * NW) accum_kernel(
 #pragma unroll
             for (int h = 0; h < RPC; ++h) red[wave][RPC * (lane + k * kWave) + h] = acc[RPC * k + h];
         __syncthreads();
+        // column groups (complex64, at most 32 row pairs): row pair q of group
+        // g sits in lane g * npairs + q
+        const int32_t npairs = (rows + 1) / 2;
+        const int G = (PAIR && RPL == 1 && npairs <= kWave / 2) ? kWave / npairs : 1;
         for (int32_t q = threadIdx.x; q < chunk; q += blockDim.x) {
             const int32_t row = r0 + q;
             if (row < rows) {
-                cplx<A> s = red[0][q];
-                for (int w = 1; w < nw; ++w) s = s + red[w][q];
+                cplx<A> s = {A(0), A(0)};
+                for (int w = 0; w < nw; ++w)
+                    for (int g = 0; g < G; ++g) s = s + red[w][q + 2 * g * npairs];
                 const int32_t p = row / 3, a = row - 3 * p;
                 const int64_t g = (3 * (int64_t)perm[L.rb + p] + a) * ldy + col;
                 if (OUT == 0) {
