@@ -82,7 +82,10 @@ typedef struct {
                               (re-captured when x, y or nrhs change) */
     int32_t unbatched;     /* 1: assembly launches its kernels once per block (the
                               comparison baseline of the batched default) */
-    int32_t reserved[6];
+    int32_t aca_scratch_mb;/* cap on the first-pass ACA factor scratch of one chunk of
+                              admissible blocks, MiB; 0 = a quarter of the free device
+                              memory (see hm_build) */
+    int32_t reserved[5];
 } hm_params;
 
 /* Fill p with the defaults: U kernel, complex128, w = 1, lambda = 2, mu = rho = 1,
@@ -104,6 +107,12 @@ typedef struct hm_matrix hm_matrix;   /* opaque; owns all device memory it alloc
  *   omega < 0, missing normals for T; HM_ERR_SINGULAR if a non-self block
  *   pairs two coincident points; HM_ERR_ALLOC / HM_ERR_HIP on device failure.
  * The library copies everything it needs; no caller pointer is retained.
+ * Memory: the admissible blocks are compressed in chunks (dealt round-robin
+ * in longest-ACA-first order); a chunk holds about aca_scratch_mb of
+ * first-pass ACA factors, and its recompressed factors are final before the
+ * next chunk starts.  Peak device
+ * memory is then about the near field + twice the compressed factors + the
+ * chunk scratch.
  */
 hm_status hm_build(const double *x, int64_t nx, const double *y, int64_t ny, const double *normals,
                    const hm_params *p, void *stream, hm_matrix **out);
@@ -171,7 +180,8 @@ typedef struct {
     int32_t n_model_hits;              /* blocks whose predicted budget sufficed */
     double t_tree, t_upload, t_nearfield, t_aca, t_recompress, t_plan, t_total; /* seconds */
     int64_t matvec_bytes;              /* algorithmic bytes of one 1-RHS matvec */
-    int64_t aca_scratch_bytes;         /* factor scratch of the first ACA pass (first budgets) */
+    int64_t aca_scratch_bytes;         /* first-pass ACA factor scratch, summed over chunks */
+    int32_t aca_chunks;                /* chunks the admissible blocks were assembled in */
     int32_t acc_waves, proj_rows;      /* 1-RHS matvec launch shape (hm_autotune may change it) */
 } hm_stats;
 
@@ -244,6 +254,15 @@ hm_status hm_export_blocklist(const hm_matrix *A, int32_t *blocks, int32_t *rank
 hm_status hm_export_block(const hm_matrix *A, int64_t block, void *host_buf);
 
 void hm_destroy(hm_matrix *A);
+
+/*
+ * Return the library's cached device memory to the driver.  Buffers of
+ * 32 MiB or more that the library releases (build temporaries, destroyed
+ * matrices) are kept for reuse, because freeing and re-allocating tens of GB
+ * costs the driver up to seconds per build; they stay allocated until this
+ * call or process exit.  Call it only when no library call is running.
+ */
+void hm_release_cache(void);
 
 /* Thread-local description of the last error, "" if none. */
 const char *hm_last_error(void);

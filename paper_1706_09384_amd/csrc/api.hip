@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <string>
 
@@ -23,6 +24,78 @@ namespace hm {
 
 void set_error(const std::string &msg) { g_last_error = msg; }
 
+namespace {
+
+struct CachedBlock {
+    void *p;
+    size_t bytes;
+    int dev;
+};
+std::mutex g_cache_mu;
+std::vector<CachedBlock> g_cache;
+constexpr size_t kCacheMin = size_t(32) << 20;
+
+// Smallest cached block on `dev` holding b bytes and at most twice b.
+bool cache_take(size_t b, int dev, void **p, size_t *cap) {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    size_t best = SIZE_MAX;
+    for (size_t i = 0; i < g_cache.size(); ++i) {
+        const CachedBlock &c = g_cache[i];
+        if (c.dev == dev && c.bytes >= b && c.bytes <= 2 * b &&
+            (best == SIZE_MAX || c.bytes < g_cache[best].bytes))
+            best = i;
+    }
+    if (best == SIZE_MAX) return false;
+    *p = g_cache[best].p;
+    *cap = g_cache[best].bytes;
+    g_cache.erase(g_cache.begin() + (std::ptrdiff_t)best);
+    return true;
+}
+
+// Bytes held in the cache for `dev`.
+size_t cache_bytes(int dev) {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    size_t s = 0;
+    for (const CachedBlock &c : g_cache)
+        if (c.dev == dev) s += c.bytes;
+    return s;
+}
+
+void cache_release_all() {
+    std::vector<CachedBlock> blocks;
+    {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        blocks.swap(g_cache);
+    }
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    for (const CachedBlock &c : blocks) {
+        (void)hipSetDevice(c.dev);
+        (void)hipFree(c.p);
+    }
+    (void)hipSetDevice(cur);
+}
+
+}  // namespace
+
+void DeviceBuf::reset() {
+    if (!p) return;
+    if (bytes >= kCacheMin) {
+        // as hipFree would: no queued work may still use the memory
+        int cur = 0;
+        (void)hipGetDevice(&cur);
+        (void)hipSetDevice(dev);
+        (void)hipDeviceSynchronize();
+        (void)hipSetDevice(cur);
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        g_cache.push_back({p, bytes, dev});
+    } else {
+        (void)hipFree(p);
+    }
+    p = nullptr;
+    bytes = 0;
+}
+
 void DeviceBuf::alloc(size_t b) {
     reset();
     if (b == 0) return;
@@ -31,7 +104,15 @@ void DeviceBuf::alloc(size_t b) {
         static thread_local long counter = 0;
         if (++counter == std::atol(inj)) throw StatusError(HM_ERR_ALLOC, "injected allocation failure");
     }
+    HM_HIP_CHECK(hipGetDevice(&dev));
+    if (b >= kCacheMin / 2 && cache_take(b, dev, &p, &bytes)) return;
     hipError_t e = hipMalloc(&p, b);
+    if (e == hipErrorOutOfMemory) {
+        // give the cached blocks back and try once more
+        (void)hipGetLastError();
+        cache_release_all();
+        e = hipMalloc(&p, b);
+    }
     if (e != hipSuccess) {
         p = nullptr;
         (void)hipGetLastError();
@@ -397,13 +478,6 @@ void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vect
             from_model[k] = 1;
         }
     }
-    // Per low-rank block: which pass holds its factors, and where.
-    std::vector<int32_t> pass_of(nlr, -1), aca_rank(nlr, 0);
-    std::vector<int64_t> aca_u(nlr), aca_v(nlr);
-    std::vector<std::unique_ptr<DeviceBuf>> pass_scratch;
-    std::vector<std::vector<int64_t>> pass_members;
-    std::vector<int64_t> todo(nlr);
-    std::iota(todo.begin(), todo.end(), 0);
     int32_t overflow = 0, fallbacks = 0, capped = 0, hits = 0;
     // The ACA kernel keeps the pivot row (3 x budget, compute type) and the V
     // Gram column (budget x 3, complex FP64) in LDS: cap the budget so that
@@ -412,166 +486,228 @@ void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vect
     const int32_t budget_cap =
         (int32_t)((60 * 1024) / (3 * (sizeof(cplx<R>) + sizeof(cplx<double>)))) / 3 * 3;
     for (auto &bg : budget) bg = std::min(bg, budget_cap);
-    while (!todo.empty()) {
-        // longest first (cost ~ budget * (m + n))
-        std::stable_sort(todo.begin(), todo.end(), [&](int64_t a, int64_t b) {
-            // ACA step k costs O(k (m + n)): a block costs about budget^2 (m + n)
-            return (int64_t)(lm[a] + ln[a]) * budget[a] * budget[a] >
-                   (int64_t)(lm[b] + ln[b]) * budget[b] * budget[b];
-        });
-        std::vector<AcaBlk> ab(todo.size());
-        int64_t fac = 0, flg = 0;
-        int32_t maxb = 3;
-        for (size_t q = 0; q < todo.size(); ++q) {
-            const int64_t k = todo[q];
-            const Block &B = M->blocks[lr_ids[k]];
-            AcaBlk &a = ab[q];
-            a.rb = tx.begin[B.row];
-            a.m = lm[k];
-            a.cb = ty.begin[B.col];
-            a.n = ln[k];
-            a.budget = budget[k];
-            a.uoff = fac;
-            fac += 3 * (int64_t)a.m * a.budget;
-            a.voff = fac;
-            fac += 3 * (int64_t)a.n * a.budget;
-            a.foff = flg;
-            flg += a.m + a.n;
-            maxb = std::max(maxb, a.budget);
-        }
-        if (pass_scratch.empty()) S.aca_scratch_bytes = fac * (int64_t)sizeof(cplx<R>);
-        auto scratch = std::make_unique<DeviceBuf>();
-        scratch->alloc(std::max<int64_t>(fac, 1) * sizeof(cplx<R>));
-        DeviceBuf flags, d_ab, d_out;
-        flags.alloc(std::max<int64_t>(flg, 1));
-        upload(d_ab, ab, st);
-        d_out.alloc(ab.size() * sizeof(AcaOut));
-        run_aca<R>(g, gp, ab, d_ab.as<AcaBlk>(), scratch->as<cplx<R>>(), flags.as<uint8_t>(),
-                   d_out.as<AcaOut>(), p.eps, tau_piv, maxb, st, p.unbatched != 0);
-        std::vector<AcaOut> res(ab.size());
-        HM_HIP_CHECK(hipMemcpyAsync(res.data(), d_out.p, res.size() * sizeof(AcaOut),
-                                    hipMemcpyDeviceToHost, st));
-        HM_HIP_CHECK(hipStreamSynchronize(st));
-        std::vector<int64_t> next;
-        const int32_t pass = (int32_t)pass_scratch.size();
-        pass_members.emplace_back();
-        for (size_t q = 0; q < todo.size(); ++q) {
-            const int64_t k = todo[q];
-            if (res[q].status == 1 && budget[k] < budget_cap) {
-                ++overflow;
-                budget[k] = std::min({3 * std::min(lm[k], ln[k]), 2 * budget[k], budget_cap});
-                next.push_back(k);
-                continue;
-            }
-            if (res[q].status == 1) ++capped;
-            if (pass == 0 && from_model[k]) ++hits;
-            pass_of[k] = pass;
-            aca_rank[k] = res[q].rank;
-            aca_u[k] = ab[q].uoff;
-            aca_v[k] = ab[q].voff;
-            fallbacks += res[q].fallbacks;
-            pass_members[pass].push_back(k);
-        }
-        pass_scratch.push_back(std::move(scratch));
-        todo.swap(next);
+    // Longest first: ACA step k costs O(k (m + n)), a block about budget^2 (m + n).
+    auto lpt = [&](int64_t a, int64_t b) {
+        return (int64_t)(lm[a] + ln[a]) * budget[a] * budget[a] >
+               (int64_t)(lm[b] + ln[b]) * budget[b] * budget[b];
+    };
+    std::vector<int64_t> order(nlr);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), lpt);
+    // The admissible blocks are processed in chunks whose first-pass factor
+    // scratch stays about under a cap (default: a quarter of the free device
+    // memory): a chunk's ACA, recompression and final factors are done, and
+    // its scratch released, before the next chunk starts.  Blocks are dealt
+    // to the chunks round-robin in the longest-first order, so that every
+    // chunk has the same mix of long and short blocks.
+    int64_t cap_bytes = (int64_t)p.aca_scratch_mb << 20;
+    if (cap_bytes <= 0) {
+        size_t fr = 0, tot = 0;
+        int dev = 0;
+        HM_HIP_CHECK(hipMemGetInfo(&fr, &tot));
+        HM_HIP_CHECK(hipGetDevice(&dev));
+        // the library's own cached blocks count as available
+        cap_bytes = std::max<int64_t>(int64_t(1) << 30, (int64_t)((fr + cache_bytes(dev)) / 4));
     }
+    int64_t total_need = 0;
+    for (int64_t k = 0; k < nlr; ++k) total_need += 3 * (int64_t)(lm[k] + ln[k]) * budget[k];
+    const int64_t nchunks = std::max<int64_t>(
+        1, std::min<int64_t>(nlr, ceil_div(total_need * (int64_t)sizeof(cplx<R>), cap_bytes)));
+    std::vector<int32_t> aca_rank(nlr, 0), final_rank(nlr, 0);
+    std::vector<int64_t> aca_u(nlr), aca_v(nlr), fu(nlr), fv(nlr);
+    std::vector<std::unique_ptr<DeviceBuf>> chunk_out;
+    std::vector<int64_t> chunk_base, chunk_len;
+    int64_t lr_entries = 0, t_len = 0;
+    double t_aca = 0.0, t_rc = 0.0;
+    S.aca_scratch_bytes = 0;
+    for (int64_t ch = 0; ch < nchunks; ++ch) {
+        std::vector<int64_t> members;
+        for (int64_t q = ch; q < nlr; q += nchunks) members.push_back(order[q]);
+        double tc = now_s();
+        // ---- vector ACA passes of the chunk (re-runs with doubled budgets) ----
+        std::vector<std::unique_ptr<DeviceBuf>> pass_scratch;
+        std::vector<std::vector<int64_t>> pass_members;
+        std::vector<int64_t> todo(members);
+        while (!todo.empty()) {
+            std::stable_sort(todo.begin(), todo.end(), lpt);
+            std::vector<AcaBlk> ab(todo.size());
+            int64_t fac = 0, flg = 0;
+            int32_t maxb = 3;
+            for (size_t q = 0; q < todo.size(); ++q) {
+                const int64_t k = todo[q];
+                const Block &B = M->blocks[lr_ids[k]];
+                AcaBlk &a = ab[q];
+                a.rb = tx.begin[B.row];
+                a.m = lm[k];
+                a.cb = ty.begin[B.col];
+                a.n = ln[k];
+                a.budget = budget[k];
+                a.uoff = fac;
+                fac += 3 * (int64_t)a.m * a.budget;
+                a.voff = fac;
+                fac += 3 * (int64_t)a.n * a.budget;
+                a.foff = flg;
+                flg += a.m + a.n;
+                maxb = std::max(maxb, a.budget);
+            }
+            if (pass_scratch.empty()) S.aca_scratch_bytes += fac * (int64_t)sizeof(cplx<R>);
+            auto scratch = std::make_unique<DeviceBuf>();
+            scratch->alloc(std::max<int64_t>(fac, 1) * sizeof(cplx<R>));
+            DeviceBuf flags, d_ab, d_out;
+            flags.alloc(std::max<int64_t>(flg, 1));
+            upload(d_ab, ab, st);
+            d_out.alloc(ab.size() * sizeof(AcaOut));
+            run_aca<R>(g, gp, ab, d_ab.as<AcaBlk>(), scratch->as<cplx<R>>(), flags.as<uint8_t>(),
+                       d_out.as<AcaOut>(), p.eps, tau_piv, maxb, st, p.unbatched != 0);
+            std::vector<AcaOut> res(ab.size());
+            HM_HIP_CHECK(hipMemcpyAsync(res.data(), d_out.p, res.size() * sizeof(AcaOut),
+                                        hipMemcpyDeviceToHost, st));
+            HM_HIP_CHECK(hipStreamSynchronize(st));
+            std::vector<int64_t> next;
+            const int32_t pass = (int32_t)pass_scratch.size();
+            pass_members.emplace_back();
+            for (size_t q = 0; q < todo.size(); ++q) {
+                const int64_t k = todo[q];
+                if (res[q].status == 1 && budget[k] < budget_cap) {
+                    ++overflow;
+                    budget[k] = std::min({3 * std::min(lm[k], ln[k]), 2 * budget[k], budget_cap});
+                    next.push_back(k);
+                    continue;
+                }
+                if (res[q].status == 1) ++capped;
+                if (pass == 0 && from_model[k]) ++hits;
+                aca_rank[k] = res[q].rank;
+                aca_u[k] = ab[q].uoff;
+                aca_v[k] = ab[q].voff;
+                fallbacks += res[q].fallbacks;
+                pass_members[pass].push_back(k);
+            }
+            pass_scratch.push_back(std::move(scratch));
+            todo.swap(next);
+        }
+        t_aca += now_s() - tc;
+        tc = now_s();
+        // ---- recompression of the chunk, pass by pass -------------------------
+        const size_t np = pass_scratch.size();
+        std::vector<std::unique_ptr<DeviceBuf>> pass_work(np), pass_newrank(np), pass_drc(np);
+        std::vector<std::vector<RcBlk>> pass_rc(np);
+        for (size_t ps = 0; ps < np; ++ps) {
+            auto &mem = pass_members[ps];
+            auto &rc = pass_rc[ps];
+            int64_t goff = 0;
+            for (int64_t k : mem) {
+                RcBlk c;
+                c.uoff = aca_u[k];
+                c.voff = aca_v[k];
+                c.m = lm[k];
+                c.rb = tx.begin[M->blocks[lr_ids[k]].row];
+                c.n = ln[k];
+                c.r = aca_rank[k];
+                c.goff = goff;
+                // slot 6 holds r^2 + 2r entries (see the recompression work layout)
+                goff += 8 * (int64_t)c.r * c.r + 2 * (int64_t)c.r;
+                rc.push_back(c);
+            }
+            pass_drc[ps] = std::make_unique<DeviceBuf>();
+            upload(*pass_drc[ps], rc, st);
+            pass_newrank[ps] = std::make_unique<DeviceBuf>();
+            pass_newrank[ps]->alloc(std::max<size_t>(rc.size(), 1) * sizeof(int32_t));
+            if (p.recompress && !rc.empty()) {
+                pass_work[ps] = std::make_unique<DeviceBuf>();
+                pass_work[ps]->alloc(std::max<int64_t>(goff, 1) * sizeof(cplx<double>));
+                run_recompress<R>(rc, pass_drc[ps]->as<RcBlk>(), pass_scratch[ps]->as<cplx<R>>(),
+                                  pass_work[ps]->as<double>(), pass_newrank[ps]->as<int32_t>(),
+                                  p.eps, 0, st, p.unbatched != 0);
+                std::vector<int32_t> nr(rc.size());
+                HM_HIP_CHECK(hipMemcpyAsync(nr.data(), pass_newrank[ps]->p,
+                                            nr.size() * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+                HM_HIP_CHECK(hipStreamSynchronize(st));
+                for (size_t q = 0; q < mem.size(); ++q) final_rank[mem[q]] = nr[q];
+            } else {
+                for (size_t q = 0; q < mem.size(); ++q) final_rank[mem[q]] = aca_rank[mem[q]];
+            }
+        }
+        // ---- the chunk's final factors, in chunk order ---------------------------
+        int64_t len = 0;
+        for (int64_t k : members) {
+            const Block &B = M->blocks[lr_ids[k]];
+            fu[k] = lr_entries + len;
+            len += (int64_t)padded_rows(rowpad, tx.begin[B.row], lm[k]) * final_rank[k];
+            fv[k] = lr_entries + len;
+            len += 3 * (int64_t)ln[k] * even_up(final_rank[k]);
+            len += (kSegRows - len % kSegRows) % kSegRows;   // next U on a segment boundary
+        }
+        auto out = std::make_unique<DeviceBuf>();
+        out->alloc((len + 2) * sizeof(cplx<R>));
+        HM_HIP_CHECK(hipMemsetAsync(out->p, 0, (len + 2) * sizeof(cplx<R>), st));
+        for (size_t ps = 0; ps < np; ++ps) {
+            auto &mem = pass_members[ps];
+            if (mem.empty()) continue;
+            std::vector<int64_t> ou(mem.size()), ov(mem.size());
+            std::vector<int32_t> kp(mem.size());
+            for (size_t q = 0; q < mem.size(); ++q) {
+                kp[q] = final_rank[mem[q]];
+                ou[q] = fu[mem[q]] - lr_entries;
+                ov[q] = fv[mem[q]] - lr_entries;
+            }
+            DeviceBuf d_ou, d_ov;
+            upload(d_ou, ou, st);
+            upload(d_ov, ov, st);
+            if (p.recompress) {
+                run_recompress_apply<R>(pass_rc[ps], pass_drc[ps]->as<RcBlk>(),
+                                        pass_scratch[ps]->as<cplx<R>>(),
+                                        pass_work[ps]->as<double>(), d_ou.as<int64_t>(),
+                                        d_ov.as<int64_t>(), pass_newrank[ps]->as<int32_t>(),
+                                        out->as<cplx<R>>(), kp, M->d_rowpad.as<int32_t>(), st,
+                                        p.unbatched != 0);
+            } else {
+                hipLaunchKernelGGL(copy_factors_kernel<R>, dim3(64, (unsigned)mem.size()),
+                                   dim3(256), 0, st, pass_drc[ps]->as<RcBlk>(),
+                                   pass_scratch[ps]->as<cplx<R>>(), d_ou.as<int64_t>(),
+                                   d_ov.as<int64_t>(), out->as<cplx<R>>(),
+                                   M->d_rowpad.as<int32_t>());
+                HM_HIP_CHECK(hipGetLastError());
+            }
+            HM_HIP_CHECK(hipStreamSynchronize(st));
+            pass_work[ps].reset();
+            pass_scratch[ps].reset();
+        }
+        chunk_out.push_back(std::move(out));
+        chunk_base.push_back(lr_entries);
+        chunk_len.push_back(len);
+        lr_entries += len;
+        t_rc += now_s() - tc;
+    }
+    // ---- one slab for all low-rank factors ------------------------------------
+    {
+        const double tc = now_s();
+        if (chunk_out.size() == 1) {
+            std::swap(M->lowrank.p, chunk_out[0]->p);
+            std::swap(M->lowrank.bytes, chunk_out[0]->bytes);
+            std::swap(M->lowrank.dev, chunk_out[0]->dev);
+        } else {
+            M->lowrank.alloc((lr_entries + 2) * sizeof(cplx<R>));
+            for (size_t c = 0; c < chunk_out.size(); ++c)
+                if (chunk_len[c] > 0)
+                    HM_HIP_CHECK(hipMemcpyAsync(M->lowrank.as<cplx<R>>() + chunk_base[c],
+                                                chunk_out[c]->p, chunk_len[c] * sizeof(cplx<R>),
+                                                hipMemcpyDeviceToDevice, st));
+            HM_HIP_CHECK(hipMemsetAsync(M->lowrank.as<cplx<R>>() + lr_entries, 0,
+                                        2 * sizeof(cplx<R>), st));
+            HM_HIP_CHECK(hipStreamSynchronize(st));
+        }
+        chunk_out.clear();
+        t_rc += now_s() - tc;
+    }
+    S.aca_chunks = (int32_t)chunk_base.size();
     S.n_overflow = overflow + capped;
     if (capped)
         std::fprintf(stderr, "hmat: %d admissible blocks reached the ACA rank cap %d\n", capped,
                      budget_cap);
     S.n_fallback = fallbacks;
     S.n_model_hits = hits;
-    HM_HIP_CHECK(hipStreamSynchronize(st));
-    S.t_aca = now_s() - t;
-    t = now_s();
-    // ---- recompression -------------------------------------------------------
-    std::vector<int32_t> final_rank(nlr);
-    std::vector<std::unique_ptr<DeviceBuf>> pass_work(pass_scratch.size());
-    std::vector<std::unique_ptr<DeviceBuf>> pass_newrank(pass_scratch.size());
-    std::vector<std::vector<RcBlk>> pass_rc(pass_scratch.size());
-    std::vector<std::unique_ptr<DeviceBuf>> pass_drc(pass_scratch.size());
-    for (size_t ps = 0; ps < pass_scratch.size(); ++ps) {
-        auto &mem = pass_members[ps];
-        auto &rc = pass_rc[ps];
-        int64_t goff = 0;
-        for (int64_t k : mem) {
-            RcBlk c;
-            c.uoff = aca_u[k];
-            c.voff = aca_v[k];
-            c.m = lm[k];
-            c.rb = tx.begin[M->blocks[lr_ids[k]].row];
-            c.n = ln[k];
-            c.r = aca_rank[k];
-            c.goff = goff;
-            // slot 6 holds r^2 + 2r entries (see the recompression work layout)
-            goff += 8 * (int64_t)c.r * c.r + 2 * (int64_t)c.r;
-            rc.push_back(c);
-        }
-        pass_drc[ps] = std::make_unique<DeviceBuf>();
-        upload(*pass_drc[ps], rc, st);
-        pass_newrank[ps] = std::make_unique<DeviceBuf>();
-        pass_newrank[ps]->alloc(std::max<size_t>(rc.size(), 1) * sizeof(int32_t));
-        if (p.recompress && !rc.empty()) {
-            pass_work[ps] = std::make_unique<DeviceBuf>();
-            pass_work[ps]->alloc(std::max<int64_t>(goff, 1) * sizeof(cplx<double>));
-            run_recompress<R>(rc, pass_drc[ps]->as<RcBlk>(), pass_scratch[ps]->as<cplx<R>>(),
-                              pass_work[ps]->as<double>(), pass_newrank[ps]->as<int32_t>(), p.eps,
-                              0, st, p.unbatched != 0);
-            std::vector<int32_t> nr(rc.size());
-            HM_HIP_CHECK(hipMemcpyAsync(nr.data(), pass_newrank[ps]->p, nr.size() * sizeof(int32_t),
-                                        hipMemcpyDeviceToHost, st));
-            HM_HIP_CHECK(hipStreamSynchronize(st));
-            for (size_t q = 0; q < mem.size(); ++q) final_rank[mem[q]] = nr[q];
-        } else {
-            for (size_t q = 0; q < mem.size(); ++q) final_rank[mem[q]] = aca_rank[mem[q]];
-        }
-    }
-    // Final compact slab in block order.
-    int64_t lr_entries = 0, t_len = 0;
-    std::vector<int64_t> fu(nlr), fv(nlr);
-    for (int64_t k = 0; k < nlr; ++k) {
-        const Block &B = M->blocks[lr_ids[k]];
-        fu[k] = lr_entries;
-        lr_entries += (int64_t)padded_rows(rowpad, tx.begin[B.row], lm[k]) * final_rank[k];
-        fv[k] = lr_entries;
-        lr_entries += 3 * (int64_t)ln[k] * even_up(final_rank[k]);
-        lr_entries += (kSegRows - lr_entries % kSegRows) % kSegRows;   // next U on a segment boundary
-    }
-    M->lowrank.alloc((lr_entries + 2) * sizeof(cplx<R>));
-    HM_HIP_CHECK(hipMemsetAsync(M->lowrank.p, 0, (lr_entries + 2) * sizeof(cplx<R>), st));
-    for (size_t ps = 0; ps < pass_scratch.size(); ++ps) {
-        auto &mem = pass_members[ps];
-        if (mem.empty()) continue;
-        std::vector<int64_t> ou(mem.size()), ov(mem.size());
-        std::vector<int32_t> kp(mem.size());
-        for (size_t q = 0; q < mem.size(); ++q) kp[q] = final_rank[mem[q]];
-        int32_t maxrows = 0;
-        for (size_t q = 0; q < mem.size(); ++q) {
-            ou[q] = fu[mem[q]];
-            ov[q] = fv[mem[q]];
-            maxrows = std::max(maxrows, 3 * std::max(lm[mem[q]], ln[mem[q]]));
-        }
-        DeviceBuf d_ou, d_ov;
-        upload(d_ou, ou, st);
-        upload(d_ov, ov, st);
-        if (p.recompress) {
-            run_recompress_apply<R>(pass_rc[ps], pass_drc[ps]->as<RcBlk>(),
-                                    pass_scratch[ps]->as<cplx<R>>(), pass_work[ps]->as<double>(),
-                                    d_ou.as<int64_t>(), d_ov.as<int64_t>(),
-                                    pass_newrank[ps]->as<int32_t>(), M->lowrank.as<cplx<R>>(),
-                                    kp, M->d_rowpad.as<int32_t>(), st, p.unbatched != 0);
-        } else {
-            hipLaunchKernelGGL(copy_factors_kernel<R>, dim3(64, (unsigned)mem.size()), dim3(256), 0,
-                               st, pass_drc[ps]->as<RcBlk>(), pass_scratch[ps]->as<cplx<R>>(),
-                               d_ou.as<int64_t>(), d_ov.as<int64_t>(), M->lowrank.as<cplx<R>>(),
-                               M->d_rowpad.as<int32_t>());
-            HM_HIP_CHECK(hipGetLastError());
-        }
-        HM_HIP_CHECK(hipStreamSynchronize(st));
-        pass_work[ps].reset();
-        pass_scratch[ps].reset();
-    }
-    S.t_recompress = now_s() - t;
+    S.t_aca = t_aca;
+    S.t_recompress = t_rc;
     t = now_s();
     // ---- matvec plan -----------------------------------------------------------
     int32_t maxr_aca = 0, maxr = 0;
@@ -1030,3 +1166,5 @@ extern "C" hm_status hm_export_block(const hm_matrix *A, int64_t b, void *host_b
 }
 
 extern "C" void hm_destroy(hm_matrix *A) { delete A; }
+
+extern "C" void hm_release_cache(void) { cache_release_all(); }

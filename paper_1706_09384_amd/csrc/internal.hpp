@@ -100,18 +100,21 @@ struct RcBlk {
     int32_t m, n, r, rb;  // rb: first row point (cluster order) for the padded U layout
 };
 
+// Owning device buffer.  Memory comes from the library's device cache:
+// buffers of at least 32 MiB are kept on release and handed out again for
+// requests of up to that size (and at least half of it), because freeing and
+// re-allocating tens of GB costs the driver up to seconds; release
+// synchronizes the device first, as hipFree would.  hm_release_cache()
+// returns the cached memory to the driver.
 struct DeviceBuf {
     void *p = nullptr;
-    size_t bytes = 0;
+    size_t bytes = 0;   // capacity
+    int dev = 0;
     DeviceBuf() = default;
     DeviceBuf(const DeviceBuf &) = delete;
     DeviceBuf &operator=(const DeviceBuf &) = delete;
     ~DeviceBuf() { reset(); }
-    void reset() {
-        if (p) (void)hipFree(p);
-        p = nullptr;
-        bytes = 0;
-    }
+    void reset();
     void alloc(size_t b);
     template <typename T>
     T *as() const { return static_cast<T *>(p); }

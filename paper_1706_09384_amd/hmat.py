@@ -47,7 +47,8 @@ class Params(ctypes.Structure):
         ("tau_piv", ctypes.c_double),
         ("rank_model", ctypes.c_void_p),
         ("matvec_graph", ctypes.c_int32), ("unbatched", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 6),
+        ("aca_scratch_mb", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 5),
     ]
 
 
@@ -70,7 +71,7 @@ class Stats(ctypes.Structure):
         ("t_recompress", ctypes.c_double), ("t_plan", ctypes.c_double),
         ("t_total", ctypes.c_double),
         ("matvec_bytes", ctypes.c_int64),
-        ("aca_scratch_bytes", ctypes.c_int64),
+        ("aca_scratch_bytes", ctypes.c_int64), ("aca_chunks", ctypes.c_int32),
         ("acc_waves", ctypes.c_int32), ("proj_rows", ctypes.c_int32),
     ]
 
@@ -107,6 +108,7 @@ def _load():
         "hm_export_blocklist": ([P, P, P, P], i32),
         "hm_export_block": ([P, i64, P], i32),
         "hm_destroy": ([P], None),
+        "hm_release_cache": ([], None),
         "hm_last_error": ([], ctypes.c_char_p),
         "hm_rank_samples": ([P, P, P], i32),
         "hm_rank_model_train": ([P, P, i64, P, i32, i32, ctypes.c_float, ctypes.c_uint64, P, P], i32),
@@ -124,6 +126,7 @@ LIB = _load()
 EXPORTED = ["hm_params_default", "hm_build", "hm_matvec", "hm_residual", "hm_gmres", "hm_info",
             "hm_profile_matvec", "hm_profile_matvec_multi", "hm_autotune",
             "hm_export_tree", "hm_export_blocklist", "hm_export_block", "hm_destroy",
+            "hm_release_cache",
             "hm_last_error", "hm_rank_samples", "hm_rank_model_train", "hm_rank_model_predict",
             "hm_rank_model_grad"]
 
@@ -151,7 +154,7 @@ def _ptr(t):
 def make_params(kernel=KERNEL_U, prec=C128, omega=1.0, lam=2.0, mu=1.0, rho=1.0, eta=3.0,
                 eps=1e-4, leaf=32, same=True, self_re=0.0, self_im=0.0, points_on_host=False,
                 plan_only=False, rank_budget=0, recompress=True, tau_piv=0.0, rank_model=None,
-                matvec_graph=False, unbatched=False):
+                matvec_graph=False, unbatched=False, aca_scratch_mb=0):
     p = Params()
     _check(LIB.hm_params_default(ctypes.byref(p)))
     p.kernel, p.prec = int(kernel), int(prec)
@@ -161,6 +164,7 @@ def make_params(kernel=KERNEL_U, prec=C128, omega=1.0, lam=2.0, mu=1.0, rho=1.0,
     p.points_on_host, p.plan_only = int(bool(points_on_host)), int(bool(plan_only))
     p.rank_budget, p.recompress, p.tau_piv = int(rank_budget), int(bool(recompress)), float(tau_piv)
     p.matvec_graph, p.unbatched = int(bool(matvec_graph)), int(bool(unbatched))
+    p.aca_scratch_mb = int(aca_scratch_mb)
     p._model_keepalive = None
     if rank_model is not None:
         w = np.ascontiguousarray(rank_model, dtype=np.float32)
@@ -314,6 +318,11 @@ class HMatrix:
         U = buf[:3 * m * r].reshape(r, 3 * m).T.copy()
         V = buf[3 * m * r:].reshape(r, 3 * n).T.copy()
         return U, V
+
+
+def release_cache():
+    """Return the library's cached device memory to the driver (hm_release_cache)."""
+    LIB.hm_release_cache()
 
 
 def rank_model_init(seed=0):

@@ -123,3 +123,18 @@ def test_cube100k_T_sampled_rows(hm, orc, leaf):
     e = rel(y.astype(np.complex128)[idx], ref)
     say("sampled e", e)
     assert e <= 5 * w.eps
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_chunked_assembly_is_bit_identical(hm, prec):
+    """A tiny scratch cap splits the admissible blocks into many chunks; every factor is
+    the same as in the single-chunk build."""
+    say(f"case chunked prec={prec}")
+    w = W.small_sphere(4000, omega=11.0, leaf=32, eps=1e-4)
+    X, _ = w.points()
+    H0 = hm.build_workload(w, X=X, prec=prec)
+    H1 = hm.build_workload(w, X=X, prec=prec, aca_scratch_mb=2)
+    s0, s1 = H0.info(), H1.info()
+    say("chunks", s0["aca_chunks"], s1["aca_chunks"])
+    assert s0["aca_chunks"] == 1 and s1["aca_chunks"] > 4
+    same_blocks(H0, H1)
