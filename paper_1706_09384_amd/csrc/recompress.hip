@@ -572,7 +572,7 @@ void run_recompress(const std::vector<RcBlk> &blk, RcBlk *d_blk, const cplx<R> *
     d_order.alloc(order.size() * sizeof(int32_t));
     HM_HIP_CHECK(hipMemcpyAsync(d_order.p, order.data(), order.size() * sizeof(int32_t),
                                 hipMemcpyHostToDevice, st));
-    const int classes[] = {16, 24, 32, 48, 64, 1 << 30};
+    const int classes[] = {16, 24, 32, 48, 64, 100, 1 << 30};
     size_t q0 = 0;
     while (q0 < order.size()) {
         const int rmax = blk[order[q0]].r;
