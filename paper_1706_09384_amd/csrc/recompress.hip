@@ -134,7 +134,8 @@ __device__ void chol_upper(cplx<double> *G, int r, double tol, double *sh) {
 // Returns true if a rotation was applied.
 template <bool WITHJ>
 __device__ inline bool jacobi_pair(cplx<double> *x, cplx<double> *y, cplx<double> *jx,
-                                   cplx<double> *jy, int r, double tol, int gl, int gs) {
+                                   cplx<double> *jy, int r, double tol, double tiny, int gl,
+                                   int gs) {
     double al = 0, be = 0, gr = 0, gi = 0;
     for (int i = gl; i < r; i += gs) {
         const cplx<double> a = x[i], b = y[i];
@@ -149,6 +150,10 @@ __device__ inline bool jacobi_pair(cplx<double> *x, cplx<double> *y, cplx<double
         gr += __shfl_xor(gr, o, gs);
         gi += __shfl_xor(gi, o, gs);
     }
+    // A column whose squared norm is at the rounding level of the whole
+    // matrix (tiny) is numerically zero: its orthogonality is noise, and
+    // rotating it would only keep the sweeps from terminating.
+    if (al <= tiny || be <= tiny) return false;
     const double ag = sqrt(gr * gr + gi * gi);
     if (!(ag > tol * sqrt(al * be))) return false;
     // Unitary [[c, s], [-s e^{-i phi}, c e^{-i phi}]] diagonalising the 2x2 Gram.
@@ -182,7 +187,7 @@ __device__ inline int rr_slot(int pos, int round, int n) {
 // whether anything rotated.
 template <bool WITHJ>
 __device__ bool lds_sweep(cplx<double> *lds, cplx<double> *ldj, int nc, int r, double tol,
-                          int *sh_flag) {
+                          double tiny, int *sh_flag) {
     const int ne = (nc + 1) & ~1;
     const int npairs = ne / 2;
     int gs = 64;
@@ -203,7 +208,8 @@ __device__ bool lds_sweep(cplx<double> *lds, cplx<double> *ldj, int nc, int r, d
             }
             any |= jacobi_pair<WITHJ>(lds + (int64_t)p * r, lds + (int64_t)q * r,
                                       WITHJ ? ldj + (int64_t)p * r : nullptr,
-                                      WITHJ ? ldj + (int64_t)q * r : nullptr, r, tol, gl, gs);
+                                      WITHJ ? ldj + (int64_t)q * r : nullptr, r, tol, tiny, gl,
+                                      gs);
         }
         __syncthreads();
     }
@@ -227,6 +233,23 @@ __device__ void jacobi_svd(cplx<double> *M, cplx<double> *J, int r, cplx<double>
     const double tol = fmax(1e-14, 4.0 * r * 1.1e-16);
     const int tid = threadIdx.x;
     constexpr int NJ = WITHJ ? 2 : 1;
+    // |M|_F^2 (invariant under the rotations) sets the negligible column norm
+    __shared__ double sh_nrm[16];
+    {
+        double v = 0;
+        for (int64_t q = tid; q < (int64_t)r * r; q += blockDim.x) v += abs2(M[q]);
+        v = wave_sumd(v);
+        if (tid % 64 == 0) sh_nrm[tid / 64] = v;
+        __syncthreads();
+        if (tid == 0) {
+            double t = 0;
+            for (int w = 0; w < (int)blockDim.x / 64; ++w) t += sh_nrm[w];
+            sh_nrm[0] = t;
+        }
+        __syncthreads();
+    }
+    const double tiny = r * (2.3e-16 * 2.3e-16) * sh_nrm[0];
+    __syncthreads();   // sh_nrm is read before any later reuse
     if (NJ * (int64_t)r * r <= lds_elems) {
         cplx<double> *ldj = lds + (int64_t)r * r;
         for (int64_t q = tid; q < (int64_t)r * r; q += blockDim.x) {
@@ -235,7 +258,7 @@ __device__ void jacobi_svd(cplx<double> *M, cplx<double> *J, int r, cplx<double>
         }
         __syncthreads();
         for (int sweep = 0; sweep < 30; ++sweep)
-            if (!lds_sweep<WITHJ>(lds, ldj, r, r, tol, sh_flag)) break;
+            if (!lds_sweep<WITHJ>(lds, ldj, r, r, tol, tiny, sh_flag)) break;
         for (int64_t q = tid; q < (int64_t)r * r; q += blockDim.x) {
             M[q] = lds[q];
             if constexpr (WITHJ) J[q] = ldj[q];
@@ -263,7 +286,7 @@ __device__ void jacobi_svd(cplx<double> *M, cplx<double> *J, int r, cplx<double>
                     if constexpr (WITHJ) ldj[q] = J[(int64_t)col * r + i];
                 }
                 __syncthreads();
-                any |= lds_sweep<WITHJ>(lds, ldj, nc, r, tol, sh_flag);
+                any |= lds_sweep<WITHJ>(lds, ldj, nc, r, tol, tiny, sh_flag);
                 for (int64_t q = tid; q < (int64_t)nc * r; q += blockDim.x) {
                     const int cc = (int)(q / r), i = (int)(q % r);
                     const int col = cc < n0 ? c0 + cc : c1 + (cc - n0);
