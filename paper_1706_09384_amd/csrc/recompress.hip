@@ -309,12 +309,13 @@ __device__ void small_gemm(int mC, int nC, int K, FA fa, FB fb, FC fc, cplx<doub
     constexpr int T = 32, P = T + 1;
     cplx<double> *As = sh, *Bs = sh + T * P;
     const int tid = threadIdx.x;
-    const int tx = tid % T, ty = tid / T;   // ty in 0..7
+    const int tx = tid % T, ty = tid / T;   // ty in 0..7 for the 256 computing threads
+    const bool act = tid < 256;             // larger workgroups: the rest only stage
     for (int i0 = 0; i0 < mC; i0 += T)
         for (int j0 = 0; j0 < nC; j0 += T) {
             cplx<double> acc[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
             for (int k0 = 0; k0 < K; k0 += T) {
-                for (int q = tid; q < T * T; q += 256) {
+                for (int q = tid; q < T * T; q += blockDim.x) {
                     const int a = q % T, c = q / T;   // a fastest: contiguous rows
                     As[c * P + a] = (i0 + a < mC && k0 + c < K) ? fa(i0 + a, k0 + c)
                                                                   : cplx<double>{0, 0};
@@ -322,25 +323,29 @@ __device__ void small_gemm(int mC, int nC, int K, FA fa, FB fb, FC fc, cplx<doub
                                                                   : cplx<double>{0, 0};
                 }
                 __syncthreads();
+                if (act) {
 #pragma unroll 8
-                for (int kk = 0; kk < T; ++kk) {
-                    const cplx<double> bv = Bs[kk * P + tx];
+                    for (int kk = 0; kk < T; ++kk) {
+                        const cplx<double> bv = Bs[kk * P + tx];
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) acc[u] = acc[u] + As[kk * P + ty * 4 + u] * bv;
+                        for (int u = 0; u < 4; ++u) acc[u] = acc[u] + As[kk * P + ty * 4 + u] * bv;
+                    }
                 }
                 __syncthreads();
             }
+            if (act) {
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int i = i0 + ty * 4 + u, j = j0 + tx;
-                if (i < mC && j < nC) fc(i, j, acc[u]);
+                for (int u = 0; u < 4; ++u) {
+                    const int i = i0 + ty * 4 + u, j = j0 + tx;
+                    if (i < mC && j < nC) fc(i, j, acc[u]);
+                }
             }
         }
     __syncthreads();
 }
 
-template <typename R>
-__global__ void __launch_bounds__(256) factor_kernel(const RcBlk *__restrict__ blks,
+template <typename R, int NT>
+__global__ void __launch_bounds__(NT) factor_kernel(const RcBlk *__restrict__ blks,
                                                      const int32_t *__restrict__ order,
                                                      cplx<double> *__restrict__ work,
                                                      int32_t *__restrict__ newrank, double eps,
@@ -366,14 +371,14 @@ __global__ void __launch_bounds__(256) factor_kernel(const RcBlk *__restrict__ b
     double *sv = dv + r;
     int *idx = reinterpret_cast<int *>(sv + r);
     // Column equilibration: G~ = D^-1 G D^-1, D = sqrt(diag G).
-    for (int k = tid; k < r; k += 256) {
+    for (int k = tid; k < r; k += NT) {
         const double a = sqrt(fmax(RU[k + (int64_t)k * r].re, 0.0));
         const double c = sqrt(fmax(RV[k + (int64_t)k * r].re, 0.0));
         du[k] = a > 0 ? a : 1.0;
         dv[k] = c > 0 ? c : 1.0;
     }
     __syncthreads();
-    for (int64_t q = tid; q < (int64_t)r * r; q += 256) {
+    for (int64_t q = tid; q < (int64_t)r * r; q += NT) {
         const int i = (int)(q % r), j = (int)(q / r);
         RU[q] = (1.0 / (du[i] * du[j])) * RU[q];
         RV[q] = (1.0 / (dv[i] * dv[j])) * RV[q];
@@ -385,10 +390,10 @@ __global__ void __launch_bounds__(256) factor_kernel(const RcBlk *__restrict__ b
         if ((int64_t)r * r <= lds_elems) {
             // factor in LDS (the dot products of the left-looking sweep are
             // then LDS reads instead of dependent global loads)
-            for (int64_t q = tid; q < (int64_t)r * r; q += 256) lds[q] = G[q];
+            for (int64_t q = tid; q < (int64_t)r * r; q += NT) lds[q] = G[q];
             __syncthreads();
             chol_upper(lds, r, ctol, sh_s);
-            for (int64_t q = tid; q < (int64_t)r * r; q += 256) G[q] = lds[q];
+            for (int64_t q = tid; q < (int64_t)r * r; q += NT) G[q] = lds[q];
             __syncthreads();
         } else {
             chol_upper(G, r, ctol, sh_s);
@@ -407,14 +412,14 @@ __global__ void __launch_bounds__(256) factor_kernel(const RcBlk *__restrict__ b
     // singular values = column norms of M J, ranked in descending order; keep =
     // smallest k with sum_{i >= k} s_i^2 <= eps^2 sum s_i^2 (Frobenius tail)
     auto rank_and_keep = [&]() -> int {
-        for (int c = wave; c < r; c += 4) {
+        for (int c = wave; c < r; c += NT / 64) {
             double s = 0;
             for (int i = lane; i < r; i += 64) s += abs2(M[i + (int64_t)c * r]);
             s = wave_sumd(s);
             if (lane == 0) sv[c] = sqrt(s);
         }
         __syncthreads();
-        for (int c = tid; c < r; c += 256) {
+        for (int c = tid; c < r; c += NT) {
             const double v = sv[c];
             int pos = 0;
             for (int k = 0; k < r; ++k) {
@@ -453,7 +458,7 @@ __global__ void __launch_bounds__(256) factor_kernel(const RcBlk *__restrict__ b
     const bool useJ = keep > 0 && sv[idx[keep - 1]] < 1e-6 * sv[idx[0]];
     if (useJ) {
         form_core(M);
-        for (int64_t q = tid; q < (int64_t)r * r; q += 256)
+        for (int64_t q = tid; q < (int64_t)r * r; q += NT)
             J[q] = (q % r == q / r) ? cplx<double>{1, 0} : cplx<double>{0, 0};
         __syncthreads();
         jacobi_svd<true>(M, J, r, lds, lds_elems, &sh_i[0]);
@@ -583,9 +588,12 @@ void run_recompress(const std::vector<RcBlk> &blk, RcBlk *d_blk, const cplx<R> *
         if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
             v = 65536;
         max_lds = std::min(v, 160 * 1024) - 1024;
-        if (max_lds > 65536)
-            HM_HIP_CHECK(hipFuncSetAttribute((const void *)factor_kernel<R>,
+        if (max_lds > 65536) {
+            HM_HIP_CHECK(hipFuncSetAttribute((const void *)factor_kernel<R, 256>,
                                              hipFuncAttributeMaxDynamicSharedMemorySize, max_lds));
+            HM_HIP_CHECK(hipFuncSetAttribute((const void *)factor_kernel<R, 1024>,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, max_lds));
+        }
     }
     std::vector<int32_t> order(blk.size());
     for (size_t i = 0; i < blk.size(); ++i) order[i] = (int32_t)i;
@@ -609,15 +617,19 @@ void run_recompress(const std::vector<RcBlk> &blk, RcBlk *d_blk, const cplx<R> *
         const int64_t bytes = std::min<int64_t>(
             std::max<int64_t>(need, 2 * 32 * 33 * (int64_t)sizeof(cplx<double>)), max_lds);
         const int64_t lds_elems = bytes / (int64_t)sizeof(cplx<double>);
+        // ranks above 64 leave room for one workgroup per CU (LDS): give it
+        // 1024 threads (more lanes per Jacobi pair and per Cholesky column)
+        auto kern = rmax > 64 ? factor_kernel<R, 1024> : factor_kernel<R, 256>;
+        const unsigned nt = rmax > 64 ? 1024u : 256u;
         if (unbatched) {
             for (size_t q = q0; q < q1; ++q)
-                hipLaunchKernelGGL(factor_kernel<R>, dim3(1), dim3(256), (size_t)bytes, st, d_blk,
+                hipLaunchKernelGGL(kern, dim3(1), dim3(nt), (size_t)bytes, st, d_blk,
                                    d_order.as<int32_t>() + q,
                                    reinterpret_cast<cplx<double> *>(work), d_newrank, eps,
                                    lds_elems);
         } else {
-            hipLaunchKernelGGL(factor_kernel<R>, dim3((unsigned)(q1 - q0)), dim3(256),
-                               (size_t)bytes, st, d_blk, d_order.as<int32_t>() + q0,
+            hipLaunchKernelGGL(kern, dim3((unsigned)(q1 - q0)), dim3(nt), (size_t)bytes, st,
+                               d_blk, d_order.as<int32_t>() + q0,
                                reinterpret_cast<cplx<double> *>(work), d_newrank, eps, lds_elems);
         }
         HM_HIP_CHECK(hipGetLastError());
