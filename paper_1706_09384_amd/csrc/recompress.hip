@@ -18,6 +18,7 @@
 // zeroes that row of R: the dependent column adds nothing to the range.
 #include <algorithm>
 #include <climits>
+#include <mutex>
 
 #include "internal.hpp"
 
@@ -544,6 +545,19 @@ __global__ void __launch_bounds__(256) apply_kernel(const RcBlk *__restrict__ bl
         sh);
 }
 
+// A second stream per device for independent work of the same build
+// (default priority, non-blocking), created on first use.
+static hipStream_t side_stream() {
+    static std::mutex mu;
+    static hipStream_t streams[64] = {};
+    int dev = 0;
+    HM_HIP_CHECK(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(mu);
+    if (dev < 0 || dev >= 64) throw StatusError(HM_ERR_HIP, "device index out of range");
+    if (!streams[dev]) HM_HIP_CHECK(hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking));
+    return streams[dev];
+}
+
 template <typename R>
 void run_recompress(const std::vector<RcBlk> &blk, RcBlk *d_blk, const cplx<R> *acaslab,
                     double *work, int32_t *d_newrank, double eps, int32_t rmax, hipStream_t st,
@@ -604,6 +618,17 @@ void run_recompress(const std::vector<RcBlk> &blk, RcBlk *d_blk, const cplx<R> *
     HM_HIP_CHECK(hipMemcpyAsync(d_order.p, order.data(), order.size() * sizeof(int32_t),
                                 hipMemcpyHostToDevice, st));
     const int classes[] = {16, 24, 32, 48, 64, 100, 1 << 30};
+    // The classes of ranks above 64 run one workgroup per CU and leave CUs
+    // idle; the smaller classes go to a second stream and fill them.
+    hipStream_t side = st;
+    hipEvent_t ev_ready = nullptr, ev_done = nullptr;
+    if (!unbatched) {
+        side = side_stream();
+        HM_HIP_CHECK(hipEventCreateWithFlags(&ev_ready, hipEventDisableTiming));
+        HM_HIP_CHECK(hipEventCreateWithFlags(&ev_done, hipEventDisableTiming));
+        HM_HIP_CHECK(hipEventRecord(ev_ready, st));   // gram products and d_order are queued
+        HM_HIP_CHECK(hipStreamWaitEvent(side, ev_ready, 0));
+    }
     size_t q0 = 0;
     while (q0 < order.size()) {
         const int rmax = blk[order[q0]].r;
@@ -628,12 +653,19 @@ void run_recompress(const std::vector<RcBlk> &blk, RcBlk *d_blk, const cplx<R> *
                                    reinterpret_cast<cplx<double> *>(work), d_newrank, eps,
                                    lds_elems);
         } else {
-            hipLaunchKernelGGL(kern, dim3((unsigned)(q1 - q0)), dim3(nt), (size_t)bytes, st,
-                               d_blk, d_order.as<int32_t>() + q0,
+            hipLaunchKernelGGL(kern, dim3((unsigned)(q1 - q0)), dim3(nt), (size_t)bytes,
+                               rmax > 64 ? st : side, d_blk, d_order.as<int32_t>() + q0,
                                reinterpret_cast<cplx<double> *>(work), d_newrank, eps, lds_elems);
         }
         HM_HIP_CHECK(hipGetLastError());
         q0 = q1;
+    }
+    if (!unbatched) {
+        HM_HIP_CHECK(hipEventRecord(ev_done, side));
+        HM_HIP_CHECK(hipStreamWaitEvent(st, ev_done, 0));
+        HM_HIP_CHECK(hipStreamSynchronize(st));
+        HM_HIP_CHECK(hipEventDestroy(ev_ready));
+        HM_HIP_CHECK(hipEventDestroy(ev_done));
     }
     HM_HIP_CHECK(hipGetLastError());
     // items (pageable) and d_items must outlive the copy and the kernels.

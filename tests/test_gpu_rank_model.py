@@ -157,8 +157,12 @@ def test_model_changes_budgets_not_factors(hm, samples):
     H0 = hm.build_workload(wl, X=X, prec=1)
     H1 = hm.build_workload(wl, X=X, prec=1, rank_model=w)
     s0, s1 = H0.info(), H1.info()
-    say("hits", s1["n_model_hits"], "of", s1["n_lowrank"], "overflow", s0["n_overflow"], s1["n_overflow"])
+    say("hits", s1["n_model_hits"], "of", s1["n_lowrank"], "overflow", s0["n_overflow"], s1["n_overflow"],
+        "scratch", s0["aca_scratch_bytes"], s1["aca_scratch_bytes"])
     assert s1["n_model_hits"] > 0 and s0["n_model_hits"] == 0
+    # what the model gains over the size rule: no more re-runs, less first-pass scratch
+    assert s1["n_overflow"] <= s0["n_overflow"]
+    assert s1["aca_scratch_bytes"] < 0.8 * s0["aca_scratch_bytes"]
     b0, r0, a0 = H0.export_blocklist()
     b1, r1, a1 = H1.export_blocklist()
     assert np.array_equal(b0, b1) and np.array_equal(r0, r1) and np.array_equal(a0, a1)
