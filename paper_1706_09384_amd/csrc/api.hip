@@ -78,6 +78,19 @@ void cache_release_all() {
 
 }  // namespace
 
+hipStream_t side_stream(int which) {
+    static std::mutex mu;
+    static hipStream_t streams[2][64] = {};
+    int dev = 0;
+    HM_HIP_CHECK(hipGetDevice(&dev));
+    if (which < 0 || which > 1 || dev < 0 || dev >= 64)
+        throw StatusError(HM_ERR_HIP, "side stream index out of range");
+    std::lock_guard<std::mutex> lk(mu);
+    if (!streams[which][dev])
+        HM_HIP_CHECK(hipStreamCreateWithFlags(&streams[which][dev], hipStreamNonBlocking));
+    return streams[which][dev];
+}
+
 void DeviceBuf::reset() {
     if (!p) return;
     if (bytes >= kCacheMin) {
@@ -524,19 +537,30 @@ void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vect
         std::vector<int64_t> members;
         for (int64_t q = ch; q < nlr; q += nchunks) members.push_back(order[q]);
         double tc = now_s();
-        // ---- vector ACA passes of the chunk (re-runs with doubled budgets) ----
+        // ---- vector ACA passes of the chunk, pipelined with recompression ------
+        // Pass 0 runs every block of the chunk; blocks that use up their budget
+        // run again with a doubled budget in the next pass.  Pass p + 1 runs on
+        // its own stream while pass p is recompressed.
         std::vector<std::unique_ptr<DeviceBuf>> pass_scratch;
         std::vector<std::vector<int64_t>> pass_members;
-        std::vector<int64_t> todo(members);
-        while (!todo.empty()) {
+        std::vector<std::unique_ptr<DeviceBuf>> pass_work, pass_newrank, pass_drc;
+        std::vector<std::vector<RcBlk>> pass_rc;
+        struct AcaLaunch {
+            std::vector<int64_t> todo;
+            std::vector<AcaBlk> ab;
+            std::unique_ptr<DeviceBuf> scratch, flags, d_ab, d_out;
+            hipStream_t s = nullptr;
+        };
+        auto launch = [&](std::vector<int64_t> todo, hipStream_t s) {
+            AcaLaunch L;
             std::stable_sort(todo.begin(), todo.end(), lpt);
-            std::vector<AcaBlk> ab(todo.size());
+            L.ab.resize(todo.size());
             int64_t fac = 0, flg = 0;
             int32_t maxb = 3;
             for (size_t q = 0; q < todo.size(); ++q) {
                 const int64_t k = todo[q];
                 const Block &B = M->blocks[lr_ids[k]];
-                AcaBlk &a = ab[q];
+                AcaBlk &a = L.ab[q];
                 a.rb = tx.begin[B.row];
                 a.m = lm[k];
                 a.cb = ty.begin[B.col];
@@ -551,23 +575,33 @@ void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vect
                 maxb = std::max(maxb, a.budget);
             }
             if (pass_scratch.empty()) S.aca_scratch_bytes += fac * (int64_t)sizeof(cplx<R>);
-            auto scratch = std::make_unique<DeviceBuf>();
-            scratch->alloc(std::max<int64_t>(fac, 1) * sizeof(cplx<R>));
-            DeviceBuf flags, d_ab, d_out;
-            flags.alloc(std::max<int64_t>(flg, 1));
-            upload(d_ab, ab, st);
-            d_out.alloc(ab.size() * sizeof(AcaOut));
-            run_aca<R>(g, gp, ab, d_ab.as<AcaBlk>(), scratch->as<cplx<R>>(), flags.as<uint8_t>(),
-                       d_out.as<AcaOut>(), p.eps, tau_piv, maxb, st, p.unbatched != 0);
-            std::vector<AcaOut> res(ab.size());
-            HM_HIP_CHECK(hipMemcpyAsync(res.data(), d_out.p, res.size() * sizeof(AcaOut),
-                                        hipMemcpyDeviceToHost, st));
-            HM_HIP_CHECK(hipStreamSynchronize(st));
+            L.scratch = std::make_unique<DeviceBuf>();
+            L.flags = std::make_unique<DeviceBuf>();
+            L.d_ab = std::make_unique<DeviceBuf>();
+            L.d_out = std::make_unique<DeviceBuf>();
+            L.scratch->alloc(std::max<int64_t>(fac, 1) * sizeof(cplx<R>));
+            L.flags->alloc(std::max<int64_t>(flg, 1));
+            upload(*L.d_ab, L.ab, s);
+            L.d_out->alloc(L.ab.size() * sizeof(AcaOut));
+            run_aca<R>(g, gp, L.ab, static_cast<AcaBlk *>(L.d_ab->p),
+                       static_cast<cplx<R> *>(L.scratch->p), static_cast<uint8_t *>(L.flags->p),
+                       static_cast<AcaOut *>(L.d_out->p), p.eps, tau_piv, maxb, s,
+                       p.unbatched != 0);
+            L.todo.swap(todo);
+            L.s = s;
+            return L;
+        };
+        // Waits for a launched pass and records it; returns the blocks to re-run.
+        auto finish = [&](AcaLaunch &L) {
+            std::vector<AcaOut> res(L.ab.size());
+            HM_HIP_CHECK(hipMemcpyAsync(res.data(), L.d_out->p, res.size() * sizeof(AcaOut),
+                                        hipMemcpyDeviceToHost, L.s));
+            HM_HIP_CHECK(hipStreamSynchronize(L.s));
             std::vector<int64_t> next;
             const int32_t pass = (int32_t)pass_scratch.size();
             pass_members.emplace_back();
-            for (size_t q = 0; q < todo.size(); ++q) {
-                const int64_t k = todo[q];
+            for (size_t q = 0; q < L.todo.size(); ++q) {
+                const int64_t k = L.todo[q];
                 if (res[q].status == 1 && budget[k] < budget_cap) {
                     ++overflow;
                     budget[k] = std::min({3 * std::min(lm[k], ln[k]), 2 * budget[k], budget_cap});
@@ -577,21 +611,23 @@ void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vect
                 if (res[q].status == 1) ++capped;
                 if (pass == 0 && from_model[k]) ++hits;
                 aca_rank[k] = res[q].rank;
-                aca_u[k] = ab[q].uoff;
-                aca_v[k] = ab[q].voff;
+                aca_u[k] = L.ab[q].uoff;
+                aca_v[k] = L.ab[q].voff;
                 fallbacks += res[q].fallbacks;
                 pass_members[pass].push_back(k);
             }
-            pass_scratch.push_back(std::move(scratch));
-            todo.swap(next);
-        }
-        t_aca += now_s() - tc;
-        tc = now_s();
-        // ---- recompression of the chunk, pass by pass -------------------------
-        const size_t np = pass_scratch.size();
-        std::vector<std::unique_ptr<DeviceBuf>> pass_work(np), pass_newrank(np), pass_drc(np);
-        std::vector<std::vector<RcBlk>> pass_rc(np);
-        for (size_t ps = 0; ps < np; ++ps) {
+            pass_scratch.push_back(std::move(L.scratch));
+            L.flags.reset();
+            L.d_ab.reset();
+            L.d_out.reset();
+            return next;
+        };
+        // Recompression of pass ps on the build stream.
+        auto recompress_pass = [&](size_t ps) {
+            pass_work.emplace_back();
+            pass_newrank.emplace_back();
+            pass_drc.emplace_back();
+            pass_rc.emplace_back();
             auto &mem = pass_members[ps];
             auto &rc = pass_rc[ps];
             int64_t goff = 0;
@@ -626,7 +662,23 @@ void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vect
             } else {
                 for (size_t q = 0; q < mem.size(); ++q) final_rank[mem[q]] = aca_rank[mem[q]];
             }
+        };
+        hipStream_t aca_side = p.unbatched ? st : side_stream(1);
+        {
+            AcaLaunch first = launch(members, st);
+            std::vector<int64_t> next = finish(first);
+            t_aca += now_s() - tc;
+            tc = now_s();
+            for (size_t ps = 0;; ++ps) {
+                const bool more = !next.empty();
+                AcaLaunch rerun;
+                if (more) rerun = launch(next, aca_side);   // runs beside ...
+                recompress_pass(ps);                        // ... this recompression
+                if (!more) break;
+                next = finish(rerun);
+            }
         }
+        const size_t np = pass_scratch.size();
         // ---- the chunk's final factors, in chunk order ---------------------------
         int64_t len = 0;
         for (int64_t k : members) {

@@ -202,6 +202,10 @@ void ensure_mrhs_workspace(const hm_matrix *M);
 void launch_matvec_mrhs(const hm_matrix *M, const void *x, int64_t ldx, int32_t col0,
                         int32_t ncols, void *y, int64_t ldy, hipStream_t st, hipEvent_t *ev);
 
+// Extra streams per device (which = 0, 1) for independent work of one build:
+// default priority, non-blocking, created on first use, kept until exit.
+hipStream_t side_stream(int which);
+
 // Rank-model features of the admissible blocks (block-list order) and a
 // forward pass of the model on them.
 void rank_features(const hm_matrix *M, std::vector<float> &feats, std::vector<int64_t> &ids);

@@ -545,19 +545,6 @@ __global__ void __launch_bounds__(256) apply_kernel(const RcBlk *__restrict__ bl
         sh);
 }
 
-// A second stream per device for independent work of the same build
-// (default priority, non-blocking), created on first use.
-static hipStream_t side_stream() {
-    static std::mutex mu;
-    static hipStream_t streams[64] = {};
-    int dev = 0;
-    HM_HIP_CHECK(hipGetDevice(&dev));
-    std::lock_guard<std::mutex> lk(mu);
-    if (dev < 0 || dev >= 64) throw StatusError(HM_ERR_HIP, "device index out of range");
-    if (!streams[dev]) HM_HIP_CHECK(hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking));
-    return streams[dev];
-}
-
 template <typename R>
 void run_recompress(const std::vector<RcBlk> &blk, RcBlk *d_blk, const cplx<R> *acaslab,
                     double *work, int32_t *d_newrank, double eps, int32_t rmax, hipStream_t st,
@@ -623,7 +610,7 @@ void run_recompress(const std::vector<RcBlk> &blk, RcBlk *d_blk, const cplx<R> *
     hipStream_t side = st;
     hipEvent_t ev_ready = nullptr, ev_done = nullptr;
     if (!unbatched) {
-        side = side_stream();
+        side = side_stream(0);
         HM_HIP_CHECK(hipEventCreateWithFlags(&ev_ready, hipEventDisableTiming));
         HM_HIP_CHECK(hipEventCreateWithFlags(&ev_done, hipEventDisableTiming));
         HM_HIP_CHECK(hipEventRecord(ev_ready, st));   // gram products and d_order are queued
