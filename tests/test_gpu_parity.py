@@ -296,3 +296,61 @@ def test_sphere20k_sampled_rows(hm, orc, eps):
     e = rel(y[idx], ref)
     say("sampled e =", e)
     assert e <= 5 * eps
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 3e-6)])
+def test_leaf_one_point(hm, orc, prec, tol):
+    """Leaves of one point (3-row segments, all padded): with eta = 0 everything is a 3x3
+    dense tile; with eta = 3 the low-rank blocks span many padded segments."""
+    say(f"case leaf=1 prec={prec}")
+    w = W.small_sphere(60, leaf=1, eps=1e-6)
+    X, _ = w.points()
+    A = orc.dense(orc.Problem.from_workload(w, X))
+    b = W.complex_normal(180, 3, seed=12)
+    H0 = hm.build_workload(w, X=X, prec=prec, eta=0.0)
+    y0 = H0.matvec(to_dev(b, H0.complex_dtype)).cpu().numpy().astype(np.complex128)
+    assert rel(y0, A @ b) <= tol
+    H = hm.build_workload(w, X=X, prec=prec)
+    assert H.info()["n_lowrank"] > 0
+    y = H.matvec(to_dev(b, H.complex_dtype)).cpu().numpy().astype(np.complex128)
+    assert rel(y, A @ b) <= 5 * w.eps + tol
+
+
+def test_loose_eps(hm, orc, sphere1k):
+    w, X, pb, A, b = sphere1k
+    say("case eps=1e-2")
+    H = hm.build_workload(w, X=X, prec=1, eps=1e-2)
+    y = H.matvec(to_dev(b, H.complex_dtype)).cpu().numpy().astype(np.complex128)
+    e = rel(y, A @ b)
+    say("e =", e, "max rank", H.info()["max_rank"])
+    assert e <= 5e-2
+
+
+@pytest.mark.parametrize("kernel", [0, 1])
+def test_single_admissible_block(hm, orc, kernel):
+    """Two far clouds: the root pair is admissible, so the whole matrix is one ACA block."""
+    say(f"case one low-rank block kernel={kernel}")
+    X = W.fibonacci_sphere(300)
+    Y = W.uniform_ball(250, seed=5) + np.array([40.0, 0.0, 0.0])
+    Nrm = Y / np.linalg.norm(Y, axis=1, keepdims=True)
+    pb = orc.Problem(kernel, X, Y, Nrm if kernel == 1 else None, 2.0, same=False)
+    A = orc.dense(pb)
+    b = W.complex_normal(750, 2, seed=6)
+    for prec in (0, 1):
+        H = hm.build(to_dev(X), to_dev(Y), normals=to_dev(Nrm) if kernel == 1 else None,
+                     kernel=kernel, omega=2.0, leaf=16, eps=1e-6, prec=prec)
+        s = H.info()
+        assert s["n_blocks"] == 1 and s["n_lowrank"] == 1
+        y = H.matvec(to_dev(b, H.complex_dtype)).cpu().numpy().astype(np.complex128)
+        assert rel(y, A @ b) <= 5e-6 + (3e-6 if prec else 0), (prec, rel(y, A @ b))
+
+
+def test_many_rhs_ragged_panels(hm, orc, sphere1k):
+    """200 right-hand sides: three full 64-column panels and a ragged one of 8."""
+    w, X, pb, A, b = sphere1k
+    say("case nrhs=200")
+    H = hm.build_workload(w, X=X, prec=1)
+    B = W.complex_normal(3 * w.n_points, 200, seed=13)
+    Y = H.matvec(to_dev(B, H.complex_dtype)).cpu().numpy().astype(np.complex128)
+    E = np.linalg.norm(Y - A @ B, axis=0) / np.linalg.norm(A @ B, axis=0)
+    assert E.max() <= 5 * w.eps
