@@ -34,8 +34,9 @@
 
 namespace hm {
 
-constexpr int kAcaThreads = 256;
-constexpr int kAcaWaves = kAcaThreads / 64;
+constexpr int kAcaThreads = 256;      // workgroup of an ordinary block
+constexpr int kAcaBigThreads = 512;   // workgroup of a block with many points
+constexpr int kAcaBigPoints = 1500;   // m + n from which a block counts as big
 
 struct Inv3 {
     double s3sq, fro2;
@@ -109,7 +110,7 @@ __device__ inline Best2 block_best2(Best2 b, Best2 *sh) {
     if (lane == 0) sh[wave] = b;
     __syncthreads();
     Best2 r = sh[0];
-    for (int w = 1; w < kAcaWaves; ++w) {
+    for (int w = 1; w < (int)(blockDim.x / 64); ++w) {
         cand_better(r.s3, r.i3, sh[w].s3, sh[w].i3);
         cand_better(r.fro, r.ifro, sh[w].fro, sh[w].ifro);
     }
@@ -180,7 +181,7 @@ __device__ inline void herm3_eig(cplx<double> G[9], double lam[3], cplx<double> 
 // Block-wide sum of NV doubles per thread (NV <= 24); the result is returned
 // in out[] (LDS) visible to all threads after the call.
 template <int NV>
-__device__ inline void block_sum(double (&v)[NV], double *sh /* [kAcaWaves][NV] */, double *out) {
+__device__ inline void block_sum(double (&v)[NV], double *sh /* [waves][NV] */, double *out) {
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
 #pragma unroll
@@ -193,7 +194,7 @@ __device__ inline void block_sum(double (&v)[NV], double *sh /* [kAcaWaves][NV] 
     __syncthreads();
     if (threadIdx.x < NV) {
         double s = 0;
-        for (int w = 0; w < kAcaWaves; ++w) s += sh[w * NV + threadIdx.x];
+        for (int w = 0; w < (int)(blockDim.x / 64); ++w) s += sh[w * NV + threadIdx.x];
         out[threadIdx.x] = s;
     }
     __syncthreads();
@@ -203,13 +204,13 @@ __device__ inline void block_sum(double (&v)[NV], double *sh /* [kAcaWaves][NV] 
 // part[l][c] = sum over my rows q of conj(X[q, l]) X[q, base + c], for the
 // chunk l = l0..l0+3, c < 3, products in R, partial sums promoted to FP64.
 // X column-major with leading dimension ld; rows owned: 3*idx + a for idx
-// = tid, tid + 256, ... < npts.
+// = tid, tid + blockDim, ... < npts.
 template <typename R>
 __device__ inline void gram_chunk(const cplx<R> *X, int64_t ld, int npts, int l0, int lmax,
                                   int base, double (&part)[24]) {
 #pragma unroll
     for (int k = 0; k < 24; ++k) part[k] = 0.0;
-    for (int idx = threadIdx.x; idx < npts; idx += kAcaThreads) {
+    for (int idx = threadIdx.x; idx < npts; idx += (int)blockDim.x) {
         R acc[24];
 #pragma unroll
         for (int k = 0; k < 24; ++k) acc[k] = R(0);
@@ -237,8 +238,8 @@ __device__ inline void gram_chunk(const cplx<R> *X, int64_t ld, int npts, int l0
     }
 }
 
-template <typename R>
-__global__ void __launch_bounds__(kAcaThreads)
+template <typename R, int NT>
+__global__ void __launch_bounds__(NT)
     aca_kernel(Geometry g, GreenParams<R> gp, const AcaBlk *__restrict__ blks,
                cplx<R> *__restrict__ fac, uint8_t *__restrict__ flags,
                AcaOut *__restrict__ outs, double eps, double tau_piv, double nu2,
@@ -247,8 +248,8 @@ __global__ void __launch_bounds__(kAcaThreads)
     // dynamic LDS: pivot row (3 x budget, type R) then cv (budget x 3 complex doubles)
     cplx<double> *cv = reinterpret_cast<cplx<double> *>(smem_raw);
     cplx<R> *piv = reinterpret_cast<cplx<R> *>(cv + 3 * (int64_t)max_budget);
-    __shared__ Best2 sh_best[kAcaWaves];
-    __shared__ double sh_sum[kAcaWaves * 24];
+    __shared__ Best2 sh_best[(NT / 64)];
+    __shared__ double sh_sum[(NT / 64) * 24];
     __shared__ double sh_out[24];
     __shared__ cplx<double> sh_T[9];   // M^-1 (mode 0) or Z_p Sigma_p^-1 (mode 1)
     __shared__ cplx<double> sh_W[9];   // W_p (mode 1)
@@ -263,7 +264,7 @@ __global__ void __launch_bounds__(kAcaThreads)
     cplx<R> *V = fac + b.voff;
     uint8_t *used_i = flags + b.foff;
     uint8_t *used_j = used_i + m;
-    for (int k = tid; k < m + n; k += kAcaThreads) used_i[k] = 0;
+    for (int k = tid; k < m + n; k += NT) used_i[k] = 0;
     if (tid == 0) {
         sh_ctl[0] = 0;
         sh_ctl[5] = 0;
@@ -286,7 +287,7 @@ __global__ void __launch_bounds__(kAcaThreads)
         }
         const int ih = sh_ctl[0];
         // ---- 1. residual row --------------------------------------------
-        for (int k = tid; k < 3 * r; k += kAcaThreads) {
+        for (int k = tid; k < 3 * r; k += NT) {
             const int a = k / r, l = k - a * r;
             piv[a * r + l] = U[l * ldu + 3 * ih + a];
         }
@@ -294,7 +295,7 @@ __global__ void __launch_bounds__(kAcaThreads)
         const int pi = b.rb + ih;
         const double xi0 = g.x[0][pi], xi1 = g.x[1][pi], xi2 = g.x[2][pi];
         Best2 best = {-1.0, INT_MAX, -1.0, INT_MAX};
-        for (int j = tid; j < n; j += kAcaThreads) {
+        for (int j = tid; j < n; j += NT) {
             const int pj = b.cb + j;
             cplx<R> K[9];
             R nx = 0, ny = 0, nz = 0;
@@ -358,7 +359,7 @@ __global__ void __launch_bounds__(kAcaThreads)
             // Zero residual row: move to the next unused row, no new term.
             __syncthreads();
             int cand = INT_MAX;
-            for (int i = tid; i < m; i += kAcaThreads)
+            for (int i = tid; i < m; i += NT)
                 if (!used_i[i]) {
                     cand = i;
                     break;
@@ -381,13 +382,13 @@ __global__ void __launch_bounds__(kAcaThreads)
             double part[24];
             gram_chunk<R>(V, ldv, n, l0, r + 3, r, part);
             block_sum<24>(part, sh_sum, sh_out);
-            for (int k = tid; k < 12; k += kAcaThreads) {
+            for (int k = tid; k < 12; k += NT) {
                 const int u = k / 3, c = k % 3;
                 if (l0 + u < r + 3) cv[3 * (l0 + u) + c] = {sh_out[2 * k], sh_out[2 * k + 1]};
             }
         }
         // ---- pivot block and its (pseudo-)inverse ------------------------
-        if (jh % kAcaThreads == tid) {
+        if (jh % NT == tid) {
             // This thread wrote V(3jh + be, r + a) above; read back M(a, be).
             for (int a = 0; a < 3; ++a)
                 for (int be = 0; be < 3; ++be)
@@ -469,7 +470,7 @@ __global__ void __launch_bounds__(kAcaThreads)
         if (mode == 1) {
             ++fallbacks;
             // V_new = R_row^* W_p: rows 3j + be of V columns r..r+2 hold conj(R_row)^T.
-            for (int j = tid; j < n; j += kAcaThreads) {
+            for (int j = tid; j < n; j += NT) {
                 cplx<double> v[3][3];
                 for (int a = 0; a < 3; ++a)
                     for (int be = 0; be < 3; ++be)
@@ -484,7 +485,7 @@ __global__ void __launch_bounds__(kAcaThreads)
             }
             // cv[l][:] <- cv[l][:] W for old columns; the new-new Gram block
             // becomes W^* G W.
-            for (int l = tid; l < r + 3; l += kAcaThreads) {
+            for (int l = tid; l < r + 3; l += NT) {
                 cplx<double> row[3] = {cv[3 * l], cv[3 * l + 1], cv[3 * l + 2]};
                 for (int c = 0; c < 3; ++c) {
                     cplx<double> s = {0, 0};
@@ -504,7 +505,7 @@ __global__ void __launch_bounds__(kAcaThreads)
             if (tid < 9) cv[3 * (r + tid / 3) + tid % 3] = {sh_out[2 * tid], sh_out[2 * tid + 1]};
         }
         // ---- 3. residual column, 4. next row pivot, 5. U_new --------------
-        for (int k = tid; k < 3 * r; k += kAcaThreads) {
+        for (int k = tid; k < 3 * r; k += NT) {
             const int be = k / r, l = k - be * r;
             piv[be * r + l] = V[l * ldv + 3 * jh + be];
         }
@@ -518,7 +519,7 @@ __global__ void __launch_bounds__(kAcaThreads)
             njz = R(g.n[2][pj]);
         }
         best = {-1.0, INT_MAX, -1.0, INT_MAX};
-        for (int i = tid; i < m; i += kAcaThreads) {
+        for (int i = tid; i < m; i += NT) {
             const int pii = b.rb + i;
             cplx<R> K[9];
             green_block<R>(gp, g.x[0][pii] - yj0, g.x[1][pii] - yj1, g.x[2][pii] - yj2,
@@ -632,7 +633,8 @@ __global__ void __launch_bounds__(kAcaThreads)
 template <typename R>
 void run_aca(const Geometry &g, const GreenParams<R> &gp, const std::vector<AcaBlk> &blk,
              AcaBlk *d_blk, cplx<R> *scratch, uint8_t *flags, AcaOut *d_out, double eps,
-             double tau_piv, int32_t max_budget, hipStream_t st, bool unbatched) {
+             double tau_piv, int32_t max_budget, hipStream_t st, bool unbatched,
+             hipStream_t aux) {
     if (blk.empty()) return;
     const size_t smem = 3 * (size_t)max_budget * (sizeof(cplx<R>) + sizeof(cplx<double>));
     // Rounding-noise floor of a residual 3x3 block relative to the Frobenius
@@ -643,23 +645,64 @@ void run_aca(const Geometry &g, const GreenParams<R> &gp, const std::vector<AcaB
         // comparison baseline: one launch per block, each with the LDS its own budget needs
         for (size_t q = 0; q < blk.size(); ++q) {
             const size_t sm = 3 * (size_t)blk[q].budget * (sizeof(cplx<R>) + sizeof(cplx<double>));
-            hipLaunchKernelGGL(aca_kernel<R>, dim3(1), dim3(kAcaThreads), sm, st, g, gp,
-                               d_blk + q, scratch, flags, d_out + q, eps, tau_piv, nu * nu,
-                               blk[q].budget);
+            bool big = false;
+            if constexpr (sizeof(R) == 4) big = blk[q].m + blk[q].n >= kAcaBigPoints;
+            if (big) {
+                if constexpr (sizeof(R) == 4)
+                    hipLaunchKernelGGL((aca_kernel<R, kAcaBigThreads>), dim3(1),
+                                       dim3(kAcaBigThreads), sm, st, g, gp, d_blk + q, scratch,
+                                       flags, d_out + q, eps, tau_piv, nu * nu, blk[q].budget);
+            } else {
+                hipLaunchKernelGGL((aca_kernel<R, kAcaThreads>), dim3(1), dim3(kAcaThreads), sm,
+                                   st, g, gp, d_blk + q, scratch, flags, d_out + q, eps, tau_piv,
+                                   nu * nu, blk[q].budget);
+            }
         }
         HM_HIP_CHECK(hipGetLastError());
         return;
     }
-    hipLaunchKernelGGL(aca_kernel<R>, dim3((unsigned)blk.size()), dim3(kAcaThreads), smem, st, g,
-                       gp, d_blk, scratch, flags, d_out, eps, tau_piv, nu * nu, max_budget);
+    // Blocks with many points stream long factor columns every step: they
+    // get 512-thread workgroups (the most that keep every value in registers).  The list is longest first, so they form a
+    // prefix; the rest runs with 256 threads on the auxiliary stream (when
+    // given) beside them.
+    size_t nbig = 0;
+    // (complex128 would spill registers at 512 threads: it keeps 256)
+    if constexpr (sizeof(R) == 4)
+        while (nbig < blk.size() && blk[nbig].m + blk[nbig].n >= kAcaBigPoints) ++nbig;
+    hipStream_t s_small = (aux && nbig > 0) ? aux : st;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    if (s_small != st) {
+        HM_HIP_CHECK(hipEventCreateWithFlags(&ev0, hipEventDisableTiming));
+        HM_HIP_CHECK(hipEventCreateWithFlags(&ev1, hipEventDisableTiming));
+        HM_HIP_CHECK(hipEventRecord(ev0, st));   // inputs uploaded on st
+        HM_HIP_CHECK(hipStreamWaitEvent(s_small, ev0, 0));
+    }
+    if constexpr (sizeof(R) == 4) {
+        if (nbig > 0)
+            hipLaunchKernelGGL((aca_kernel<R, kAcaBigThreads>), dim3((unsigned)nbig),
+                               dim3(kAcaBigThreads), smem, st, g, gp, d_blk, scratch, flags, d_out,
+                               eps, tau_piv, nu * nu, max_budget);
+    }
+    if (nbig < blk.size())
+        hipLaunchKernelGGL((aca_kernel<R, kAcaThreads>), dim3((unsigned)(blk.size() - nbig)),
+                           dim3(kAcaThreads), smem, s_small, g, gp, d_blk + nbig, scratch, flags,
+                           d_out + nbig, eps, tau_piv, nu * nu, max_budget);
     HM_HIP_CHECK(hipGetLastError());
+    if (s_small != st) {
+        HM_HIP_CHECK(hipEventRecord(ev1, s_small));
+        HM_HIP_CHECK(hipStreamWaitEvent(st, ev1, 0));
+        HM_HIP_CHECK(hipEventDestroy(ev0));   // released once the event completes
+        HM_HIP_CHECK(hipEventDestroy(ev1));
+    }
 }
 
 template void run_aca<float>(const Geometry &, const GreenParams<float> &,
                              const std::vector<AcaBlk> &, AcaBlk *, cplx<float> *, uint8_t *,
-                             AcaOut *, double, double, int32_t, hipStream_t, bool);
+                             AcaOut *, double, double, int32_t, hipStream_t, bool,
+                             hipStream_t);
 template void run_aca<double>(const Geometry &, const GreenParams<double> &,
                               const std::vector<AcaBlk> &, AcaBlk *, cplx<double> *, uint8_t *,
-                              AcaOut *, double, double, int32_t, hipStream_t, bool);
+                              AcaOut *, double, double, int32_t, hipStream_t, bool,
+                             hipStream_t);
 
 }  // namespace hm

@@ -586,7 +586,7 @@ void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vect
             run_aca<R>(g, gp, L.ab, static_cast<AcaBlk *>(L.d_ab->p),
                        static_cast<cplx<R> *>(L.scratch->p), static_cast<uint8_t *>(L.flags->p),
                        static_cast<AcaOut *>(L.d_out->p), p.eps, tau_piv, maxb, s,
-                       p.unbatched != 0);
+                       p.unbatched != 0, s == st && !p.unbatched ? side_stream(0) : nullptr);
             L.todo.swap(todo);
             L.s = s;
             return L;

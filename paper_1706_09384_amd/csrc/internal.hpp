@@ -218,7 +218,8 @@ void profile_matvec_col(const hm_matrix *M, const void *x, void *y, hipStream_t 
 template <typename R>
 void run_aca(const Geometry &g, const GreenParams<R> &gp, const std::vector<AcaBlk> &blk,
              AcaBlk *d_blk, cplx<R> *scratchU, uint8_t *flags, AcaOut *d_out, double eps,
-             double tau_piv, int32_t max_budget, hipStream_t st, bool unbatched);
+             double tau_piv, int32_t max_budget, hipStream_t st, bool unbatched,
+             hipStream_t aux);
 
 // Recompression of ACA factors in place into compact output.
 template <typename R>
