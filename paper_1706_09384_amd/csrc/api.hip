@@ -533,9 +533,21 @@ void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vect
     int64_t lr_entries = 0, t_len = 0;
     double t_aca = 0.0, t_rc = 0.0;
     S.aca_scratch_bytes = 0;
-    for (int64_t ch = 0; ch < nchunks; ++ch) {
+    // With several chunks, the blocks that outgrow their first budget are
+    // collected from every chunk and compressed together in one last chunk,
+    // so that their long re-runs and large recompressions overlap each other
+    // instead of ending every chunk.
+    std::vector<int64_t> deferred;
+    for (int64_t ch = 0; ch <= nchunks; ++ch) {
+        const bool last = ch == nchunks;
         std::vector<int64_t> members;
-        for (int64_t q = ch; q < nlr; q += nchunks) members.push_back(order[q]);
+        if (!last) {
+            for (int64_t q = ch; q < nlr; q += nchunks) members.push_back(order[q]);
+        } else {
+            if (deferred.empty()) break;
+            members.swap(deferred);
+        }
+        const bool defer = !last && nchunks > 1;
         double tc = now_s();
         // ---- vector ACA passes of the chunk, pipelined with recompression ------
         // Pass 0 runs every block of the chunk; blocks that use up their budget
@@ -574,7 +586,7 @@ void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vect
                 flg += a.m + a.n;
                 maxb = std::max(maxb, a.budget);
             }
-            if (pass_scratch.empty()) S.aca_scratch_bytes += fac * (int64_t)sizeof(cplx<R>);
+            if (pass_scratch.empty() && !last) S.aca_scratch_bytes += fac * (int64_t)sizeof(cplx<R>);
             L.scratch = std::make_unique<DeviceBuf>();
             L.flags = std::make_unique<DeviceBuf>();
             L.d_ab = std::make_unique<DeviceBuf>();
@@ -609,7 +621,7 @@ void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vect
                     continue;
                 }
                 if (res[q].status == 1) ++capped;
-                if (pass == 0 && from_model[k]) ++hits;
+                if (pass == 0 && !last && from_model[k]) ++hits;
                 aca_rank[k] = res[q].rank;
                 aca_u[k] = L.ab[q].uoff;
                 aca_v[k] = L.ab[q].voff;
@@ -667,6 +679,10 @@ void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vect
         {
             AcaLaunch first = launch(members, st);
             std::vector<int64_t> next = finish(first);
+            if (defer) {
+                deferred.insert(deferred.end(), next.begin(), next.end());
+                next.clear();
+            }
             t_aca += now_s() - tc;
             tc = now_s();
             for (size_t ps = 0;; ++ps) {
@@ -679,9 +695,11 @@ void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vect
             }
         }
         const size_t np = pass_scratch.size();
-        // ---- the chunk's final factors, in chunk order ---------------------------
+        // ---- the chunk's final factors, in pass order ------------------------------
+        std::vector<int64_t> held;   // blocks whose factors this chunk computed
+        for (const auto &pm : pass_members) held.insert(held.end(), pm.begin(), pm.end());
         int64_t len = 0;
-        for (int64_t k : members) {
+        for (int64_t k : held) {
             const Block &B = M->blocks[lr_ids[k]];
             fu[k] = lr_entries + len;
             len += (int64_t)padded_rows(rowpad, tx.begin[B.row], lm[k]) * final_rank[k];
