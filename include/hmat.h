@@ -83,7 +83,7 @@ typedef struct {
     int32_t unbatched;     /* 1: assembly launches its kernels once per block (the
                               comparison baseline of the batched default) */
     int32_t aca_scratch_mb;/* cap on the first-pass ACA factor scratch of one chunk of
-                              admissible blocks, MiB; 0 = a quarter of the free device
+                              admissible blocks, MiB; 0 = half of the free device
                               memory (see hm_build) */
     int32_t reserved[5];
 } hm_params;

@@ -508,8 +508,8 @@ void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vect
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), lpt);
     // The admissible blocks are processed in chunks whose first-pass factor
-    // scratch stays about under a cap (default: a quarter of the free device
-    // memory): a chunk's ACA, recompression and final factors are done, and
+    // scratch stays about under a cap (default: half of the free device
+    // memory, counting the library's cached blocks as free): a chunk's ACA, recompression and final factors are done, and
     // its scratch released, before the next chunk starts.  Blocks are dealt
     // to the chunks round-robin in the longest-first order, so that every
     // chunk has the same mix of long and short blocks.
@@ -520,7 +520,7 @@ void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vect
         HM_HIP_CHECK(hipMemGetInfo(&fr, &tot));
         HM_HIP_CHECK(hipGetDevice(&dev));
         // the library's own cached blocks count as available
-        cap_bytes = std::max<int64_t>(int64_t(1) << 30, (int64_t)((fr + cache_bytes(dev)) / 4));
+        cap_bytes = std::max<int64_t>(int64_t(1) << 30, (int64_t)((fr + cache_bytes(dev)) / 2));
     }
     int64_t total_need = 0;
     for (int64_t k = 0; k < nlr; ++k) total_need += 3 * (int64_t)(lm[k] + ln[k]) * budget[k];
