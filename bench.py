@@ -298,8 +298,8 @@ def main():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-batching", action="store_true")
     ap.add_argument("--counters", action="store_true",
-                    help="profiling mode: one build, 10 matvecs, then a 256 MiB device copy "
-                         "(x3) whose known byte count calibrates FETCH_SIZE / WRITE_SIZE")
+                    help="profiling mode: one build, the autotuner, 10 matvecs, then a 256 MiB "
+                         "device copy (x3) whose known byte count calibrates FETCH_SIZE / WRITE_SIZE")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -325,6 +325,8 @@ def main():
 
     if args.counters:
         H, _ = step(hmat.C64)
+        H.autotune(reps=2)
+        log(f"[counters] autotuned shape {H.info()['acc_waves']} waves, {H.info()['proj_rows']} rows")
         for k in range(10):
             H.matvec(b64)
         torch.cuda.synchronize()
