@@ -4,7 +4,8 @@
 // GMRES(restart) with classical Gram-Schmidt applied twice (CGS2) for the
 // Arnoldi step, Givens rotations on the host for the small least-squares
 // problem, convergence on the recursive residual, confirmed by an explicit
-// residual at every restart.  nrhs right-hand sides run as independent GMRES
+// residual at every restart.  The Gram-Schmidt coefficients and norms stay
+// on the device; each Arnoldi step makes one device-to-host copy.  nrhs right-hand sides run as independent GMRES
 // instances in lockstep: one multi-column H-matvec per iteration, the
 // BLAS-1 kernels work on all columns at once, Hessenberg data per column.
 // Complex64 operators: iterative refinement with an FP64 residual
@@ -82,6 +83,18 @@ __global__ void scale_copy_kernel(const cplx<TS> *__restrict__ src, cplx<TD> *__
         dst[k] = cvt<TD>(scale[k % nrhs] * cvt<double>(src[k]));
 }
 
+// dst[k] = src[k] / |w_c| with |w_c|^2 = nsq[c].re (zero when the norm is 0 or not finite)
+template <typename TS, typename TD>
+__global__ void normalize_kernel(const cplx<TS> *__restrict__ src, cplx<TD> *__restrict__ dst,
+                                 const cplx<double> *__restrict__ nsq, int64_t len, int nrhs) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < len; k += stride) {
+        const double nn = sqrt(fmax(nsq[k % nrhs].re, 0.0));
+        const double s = (nn > 0.0 && isfinite(nn)) ? 1.0 / nn : 0.0;
+        dst[k] = cvt<TD>(s * cvt<double>(src[k]));
+    }
+}
+
 // r = b - r  (in place on r)
 template <typename T>
 __global__ void bminus_kernel(const cplx<T> *__restrict__ b, cplx<T> *__restrict__ r, int64_t len) {
@@ -124,6 +137,31 @@ class Blas {
                                     hipMemcpyDeviceToHost, st_));
         HM_HIP_CHECK(hipStreamSynchronize(st_));
         return host_;
+    }
+    // V_i^* w (nvec x nrhs) into the device slot `out` (no host copy)
+    void dots_dev(const cplx<T> *V, int64_t vstride, int nvec, const cplx<T> *w,
+                  cplx<double> *out) {
+        hipLaunchKernelGGL(dots_kernel<T>, dim3(nblk_, nvec), dim3(bdim_), 0, st_, V, vstride,
+                           nvec, w, len_, nrhs_, partial_.as<cplx<double>>());
+        HM_HIP_CHECK(hipGetLastError());
+        hipLaunchKernelGGL(dots_finish_kernel, dim3((unsigned)ceil_div(nvec * nrhs_, 256)),
+                           dim3(256), 0, st_, partial_.as<cplx<double>>(), nblk_, nvec, nrhs_, out);
+        HM_HIP_CHECK(hipGetLastError());
+    }
+    // w += sign * sum_i V_i coef[i][c] with device coefficients
+    template <typename TX>
+    void combine_dev(const cplx<T> *V, int64_t vstride, int nvec, const cplx<double> *coef,
+                     cplx<TX> *w, double sign) {
+        hipLaunchKernelGGL((combine_kernel<T, TX>), dim3(grid()), dim3(256), 0, st_, V, vstride,
+                           nvec, coef, w, len_, nrhs_, sign);
+        HM_HIP_CHECK(hipGetLastError());
+    }
+    // dst = src / |src| per column, |src|^2 from the device slot nsq
+    template <typename TS, typename TD>
+    void normalize_dev(const cplx<TS> *src, cplx<TD> *dst, const cplx<double> *nsq) {
+        hipLaunchKernelGGL((normalize_kernel<TS, TD>), dim3(grid()), dim3(256), 0, st_, src, dst,
+                           nsq, len_, nrhs_);
+        HM_HIP_CHECK(hipGetLastError());
     }
     std::vector<double> norms(const cplx<T> *w) {
         const auto &h = dots(w, 0, 1, w);
@@ -192,6 +230,11 @@ GmresResult gmres_core(const hm_matrix *A, const cplx<T> *b, cplx<T> *x, int nrh
     wb.alloc((size_t)len * sizeof(cplx<T>));
     cplx<T> *V = Vb.as<cplx<T>>(), *w = wb.as<cplx<T>>();
     Blas<T> blas(len, nrhs, m + 1, st);
+    // device slots of one Arnoldi step: two CGS passes ((m + 1) x nrhs each) and |w|^2
+    DeviceBuf hb_dev;
+    hb_dev.alloc((size_t)(2 * (m + 1) + 1) * nrhs * sizeof(cplx<double>));
+    cplx<double> *hslots = hb_dev.as<cplx<double>>();
+    std::vector<zd> hhost((size_t)(2 * (m + 1) + 1) * nrhs);
     HM_HIP_CHECK(hipMemsetAsync(x, 0, len * sizeof(cplx<T>), st));
     const std::vector<double> bn = blas.norms(b);
     std::vector<char> done(nrhs, 0);
@@ -227,17 +270,23 @@ GmresResult gmres_core(const hm_matrix *A, const cplx<T> *b, cplx<T> *x, int nrh
         for (; j < m && res.iters < maxit; ++j) {
             cplx<T> *vj = V + (size_t)j * len, *vn = V + (size_t)(j + 1) * len;
             if (hm_matvec(A, vj, w, nrhs, st) != HM_OK) throw StatusError(HM_ERR_HIP, "matvec failed");
-            std::vector<zd> h((size_t)(j + 1) * nrhs, zd(0));
-            for (int pass = 0; pass < 2; ++pass) {
-                const auto &d = blas.dots(V, len, j + 1, w);
-                std::vector<zd> coef(d.begin(), d.begin() + (size_t)(j + 1) * nrhs);
-                for (size_t q = 0; q < coef.size(); ++q) h[q] += coef[q];
-                blas.combine(V, len, j + 1, coef, w, -1.0);
-            }
-            const std::vector<double> hb = blas.norms(w);
-            std::vector<double> sc(nrhs);
-            for (int c = 0; c < nrhs; ++c) sc[c] = (hb[c] > 0 && std::isfinite(hb[c])) ? 1.0 / hb[c] : 0.0;
-            blas.scale_copy(w, vn, sc);
+            // CGS2 and the normalisation stay on the device; one copy brings the
+            // two coefficient passes and |w|^2 to the host for the Givens update.
+            const size_t nc = (size_t)(j + 1) * nrhs;
+            cplx<double> *c1 = hslots, *c2 = hslots + nc, *nsq = hslots + 2 * nc;
+            blas.dots_dev(V, len, j + 1, w, c1);
+            blas.combine_dev(V, len, j + 1, c1, w, -1.0);
+            blas.dots_dev(V, len, j + 1, w, c2);
+            blas.combine_dev(V, len, j + 1, c2, w, -1.0);
+            blas.dots_dev(w, 0, 1, w, nsq);
+            blas.normalize_dev(w, vn, nsq);
+            HM_HIP_CHECK(hipMemcpyAsync(hhost.data(), hslots, (2 * nc + nrhs) * sizeof(zd),
+                                        hipMemcpyDeviceToHost, st));
+            HM_HIP_CHECK(hipStreamSynchronize(st));
+            std::vector<zd> h(nc);
+            for (size_t q = 0; q < nc; ++q) h[q] = hhost[q] + hhost[nc + q];
+            std::vector<double> hb(nrhs);
+            for (int c = 0; c < nrhs; ++c) hb[c] = std::sqrt(std::max(0.0, hhost[2 * nc + c].real()));
             ++res.iters;
             bool cycle_done = true;
             for (int c = 0; c < nrhs; ++c) {
