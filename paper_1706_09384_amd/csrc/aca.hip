@@ -670,12 +670,10 @@ void run_aca(const Geometry &g, const GreenParams<R> &gp, const std::vector<AcaB
     if constexpr (sizeof(R) == 4)
         while (nbig < blk.size() && blk[nbig].m + blk[nbig].n >= kAcaBigPoints) ++nbig;
     hipStream_t s_small = (aux && nbig > 0) ? aux : st;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    ScopedEvent ev0, ev1;
     if (s_small != st) {
-        HM_HIP_CHECK(hipEventCreateWithFlags(&ev0, hipEventDisableTiming));
-        HM_HIP_CHECK(hipEventCreateWithFlags(&ev1, hipEventDisableTiming));
-        HM_HIP_CHECK(hipEventRecord(ev0, st));   // inputs uploaded on st
-        HM_HIP_CHECK(hipStreamWaitEvent(s_small, ev0, 0));
+        HM_HIP_CHECK(hipEventRecord(ev0.e, st));   // inputs uploaded on st
+        HM_HIP_CHECK(hipStreamWaitEvent(s_small, ev0.e, 0));
     }
     if constexpr (sizeof(R) == 4) {
         if (nbig > 0)
@@ -689,10 +687,8 @@ void run_aca(const Geometry &g, const GreenParams<R> &gp, const std::vector<AcaB
                            d_out + nbig, eps, tau_piv, nu * nu, max_budget);
     HM_HIP_CHECK(hipGetLastError());
     if (s_small != st) {
-        HM_HIP_CHECK(hipEventRecord(ev1, s_small));
-        HM_HIP_CHECK(hipStreamWaitEvent(st, ev1, 0));
-        HM_HIP_CHECK(hipEventDestroy(ev0));   // released once the event completes
-        HM_HIP_CHECK(hipEventDestroy(ev1));
+        HM_HIP_CHECK(hipEventRecord(ev1.e, s_small));
+        HM_HIP_CHECK(hipStreamWaitEvent(st, ev1.e, 0));
     }
 }
 

@@ -120,6 +120,21 @@ struct DeviceBuf {
     T *as() const { return static_cast<T *>(p); }
 };
 
+// HIP event without timing, destroyed with its scope.
+struct ScopedEvent {
+    hipEvent_t e = nullptr;
+    ScopedEvent() {
+        const hipError_t r = hipEventCreateWithFlags(&e, hipEventDisableTiming);
+        if (r != hipSuccess) throw HipError(std::string("hipEventCreateWithFlags: ") +
+                                                hipGetErrorString(r), r);
+    }
+    ScopedEvent(const ScopedEvent &) = delete;
+    ScopedEvent &operator=(const ScopedEvent &) = delete;
+    ~ScopedEvent() {
+        if (e) (void)hipEventDestroy(e);
+    }
+};
+
 size_t elem_bytes(int prec);  // bytes of one complex element
 
 }  // namespace hm

@@ -582,8 +582,8 @@ void run_recompress(const std::vector<RcBlk> &blk, RcBlk *d_blk, const cplx<R> *
     // block of the class need (whole-matrix mode), capped at what the device
     // grants one workgroup (block mode above that), so that small blocks keep
     // several workgroups per CU.
-    static int max_lds = -1;
-    if (max_lds < 0) {
+    int max_lds = 0;
+    {
         int dev = 0, v = 65536;
         HM_HIP_CHECK(hipGetDevice(&dev));
         if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
@@ -608,13 +608,11 @@ void run_recompress(const std::vector<RcBlk> &blk, RcBlk *d_blk, const cplx<R> *
     // The classes of ranks above 64 run one workgroup per CU and leave CUs
     // idle; the smaller classes go to a second stream and fill them.
     hipStream_t side = st;
-    hipEvent_t ev_ready = nullptr, ev_done = nullptr;
+    ScopedEvent ev_ready, ev_done;
     if (!unbatched) {
         side = side_stream(0);
-        HM_HIP_CHECK(hipEventCreateWithFlags(&ev_ready, hipEventDisableTiming));
-        HM_HIP_CHECK(hipEventCreateWithFlags(&ev_done, hipEventDisableTiming));
-        HM_HIP_CHECK(hipEventRecord(ev_ready, st));   // gram products and d_order are queued
-        HM_HIP_CHECK(hipStreamWaitEvent(side, ev_ready, 0));
+        HM_HIP_CHECK(hipEventRecord(ev_ready.e, st));   // gram products and d_order are queued
+        HM_HIP_CHECK(hipStreamWaitEvent(side, ev_ready.e, 0));
     }
     size_t q0 = 0;
     while (q0 < order.size()) {
@@ -648,11 +646,9 @@ void run_recompress(const std::vector<RcBlk> &blk, RcBlk *d_blk, const cplx<R> *
         q0 = q1;
     }
     if (!unbatched) {
-        HM_HIP_CHECK(hipEventRecord(ev_done, side));
-        HM_HIP_CHECK(hipStreamWaitEvent(st, ev_done, 0));
+        HM_HIP_CHECK(hipEventRecord(ev_done.e, side));
+        HM_HIP_CHECK(hipStreamWaitEvent(st, ev_done.e, 0));
         HM_HIP_CHECK(hipStreamSynchronize(st));
-        HM_HIP_CHECK(hipEventDestroy(ev_ready));
-        HM_HIP_CHECK(hipEventDestroy(ev_done));
     }
     HM_HIP_CHECK(hipGetLastError());
     // items (pageable) and d_items must outlive the copy and the kernels.
