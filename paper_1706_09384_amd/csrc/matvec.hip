@@ -26,6 +26,24 @@ namespace hm {
 
 constexpr int kWave = 64;
 
+// Stored factors are streamed once per product: non-temporal loads keep them
+// from displacing the reused x and t vectors in the caches.
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef float f2v __attribute__((ext_vector_type(2)));
+typedef double d2v __attribute__((ext_vector_type(2)));
+__device__ inline float4 ld_stream(const float4 *p) {
+    const f4v v = __builtin_nontemporal_load(reinterpret_cast<const f4v *>(p));
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ inline cplx<float> ld_stream(const cplx<float> *p) {
+    const f2v v = __builtin_nontemporal_load(reinterpret_cast<const f2v *>(p));
+    return {v.x, v.y};
+}
+__device__ inline cplx<double> ld_stream(const cplx<double> *p) {
+    const d2v v = __builtin_nontemporal_load(reinterpret_cast<const d2v *>(p));
+    return {v.x, v.y};
+}
+
 template <typename S, typename A>
 __global__ void gather_kernel(const cplx<S> *__restrict__ x, int64_t ldx, int32_t col,
                               const int32_t *__restrict__ perm, int64_t npts,
@@ -79,7 +97,7 @@ __global__ void __launch_bounds__(256) project_kernel(const LowRankBlk *__restri
                     cplx<A> xv[8];
 #pragma unroll
                     for (int u = 0; u < 8; ++u) {
-                        vv[u] = *reinterpret_cast<const float4 *>(v + (int64_t)(i + u * G) * ldv);
+                        vv[u] = ld_stream(reinterpret_cast<const float4 *>(v + (int64_t)(i + u * G) * ldv));
                         xv[u] = xs[i + u * G];
                     }
 #pragma unroll
@@ -92,7 +110,7 @@ __global__ void __launch_bounds__(256) project_kernel(const LowRankBlk *__restri
                     }
                 }
                 for (; i < rows; i += G) {
-                    const float4 vv = *reinterpret_cast<const float4 *>(v + (int64_t)i * ldv);
+                    const float4 vv = ld_stream(reinterpret_cast<const float4 *>(v + (int64_t)i * ldv));
                     const cplx<A> xv = xs[i];
                     acc[0].re += vv.x * xv.re + vv.y * xv.im;
                     acc[0].im += vv.x * xv.im - vv.y * xv.re;
@@ -105,7 +123,7 @@ __global__ void __launch_bounds__(256) project_kernel(const LowRankBlk *__restri
                     cplx<A> xv[8];
 #pragma unroll
                     for (int u = 0; u < 8; ++u) {
-                        vv[u] = v[(int64_t)(i + u * G) * ldv];
+                        vv[u] = ld_stream(v + (int64_t)(i + u * G) * ldv);
                         xv[u] = xs[i + u * G];
                     }
 #pragma unroll
@@ -116,7 +134,7 @@ __global__ void __launch_bounds__(256) project_kernel(const LowRankBlk *__restri
                     }
                 }
                 for (; i < rows; i += G) {
-                    const cplx<A> a = cvt<A>(v[(int64_t)i * ldv]);
+                    const cplx<A> a = cvt<A>(ld_stream(v + (int64_t)i * ldv));
                     const cplx<A> xv = xs[i];
                     acc[0].re += a.re * xv.re + a.im * xv.im;
                     acc[0].im += a.re * xv.im - a.im * xv.re;
@@ -173,7 +191,7 @@ __device__ inline void panel_accum(cplx<A> (&acc)[RPL], const cplx<S> *__restric
             if (row < rows) {
                 cplx<S> c[8];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) c[u] = base[(j + u) * ld + row];
+                for (int u = 0; u < 8; ++u) c[u] = ld_stream(base + (j + u) * ld + row);
 #pragma unroll
                 for (int u = 0; u < 8; ++u) fma_(acc[k], cvt<A>(c[u]), w[u]);
             }
@@ -184,7 +202,7 @@ __device__ inline void panel_accum(cplx<A> (&acc)[RPL], const cplx<S> *__restric
 #pragma unroll
         for (int k = 0; k < RPL; ++k) {
             const int32_t row = r0 + lane + k * kWave;
-            if (row < rows) fma_(acc[k], cvt<A>(base[j * ld + row]), w);
+            if (row < rows) fma_(acc[k], cvt<A>(ld_stream(base + j * ld + row)), w);
         }
     }
 }
@@ -212,7 +230,7 @@ __device__ inline void panel_accum_pair(cplx<float> (&acc)[2 * RPL],
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 w[u] = wv[j + u * G];
-                c[u] = b4[(int64_t)(j + u * G) * ld4 + q];
+                c[u] = ld_stream(b4 + (int64_t)(j + u * G) * ld4 + q);
             }
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
@@ -222,7 +240,7 @@ __device__ inline void panel_accum_pair(cplx<float> (&acc)[2 * RPL],
         }
         for (; j < ncol; j += G) {
             const cplx<float> w = wv[j];
-            const float4 c = b4[(int64_t)j * ld4 + q];
+            const float4 c = ld_stream(b4 + (int64_t)j * ld4 + q);
             fma_(acc[0], cplx<float>{c.x, c.y}, w);
             fma_(acc[1], cplx<float>{c.z, c.w}, w);
         }
@@ -239,7 +257,7 @@ __device__ inline void panel_accum_pair(cplx<float> (&acc)[2 * RPL],
             if (q < npairs) {
                 float4 c[8];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) c[u] = b4[(j + u) * ld4 + q];
+                for (int u = 0; u < 8; ++u) c[u] = ld_stream(b4 + (j + u) * ld4 + q);
 #pragma unroll
                 for (int u = 0; u < 8; ++u) {
                     fma_(acc[2 * k], cplx<float>{c[u].x, c[u].y}, w[u]);
@@ -254,7 +272,7 @@ __device__ inline void panel_accum_pair(cplx<float> (&acc)[2 * RPL],
         for (int k = 0; k < RPL; ++k) {
             const int32_t q = p0 + lane + k * kWave;
             if (q < npairs) {
-                const float4 c = b4[j * ld4 + q];
+                const float4 c = ld_stream(b4 + j * ld4 + q);
                 fma_(acc[2 * k], cplx<float>{c.x, c.y}, w);
                 fma_(acc[2 * k + 1], cplx<float>{c.z, c.w}, w);
             }
