@@ -136,15 +136,18 @@ def test_panels_single_point(hm, orc):
     check_panels(hm, orc, H, A, B, 1e-4, 1e-6)
 
 
-def test_lockstep_gmres_on_panels(hm, orc, sphere1k):
-    """Twelve right-hand sides share each panel product of the inner complex64 GMRES."""
+@pytest.mark.parametrize("nrhs", [4, 12])
+def test_lockstep_gmres_on_panels(hm, orc, sphere1k, nrhs):
+    """Several right-hand sides share each panel product of the inner complex64 GMRES.
+    With 4 columns the Gram-Schmidt dots reduce per column inside a wave (4 divides 64);
+    with 12 they take the per-block fallback."""
     w, X, A = sphere1k
-    say("case multirhs gmres 12 rhs")
+    say(f"case multirhs gmres {nrhs} rhs")
     H = hm.build_workload(w, X=X, prec=1)
-    B = W.complex_normal(3 * w.n_points, 12, seed=11)
+    B = W.complex_normal(3 * w.n_points, nrhs, seed=11)
     x, info = H.gmres(to_dev(B), tol=1e-8, restart=50, maxit=6000)
     say("gmres", info)
-    assert info["converged"] == 12
+    assert info["converged"] == nrhs
     x = x.cpu().numpy()
     p0, n0, _ = H.export_tree(0)
     p1, n1, _ = H.export_tree(1)
