@@ -15,9 +15,10 @@
 //   5. U_new = R(:, j^) M^-1, V_new = R(i^, :)^* with M = R(i^, j^);
 //   6. stopping test ||U_k V_k^*||_F <= eps ||B_k||_F with both norms from
 //      FP64 recurrences over the 3x3 Gram blocks.  The Gram columns
-//      V^* V_new and U^* U_new are reduced right after each residual pass
-//      (each thread sums its own rows, the workgroup sums in FP64); the
-//      V-side results stay in LDS until the U side is reduced.
+//      V^* V_new and U^* U_new are reduced right after each residual pass:
+//      one wave per chunk of four old columns sums over all rows in FP64 and
+//      reduces its lanes by recursive halving, so the pass needs no block
+//      barrier; the V-side results stay in LDS until the U side is reduced.
 // Rows/columns whose every candidate 3x3 block is numerically singular
 // (sigma_3 <= tau_piv |block|_F, e.g. T between coplanar points) fall back
 // to the largest-Frobenius candidate and a rank-p pseudo-inverse update.
@@ -178,39 +179,39 @@ __device__ inline void herm3_eig(cplx<double> G[9], double lam[3], cplx<double> 
             }
 }
 
-// Block-wide sum of NV doubles per thread (NV <= 24); the result is returned
-// in out[] (LDS) visible to all threads after the call.
-template <int NV>
-__device__ inline void block_sum(double (&v)[NV], double *sh /* [waves][NV] */, double *out) {
+// One recursive-halving step of a wave reduction: lanes l and l ^ off
+// exchange half of their V partial sums; the lane with the offset bit set
+// keeps the upper half, its partner the lower half.
+template <int V>
+__device__ inline void halve(const double (&v)[V], double (&o)[V / 2], int off, bool hi) {
 #pragma unroll
-    for (int k = 0; k < NV; ++k) {
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) v[k] += __shfl_xor(v[k], o, 64);
+    for (int k = 0; k < V / 2; ++k) {
+        const double send = hi ? v[k] : v[V / 2 + k];
+        const double keep = hi ? v[V / 2 + k] : v[k];
+        o[k] = keep + __shfl_xor(send, off, 64);
     }
-    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-    if (lane == 0)
-#pragma unroll
-        for (int k = 0; k < NV; ++k) sh[wave * NV + k] = v[k];
-    __syncthreads();
-    if (threadIdx.x < NV) {
-        double s = 0;
-        for (int w = 0; w < (int)(blockDim.x / 64); ++w) s += sh[w * NV + threadIdx.x];
-        out[threadIdx.x] = s;
-    }
-    __syncthreads();
 }
 
-// Gram of old and new factor columns over this thread's rows:
-// part[l][c] = sum over my rows q of conj(X[q, l]) X[q, base + c], for the
-// chunk l = l0..l0+3, c < 3, products in R, partial sums promoted to FP64.
-// X column-major with leading dimension ld; rows owned: 3*idx + a for idx
-// = tid, tid + blockDim, ... < npts.
+// Gram of old and new factor columns, computed by one wave over all rows:
+// entry (u, c) = sum over points idx < npts and components a of
+// conj(X[3 idx + a, l0 + u]) X[3 idx + a, base + c], for u < 4 (l0 + u <
+// lmax) and c < 3; products and the sum over a in R, the sum over points in
+// FP64.  X is column-major with leading dimension ld.  The 24 doubles
+// (index 6u + 2c + {0: re, 1: im}) are reduced over the wave by halving
+// three times (offsets 32, 16, 8) and then summing the last three values
+// over offsets 4, 2, 1: on return lane l holds values gram_vbase(l) + k,
+// k < 3, summed over the whole wave.
+__device__ inline int gram_vbase(int lane) {
+    return ((lane & 32) ? 12 : 0) + ((lane & 16) ? 6 : 0) + ((lane & 8) ? 3 : 0);
+}
+
 template <typename R>
-__device__ inline void gram_chunk(const cplx<R> *X, int64_t ld, int npts, int l0, int lmax,
-                                  int base, double (&part)[24]) {
+__device__ inline void gram_wave(const cplx<R> *X, int64_t ld, int npts, int l0, int lmax,
+                                 int base, int lane, double (&out)[3]) {
+    double part[24];
 #pragma unroll
     for (int k = 0; k < 24; ++k) part[k] = 0.0;
-    for (int idx = threadIdx.x; idx < npts; idx += (int)blockDim.x) {
+    for (int idx = lane; idx < npts; idx += 64) {
         R acc[24];
 #pragma unroll
         for (int k = 0; k < 24; ++k) acc[k] = R(0);
@@ -236,6 +237,14 @@ __device__ inline void gram_chunk(const cplx<R> *X, int64_t ld, int npts, int l0
 #pragma unroll
         for (int k = 0; k < 24; ++k) part[k] += double(acc[k]);
     }
+    double h12[12], h6[6];
+    halve<24>(part, h12, 32, (lane & 32) != 0);
+    halve<12>(h12, h6, 16, (lane & 16) != 0);
+    halve<6>(h6, out, 8, (lane & 8) != 0);
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int o = 4; o > 0; o >>= 1) out[k] += __shfl_xor(out[k], o, 64);
 }
 
 template <typename R, int NT>
@@ -244,20 +253,21 @@ __global__ void __launch_bounds__(NT)
                cplx<R> *__restrict__ fac, uint8_t *__restrict__ flags,
                AcaOut *__restrict__ outs, double eps, double tau_piv, double nu2,
                int32_t max_budget) {
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     // dynamic LDS: pivot row (3 x budget, type R) then cv (budget x 3 complex doubles)
     cplx<double> *cv = reinterpret_cast<cplx<double> *>(smem_raw);
     cplx<R> *piv = reinterpret_cast<cplx<R> *>(cv + 3 * (int64_t)max_budget);
     __shared__ Best2 sh_best[(NT / 64)];
-    __shared__ double sh_sum[(NT / 64) * 24];
+    __shared__ double sh_sum[(NT / 64) * 2];
     __shared__ double sh_out[24];
     __shared__ cplx<double> sh_T[9];   // M^-1 (mode 0) or Z_p Sigma_p^-1 (mode 1)
     __shared__ cplx<double> sh_W[9];   // W_p (mode 1)
     __shared__ int sh_ctl[8];          // 0 ihat, 2 mode, 3 p, 5 stop
-    __shared__ double sh_norm2, sh_cross, sh_new, sh_anorm;
+    __shared__ double sh_norm2, sh_anorm;
 
     const AcaBlk b = blks[blockIdx.x];
     const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
     const int m = b.m, n = b.n;
     const int64_t ldu = 3 * (int64_t)m, ldv = 3 * (int64_t)n;
     cplx<R> *U = fac + b.uoff;
@@ -377,14 +387,19 @@ __global__ void __launch_bounds__(NT)
         const bool degenerate = best.s3 <= tau_piv * tau_piv * best.fro;
         const int jh = degenerate ? best.ifro : best.i3;
         // ---- FP64 Gram of the raw new V columns against all V columns ------
-        // cv[l][c] = V[:, l]^* Vraw[:, r + c] for l < r + 3
-        for (int l0 = 0; l0 < r + 3; l0 += 4) {
-            double part[24];
-            gram_chunk<R>(V, ldv, n, l0, r + 3, r, part);
-            block_sum<24>(part, sh_sum, sh_out);
-            for (int k = tid; k < 12; k += NT) {
-                const int u = k / 3, c = k % 3;
-                if (l0 + u < r + 3) cv[3 * (l0 + u) + c] = {sh_out[2 * k], sh_out[2 * k + 1]};
+        // cv[l][c] = V[:, l]^* Vraw[:, r + c] for l < r + 3; wave w takes the
+        // column chunks l0 = 4w, 4w + 4 NT / 64, ... (the barrier before the
+        // pivot inverse publishes cv)
+        for (int l0 = 4 * wave; l0 < r + 3; l0 += 4 * (NT / 64)) {
+            double v3[3];
+            gram_wave<R>(V, ldv, n, l0, r + 3, r, lane, v3);
+            if ((lane & 7) == 0) {
+                const int vb = gram_vbase(lane);
+                for (int k = 0; k < 3; ++k) {
+                    const int v = vb + k;
+                    if (l0 + v / 6 < r + 3)
+                        reinterpret_cast<double *>(cv)[6 * l0 + v] = v3[k];
+                }
             }
         }
         // ---- pivot block and its (pseudo-)inverse ------------------------
@@ -579,34 +594,46 @@ __global__ void __launch_bounds__(NT)
         // ---- 6. FP64 norm recurrences ------------------------------------
         // cu[l][c] = U[:, l]^* U[:, r + c]; cross = 2 Re sum_{l<r,c} cu conj(cv),
         // new = Re sum_{a,c < p} G_U[a][c] conj(G_V[a][c]).
-        if (tid == 0) {
-            sh_cross = 0.0;
-            sh_new = 0.0;
-        }
-        for (int l0 = 0; l0 < r + p; l0 += 4) {
-            double part[24];
-            gram_chunk<R>(U, ldu, m, l0, r + p, r, part);
-            block_sum<24>(part, sh_sum, sh_out);
-            if (tid == 0) {
-                for (int u = 0; u < 4 && l0 + u < r + p; ++u) {
-                    const int l = l0 + u;
-                    double s = 0;
-                    for (int c = 0; c < p; ++c) {
-                        const double cr = sh_out[2 * (3 * u + c)], ci = sh_out[2 * (3 * u + c) + 1];
-                        const cplx<double> v = cv[3 * l + c];
-                        s += cr * v.re + ci * v.im;   // Re(cu * conj(cv))
+        {
+            double cross = 0.0, fresh = 0.0;
+            for (int l0 = 4 * wave; l0 < r + p; l0 += 4 * (NT / 64)) {
+                double v3[3];
+                gram_wave<R>(U, ldu, m, l0, r + p, r, lane, v3);
+                if ((lane & 7) == 0) {
+                    const int vb = gram_vbase(lane);
+                    for (int k = 0; k < 3; ++k) {
+                        const int v = vb + k, l = l0 + v / 6, c = (v % 6) >> 1;
+                        if (l < r + p && c < p) {
+                            // Re(cu conj(cv)) split into its re*re and im*im parts
+                            const cplx<double> w = cv[3 * l + c];
+                            const double t = v3[k] * ((v & 1) ? w.im : w.re);
+                            if (l < r)
+                                cross += 2.0 * t;
+                            else
+                                fresh += t;
+                        }
                     }
-                    if (l < r)
-                        sh_cross += 2.0 * s;
-                    else
-                        sh_new += s;
                 }
+            }
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                cross += __shfl_xor(cross, o, 64);
+                fresh += __shfl_xor(fresh, o, 64);
+            }
+            if (lane == 0) {
+                sh_sum[2 * wave] = cross;
+                sh_sum[2 * wave + 1] = fresh;
             }
         }
         __syncthreads();
         if (tid == 0) {
-            sh_norm2 += sh_cross + sh_new;
-            const bool stop = (sh_new <= eps * eps * sh_norm2) || next_i < 0;
+            double cross = 0.0, fresh = 0.0;
+            for (int w = 0; w < NT / 64; ++w) {
+                cross += sh_sum[2 * w];
+                fresh += sh_sum[2 * w + 1];
+            }
+            sh_norm2 += cross + fresh;
+            const bool stop = (fresh <= eps * eps * sh_norm2) || next_i < 0;
             sh_ctl[5] = stop ? 1 : 0;
             sh_ctl[0] = next_i;
         }

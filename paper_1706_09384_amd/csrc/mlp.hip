@@ -75,7 +75,7 @@ __global__ void __launch_bounds__(kThreads) mlp_grad_kernel(
     float *__restrict__ gpart, float *__restrict__ lpart,
     // Adam state (MODE 1)
     float *__restrict__ am, float *__restrict__ av, float lr, float b1c, float b2c) {
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     GradLds &L = *reinterpret_cast<GradLds *>(smem_raw);
     const int tid = threadIdx.x;
     const int64_t base = s0 + (int64_t)blockIdx.x * kThreads;

@@ -222,6 +222,35 @@ __device__ bool lds_sweep(cplx<double> *lds, cplx<double> *ldj, int nc, int r, d
     return res;
 }
 
+// Squared column norm below which a column of the r x r matrix M counts as
+// numerically zero: r u^2 |M|_F^2 (|M|_F is invariant under the rotations).
+// Block-wide; every thread returns the value.
+__device__ double jacobi_tiny(const cplx<double> *M, int r) {
+    __shared__ double sh_nrm[16];
+    const int tid = threadIdx.x;
+    double v = 0;
+    for (int64_t q = tid; q < (int64_t)r * r; q += blockDim.x) v += abs2(M[q]);
+    v = wave_sumd(v);
+    if (tid % 64 == 0) sh_nrm[tid / 64] = v;
+    __syncthreads();
+    if (tid == 0) {
+        double t = 0;
+        for (int w = 0; w < (int)blockDim.x / 64; ++w) t += sh_nrm[w];
+        sh_nrm[0] = t;
+    }
+    __syncthreads();
+    const double tiny = r * (2.3e-16 * 2.3e-16) * sh_nrm[0];
+    __syncthreads();   // sh_nrm is read before any later reuse
+    return tiny;
+}
+
+// Columns per LDS block of the block Jacobi method (two blocks, with J when
+// the rotations are accumulated, fill lds_elems complex doubles).
+__host__ __device__ inline int jacobi_bw(int r, int64_t lds_elems, int nj) {
+    const int64_t w = lds_elems / (2 * nj * (int64_t)r);
+    return (int)(w > 1 ? w : 1);
+}
+
 // One-sided Jacobi SVD of the r x r column-major matrix M (global), in place:
 // on exit the columns of M J are mutually orthogonal, M J = P S.  With WITHJ
 // the rotations are also applied to J (global, identity on entry), giving
@@ -234,23 +263,7 @@ __device__ void jacobi_svd(cplx<double> *M, cplx<double> *J, int r, cplx<double>
     const double tol = fmax(1e-14, 4.0 * r * 1.1e-16);
     const int tid = threadIdx.x;
     constexpr int NJ = WITHJ ? 2 : 1;
-    // |M|_F^2 (invariant under the rotations) sets the negligible column norm
-    __shared__ double sh_nrm[16];
-    {
-        double v = 0;
-        for (int64_t q = tid; q < (int64_t)r * r; q += blockDim.x) v += abs2(M[q]);
-        v = wave_sumd(v);
-        if (tid % 64 == 0) sh_nrm[tid / 64] = v;
-        __syncthreads();
-        if (tid == 0) {
-            double t = 0;
-            for (int w = 0; w < (int)blockDim.x / 64; ++w) t += sh_nrm[w];
-            sh_nrm[0] = t;
-        }
-        __syncthreads();
-    }
-    const double tiny = r * (2.3e-16 * 2.3e-16) * sh_nrm[0];
-    __syncthreads();   // sh_nrm is read before any later reuse
+    const double tiny = jacobi_tiny(M, r);
     if (NJ * (int64_t)r * r <= lds_elems) {
         cplx<double> *ldj = lds + (int64_t)r * r;
         for (int64_t q = tid; q < (int64_t)r * r; q += blockDim.x) {
@@ -267,7 +280,7 @@ __device__ void jacobi_svd(cplx<double> *M, cplx<double> *J, int r, cplx<double>
         __syncthreads();
         return;
     }
-    const int bw = (int)max<int64_t>(1, lds_elems / (2 * NJ * (int64_t)r));
+    const int bw = jacobi_bw(r, lds_elems, NJ);
     const int nb = (r + bw - 1) / bw;
     const int ne = (nb + 1) & ~1;
     cplx<double> *ldj = lds + 2 * (int64_t)bw * r;
@@ -345,13 +358,18 @@ __device__ void small_gemm(int mC, int nC, int K, FA fa, FB fb, FC fc, cplx<doub
     __syncthreads();
 }
 
-template <typename R, int NT>
+// PHASE 0 runs the whole factorisation of a block in one workgroup.  Blocks
+// whose core does not fit in LDS split it: PHASE 1 stops once the core M and
+// its negligible column norm (tiny[blockIdx.x]) are formed, the block Jacobi
+// sweeps then run as one launch per round over all such blocks
+// (jacobi_round_kernel), and PHASE 2 continues from the rotated core.
+template <typename R, int NT, int PHASE>
 __global__ void __launch_bounds__(NT) factor_kernel(const RcBlk *__restrict__ blks,
                                                      const int32_t *__restrict__ order,
                                                      cplx<double> *__restrict__ work,
                                                      int32_t *__restrict__ newrank, double eps,
-                                                     int64_t lds_elems) {
-    extern __shared__ unsigned char smem_raw[];
+                                                     int64_t lds_elems, double *__restrict__ tiny) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     cplx<double> *lds = reinterpret_cast<cplx<double> *>(smem_raw);
     __shared__ double sh_s[1];
     __shared__ int sh_i[4];
@@ -360,7 +378,7 @@ __global__ void __launch_bounds__(NT) factor_kernel(const RcBlk *__restrict__ bl
     const int r = b.r;
     const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
     if (r == 0) {
-        if (tid == 0) newrank[bi] = 0;
+        if (tid == 0 && PHASE != 2) newrank[bi] = 0;
         return;
     }
     cplx<double> *W = work + b.goff;
@@ -372,6 +390,7 @@ __global__ void __launch_bounds__(NT) factor_kernel(const RcBlk *__restrict__ bl
     double *sv = dv + r;
     int *idx = reinterpret_cast<int *>(sv + r);
     // Column equilibration: G~ = D^-1 G D^-1, D = sqrt(diag G).
+    if (PHASE != 2) {
     for (int k = tid; k < r; k += NT) {
         const double a = sqrt(fmax(RU[k + (int64_t)k * r].re, 0.0));
         const double c = sqrt(fmax(RV[k + (int64_t)k * r].re, 0.0));
@@ -399,6 +418,7 @@ __global__ void __launch_bounds__(NT) factor_kernel(const RcBlk *__restrict__ bl
         } else {
             chol_upper(G, r, ctol, sh_s);
         }
+    }
     }
     // core M = R_U D R_V^*, D = du dv (the block is U~ D V~^*), written to dst
     auto form_core = [&](cplx<double> *dst) {
@@ -450,8 +470,16 @@ __global__ void __launch_bounds__(NT) factor_kernel(const RcBlk *__restrict__ bl
         __syncthreads();
         return sh_i[1];
     };
-    form_core(M);
-    jacobi_svd<false>(M, nullptr, r, lds, lds_elems, &sh_i[0]);
+    if (PHASE == 1) {
+        form_core(M);
+        const double t = jacobi_tiny(M, r);
+        if (tid == 0) tiny[blockIdx.x] = t;
+        return;
+    }
+    if (PHASE == 0) {
+        form_core(M);
+        jacobi_svd<false>(M, nullptr, r, lds, lds_elems, &sh_i[0]);
+    }
     int keep = rank_and_keep();
     // Right singular vectors: L = M0^* P S^-1 from the unrotated core M0 has an
     // error of order u s_1 / s_c, harmless unless a kept singular value is far
@@ -496,6 +524,55 @@ __global__ void __launch_bounds__(NT) factor_kernel(const RcBlk *__restrict__ bl
         },
         lds);
     if (tid == 0) newrank[bi] = keep;
+}
+
+// One round of the block Jacobi sweep of every split block: task t pairs
+// the column blocks bi and bj of block order[slot]; the pairs of one round
+// are disjoint, so running them side by side gives what the one-workgroup
+// sweep computes.  rotated[slot] is set when any pair rotated.
+struct JacTask {
+    int32_t slot, bi, bj, pad;
+};
+
+__global__ void __launch_bounds__(1024) jacobi_round_kernel(const RcBlk *__restrict__ blks,
+                                                            const int32_t *__restrict__ order,
+                                                            const JacTask *__restrict__ tasks,
+                                                            cplx<double> *__restrict__ work,
+                                                            const double *__restrict__ tiny,
+                                                            const int32_t *__restrict__ active,
+                                                            int32_t *__restrict__ rotated,
+                                                            int64_t lds_elems) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+    cplx<double> *lds = reinterpret_cast<cplx<double> *>(smem_raw);
+    __shared__ int sh_flag;
+    const JacTask t = tasks[blockIdx.x];
+    if (!active[t.slot]) return;   // the block converged in an earlier sweep
+    const RcBlk b = blks[order[t.slot]];
+    const int r = b.r;
+    cplx<double> *M = work + b.goff + rc_slot(r, 2);
+    const double tol = fmax(1e-14, 4.0 * r * 1.1e-16);
+    const int bw = jacobi_bw(r, lds_elems, 1);
+    const int c0 = t.bi * bw, n0 = min(bw, r - c0);
+    const int c1 = t.bj * bw, n1 = min(bw, r - c1);
+    const int nc = n0 + n1;
+    for (int64_t q = threadIdx.x; q < (int64_t)nc * r; q += blockDim.x) {
+        const int cc = (int)(q / r), i = (int)(q % r);
+        const int col = cc < n0 ? c0 + cc : c1 + (cc - n0);
+        lds[q] = M[(int64_t)col * r + i];
+    }
+    __syncthreads();
+    const bool any = lds_sweep<false>(lds, nullptr, nc, r, tol, tiny[t.slot], &sh_flag);
+    for (int64_t q = threadIdx.x; q < (int64_t)nc * r; q += blockDim.x) {
+        const int cc = (int)(q / r), i = (int)(q % r);
+        const int col = cc < n0 ? c0 + cc : c1 + (cc - n0);
+        M[(int64_t)col * r + i] = lds[q];
+    }
+    if (any && threadIdx.x == 0) rotated[t.slot] = 1;
+}
+
+// Position -> column block of the round-robin tournament (host twin of rr_slot).
+inline int rr_slot_host(int pos, int round, int n) {
+    return pos == 0 ? 0 : 1 + (pos - 1 + round) % (n - 1);
 }
 
 // U' = U W_U (3m x keep), V' = V W_V (3n x keep) into the compact slab, one
@@ -545,6 +622,82 @@ __global__ void __launch_bounds__(256) apply_kernel(const RcBlk *__restrict__ bl
         sh);
 }
 
+// Factorisation of the blocks order[q0, q1) whose r x r core exceeds the LDS:
+// the core is formed per block (one workgroup each), the block Jacobi sweeps
+// run as one launch per tournament round over all of these blocks, with a
+// 4-byte-per-block readback after every sweep to retire converged blocks,
+// and the truncation and update matrices follow per block.  The sequence of
+// rotations applied to each block is the one the one-workgroup sweep applies.
+template <typename R>
+static void split_jacobi(const std::vector<RcBlk> &blk, const std::vector<int32_t> &order,
+                         size_t q0, size_t q1, const RcBlk *d_blk, const int32_t *d_order,
+                         double *work, int32_t *d_newrank, double eps, size_t bytes,
+                         int64_t lds_elems, hipStream_t st) {
+    const int nbig = (int)(q1 - q0);
+    auto *W = reinterpret_cast<cplx<double> *>(work);
+    DeviceBuf d_tiny, d_active, d_rot, d_tasks;
+    d_tiny.alloc(nbig * sizeof(double));
+    d_active.alloc(nbig * sizeof(int32_t));
+    d_rot.alloc(nbig * sizeof(int32_t));
+    hipLaunchKernelGGL((factor_kernel<R, 1024, 1>), dim3((unsigned)nbig), dim3(1024), bytes, st,
+                       d_blk, d_order + q0, W, d_newrank, eps, lds_elems, d_tiny.as<double>());
+    HM_HIP_CHECK(hipGetLastError());
+    // tournament rounds of every block; round t of all blocks in one list
+    std::vector<std::vector<JacTask>> rounds;
+    for (int s = 0; s < nbig; ++s) {
+        const int r = blk[order[q0 + s]].r;
+        if (r == 0) continue;
+        const int bw = jacobi_bw(r, lds_elems, 1);
+        const int nb = (r + bw - 1) / bw;
+        const int ne = (nb + 1) & ~1;
+        if ((int)rounds.size() < ne - 1) rounds.resize(ne - 1);
+        for (int t = 0; t < ne - 1; ++t)
+            for (int pr = 0; pr < ne / 2; ++pr) {
+                const int bi = rr_slot_host(pr, t, ne), bj = rr_slot_host(ne - 1 - pr, t, ne);
+                if (bi < nb && bj < nb) rounds[t].push_back({s, bi, bj, 0});
+            }
+    }
+    std::vector<JacTask> all;
+    std::vector<size_t> t0;
+    for (const auto &rt : rounds) {
+        t0.push_back(all.size());
+        all.insert(all.end(), rt.begin(), rt.end());
+    }
+    std::vector<int32_t> active(nbig), rot(nbig);
+    for (int s = 0; s < nbig; ++s) active[s] = blk[order[q0 + s]].r > 0;
+    if (!all.empty()) {
+        d_tasks.alloc(all.size() * sizeof(JacTask));
+        HM_HIP_CHECK(hipMemcpyAsync(d_tasks.p, all.data(), all.size() * sizeof(JacTask),
+                                    hipMemcpyHostToDevice, st));
+        for (int sweep = 0; sweep < 30; ++sweep) {
+            HM_HIP_CHECK(hipMemcpyAsync(d_active.p, active.data(), nbig * sizeof(int32_t),
+                                        hipMemcpyHostToDevice, st));
+            HM_HIP_CHECK(hipMemsetAsync(d_rot.p, 0, nbig * sizeof(int32_t), st));
+            for (size_t t = 0; t < rounds.size(); ++t)
+                if (!rounds[t].empty())
+                    hipLaunchKernelGGL(jacobi_round_kernel, dim3((unsigned)rounds[t].size()),
+                                       dim3(1024), bytes, st, d_blk, d_order + q0,
+                                       d_tasks.as<JacTask>() + t0[t], W, d_tiny.as<double>(),
+                                       d_active.as<int32_t>(), d_rot.as<int32_t>(), lds_elems);
+            HM_HIP_CHECK(hipGetLastError());
+            HM_HIP_CHECK(hipMemcpyAsync(rot.data(), d_rot.p, nbig * sizeof(int32_t),
+                                        hipMemcpyDeviceToHost, st));
+            HM_HIP_CHECK(hipStreamSynchronize(st));
+            bool any = false;
+            for (int s = 0; s < nbig; ++s) {
+                active[s] = active[s] && rot[s];
+                any = any || active[s];
+            }
+            if (!any) break;
+        }
+    }
+    hipLaunchKernelGGL((factor_kernel<R, 1024, 2>), dim3((unsigned)nbig), dim3(1024), bytes, st,
+                       d_blk, d_order + q0, W, d_newrank, eps, lds_elems, nullptr);
+    HM_HIP_CHECK(hipGetLastError());
+    // the host vectors above outlive their copies
+    HM_HIP_CHECK(hipStreamSynchronize(st));
+}
+
 template <typename R>
 void run_recompress(const std::vector<RcBlk> &blk, RcBlk *d_blk, const cplx<R> *acaslab,
                     double *work, int32_t *d_newrank, double eps, int32_t rmax, hipStream_t st,
@@ -590,10 +743,14 @@ void run_recompress(const std::vector<RcBlk> &blk, RcBlk *d_blk, const cplx<R> *
             v = 65536;
         max_lds = std::min(v, 160 * 1024) - 1024;
         if (max_lds > 65536) {
-            HM_HIP_CHECK(hipFuncSetAttribute((const void *)factor_kernel<R, 256>,
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, max_lds));
-            HM_HIP_CHECK(hipFuncSetAttribute((const void *)factor_kernel<R, 1024>,
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, max_lds));
+            const void *kerns[] = {(const void *)factor_kernel<R, 256, 0>,
+                                   (const void *)factor_kernel<R, 1024, 0>,
+                                   (const void *)factor_kernel<R, 1024, 1>,
+                                   (const void *)factor_kernel<R, 1024, 2>,
+                                   (const void *)jacobi_round_kernel};
+            for (const void *k : kerns)
+                HM_HIP_CHECK(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                 max_lds));
         }
     }
     std::vector<int32_t> order(blk.size());
@@ -614,6 +771,10 @@ void run_recompress(const std::vector<RcBlk> &blk, RcBlk *d_blk, const cplx<R> *
         HM_HIP_CHECK(hipEventRecord(ev_ready.e, st));   // gram products and d_order are queued
         HM_HIP_CHECK(hipStreamWaitEvent(side, ev_ready.e, 0));
     }
+    struct {
+        size_t q0 = 0, q1 = 0, bytes = 0;
+        int64_t lds_elems = 0;
+    } split;
     size_t q0 = 0;
     while (q0 < order.size()) {
         const int rmax = blk[order[q0]].r;
@@ -629,22 +790,29 @@ void run_recompress(const std::vector<RcBlk> &blk, RcBlk *d_blk, const cplx<R> *
         const int64_t lds_elems = bytes / (int64_t)sizeof(cplx<double>);
         // ranks above 64 leave room for one workgroup per CU (LDS): give it
         // 1024 threads (more lanes per Jacobi pair and per Cholesky column)
-        auto kern = rmax > 64 ? factor_kernel<R, 1024> : factor_kernel<R, 256>;
+        auto kern = rmax > 64 ? factor_kernel<R, 1024, 0> : factor_kernel<R, 256, 0>;
         const unsigned nt = rmax > 64 ? 1024u : 256u;
         if (unbatched) {
             for (size_t q = q0; q < q1; ++q)
                 hipLaunchKernelGGL(kern, dim3(1), dim3(nt), (size_t)bytes, st, d_blk,
                                    d_order.as<int32_t>() + q,
                                    reinterpret_cast<cplx<double> *>(work), d_newrank, eps,
-                                   lds_elems);
-        } else {
+                                   lds_elems, nullptr);
+        } else if ((int64_t)rmax * rmax <= lds_elems) {
             hipLaunchKernelGGL(kern, dim3((unsigned)(q1 - q0)), dim3(nt), (size_t)bytes,
                                rmax > 64 ? st : side, d_blk, d_order.as<int32_t>() + q0,
-                               reinterpret_cast<cplx<double> *>(work), d_newrank, eps, lds_elems);
+                               reinterpret_cast<cplx<double> *>(work), d_newrank, eps, lds_elems,
+                               nullptr);
+        } else {
+            // after the other classes are queued: its host loop waits on the GPU
+            split = {q0, q1, (size_t)bytes, lds_elems};
         }
         HM_HIP_CHECK(hipGetLastError());
         q0 = q1;
     }
+    if (split.q1 > split.q0)
+        split_jacobi<R>(blk, order, split.q0, split.q1, d_blk, d_order.as<int32_t>(), work,
+                        d_newrank, eps, split.bytes, split.lds_elems, st);
     if (!unbatched) {
         HM_HIP_CHECK(hipEventRecord(ev_done.e, side));
         HM_HIP_CHECK(hipStreamWaitEvent(st, ev_done.e, 0));

@@ -67,20 +67,31 @@ def test_graph_replays_match_eager(hm, prec, nrhs):
     assert torch.equal(y2, yg)
 
 
-@pytest.mark.parametrize("which", ["sphere_c64", "cube_T_c64", "sphere_c128"])
+@pytest.mark.parametrize("which", ["sphere_c64", "cube_T_c64", "sphere_c128", "bigrank_c64",
+                                   "bigrank_c128"])
 def test_unbatched_assembly_is_bit_identical(hm, which):
-    """Per-block launches run the same kernels on the same blocks: identical factors."""
+    """Per-block launches run the same kernels on the same blocks: identical factors.
+    The bigrank cases have ACA ranks above 100, whose cores the batched build
+    factorises with one launch per Jacobi round over many workgroups, and the
+    per-block build inside one workgroup."""
     say(f"case unbatched {which}")
     if which == "cube_T_c64":
         P, Nrm = W.cube_surface(2000, seed=3)
         w = W.Workload("cube2k", 2000, 1, omega=1.1547, eps=1e-4, leaf=32,
                        self_re=W._t_self(W.CUBE_AREA, 2000), geometry="cube")
         X, N, prec = P, Nrm, 1
+    elif which.startswith("bigrank"):
+        w = W.small_sphere(4000, omega=25.0, leaf=32, eps=1e-4)
+        X, _ = w.points()
+        N, prec = None, (1 if which.endswith("c64") else 0)
     else:
         w = W.small_sphere(1500, omega=7.0, leaf=24, eps=1e-5)
         X, _ = w.points()
         N, prec = None, (1 if which == "sphere_c64" else 0)
     H0 = hm.build_workload(w, X=X, N=N, prec=prec)
+    if which.startswith("bigrank"):
+        say("max ACA rank", H0.info()["max_rank_aca"])
+        assert H0.info()["max_rank_aca"] > 100
     H1 = hm.build_workload(w, X=X, N=N, prec=prec, unbatched=True)
     same_blocks(H0, H1)
 
