@@ -82,6 +82,63 @@ __device__ inline Inv3 invariants3(const cplx<double> M[9]) {
     return {fmax(t, 0.0) * mx * mx, e1 * mx * mx};
 }
 
+// Squared singular values of a 3x3 complex matrix, descending: the roots of
+// t^3 - e1 t^2 + e2 t - e3 (e1 = |M|_F^2, e2 = sum of squared 2x2 minors,
+// e3 = |det M|^2, the characteristic polynomial of M^* M), the smallest by
+// Newton from 0 as in invariants3, the largest by Newton from e1 (an upper
+// bound, where the cubic is convex), the middle one from the trace.
+__device__ inline void sv3_squares(const cplx<double> M[9], double lam[3]) {
+    double mx = 0;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) mx = fmax(mx, fmax(fabs(M[k].re), fabs(M[k].im)));
+    lam[0] = lam[1] = lam[2] = 0.0;
+    if (mx == 0.0) return;
+    const double sc = 1.0 / mx;
+    cplx<double> a[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) a[k] = sc * M[k];
+    double e1 = 0;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) e1 += abs2(a[k]);
+    const cplx<double> c00 = a[4] * a[8] - a[5] * a[7];
+    const cplx<double> c01 = a[5] * a[6] - a[3] * a[8];
+    const cplx<double> c02 = a[3] * a[7] - a[4] * a[6];
+    const cplx<double> c10 = a[2] * a[7] - a[1] * a[8];
+    const cplx<double> c11 = a[0] * a[8] - a[2] * a[6];
+    const cplx<double> c12 = a[1] * a[6] - a[0] * a[7];
+    const cplx<double> c20 = a[1] * a[5] - a[2] * a[4];
+    const cplx<double> c21 = a[2] * a[3] - a[0] * a[5];
+    const cplx<double> c22 = a[0] * a[4] - a[1] * a[3];
+    const double e2 = abs2(c00) + abs2(c01) + abs2(c02) + abs2(c10) + abs2(c11) + abs2(c12) +
+                      abs2(c20) + abs2(c21) + abs2(c22);
+    const cplx<double> det = a[0] * c00 + a[1] * c01 + a[2] * c02;
+    const double e3 = abs2(det);
+    double lo = 0.0, hi = e1;
+    for (int it = 0; it < 16; ++it) {
+        const double p = ((lo - e1) * lo + e2) * lo - e3;
+        const double dp = (3.0 * lo - 2.0 * e1) * lo + e2;
+        if (!(dp > 0.0)) break;
+        const double dt = p / dp;
+        lo -= dt;
+        if (fabs(dt) <= 1e-15 * lo) break;
+    }
+    for (int it = 0; it < 32; ++it) {
+        const double p = ((hi - e1) * hi + e2) * hi - e3;
+        const double dp = (3.0 * hi - 2.0 * e1) * hi + e2;
+        if (!(dp > 0.0)) break;
+        const double dt = p / dp;
+        hi -= dt;
+        if (fabs(dt) <= 1e-15 * hi) break;
+    }
+    lo = fmax(lo, 0.0);
+    hi = fmax(hi, lo);
+    const double mid = fmin(fmax(e1 - hi - lo, lo), hi);
+    const double s2 = mx * mx;
+    lam[0] = hi * s2;
+    lam[1] = mid * s2;
+    lam[2] = lo * s2;
+}
+
 // Candidate comparison: larger value wins, ties -> smaller index.
 __device__ inline void cand_better(double &v, int &i, double v2, int i2) {
     if (v2 > v || (v2 == v && i2 < i)) {
@@ -427,14 +484,10 @@ __global__ void __launch_bounds__(NT)
         if (tid == 0) {
             cplx<double> M[9], G[9], Z[9];
             for (int e = 0; e < 9; ++e) M[e] = sh_W[e];
-            for (int a = 0; a < 3; ++a)
-                for (int c = 0; c < 3; ++c) {
-                    cplx<double> s = {0, 0};
-                    for (int k = 0; k < 3; ++k) s = s + cmul(M[3 * k + a], M[3 * k + c]);
-                    G[3 * a + c] = s;
-                }
+            // singular values from the characteristic cubic; the eigenvectors
+            // of M^* M are needed only when M is numerically singular
             double lam[3];
-            herm3_eig(G, lam, Z);
+            sv3_squares(M, lam);
             const double s1 = sqrt(fmax(lam[0], 0.0));
             // singular values at or below the rounding-noise floor of the
             // entries (nu |A(i, j)|_F) do not count as pivot directions
@@ -466,6 +519,21 @@ __global__ void __launch_bounds__(NT)
                 sh_ctl[2] = 0;
                 sh_ctl[3] = 3;
             } else {
+                for (int a = 0; a < 3; ++a)
+                    for (int c = 0; c < 3; ++c) {
+                        cplx<double> s = {0, 0};
+                        for (int k = 0; k < 3; ++k) s = s + cmul(M[3 * k + a], M[3 * k + c]);
+                        G[3 * a + c] = s;
+                    }
+                herm3_eig(G, lam, Z);
+                // the pivot directions counted again from the eigenvalues that
+                // go with Z
+                const double fl = fmax(tau_piv * sqrt(fmax(lam[0], 0.0)), sqrt(nu2) * sh_anorm);
+                p = 0;
+                for (int k = 0; k < 3; ++k) {
+                    sv[k] = sqrt(fmax(lam[k], 0.0));
+                    if (sv[k] > fl) ++p;
+                }
                 if (p == 0) p = 1;  // best.fro > 0 guarantees sigma_1 > 0
                 for (int c = 0; c < 3; ++c) {
                     const double is = c < p ? 1.0 / sv[c] : 0.0;
