@@ -29,15 +29,16 @@
 // would otherwise blow the update up.
 // A residual row that vanishes on all unused columns marks the row used and
 // moves to the next unused row without adding a term.
+#include <algorithm>
 #include <climits>
+#include <type_traits>
+#include <vector>
 
 #include "internal.hpp"
 
 namespace hm {
 
 constexpr int kAcaThreads = 256;      // workgroup of an ordinary block
-constexpr int kAcaBigThreads = 512;   // workgroup of a block with many points
-constexpr int kAcaBigPoints = 1500;   // m + n from which a block counts as big
 
 struct Inv3 {
     double s3sq, fro2;
@@ -249,8 +250,8 @@ __device__ inline void halve(const double (&v)[V], double (&o)[V / 2], int off, 
     }
 }
 
-// Gram of old and new factor columns, computed by one wave over all rows:
-// entry (u, c) = sum over points idx < npts and components a of
+// Gram of old and new factor columns, computed by one wave over the points
+// p0 <= idx < p1: entry (u, c) = sum over those points and components a of
 // conj(X[3 idx + a, l0 + u]) X[3 idx + a, base + c], for u < 4 (l0 + u <
 // lmax) and c < 3; products and the sum over a in R, the sum over points in
 // FP64.  X is column-major with leading dimension ld.  The 24 doubles
@@ -263,12 +264,12 @@ __device__ inline int gram_vbase(int lane) {
 }
 
 template <typename R>
-__device__ inline void gram_wave(const cplx<R> *X, int64_t ld, int npts, int l0, int lmax,
+__device__ inline void gram_wave(const cplx<R> *X, int64_t ld, int p0, int p1, int l0, int lmax,
                                  int base, int lane, double (&out)[3]) {
     double part[24];
 #pragma unroll
     for (int k = 0; k < 24; ++k) part[k] = 0.0;
-    for (int idx = lane; idx < npts; idx += 64) {
+    for (int idx = p0 + lane; idx < p1; idx += 64) {
         R acc[24];
 #pragma unroll
         for (int k = 0; k < 24; ++k) acc[k] = R(0);
@@ -302,6 +303,127 @@ __device__ inline void gram_wave(const cplx<R> *X, int64_t ld, int npts, int l0,
     for (int k = 0; k < 3; ++k)
 #pragma unroll
         for (int o = 4; o > 0; o >>= 1) out[k] += __shfl_xor(out[k], o, 64);
+}
+
+// Residual row entries of column point j (local index; pj in cluster order):
+// the 3x3 block K = A(i^, j) - U(i^, :) V(j, :)^* with the pivot row of U
+// staged in piv (3 x r, row a at piv + a r), written into the next three
+// columns of V as conj(K); an unused j is offered as a column pivot.
+template <typename R>
+__device__ inline void row_point(const Geometry &g, const GreenParams<R> &gp, bool isT, double xi0,
+                                 double xi1, double xi2, int pj, int j, const cplx<R> *piv,
+                                 cplx<R> *V, int64_t ldv, int r, bool unused, double nu2,
+                                 Best2 &best) {
+    cplx<R> K[9];
+    R nx = 0, ny = 0, nz = 0;
+    if (isT) {
+        nx = R(g.n[0][pj]);
+        ny = R(g.n[1][pj]);
+        nz = R(g.n[2][pj]);
+    }
+    green_block<R>(gp, xi0 - g.y[0][pj], xi1 - g.y[1][pj], xi2 - g.y[2][pj], nx, ny, nz, K);
+    double a2 = 0.0;   // |A(i, j)|_F^2 before the update: scale of the rounding noise
+#pragma unroll
+    for (int e = 0; e < 9; ++e) a2 += (double)abs2(K[e]);
+    const cplx<R> *vrow = V + 3 * j;
+    int l = 0;
+    for (; l + 4 <= r; l += 4) {
+        cplx<R> vv[4][3];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int be = 0; be < 3; ++be) vv[u][be] = vrow[(l + u) * ldv + be];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const cplx<R> uu = piv[a * r + l + u];
+#pragma unroll
+                for (int be = 0; be < 3; ++be) fms_conj(K[3 * a + be], uu, vv[u][be]);
+            }
+    }
+    for (; l < r; ++l) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const cplx<R> uu = piv[a * r + l];
+#pragma unroll
+            for (int be = 0; be < 3; ++be) fms_conj(K[3 * a + be], uu, vrow[l * ldv + be]);
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        cplx<R> *vn = V + (r + a) * ldv + 3 * j;
+#pragma unroll
+        for (int be = 0; be < 3; ++be) vn[be] = conj(K[3 * a + be]);
+    }
+    if (unused) {
+        cplx<double> Md[9];
+#pragma unroll
+        for (int e = 0; e < 9; ++e) Md[e] = cvt<double>(K[e]);
+        const Inv3 iv = invariants3(Md);
+        cand_better(best.s3, best.i3, iv.s3sq > nu2 * a2 ? iv.s3sq : 0.0, j);
+        cand_better(best.fro, best.ifro, iv.fro2, j);
+    }
+}
+
+// Residual column entries of row point i (local index; pii in cluster order):
+// K = A(i, j^) - U(i, :) V(j^, :)^* with the pivot row of V staged in piv
+// (3 x r); an unused i is offered as the next row pivot, and the new U rows
+// 3i + a get K T (T: M^-1 or Z_p Sigma_p^-1; columns c >= p are zero).
+template <typename R>
+__device__ inline void col_point(const Geometry &g, const GreenParams<R> &gp, int pii, double yj0,
+                                 double yj1, double yj2, R njx, R njy, R njz, int i,
+                                 const cplx<R> *piv, cplx<R> *U, int64_t ldu, int r, int p,
+                                 const cplx<double> *T, bool unused, double nu2, Best2 &best) {
+    cplx<R> K[9];
+    green_block<R>(gp, g.x[0][pii] - yj0, g.x[1][pii] - yj1, g.x[2][pii] - yj2, njx, njy, njz,
+                   K);
+    double a2 = 0.0;
+#pragma unroll
+    for (int e = 0; e < 9; ++e) a2 += (double)abs2(K[e]);
+    const cplx<R> *urow = U + 3 * i;
+    int l = 0;
+    for (; l + 4 <= r; l += 4) {
+        cplx<R> uu[4][3];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) uu[u][a] = urow[(l + u) * ldu + a];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int be = 0; be < 3; ++be) {
+                const cplx<R> v = piv[be * r + l + u];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) fms_conj(K[3 * a + be], uu[u][a], v);
+            }
+    }
+    for (; l < r; ++l) {
+#pragma unroll
+        for (int be = 0; be < 3; ++be) {
+            const cplx<R> v = piv[be * r + l];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) fms_conj(K[3 * a + be], urow[l * ldu + a], v);
+        }
+    }
+    if (unused) {
+        cplx<double> Md[9];
+#pragma unroll
+        for (int e = 0; e < 9; ++e) Md[e] = cvt<double>(K[e]);
+        const Inv3 iv = invariants3(Md);
+        cand_better(best.s3, best.i3, iv.s3sq > nu2 * a2 ? iv.s3sq : 0.0, i);
+        cand_better(best.fro, best.ifro, iv.fro2, i);
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        cplx<double> kd[3];
+#pragma unroll
+        for (int be = 0; be < 3; ++be) kd[be] = cvt<double>(K[3 * a + be]);
+        for (int c = 0; c < 3; ++c) {
+            const cplx<double> s = kd[0] * T[0 * 3 + c] + kd[1] * T[1 * 3 + c] + kd[2] * T[2 * 3 + c];
+            U[(r + c) * ldu + 3 * i + a] = cvt<R>(c < p ? s : cplx<double>{0, 0});
+        }
+    }
 }
 
 template <typename R, int NT>
@@ -362,60 +484,9 @@ __global__ void __launch_bounds__(NT)
         const int pi = b.rb + ih;
         const double xi0 = g.x[0][pi], xi1 = g.x[1][pi], xi2 = g.x[2][pi];
         Best2 best = {-1.0, INT_MAX, -1.0, INT_MAX};
-        for (int j = tid; j < n; j += NT) {
-            const int pj = b.cb + j;
-            cplx<R> K[9];
-            R nx = 0, ny = 0, nz = 0;
-            if (isT) {
-                nx = R(g.n[0][pj]);
-                ny = R(g.n[1][pj]);
-                nz = R(g.n[2][pj]);
-            }
-            green_block<R>(gp, xi0 - g.y[0][pj], xi1 - g.y[1][pj], xi2 - g.y[2][pj], nx,
-                           ny, nz, K);
-            double a2 = 0.0;   // |A(i, j)|_F^2 before the update: scale of the rounding noise
-#pragma unroll
-            for (int e = 0; e < 9; ++e) a2 += (double)abs2(K[e]);
-            const cplx<R> *vrow = V + 3 * j;
-            int l = 0;
-            for (; l + 4 <= r; l += 4) {
-                cplx<R> vv[4][3];
-#pragma unroll
-                for (int u = 0; u < 4; ++u)
-#pragma unroll
-                    for (int be = 0; be < 3; ++be) vv[u][be] = vrow[(l + u) * ldv + be];
-#pragma unroll
-                for (int u = 0; u < 4; ++u)
-#pragma unroll
-                    for (int a = 0; a < 3; ++a) {
-                        const cplx<R> uu = piv[a * r + l + u];
-#pragma unroll
-                        for (int be = 0; be < 3; ++be) fms_conj(K[3 * a + be], uu, vv[u][be]);
-                    }
-            }
-            for (; l < r; ++l) {
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    const cplx<R> uu = piv[a * r + l];
-#pragma unroll
-                    for (int be = 0; be < 3; ++be) fms_conj(K[3 * a + be], uu, vrow[l * ldv + be]);
-                }
-            }
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                cplx<R> *vn = V + (r + a) * ldv + 3 * j;
-#pragma unroll
-                for (int be = 0; be < 3; ++be) vn[be] = conj(K[3 * a + be]);
-            }
-            if (!used_j[j]) {
-                cplx<double> Md[9];
-#pragma unroll
-                for (int e = 0; e < 9; ++e) Md[e] = cvt<double>(K[e]);
-                const Inv3 iv = invariants3(Md);
-                cand_better(best.s3, best.i3, iv.s3sq > nu2 * a2 ? iv.s3sq : 0.0, j);
-                cand_better(best.fro, best.ifro, iv.fro2, j);
-            }
-        }
+        for (int j = tid; j < n; j += NT)
+            row_point<R>(g, gp, isT, xi0, xi1, xi2, b.cb + j, j, piv, V, ldv, r, !used_j[j], nu2,
+                         best);
         best = block_best2(best, sh_best);
         if (tid == 0) used_i[ih] = 1;
         if (best.ifro == INT_MAX) {  // no unused column left
@@ -449,7 +520,7 @@ __global__ void __launch_bounds__(NT)
         // pivot inverse publishes cv)
         for (int l0 = 4 * wave; l0 < r + 3; l0 += 4 * (NT / 64)) {
             double v3[3];
-            gram_wave<R>(V, ldv, n, l0, r + 3, r, lane, v3);
+            gram_wave<R>(V, ldv, 0, n, l0, r + 3, r, lane, v3);
             if ((lane & 7) == 0) {
                 const int vb = gram_vbase(lane);
                 for (int k = 0; k < 3; ++k) {
@@ -602,59 +673,9 @@ __global__ void __launch_bounds__(NT)
             njz = R(g.n[2][pj]);
         }
         best = {-1.0, INT_MAX, -1.0, INT_MAX};
-        for (int i = tid; i < m; i += NT) {
-            const int pii = b.rb + i;
-            cplx<R> K[9];
-            green_block<R>(gp, g.x[0][pii] - yj0, g.x[1][pii] - yj1, g.x[2][pii] - yj2,
-                           njx, njy, njz, K);
-            double a2 = 0.0;
-#pragma unroll
-            for (int e = 0; e < 9; ++e) a2 += (double)abs2(K[e]);
-            const cplx<R> *urow = U + 3 * i;
-            int l = 0;
-            for (; l + 4 <= r; l += 4) {
-                cplx<R> uu[4][3];
-#pragma unroll
-                for (int u = 0; u < 4; ++u)
-#pragma unroll
-                    for (int a = 0; a < 3; ++a) uu[u][a] = urow[(l + u) * ldu + a];
-#pragma unroll
-                for (int u = 0; u < 4; ++u)
-#pragma unroll
-                    for (int be = 0; be < 3; ++be) {
-                        const cplx<R> v = piv[be * r + l + u];
-#pragma unroll
-                        for (int a = 0; a < 3; ++a) fms_conj(K[3 * a + be], uu[u][a], v);
-                    }
-            }
-            for (; l < r; ++l) {
-#pragma unroll
-                for (int be = 0; be < 3; ++be) {
-                    const cplx<R> v = piv[be * r + l];
-#pragma unroll
-                    for (int a = 0; a < 3; ++a) fms_conj(K[3 * a + be], urow[l * ldu + a], v);
-                }
-            }
-            if (!used_i[i]) {
-                cplx<double> Md[9];
-#pragma unroll
-                for (int e = 0; e < 9; ++e) Md[e] = cvt<double>(K[e]);
-                const Inv3 iv = invariants3(Md);
-                cand_better(best.s3, best.i3, iv.s3sq > nu2 * a2 ? iv.s3sq : 0.0, i);
-                cand_better(best.fro, best.ifro, iv.fro2, i);
-            }
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                cplx<double> kd[3];
-#pragma unroll
-                for (int be = 0; be < 3; ++be) kd[be] = cvt<double>(K[3 * a + be]);
-                for (int c = 0; c < 3; ++c) {
-                    const cplx<double> s = kd[0] * sh_T[0 * 3 + c] + kd[1] * sh_T[1 * 3 + c] +
-                                           kd[2] * sh_T[2 * 3 + c];
-                    U[(r + c) * ldu + 3 * i + a] = cvt<R>(c < p ? s : cplx<double>{0, 0});
-                }
-            }
-        }
+        for (int i = tid; i < m; i += NT)
+            col_point<R>(g, gp, b.rb + i, yj0, yj1, yj2, njx, njy, njz, i, piv, U, ldu, r, p, sh_T,
+                         !used_i[i], nu2, best);
         best = block_best2(best, sh_best);
         int next_i = -1;
         if (best.ifro != INT_MAX)
@@ -666,7 +687,7 @@ __global__ void __launch_bounds__(NT)
             double cross = 0.0, fresh = 0.0;
             for (int l0 = 4 * wave; l0 < r + p; l0 += 4 * (NT / 64)) {
                 double v3[3];
-                gram_wave<R>(U, ldu, m, l0, r + p, r, lane, v3);
+                gram_wave<R>(U, ldu, 0, m, l0, r + p, r, lane, v3);
                 if ((lane & 7) == 0) {
                     const int vb = gram_vbase(lane);
                     for (int k = 0; k < 3; ++k) {
@@ -725,6 +746,572 @@ __global__ void __launch_bounds__(NT)
     }
 }
 
+// ---------------------------------------------------------------------------
+// Split form of the same greedy loop for blocks with many points: one ACA step
+// of all such blocks is a sequence of launches over many workgroups (residual
+// row, V Gram, pivot, V update, residual column, U Gram, step end), so that a
+// block with tens of thousands of rows is not confined to one CU.  Each step
+// takes the same decisions in the same order as the one-workgroup kernel; the
+// Gram columns are summed over fixed point slices (the order depends only on
+// the block), so a block gets the same factors whichever blocks share its
+// launches.
+constexpr int kSaTile = 256;     // points per workgroup of the residual passes
+constexpr int kSaSlice = 256;    // points per Gram slice (one wave per column chunk)
+
+struct SaState {
+    int32_t r, steps, status, fallbacks;   // status -1 while running, then as AcaOut
+    int32_t ih, jh, mode, p;
+    int32_t skip, pad0, pad1, pad2;        // skip: this step found a zero residual row
+    double norm2, anorm;
+    cplx<double> T[9], W[9];
+};
+
+struct SaBlk {
+    int64_t cvoff;            // 3 budget complex doubles of V Gram columns
+    int64_t vgoff, ugoff;     // Gram partials: [slice][chunk][24] doubles
+    int32_t rowt0, colt0;     // first residual tile of the block (row / column pass)
+    int32_t nchunk, pad;      // chunks of four columns per slice: ceil(budget / 4)
+};
+
+struct SaTask {
+    int32_t s, t;             // block (split list index) and tile or slice
+};
+
+__device__ inline bool sa_running(const SaState &st) { return st.status < 0 && !st.skip; }
+
+// Finishes the AcaOut record of a block that stopped.
+__device__ inline void sa_output(const SaState &st, AcaOut *o) {
+    AcaOut r;
+    r.rank = st.r;
+    r.status = st.status;
+    r.fallbacks = st.fallbacks;
+    r.steps = st.steps;
+    r.norm2 = st.norm2;
+    *o = r;
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256)
+    sa_init_kernel(const AcaBlk *__restrict__ blks, SaState *__restrict__ state,
+                   uint8_t *__restrict__ flags, AcaOut *__restrict__ outs) {
+    const AcaBlk b = blks[blockIdx.x];
+    uint8_t *f = flags + b.foff;
+    for (int k = threadIdx.x; k < b.m + b.n; k += blockDim.x) f[k] = 0;
+    if (threadIdx.x == 0) {
+        SaState st{};
+        st.status = b.budget < 3 ? 1 : -1;
+        state[blockIdx.x] = st;
+        if (st.status >= 0) sa_output(st, outs + blockIdx.x);
+    }
+}
+
+// Residual row pass, one workgroup per kSaTile column points.
+template <typename R>
+__global__ void __launch_bounds__(256)
+    sa_row_kernel(Geometry g, GreenParams<R> gp, const AcaBlk *__restrict__ blks,
+                  const SaState *__restrict__ state, const SaTask *__restrict__ tasks,
+                  cplx<R> *__restrict__ fac, const uint8_t *__restrict__ flags,
+                  Best2 *__restrict__ bests, const SaBlk *__restrict__ sab, double nu2) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+    cplx<R> *piv = reinterpret_cast<cplx<R> *>(smem_raw);
+    __shared__ Best2 sh_best[4];
+    const SaTask tk = tasks[blockIdx.x];
+    const SaState st = state[tk.s];
+    if (!sa_running(st)) return;
+    const AcaBlk b = blks[tk.s];
+    const int r = st.r, ih = st.ih, tid = threadIdx.x;
+    const int64_t ldu = 3 * (int64_t)b.m, ldv = 3 * (int64_t)b.n;
+    const cplx<R> *U = fac + b.uoff;
+    cplx<R> *V = fac + b.voff;
+    const uint8_t *used_j = flags + b.foff + b.m;
+    for (int k = tid; k < 3 * r; k += 256) {
+        const int a = k / r, l = k - a * r;
+        piv[a * r + l] = U[l * ldu + 3 * ih + a];
+    }
+    __syncthreads();
+    const int pi = b.rb + ih;
+    Best2 best = {-1.0, INT_MAX, -1.0, INT_MAX};
+    const int j = tk.t * kSaTile + tid;
+    if (j < b.n)
+        row_point<R>(g, gp, gp.kind == 1, g.x[0][pi], g.x[1][pi], g.x[2][pi], b.cb + j, j, piv, V,
+                     ldv, r, !used_j[j], nu2, best);
+    best = block_best2(best, sh_best);
+    if (tid == 0) bests[sab[tk.s].rowt0 + tk.t] = best;
+}
+
+// Gram partials of one point slice: wave w takes the column chunks w, w + 4,
+// ...; SIDE 0 is V against its three new columns (l < r + 3), SIDE 1 is U
+// against its p new columns (l < r + p).
+template <typename R, int SIDE>
+__global__ void __launch_bounds__(256)
+    sa_gram_kernel(const AcaBlk *__restrict__ blks, const SaState *__restrict__ state,
+                   const SaTask *__restrict__ tasks, const cplx<R> *__restrict__ fac,
+                   double *__restrict__ parts, const SaBlk *__restrict__ sab) {
+    const SaTask tk = tasks[blockIdx.x];
+    const SaState st = state[tk.s];
+    if (!sa_running(st)) return;
+    const AcaBlk b = blks[tk.s];
+    const SaBlk sb = sab[tk.s];
+    const int npts = SIDE == 0 ? b.n : b.m;
+    const int64_t ld = 3 * (int64_t)npts;
+    const cplx<R> *X = fac + (SIDE == 0 ? b.voff : b.uoff);
+    const int lmax = st.r + (SIDE == 0 ? 3 : st.p);
+    const int p0 = tk.t * kSaSlice, p1 = min(npts, p0 + kSaSlice);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    double *out = parts + (SIDE == 0 ? sb.vgoff : sb.ugoff) + (int64_t)tk.t * sb.nchunk * 24;
+    for (int c = wave; 4 * c < lmax; c += 4) {
+        double v3[3];
+        gram_wave<R>(X, ld, p0, p1, 4 * c, lmax, st.r, lane, v3);
+        if ((lane & 7) == 0) {
+            const int vb = gram_vbase(lane);
+            for (int k = 0; k < 3; ++k) out[c * 24 + vb + k] = v3[k];
+        }
+    }
+}
+
+// Sum of value v of chunk c over the slices of a Gram (slice order).
+__device__ inline double sa_gram_sum(const double *parts, int nslice, int nchunk, int c, int v) {
+    double t = 0.0;
+    for (int sl = 0; sl < nslice; ++sl) t += parts[((int64_t)sl * nchunk + c) * 24 + v];
+    return t;
+}
+
+// Column pivot of the step, one workgroup per block: the row pass's best
+// candidate, the V Gram columns, the pivot block's (pseudo-)inverse.
+template <typename R>
+__global__ void __launch_bounds__(256)
+    sa_pivot_kernel(Geometry g, GreenParams<R> gp, const AcaBlk *__restrict__ blks,
+                    SaState *__restrict__ state, const Best2 *__restrict__ bests,
+                    const double *__restrict__ parts, cplx<double> *__restrict__ cvall,
+                    cplx<R> *__restrict__ fac, uint8_t *__restrict__ flags,
+                    const SaBlk *__restrict__ sab, AcaOut *__restrict__ outs, double tau_piv,
+                    double nu2) {
+    __shared__ Best2 sh_best[4];
+    __shared__ cplx<double> sh_M[9], sh_W[9];
+    __shared__ double sh_out[24];
+    __shared__ double sh_anorm;
+    __shared__ int sh_mode, sh_p;
+    const int s = blockIdx.x, tid = threadIdx.x;
+    SaState st = state[s];
+    if (!sa_running(st)) return;
+    const AcaBlk b = blks[s];
+    const SaBlk sb = sab[s];
+    const int r = st.r, ih = st.ih, m = b.m, n = b.n;
+    const int64_t ldv = 3 * (int64_t)n;
+    cplx<R> *V = fac + b.voff;
+    uint8_t *used_i = flags + b.foff, *used_j = used_i + m;
+    const int ntile = (n + kSaTile - 1) / kSaTile;
+    Best2 best = {-1.0, INT_MAX, -1.0, INT_MAX};
+    for (int t = tid; t < ntile; t += 256) {
+        const Best2 c = bests[sb.rowt0 + t];
+        cand_better(best.s3, best.i3, c.s3, c.i3);
+        cand_better(best.fro, best.ifro, c.fro, c.ifro);
+    }
+    best = block_best2(best, sh_best);
+    if (tid == 0) used_i[ih] = 1;
+    if (best.ifro == INT_MAX) {   // no unused column left
+        if (tid == 0) {
+            st.status = 0;
+            state[s] = st;
+            sa_output(st, outs + s);
+        }
+        return;
+    }
+    if (best.fro == 0.0) {
+        // Zero residual row: the next unused row, no new term this step.
+        __syncthreads();
+        int cand = INT_MAX;
+        for (int i = tid; i < m; i += 256)
+            if (!used_i[i]) {
+                cand = i;
+                break;
+            }
+        const Best2 bb = block_best2({0.0, cand, 0.0, cand}, sh_best);
+        if (tid == 0) {
+            if (bb.i3 == INT_MAX) {
+                st.status = 0;
+                sa_output(st, outs + s);
+            } else {
+                st.ih = bb.i3;
+                st.skip = 1;
+            }
+            state[s] = st;
+        }
+        return;
+    }
+    const bool degenerate = best.s3 <= tau_piv * tau_piv * best.fro;
+    const int jh = degenerate ? best.ifro : best.i3;
+    // V Gram columns cv[l][c] = V[:, l]^* Vraw[:, r + c], l < r + 3
+    cplx<double> *cv = cvall + sb.cvoff;
+    const int nsl = (n + kSaSlice - 1) / kSaSlice;
+    for (int q = tid; q < 6 * (r + 3); q += 256) {
+        // double q of cv is value 6 (l % 4) + q % 6 of chunk l / 4, l = q / 6
+        const int l = q / 6;
+        reinterpret_cast<double *>(cv)[q] =
+            sa_gram_sum(parts + sb.vgoff, nsl, sb.nchunk, l / 4, 6 * (l % 4) + q % 6);
+    }
+    if (tid == 0) {
+        for (int a = 0; a < 3; ++a)
+            for (int be = 0; be < 3; ++be)
+                sh_M[3 * a + be] = cvt<double>(conj(V[(r + a) * ldv + 3 * jh + be]));
+        used_j[jh] = 1;
+        const int pi = b.rb + ih, pjh = b.cb + jh;
+        cplx<R> K[9];
+        R nx = 0, ny = 0, nz = 0;
+        if (gp.kind == 1) {
+            nx = R(g.n[0][pjh]);
+            ny = R(g.n[1][pjh]);
+            nz = R(g.n[2][pjh]);
+        }
+        green_block<R>(gp, g.x[0][pi] - g.y[0][pjh], g.x[1][pi] - g.y[1][pjh],
+                       g.x[2][pi] - g.y[2][pjh], nx, ny, nz, K);
+        double a2 = 0.0;
+        for (int e = 0; e < 9; ++e) a2 += (double)abs2(K[e]);
+        sh_anorm = sqrt(a2);
+        cplx<double> M[9], G[9], Z[9];
+        for (int e = 0; e < 9; ++e) M[e] = sh_M[e];
+        double lam[3];
+        sv3_squares(M, lam);
+        const double s1 = sqrt(fmax(lam[0], 0.0));
+        const double floor_s = fmax(tau_piv * s1, sqrt(nu2) * sh_anorm);
+        double sv[3];
+        int p = 0;
+        for (int k = 0; k < 3; ++k) {
+            sv[k] = sqrt(fmax(lam[k], 0.0));
+            if (sv[k] > floor_s) ++p;
+        }
+        if (p == 3) {
+            const cplx<double> c00 = M[4] * M[8] - M[5] * M[7];
+            const cplx<double> c01 = M[5] * M[6] - M[3] * M[8];
+            const cplx<double> c02 = M[3] * M[7] - M[4] * M[6];
+            const cplx<double> c10 = M[2] * M[7] - M[1] * M[8];
+            const cplx<double> c11 = M[0] * M[8] - M[2] * M[6];
+            const cplx<double> c12 = M[1] * M[6] - M[0] * M[7];
+            const cplx<double> c20 = M[1] * M[5] - M[2] * M[4];
+            const cplx<double> c21 = M[2] * M[3] - M[0] * M[5];
+            const cplx<double> c22 = M[0] * M[4] - M[1] * M[3];
+            const cplx<double> det = M[0] * c00 + M[1] * c01 + M[2] * c02;
+            const double dd = abs2(det);
+            const cplx<double> idet = {det.re / dd, -det.im / dd};
+            const cplx<double> C[9] = {c00, c01, c02, c10, c11, c12, c20, c21, c22};
+            for (int a = 0; a < 3; ++a)
+                for (int c = 0; c < 3; ++c) st.T[3 * a + c] = C[3 * c + a] * idet;
+            for (int e = 0; e < 9; ++e) st.W[e] = {e % 4 == 0 ? 1.0 : 0.0, 0.0};
+            st.mode = 0;
+            st.p = 3;
+        } else {
+            for (int a = 0; a < 3; ++a)
+                for (int c = 0; c < 3; ++c) {
+                    cplx<double> t = {0, 0};
+                    for (int k = 0; k < 3; ++k) t = t + cmul(M[3 * k + a], M[3 * k + c]);
+                    G[3 * a + c] = t;
+                }
+            herm3_eig(G, lam, Z);
+            const double fl = fmax(tau_piv * sqrt(fmax(lam[0], 0.0)), sqrt(nu2) * sh_anorm);
+            p = 0;
+            for (int k = 0; k < 3; ++k) {
+                sv[k] = sqrt(fmax(lam[k], 0.0));
+                if (sv[k] > fl) ++p;
+            }
+            if (p == 0) p = 1;  // best.fro > 0 guarantees sigma_1 > 0
+            for (int c = 0; c < 3; ++c) {
+                const double is = c < p ? 1.0 / sv[c] : 0.0;
+                for (int a = 0; a < 3; ++a) {
+                    st.T[3 * a + c] = is * Z[3 * a + c];
+                    cplx<double> w = {0, 0};
+                    for (int k = 0; k < 3; ++k) w = w + M[3 * a + k] * Z[3 * k + c];
+                    st.W[3 * a + c] = is * w;
+                }
+            }
+            st.mode = 1;
+            st.p = p;
+            ++st.fallbacks;
+        }
+        for (int e = 0; e < 9; ++e) sh_W[e] = st.W[e];
+        sh_mode = st.mode;
+        sh_p = st.p;
+        st.jh = jh;
+        st.anorm = sh_anorm;
+        state[s] = st;
+    }
+    __syncthreads();
+    if (sh_mode == 1) {
+        // cv[l][:] <- cv[l][:] W for old columns; the new-new block becomes W^* G W
+        for (int l = tid; l < r + 3; l += 256) {
+            cplx<double> row[3] = {cv[3 * l], cv[3 * l + 1], cv[3 * l + 2]};
+            for (int c = 0; c < 3; ++c) {
+                cplx<double> t = {0, 0};
+                for (int a = 0; a < 3; ++a) t = t + row[a] * sh_W[3 * a + c];
+                cv[3 * l + c] = t;
+            }
+        }
+        __syncthreads();
+        if (tid < 9) {
+            const int a = tid / 3, c = tid % 3;
+            cplx<double> t = {0, 0};
+            for (int k = 0; k < 3; ++k) t = t + cmul(sh_W[3 * k + a], cv[3 * (r + k) + c]);
+            sh_out[2 * tid] = t.re;
+            sh_out[2 * tid + 1] = t.im;
+        }
+        __syncthreads();
+        if (tid < 9) cv[3 * (r + tid / 3) + tid % 3] = {sh_out[2 * tid], sh_out[2 * tid + 1]};
+    }
+}
+
+// V_new = R_row^* W_p for blocks whose pivot fell back to the pseudo-inverse.
+template <typename R>
+__global__ void __launch_bounds__(256)
+    sa_vfix_kernel(const AcaBlk *__restrict__ blks, const SaState *__restrict__ state,
+                   const SaTask *__restrict__ tasks, cplx<R> *__restrict__ fac) {
+    const SaTask tk = tasks[blockIdx.x];
+    const SaState st = state[tk.s];
+    if (!sa_running(st) || st.mode != 1) return;
+    const AcaBlk b = blks[tk.s];
+    const int j = tk.t * kSaTile + threadIdx.x;
+    if (j >= b.n) return;
+    const int r = st.r, p = st.p;
+    const int64_t ldv = 3 * (int64_t)b.n;
+    cplx<R> *V = fac + b.voff;
+    cplx<double> v[3][3];
+    for (int a = 0; a < 3; ++a)
+        for (int be = 0; be < 3; ++be) v[a][be] = cvt<double>(V[(r + a) * ldv + 3 * j + be]);
+    for (int c = 0; c < 3; ++c)
+        for (int be = 0; be < 3; ++be) {
+            cplx<double> t = {0, 0};
+            if (c < p)
+                for (int a = 0; a < 3; ++a) t = t + v[a][be] * st.W[3 * a + c];
+            V[(r + c) * ldv + 3 * j + be] = cvt<R>(t);
+        }
+}
+
+// Residual column pass and U_new, one workgroup per kSaTile row points.
+template <typename R>
+__global__ void __launch_bounds__(256)
+    sa_col_kernel(Geometry g, GreenParams<R> gp, const AcaBlk *__restrict__ blks,
+                  const SaState *__restrict__ state, const SaTask *__restrict__ tasks,
+                  cplx<R> *__restrict__ fac, const uint8_t *__restrict__ flags,
+                  Best2 *__restrict__ bests, const SaBlk *__restrict__ sab, double nu2) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+    cplx<R> *piv = reinterpret_cast<cplx<R> *>(smem_raw);
+    __shared__ Best2 sh_best[4];
+    __shared__ cplx<double> sh_T[9];
+    const SaTask tk = tasks[blockIdx.x];
+    const SaState &gst = state[tk.s];
+    if (!sa_running(gst)) return;
+    const AcaBlk b = blks[tk.s];
+    const int r = gst.r, jh = gst.jh, p = gst.p, tid = threadIdx.x;
+    const int64_t ldu = 3 * (int64_t)b.m, ldv = 3 * (int64_t)b.n;
+    cplx<R> *U = fac + b.uoff;
+    const cplx<R> *V = fac + b.voff;
+    const uint8_t *used_i = flags + b.foff;
+    for (int k = tid; k < 3 * r; k += 256) {
+        const int be = k / r, l = k - be * r;
+        piv[be * r + l] = V[l * ldv + 3 * jh + be];
+    }
+    if (tid < 9) sh_T[tid] = gst.T[tid];
+    __syncthreads();
+    const int pj = b.cb + jh;
+    R njx = 0, njy = 0, njz = 0;
+    if (gp.kind == 1) {
+        njx = R(g.n[0][pj]);
+        njy = R(g.n[1][pj]);
+        njz = R(g.n[2][pj]);
+    }
+    Best2 best = {-1.0, INT_MAX, -1.0, INT_MAX};
+    const int i = tk.t * kSaTile + tid;
+    if (i < b.m)
+        col_point<R>(g, gp, b.rb + i, g.y[0][pj], g.y[1][pj], g.y[2][pj], njx, njy, njz, i, piv,
+                     U, ldu, r, p, sh_T, !used_i[i], nu2, best);
+    best = block_best2(best, sh_best);
+    if (tid == 0) bests[sab[tk.s].colt0 + tk.t] = best;
+}
+
+// Step end, one workgroup per block: next row pivot, the norm recurrence and
+// the stopping test; counts the blocks still running.
+template <typename R>
+__global__ void __launch_bounds__(256)
+    sa_step_kernel(const AcaBlk *__restrict__ blks, SaState *__restrict__ state,
+                   const Best2 *__restrict__ bests, const double *__restrict__ parts,
+                   const cplx<double> *__restrict__ cvall, const SaBlk *__restrict__ sab,
+                   AcaOut *__restrict__ outs, double eps, double tau_piv,
+                   int *__restrict__ running) {
+    __shared__ Best2 sh_best[4];
+    __shared__ double sh_sum[8];
+    const int s = blockIdx.x, tid = threadIdx.x;
+    SaState st = state[s];
+    if (st.status >= 0) return;
+    if (st.skip) {
+        if (tid == 0) {
+            st.skip = 0;
+            if (st.steps >= min(blks[s].m, blks[s].n)) {
+                st.status = 2;
+                sa_output(st, outs + s);
+            } else if (st.r + 3 > blks[s].budget) {
+                st.status = 1;
+                sa_output(st, outs + s);
+            } else {
+                atomicAdd(running, 1);
+            }
+            state[s] = st;
+        }
+        return;
+    }
+    const AcaBlk b = blks[s];
+    const SaBlk sb = sab[s];
+    const int r = st.r, p = st.p, m = b.m;
+    const int ntile = (m + kSaTile - 1) / kSaTile;
+    Best2 best = {-1.0, INT_MAX, -1.0, INT_MAX};
+    for (int t = tid; t < ntile; t += 256) {
+        const Best2 c = bests[sb.colt0 + t];
+        cand_better(best.s3, best.i3, c.s3, c.i3);
+        cand_better(best.fro, best.ifro, c.fro, c.ifro);
+    }
+    best = block_best2(best, sh_best);
+    int next_i = -1;
+    if (best.ifro != INT_MAX)
+        next_i = (best.s3 <= tau_piv * tau_piv * best.fro) ? best.ifro : best.i3;
+    // cross = 2 Re sum_{l < r, c < p} cu conj(cv), fresh = Re sum_{l >= r, c < p} ...
+    const cplx<double> *cv = cvall + sb.cvoff;
+    const int nsl = (m + kSaSlice - 1) / kSaSlice;
+    double cross = 0.0, fresh = 0.0;
+    for (int q = tid; q < 6 * (r + p); q += 256) {
+        const int l = q / 6, c = (q % 6) >> 1;
+        if (c >= p) continue;
+        const double u = sa_gram_sum(parts + sb.ugoff, nsl, sb.nchunk, l / 4, 6 * (l % 4) + q % 6);
+        const cplx<double> w = cv[3 * l + c];
+        const double t = u * ((q & 1) ? w.im : w.re);
+        if (l < r)
+            cross += 2.0 * t;
+        else
+            fresh += t;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        cross += __shfl_xor(cross, o, 64);
+        fresh += __shfl_xor(fresh, o, 64);
+    }
+    if ((tid & 63) == 0) {
+        sh_sum[2 * (tid >> 6)] = cross;
+        sh_sum[2 * (tid >> 6) + 1] = fresh;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        cross = 0.0;
+        fresh = 0.0;
+        for (int w = 0; w < 4; ++w) {
+            cross += sh_sum[2 * w];
+            fresh += sh_sum[2 * w + 1];
+        }
+        st.norm2 += cross + fresh;
+        const bool stop = (fresh <= eps * eps * st.norm2) || next_i < 0;
+        st.r = r + p;
+        ++st.steps;
+        const int cap = min(b.m, b.n);
+        if (stop) {
+            st.status = (st.steps >= cap) ? 2 : 0;
+        } else {
+            st.ih = next_i;
+            if (st.steps >= cap)
+                st.status = 2;
+            else if (st.r + 3 > b.budget)
+                st.status = 1;
+        }
+        if (st.status >= 0)
+            sa_output(st, outs + s);
+        else
+            atomicAdd(running, 1);
+        state[s] = st;
+    }
+}
+
+// Runs the split ACA on blk[0, nblk) (device copies at d_blk, d_out).
+template <typename R>
+static void run_aca_split(const Geometry &g, const GreenParams<R> &gp, const AcaBlk *blk,
+                          size_t nblk, const AcaBlk *d_blk, cplx<R> *scratch, uint8_t *flags,
+                          AcaOut *d_out, double eps, double tau_piv, double nu2, hipStream_t st) {
+    if (nblk == 0) return;
+    std::vector<SaBlk> sab(nblk);
+    std::vector<SaTask> rowt, colt, vgt, ugt;
+    int64_t cvlen = 0, plen = 0;
+    int32_t maxb = 3, maxsteps = 1;
+    for (size_t q = 0; q < nblk; ++q) {
+        const AcaBlk &b = blk[q];
+        SaBlk &s = sab[q];
+        s.nchunk = (b.budget + 3) / 4;
+        s.cvoff = cvlen;
+        cvlen += 3 * (int64_t)b.budget;
+        const int nvs = (b.n + kSaSlice - 1) / kSaSlice, nus = (b.m + kSaSlice - 1) / kSaSlice;
+        s.vgoff = plen;
+        plen += (int64_t)nvs * s.nchunk * 24;
+        s.ugoff = plen;
+        plen += (int64_t)nus * s.nchunk * 24;
+        s.rowt0 = (int32_t)rowt.size();
+        for (int t = 0; t * kSaTile < b.n; ++t) rowt.push_back({(int32_t)q, t});
+        s.colt0 = (int32_t)colt.size();
+        for (int t = 0; t * kSaTile < b.m; ++t) colt.push_back({(int32_t)q, t});
+        for (int t = 0; t < nvs; ++t) vgt.push_back({(int32_t)q, t});
+        for (int t = 0; t < nus; ++t) ugt.push_back({(int32_t)q, t});
+        s.pad = 0;
+        maxb = std::max(maxb, b.budget);
+        // every step adds a term or marks a row used
+        maxsteps = std::max(maxsteps, b.m + b.budget / 3 + 2);
+    }
+    // column-pass bests follow the row-pass bests
+    for (auto &sb : sab) sb.colt0 += (int32_t)rowt.size();
+    DeviceBuf d_sab, d_row, d_col, d_vg, d_ug, d_state, d_cv, d_parts, d_bests, d_run;
+    auto put = [&](DeviceBuf &d, const auto &v) {
+        using E = typename std::decay_t<decltype(v)>::value_type;
+        d.alloc(std::max<size_t>(v.size(), 1) * sizeof(E));
+        if (!v.empty())
+            HM_HIP_CHECK(hipMemcpyAsync(d.p, v.data(), v.size() * sizeof(E),
+                                        hipMemcpyHostToDevice, st));
+    };
+    put(d_sab, sab);
+    put(d_row, rowt);
+    put(d_col, colt);
+    put(d_vg, vgt);
+    put(d_ug, ugt);
+    d_state.alloc(nblk * sizeof(SaState));
+    d_cv.alloc(std::max<int64_t>(cvlen, 1) * sizeof(cplx<double>));
+    d_parts.alloc(std::max<int64_t>(plen, 1) * sizeof(double));
+    d_bests.alloc((rowt.size() + colt.size()) * sizeof(Best2));
+    d_run.alloc(sizeof(int));
+    auto *bests = d_bests.as<Best2>();
+    const size_t lds = 3 * (size_t)maxb * sizeof(cplx<R>);
+    hipLaunchKernelGGL(sa_init_kernel<R>, dim3((unsigned)nblk), dim3(256), 0, st, d_blk,
+                       d_state.as<SaState>(), flags, d_out);
+    HM_HIP_CHECK(hipGetLastError());
+    int running = 1;
+    for (int step = 0; step < maxsteps && running > 0; ++step) {
+        hipLaunchKernelGGL(sa_row_kernel<R>, dim3((unsigned)rowt.size()), dim3(256), lds, st, g,
+                           gp, d_blk, d_state.as<SaState>(), d_row.as<SaTask>(), scratch, flags,
+                           bests, d_sab.as<SaBlk>(), nu2);
+        hipLaunchKernelGGL((sa_gram_kernel<R, 0>), dim3((unsigned)vgt.size()), dim3(256), 0, st,
+                           d_blk, d_state.as<SaState>(), d_vg.as<SaTask>(), scratch,
+                           d_parts.as<double>(), d_sab.as<SaBlk>());
+        hipLaunchKernelGGL(sa_pivot_kernel<R>, dim3((unsigned)nblk), dim3(256), 0, st, g, gp,
+                           d_blk, d_state.as<SaState>(), bests, d_parts.as<double>(),
+                           d_cv.as<cplx<double>>(), scratch, flags, d_sab.as<SaBlk>(), d_out,
+                           tau_piv, nu2);
+        hipLaunchKernelGGL(sa_vfix_kernel<R>, dim3((unsigned)rowt.size()), dim3(256), 0, st,
+                           d_blk, d_state.as<SaState>(), d_row.as<SaTask>(), scratch);
+        hipLaunchKernelGGL(sa_col_kernel<R>, dim3((unsigned)colt.size()), dim3(256), lds, st, g,
+                           gp, d_blk, d_state.as<SaState>(), d_col.as<SaTask>(), scratch, flags,
+                           bests, d_sab.as<SaBlk>(), nu2);
+        hipLaunchKernelGGL((sa_gram_kernel<R, 1>), dim3((unsigned)ugt.size()), dim3(256), 0, st,
+                           d_blk, d_state.as<SaState>(), d_ug.as<SaTask>(), scratch,
+                           d_parts.as<double>(), d_sab.as<SaBlk>());
+        HM_HIP_CHECK(hipMemsetAsync(d_run.p, 0, sizeof(int), st));
+        hipLaunchKernelGGL(sa_step_kernel<R>, dim3((unsigned)nblk), dim3(256), 0, st, d_blk,
+                           d_state.as<SaState>(), bests, d_parts.as<double>(),
+                           d_cv.as<cplx<double>>(), d_sab.as<SaBlk>(), d_out, eps, tau_piv,
+                           d_run.as<int>());
+        HM_HIP_CHECK(hipGetLastError());
+        HM_HIP_CHECK(hipMemcpyAsync(&running, d_run.p, sizeof(int), hipMemcpyDeviceToHost, st));
+        HM_HIP_CHECK(hipStreamSynchronize(st));
+    }
+    if (running > 0) throw StatusError(HM_ERR_STATE, "split ACA did not finish");
+}
+
 template <typename R>
 void run_aca(const Geometry &g, const GreenParams<R> &gp, const std::vector<AcaBlk> &blk,
              AcaBlk *d_blk, cplx<R> *scratch, uint8_t *flags, AcaOut *d_out, double eps,
@@ -736,51 +1323,45 @@ void run_aca(const Geometry &g, const GreenParams<R> &gp, const std::vector<AcaB
     // norm of the same block of A: float32 kernel evaluation and updates
     // leave about 1e-6 relative noise (3e-5 keeps a margin), float64 1e-15.
     const double nu = sizeof(R) == 4 ? 3e-5 : 1e-12;
+    // Blocks with many points come first (the caller orders them so) and run
+    // in the split form; the rest run one workgroup per block.
+    size_t nbig = 0;
+    while (nbig < blk.size() && blk[nbig].m + blk[nbig].n >= kAcaBigPoints) ++nbig;
+    for (size_t q = nbig; q < blk.size(); ++q)
+        if (blk[q].m + blk[q].n >= kAcaBigPoints)
+            throw StatusError(HM_ERR_STATE, "ACA blocks with many points must come first");
     if (unbatched) {
-        // comparison baseline: one launch per block, each with the LDS its own budget needs
+        // comparison baseline: one launch (sequence) per block, each with the
+        // LDS its own budget needs
         for (size_t q = 0; q < blk.size(); ++q) {
-            const size_t sm = 3 * (size_t)blk[q].budget * (sizeof(cplx<R>) + sizeof(cplx<double>));
-            bool big = false;
-            if constexpr (sizeof(R) == 4) big = blk[q].m + blk[q].n >= kAcaBigPoints;
-            if (big) {
-                if constexpr (sizeof(R) == 4)
-                    hipLaunchKernelGGL((aca_kernel<R, kAcaBigThreads>), dim3(1),
-                                       dim3(kAcaBigThreads), sm, st, g, gp, d_blk + q, scratch,
-                                       flags, d_out + q, eps, tau_piv, nu * nu, blk[q].budget);
-            } else {
-                hipLaunchKernelGGL((aca_kernel<R, kAcaThreads>), dim3(1), dim3(kAcaThreads), sm,
-                                   st, g, gp, d_blk + q, scratch, flags, d_out + q, eps, tau_piv,
-                                   nu * nu, blk[q].budget);
+            if (q < nbig) {
+                run_aca_split<R>(g, gp, blk.data() + q, 1, d_blk + q, scratch, flags, d_out + q,
+                                 eps, tau_piv, nu * nu, st);
+                continue;
             }
+            const size_t sm = 3 * (size_t)blk[q].budget * (sizeof(cplx<R>) + sizeof(cplx<double>));
+            hipLaunchKernelGGL((aca_kernel<R, kAcaThreads>), dim3(1), dim3(kAcaThreads), sm, st,
+                               g, gp, d_blk + q, scratch, flags, d_out + q, eps, tau_piv, nu * nu,
+                               blk[q].budget);
         }
         HM_HIP_CHECK(hipGetLastError());
         return;
     }
-    // Blocks with many points stream long factor columns every step: they
-    // get 512-thread workgroups (the most that keep every value in registers).  The list is longest first, so they form a
-    // prefix; the rest runs with 256 threads on the auxiliary stream (when
-    // given) beside them.
-    size_t nbig = 0;
-    // (complex128 would spill registers at 512 threads: it keeps 256)
-    if constexpr (sizeof(R) == 4)
-        while (nbig < blk.size() && blk[nbig].m + blk[nbig].n >= kAcaBigPoints) ++nbig;
+    // The one-workgroup blocks go to the auxiliary stream (when given) and
+    // run beside the split steps, which the host drives on st.
     hipStream_t s_small = (aux && nbig > 0) ? aux : st;
     ScopedEvent ev0, ev1;
     if (s_small != st) {
         HM_HIP_CHECK(hipEventRecord(ev0.e, st));   // inputs uploaded on st
         HM_HIP_CHECK(hipStreamWaitEvent(s_small, ev0.e, 0));
     }
-    if constexpr (sizeof(R) == 4) {
-        if (nbig > 0)
-            hipLaunchKernelGGL((aca_kernel<R, kAcaBigThreads>), dim3((unsigned)nbig),
-                               dim3(kAcaBigThreads), smem, st, g, gp, d_blk, scratch, flags, d_out,
-                               eps, tau_piv, nu * nu, max_budget);
-    }
     if (nbig < blk.size())
         hipLaunchKernelGGL((aca_kernel<R, kAcaThreads>), dim3((unsigned)(blk.size() - nbig)),
                            dim3(kAcaThreads), smem, s_small, g, gp, d_blk + nbig, scratch, flags,
                            d_out + nbig, eps, tau_piv, nu * nu, max_budget);
     HM_HIP_CHECK(hipGetLastError());
+    run_aca_split<R>(g, gp, blk.data(), nbig, d_blk, scratch, flags, d_out, eps, tau_piv, nu * nu,
+                     st);
     if (s_small != st) {
         HM_HIP_CHECK(hipEventRecord(ev1.e, s_small));
         HM_HIP_CHECK(hipStreamWaitEvent(st, ev1.e, 0));

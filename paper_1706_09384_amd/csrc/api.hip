@@ -565,7 +565,12 @@ void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vect
         };
         auto launch = [&](std::vector<int64_t> todo, hipStream_t s) {
             AcaLaunch L;
-            std::stable_sort(todo.begin(), todo.end(), lpt);
+            // blocks with many points first (they run in the split form), each
+            // group longest first
+            std::stable_sort(todo.begin(), todo.end(), [&](int64_t a, int64_t b) {
+                const bool ba = lm[a] + ln[a] >= kAcaBigPoints, bb = lm[b] + ln[b] >= kAcaBigPoints;
+                return ba != bb ? ba : lpt(a, b);
+            });
             L.ab.resize(todo.size());
             int64_t fac = 0, flg = 0;
             int32_t maxb = 3;

@@ -54,6 +54,10 @@ struct ProjReduce {
 };
 
 constexpr int32_t kProjRows = 512;
+// Admissible blocks with at least this many points (m + n) run their ACA in
+// the split form (each step spread over many workgroups) and come first in an
+// ACA launch.
+constexpr int kAcaBigPoints = 1500;
 
 // Multi-RHS (matrix-core) plan.  Accumulation: one wave per 16 rows of a
 // leaf row cluster's segment.  Projection: one wave per (low-rank block, 16
