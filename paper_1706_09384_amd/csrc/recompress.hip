@@ -129,6 +129,52 @@ __device__ void chol_upper(cplx<double> *G, int r, double tol, double *sh) {
     __syncthreads();
 }
 
+// The same factorisation for a matrix in global memory (ranks whose r x r
+// matrices do not fit in LDS): each off-diagonal entry R(k, j) is one wave's
+// 64-lane dot product over i < k instead of one thread's serial loop, so the
+// k-th step costs a few load latencies rather than k of them.
+__device__ void chol_upper_wide(cplx<double> *G, int r, double tol, double *sh) {
+    const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+    const int nw = blockDim.x / 64;
+    for (int k = 0; k < r; ++k) {
+        if (wave == 0) {
+            double d = 0;
+            for (int i = lane; i < k; i += 64) d += abs2(G[i + (int64_t)k * r]);
+            d = wave_sumd(d);
+            if (lane == 0) {
+                d = G[k + (int64_t)k * r].re - d;
+                const double rk = d > tol ? sqrt(d) : 0.0;
+                G[k + (int64_t)k * r] = {rk, 0.0};
+                sh[0] = rk;
+            }
+        }
+        __syncthreads();
+        const double rk = sh[0];
+        const cplx<double> *rkcol = G + (int64_t)k * r;
+        for (int j = k + 1 + wave; j < r; j += nw) {
+            cplx<double> *cj = G + (int64_t)j * r;
+            double sr = 0, si = 0;
+            for (int i = lane; i < k; i += 64) {
+                const cplx<double> t = cmul(rkcol[i], cj[i]);
+                sr += t.re;
+                si += t.im;
+            }
+            sr = wave_sumd(sr);
+            si = wave_sumd(si);
+            if (lane == 0) {
+                const cplx<double> s = cj[k] - cplx<double>{sr, si};
+                cj[k] = rk > 0.0 ? (1.0 / rk) * s : cplx<double>{0, 0};
+            }
+        }
+        __syncthreads();
+    }
+    for (int64_t q = tid; q < (int64_t)r * r; q += blockDim.x) {
+        const int i = (int)(q % r), j = (int)(q / r);
+        if (i > j) G[q] = {0, 0};
+    }
+    __syncthreads();
+}
+
 // One rotation of the one-sided Jacobi method on columns x, y (length r, LDS)
 // with the matching columns jx, jy of J, executed by a group of gs lanes
 // (gs a power of two dividing 64; gl = lane index inside the group).
@@ -416,7 +462,7 @@ __global__ void __launch_bounds__(NT) factor_kernel(const RcBlk *__restrict__ bl
             for (int64_t q = tid; q < (int64_t)r * r; q += NT) G[q] = lds[q];
             __syncthreads();
         } else {
-            chol_upper(G, r, ctol, sh_s);
+            chol_upper_wide(G, r, ctol, sh_s);
         }
     }
     }
@@ -639,8 +685,13 @@ static void split_jacobi(const std::vector<RcBlk> &blk, const std::vector<int32_
     d_tiny.alloc(nbig * sizeof(double));
     d_active.alloc(nbig * sizeof(int32_t));
     d_rot.alloc(nbig * sizeof(int32_t));
-    hipLaunchKernelGGL((factor_kernel<R, 1024, 1>), dim3((unsigned)nbig), dim3(1024), bytes, st,
-                       d_blk, d_order + q0, W, d_newrank, eps, lds_elems, d_tiny.as<double>());
+    // Forming the core stages only small_gemm tiles in LDS (its Cholesky runs
+    // in global memory for these ranks), so it asks for no more LDS than that
+    // and shares CUs with the other rank classes.
+    const int64_t gemm_elems = 2 * 32 * 33;
+    hipLaunchKernelGGL((factor_kernel<R, 1024, 1>), dim3((unsigned)nbig), dim3(1024),
+                       (size_t)gemm_elems * sizeof(cplx<double>), st, d_blk, d_order + q0, W,
+                       d_newrank, eps, gemm_elems, d_tiny.as<double>());
     HM_HIP_CHECK(hipGetLastError());
     // tournament rounds of every block; round t of all blocks in one list
     std::vector<std::vector<JacTask>> rounds;
