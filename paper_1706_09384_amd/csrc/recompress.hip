@@ -58,7 +58,8 @@ __global__ void __launch_bounds__(256) gram_kernel(const RcBlk *__restrict__ blk
     cplx<double> acc[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
     for (int64_t i0 = 0; i0 < rows; i0 += kGR) {
         for (int q = tid; q < kGR * kGT; q += 256) {
-            const int rr = q / kGT, cc = q % kGT;
+            // row fastest: 16 lanes read 16 consecutive rows of one column
+            const int rr = q % kGR, cc = q / kGR;
             const int64_t row = i0 + rr;
             const int ca = a0 + cc, ccol = c0 + cc;
             sa[rr][cc] = (row < rows && ca < r) ? cvt<double>(X[(int64_t)ca * rows + row])
