@@ -354,3 +354,30 @@ def test_many_rhs_ragged_panels(hm, orc, sphere1k):
     Y = H.matvec(to_dev(B, H.complex_dtype)).cpu().numpy().astype(np.complex128)
     E = np.linalg.norm(Y - A @ B, axis=0) / np.linalg.norm(A @ B, axis=0)
     assert E.max() <= 5 * w.eps
+
+
+def test_split_aca_complex128_sampled_rows(hm, orc):
+    """Blocks with 1,500 or more points run the split ACA (each greedy step as
+    launches over many workgroups); in complex128 at eps = 1e-6 the product
+    still meets the 5 eps gate on sampled rows."""
+    w = W.small_sphere(12000, omega=19.4, leaf=32, eps=1e-6)
+    say("case split ACA complex128 sphere12k")
+    X, _ = w.points()
+    H = hm.build_workload(w, X=X, prec=0)
+    blocks, rank, rank_aca = H.export_blocklist()
+    nx = H.export_tree(0)[1]
+    ny = H.export_tree(1)[1]
+    pts = (nx[blocks[:, 0], 1] - nx[blocks[:, 0], 0]) + (ny[blocks[:, 1], 1] - ny[blocks[:, 1], 0])
+    big = (blocks[:, 2] == 1) & (pts >= 1500)
+    say("split blocks", int(big.sum()))
+    assert big.sum() > 0
+    say("max ACA rank among them", int(rank_aca[big].max()))
+    assert np.all(rank[big] <= rank_aca[big])
+    b = w.rhs()
+    y = H.matvec(to_dev(b)).cpu().numpy()
+    rows = np.random.default_rng(3).choice(w.n_points, 256, replace=False)
+    ref = orc.matvec_rows(orc.Problem.from_workload(w, X), b, rows)
+    idx = (3 * rows[:, None] + np.arange(3)).ravel()
+    e = rel(y[idx], ref)
+    say("sampled e =", e)
+    assert e <= 5 * w.eps
