@@ -2,9 +2,10 @@
 // truncated SVD of the small r x r core R_U R_V^* = P S L^*, then
 // U' = Q_U P S^1/2 and V' = Q_V L S^1/2 keeping the leading singular values.
 //
-// GPU form (all FP64, whatever the storage precision):
+// GPU form (all FP64, whatever the storage precision; the products run on
+// the FP64 matrix cores):
 //   gram     G_U = U^* U and G_V = V^* V, 32x32 output tiles per workgroup,
-//            16-row slabs of both operands staged in LDS;
+//            one wave per 16x16 quarter;
 //   factor   per block, one workgroup: Cholesky G = R^* R (this is the R
 //            factor of a thin QR of U, Q = U R^-1 never formed), core
 //            M = R_U R_V^*, one-sided Jacobi SVD of M (parallel tournament
@@ -36,55 +37,59 @@ struct GramItem {
 };
 
 constexpr int kGT = 32;   // output tile
-constexpr int kGR = 16;   // rows per slab
 
+typedef double mf64x4 __attribute__((ext_vector_type(4)));
+
+// G_X = X^* X on the FP64 matrix cores (v_mfma_f64_16x16x4f64: lane l holds
+// A[l % 16][l / 16] and B[l / 16][l % 16], and accumulator element e is
+// C[4e + l / 16][l % 16]).  One workgroup per 32 x 32 output tile, one wave
+// per 16 x 16 quarter; the 4-deep contraction steps take the rows of a
+// 16-row slab as q0 + 4 (l / 16) + s, s = 0..3, so that every lane reads
+// four consecutive rows of its column.  Re G = Xr^T Xr + Xi^T Xi and
+// Im G = Xr^T Xi - Xi^T Xr, products of the FP32 entries exact in FP64.
 template <typename R>
-__global__ void __launch_bounds__(256) gram_kernel(const RcBlk *__restrict__ blks,
-                                                   const GramItem *__restrict__ items,
-                                                   const cplx<R> *__restrict__ fac,
-                                                   cplx<double> *__restrict__ work) {
-    __shared__ cplx<double> sa[kGR][kGT + 1];
-    __shared__ cplx<double> sc[kGR][kGT + 1];
+__global__ void __launch_bounds__(256) gram_mfma_kernel(const RcBlk *__restrict__ blks,
+                                                        const GramItem *__restrict__ items,
+                                                        const cplx<R> *__restrict__ fac,
+                                                        cplx<double> *__restrict__ work) {
     const GramItem it = items[blockIdx.x];
     const RcBlk b = blks[it.blk];
     const int r = b.r;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int ia = wave & 1, ic = wave >> 1;
+    const int abase = it.ta * kGT + 16 * ia, cbase = it.tc * kGT + 16 * ic;
+    // quarters entirely outside the matrix or below the diagonal add nothing
+    if (abase >= r || cbase >= r || abase > cbase + 15) return;
     const int64_t rows = 3 * (int64_t)(it.which == 0 ? b.m : b.n);
     const cplx<R> *X = fac + (it.which == 0 ? b.uoff : b.voff);
     cplx<double> *G = work + b.goff + rc_slot(r, it.which);
-    const int a0 = it.ta * kGT, c0 = it.tc * kGT;
-    const int tid = threadIdx.x;
-    // each thread owns 4 outputs: (a0 + ty*4 + k, c0 + tx) for k < 4
-    const int tx = tid % kGT, ty = tid / kGT;   // ty in 0..7
-    cplx<double> acc[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
-    for (int64_t i0 = 0; i0 < rows; i0 += kGR) {
-        for (int q = tid; q < kGR * kGT; q += 256) {
-            // row fastest: 16 lanes read 16 consecutive rows of one column
-            const int rr = q % kGR, cc = q / kGR;
-            const int64_t row = i0 + rr;
-            const int ca = a0 + cc, ccol = c0 + cc;
-            sa[rr][cc] = (row < rows && ca < r) ? cvt<double>(X[(int64_t)ca * rows + row])
-                                                : cplx<double>{0, 0};
-            sc[rr][cc] = (row < rows && ccol < r) ? cvt<double>(X[(int64_t)ccol * rows + row])
-                                                  : cplx<double>{0, 0};
-        }
-        __syncthreads();
-#pragma unroll 4
-        for (int rr = 0; rr < kGR; ++rr) {
-            const cplx<double> y = sc[rr][tx];
+    const int ca = abase + (lane & 15), cc = cbase + (lane & 15), g = lane >> 4;
+    const bool va = ca < r, vc = cc < r;
+    const cplx<R> *xa = X + (int64_t)(va ? ca : 0) * rows;
+    const cplx<R> *xc = X + (int64_t)(vc ? cc : 0) * rows;
+    mf64x4 gr = {0, 0, 0, 0}, gi = {0, 0, 0, 0};
+    for (int64_t q0 = 0; q0 < rows; q0 += 16) {
+        cplx<double> A[4], B[4];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const cplx<double> x = sa[rr][ty * 4 + k];
-                acc[k] = acc[k] + cmul(x, y);   // conj(x) * y
-            }
+        for (int s = 0; s < 4; ++s) {
+            const int64_t q = q0 + 4 * g + s;
+            A[s] = (va && q < rows) ? cvt<double>(xa[q]) : cplx<double>{0, 0};
+            B[s] = (vc && q < rows) ? cvt<double>(xc[q]) : cplx<double>{0, 0};
         }
-        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            gr = __builtin_amdgcn_mfma_f64_16x16x4f64(A[s].re, B[s].re, gr, 0, 0, 0);
+            gr = __builtin_amdgcn_mfma_f64_16x16x4f64(A[s].im, B[s].im, gr, 0, 0, 0);
+            gi = __builtin_amdgcn_mfma_f64_16x16x4f64(A[s].re, B[s].im, gi, 0, 0, 0);
+            gi = __builtin_amdgcn_mfma_f64_16x16x4f64(-A[s].im, B[s].re, gi, 0, 0, 0);
+        }
     }
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int a = a0 + ty * 4 + k, c = c0 + tx;
+    for (int e = 0; e < 4; ++e) {
+        const int a = abase + 4 * e + g, c = cc;
         if (a < r && c < r && a <= c) {
-            G[a + (int64_t)c * r] = acc[k];
-            G[c + (int64_t)a * r] = conj(acc[k]);
+            G[a + (int64_t)c * r] = {gr[e], gi[e]};
+            G[c + (int64_t)a * r] = {gr[e], -gi[e]};
         }
     }
 }
@@ -361,49 +366,38 @@ __device__ void jacobi_svd(cplx<double> *M, cplx<double> *J, int r, cplx<double>
     }
 }
 
-// C(i, j) = sum_k A(i, k) B(k, j) for 0 <= i < mC, 0 <= j < nC, 0 <= k < K,
-// with element accessors fa(i, k), fb(k, j) and a sink fc(i, j, value);
-// 32 x 32 output tiles, 32-deep k slabs staged in LDS (sh: 2 * 32 * 33
-// complex doubles), 4 outputs per thread of a 256-thread workgroup.
+// C(i, j) = sum_k A(i, k) B(k, j) (complex FP64) on the matrix cores: one
+// wave per 16 x 16 output tile, the workgroup's waves taking the tiles in
+// turn; each 4-deep contraction step is four v_mfma_f64_16x16x4f64 (real and
+// imaginary parts).  Element accessors fa(i, k), fb(k, j), sink fc(i, j, v);
+// the accessors are only called inside the bounds.  Ends with a barrier.
 template <typename FA, typename FB, typename FC>
-__device__ void small_gemm(int mC, int nC, int K, FA fa, FB fb, FC fc, cplx<double> *sh) {
-    constexpr int T = 32, P = T + 1;
-    cplx<double> *As = sh, *Bs = sh + T * P;
-    const int tid = threadIdx.x;
-    const int tx = tid % T, ty = tid / T;   // ty in 0..7 for the 256 computing threads
-    const bool act = tid < 256;             // larger workgroups: the rest only stage
-    for (int i0 = 0; i0 < mC; i0 += T)
-        for (int j0 = 0; j0 < nC; j0 += T) {
-            cplx<double> acc[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
-            for (int k0 = 0; k0 < K; k0 += T) {
-                for (int q = tid; q < T * T; q += blockDim.x) {
-                    const int a = q % T, c = q / T;   // a fastest: contiguous rows
-                    As[c * P + a] = (i0 + a < mC && k0 + c < K) ? fa(i0 + a, k0 + c)
-                                                                  : cplx<double>{0, 0};
-                    Bs[a * P + c] = (k0 + a < K && j0 + c < nC) ? fb(k0 + a, j0 + c)
-                                                                  : cplx<double>{0, 0};
-                }
-                __syncthreads();
-                if (act) {
-#pragma unroll 8
-                    for (int kk = 0; kk < T; ++kk) {
-                        const cplx<double> bv = Bs[kk * P + tx];
-#pragma unroll
-                        for (int u = 0; u < 4; ++u) acc[u] = acc[u] + As[kk * P + ty * 4 + u] * bv;
-                    }
-                }
-                __syncthreads();
-            }
-            if (act) {
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int i = i0 + ty * 4 + u, j = j0 + tx;
-                    if (i < mC && j < nC) fc(i, j, acc[u]);
-                }
-            }
+__device__ void mfma_gemm(int mC, int nC, int K, FA fa, FB fb, FC fc) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+    const int tm = (mC + 15) >> 4, tn = (nC + 15) >> 4;
+    const int g = lane >> 4;
+    for (int t = wave; t < tm * tn; t += nw) {
+        const int i0 = (t % tm) << 4, j0 = (t / tm) << 4;
+        const int ia = i0 + (lane & 15), jb = j0 + (lane & 15);
+        mf64x4 cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
+        for (int k0 = 0; k0 < K; k0 += 4) {
+            const int k = k0 + g;
+            const cplx<double> a = (ia < mC && k < K) ? fa(ia, k) : cplx<double>{0, 0};
+            const cplx<double> b = (k < K && jb < nC) ? fb(k, jb) : cplx<double>{0, 0};
+            cr = __builtin_amdgcn_mfma_f64_16x16x4f64(a.re, b.re, cr, 0, 0, 0);
+            cr = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.im, b.im, cr, 0, 0, 0);
+            ci = __builtin_amdgcn_mfma_f64_16x16x4f64(a.re, b.im, ci, 0, 0, 0);
+            ci = __builtin_amdgcn_mfma_f64_16x16x4f64(a.im, b.re, ci, 0, 0, 0);
         }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int i = i0 + 4 * e + g;
+            if (i < mC && jb < nC) fc(i, jb, cplx<double>{cr[e], ci[e]});
+        }
+    }
     __syncthreads();
 }
+
 
 // PHASE 0 runs the whole factorisation of a block in one workgroup.  Blocks
 // whose core does not fit in LDS split it: PHASE 1 stops once the core M and
@@ -469,13 +463,13 @@ __global__ void __launch_bounds__(NT) factor_kernel(const RcBlk *__restrict__ bl
     }
     // core M = R_U D R_V^*, D = du dv (the block is U~ D V~^*), written to dst
     auto form_core = [&](cplx<double> *dst) {
-        small_gemm(
+        mfma_gemm(
             r, r, r,
             [&](int i, int k) {
                 return (du[k] * dv[k]) * (i <= k ? RU[i + (int64_t)k * r] : cplx<double>{0, 0});
             },
             [&](int k, int j) { return j <= k ? conj(RV[j + (int64_t)k * r]) : cplx<double>{0, 0}; },
-            [&](int i, int j, cplx<double> v) { dst[i + (int64_t)j * r] = v; }, lds);
+            [&](int i, int j, cplx<double> v) { dst[i + (int64_t)j * r] = v; });
     };
     // singular values = column norms of M J, ranked in descending order; keep =
     // smallest k with sum_{i >= k} s_i^2 <= eps^2 sum s_i^2 (Frobenius tail)
@@ -542,34 +536,31 @@ __global__ void __launch_bounds__(NT) factor_kernel(const RcBlk *__restrict__ bl
     } else {
         form_core(J);   // J slot holds M0
         // L[:, c] = M0^* (M J)[:, idx_c] / s_c^2
-        small_gemm(
+        mfma_gemm(
             r, keep, r, [&](int j, int i) { return conj(J[i + (int64_t)j * r]); },
             [&](int i, int c) { return M[i + (int64_t)idx[c] * r]; },
             [&](int j, int c, cplx<double> v) {
                 const double sc = sv[idx[c]];
                 Lw[j + (int64_t)c * r] = (1.0 / (sc * sc)) * v;
-            },
-            lds);
+            });
     }
     // W_U = D_v R_V^* L_r S_r^-1/2,  W_V = D_u R_U^* P_r S_r^-1/2 with
     // P_r = (M J)[:, idx] / s
-    small_gemm(
+    mfma_gemm(
         r, keep, r,
         [&](int k, int j) { return j <= k ? conj(RV[j + (int64_t)k * r]) : cplx<double>{0, 0}; },
         [&](int j, int c) { return useJ ? J[j + (int64_t)idx[c] * r] : Lw[j + (int64_t)c * r]; },
         [&](int k, int c, cplx<double> v) {
             WU[k + (int64_t)c * r] = (dv[k] / sqrt(sv[idx[c]])) * v;
-        },
-        lds);
-    small_gemm(
+        });
+    mfma_gemm(
         r, keep, r,
         [&](int k, int i) { return i <= k ? conj(RU[i + (int64_t)k * r]) : cplx<double>{0, 0}; },
         [&](int i, int c) { return M[i + (int64_t)idx[c] * r]; },
         [&](int k, int c, cplx<double> v) {
             const double sc = sv[idx[c]];
             WV[k + (int64_t)c * r] = (du[k] / (sc * sqrt(sc))) * v;
-        },
-        lds);
+        });
     if (tid == 0) newrank[bi] = keep;
 }
 
@@ -639,7 +630,6 @@ __global__ void __launch_bounds__(256) apply_kernel(const RcBlk *__restrict__ bl
                                                     const int64_t *__restrict__ outv,
                                                     cplx<R> *__restrict__ out,
                                                     const int32_t *__restrict__ rowpad) {
-    __shared__ cplx<double> sh[2 * 32 * 33];
     const ApplyTask tk = tasks[blockIdx.x];
     const int bi = tk.blk;
     const RcBlk b = blks[bi];
@@ -656,7 +646,7 @@ __global__ void __launch_bounds__(256) apply_kernel(const RcBlk *__restrict__ bl
     const int64_t ldu = padded_rows(rowpad, b.rb, b.m);
     const int64_t ldv = even_up(keep);
     const int64_t row0 = tk.row0;
-    small_gemm(
+    mfma_gemm(
         nrow, keep, r, [&](int i, int k) { return cvt<double>(X[(int64_t)k * rows + row0 + i]); },
         [&](int k, int c) { return T[k + (int64_t)c * r]; },
         [&](int i, int c, cplx<double> v) {
@@ -665,8 +655,7 @@ __global__ void __launch_bounds__(256) apply_kernel(const RcBlk *__restrict__ bl
                 which == 0 ? (int64_t)c * ldu + padded_row(rowpad, b.rb, (int32_t)(row / 3), (int)(row % 3))
                            : row * ldv + c;
             Y[o] = cvt<R>(v);
-        },
-        sh);
+        });
 }
 
 // Factorisation of the blocks order[q0, q1) whose r x r core exceeds the LDS:
@@ -686,13 +675,11 @@ static void split_jacobi(const std::vector<RcBlk> &blk, const std::vector<int32_
     d_tiny.alloc(nbig * sizeof(double));
     d_active.alloc(nbig * sizeof(int32_t));
     d_rot.alloc(nbig * sizeof(int32_t));
-    // Forming the core stages only small_gemm tiles in LDS (its Cholesky runs
-    // in global memory for these ranks), so it asks for no more LDS than that
-    // and shares CUs with the other rank classes.
-    const int64_t gemm_elems = 2 * 32 * 33;
-    hipLaunchKernelGGL((factor_kernel<R, 1024, 1>), dim3((unsigned)nbig), dim3(1024),
-                       (size_t)gemm_elems * sizeof(cplx<double>), st, d_blk, d_order + q0, W,
-                       d_newrank, eps, gemm_elems, d_tiny.as<double>());
+    // Forming the core needs no dynamic LDS (its Cholesky runs in global
+    // memory for these ranks, its products on the matrix cores), so it shares
+    // CUs with the other rank classes.
+    hipLaunchKernelGGL((factor_kernel<R, 1024, 1>), dim3((unsigned)nbig), dim3(1024), 0, st,
+                       d_blk, d_order + q0, W, d_newrank, eps, (int64_t)0, d_tiny.as<double>());
     HM_HIP_CHECK(hipGetLastError());
     // tournament rounds of every block; round t of all blocks in one list
     std::vector<std::vector<JacTask>> rounds;
@@ -773,11 +760,11 @@ void run_recompress(const std::vector<RcBlk> &blk, RcBlk *d_blk, const cplx<R> *
         if (unbatched) {
             for (size_t i = 0; i < blk.size(); ++i)
                 if (item0[i + 1] > item0[i])
-                    hipLaunchKernelGGL(gram_kernel<R>, dim3((unsigned)(item0[i + 1] - item0[i])),
+                    hipLaunchKernelGGL(gram_mfma_kernel<R>, dim3((unsigned)(item0[i + 1] - item0[i])),
                                        dim3(256), 0, st, d_blk, d_items.as<GramItem>() + item0[i],
                                        acaslab, reinterpret_cast<cplx<double> *>(work));
         } else {
-            hipLaunchKernelGGL(gram_kernel<R>, dim3((unsigned)items.size()), dim3(256), 0, st,
+            hipLaunchKernelGGL(gram_mfma_kernel<R>, dim3((unsigned)items.size()), dim3(256), 0, st,
                                d_blk, d_items.as<GramItem>(), acaslab,
                                reinterpret_cast<cplx<double> *>(work));
         }
@@ -836,9 +823,7 @@ void run_recompress(const std::vector<RcBlk> &blk, RcBlk *d_blk, const cplx<R> *
         size_t q1 = q0;
         while (q1 < order.size() && blk[order[q1]].r > lo) ++q1;
         const int64_t need = (int64_t)rmax * rmax * (int64_t)sizeof(cplx<double>);
-        // at least what small_gemm stages (2 x 32 x 33 complex doubles)
-        const int64_t bytes = std::min<int64_t>(
-            std::max<int64_t>(need, 2 * 32 * 33 * (int64_t)sizeof(cplx<double>)), max_lds);
+        const int64_t bytes = std::min<int64_t>(need, max_lds);
         const int64_t lds_elems = bytes / (int64_t)sizeof(cplx<double>);
         // ranks above 64 leave room for one workgroup per CU (LDS): give it
         // 1024 threads (more lanes per Jacobi pair and per Cholesky column)
