@@ -757,6 +757,7 @@ __global__ void __launch_bounds__(NT)
 // launches.
 constexpr int kSaTile = 256;     // points per workgroup of the residual passes
 constexpr int kSaSlice = 256;    // points per Gram slice (one wave per column chunk)
+constexpr int kSaSync = 4;       // steps queued between readbacks of the running count
 
 struct SaState {
     int32_t r, steps, status, fallbacks;   // status -1 while running, then as AcaOut
@@ -1306,8 +1307,12 @@ static void run_aca_split(const Geometry &g, const GreenParams<R> &gp, const Aca
                            d_cv.as<cplx<double>>(), d_sab.as<SaBlk>(), d_out, eps, tau_piv,
                            d_run.as<int>());
         HM_HIP_CHECK(hipGetLastError());
-        HM_HIP_CHECK(hipMemcpyAsync(&running, d_run.p, sizeof(int), hipMemcpyDeviceToHost, st));
-        HM_HIP_CHECK(hipStreamSynchronize(st));
+        // the running count is read every kSaSync steps; a block that stops
+        // in between makes the following launches exit at once
+        if ((step + 1) % kSaSync == 0 || step + 1 >= maxsteps) {
+            HM_HIP_CHECK(hipMemcpyAsync(&running, d_run.p, sizeof(int), hipMemcpyDeviceToHost, st));
+            HM_HIP_CHECK(hipStreamSynchronize(st));
+        }
     }
     if (running > 0) throw StatusError(HM_ERR_STATE, "split ACA did not finish");
 }
