@@ -802,7 +802,9 @@ void run_recompress(const std::vector<RcBlk> &blk, RcBlk *d_blk, const cplx<R> *
                                 hipMemcpyHostToDevice, st));
     const int classes[] = {16, 24, 32, 48, 64, 100, 1 << 30};
     // The classes of ranks above 64 run one workgroup per CU and leave CUs
-    // idle; the smaller classes go to a second stream and fill them.
+    // idle; the smaller classes go to a second stream and fill them.  When
+    // some cores are too large for LDS, their split sweeps hold the build
+    // stream, and every other class goes to the second stream.
     hipStream_t side = st;
     ScopedEvent ev_ready, ev_done;
     if (!unbatched) {
@@ -837,7 +839,8 @@ void run_recompress(const std::vector<RcBlk> &blk, RcBlk *d_blk, const cplx<R> *
                                    lds_elems, nullptr);
         } else if ((int64_t)rmax * rmax <= lds_elems) {
             hipLaunchKernelGGL(kern, dim3((unsigned)(q1 - q0)), dim3(nt), (size_t)bytes,
-                               rmax > 64 ? st : side, d_blk, d_order.as<int32_t>() + q0,
+                               split.q1 > split.q0 || rmax <= 64 ? side : st, d_blk,
+                               d_order.as<int32_t>() + q0,
                                reinterpret_cast<cplx<double> *>(work), d_newrank, eps, lds_elems,
                                nullptr);
         } else {
