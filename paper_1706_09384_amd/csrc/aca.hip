@@ -756,7 +756,7 @@ __global__ void __launch_bounds__(NT)
 // the block), so a block gets the same factors whichever blocks share its
 // launches.
 constexpr int kSaTile = 256;     // points per workgroup of the residual passes
-constexpr int kSaSlice = 256;    // points per Gram slice (one wave per column chunk)
+constexpr int kSaSlice = kSaTile; // points per Gram slice: the residual tile's points
 constexpr int kSaSync = 4;       // steps queued between readbacks of the running count
 
 struct SaState {
@@ -806,13 +806,39 @@ __global__ void __launch_bounds__(256)
     }
 }
 
+// Gram partials of one point slice (the points of residual tile t): wave w
+// takes the column chunks w, w + 4, ...; SIDE 0 is V against its three new
+// columns (l < r + 3), SIDE 1 is U against its p new columns (l < r + p).
+// Called by the residual kernels after the new columns are written (their
+// last barrier makes them visible to the whole workgroup).
+template <typename R, int SIDE>
+__device__ inline void sa_gram_slice(const AcaBlk &b, const SaBlk &sb, int r, int p, int t,
+                                     const cplx<R> *__restrict__ fac, double *__restrict__ parts) {
+    const int npts = SIDE == 0 ? b.n : b.m;
+    const int64_t ld = 3 * (int64_t)npts;
+    const cplx<R> *X = fac + (SIDE == 0 ? b.voff : b.uoff);
+    const int lmax = r + (SIDE == 0 ? 3 : p);
+    const int p0 = t * kSaSlice, p1 = min(npts, p0 + kSaSlice);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    double *out = parts + (SIDE == 0 ? sb.vgoff : sb.ugoff) + (int64_t)t * sb.nchunk * 24;
+    for (int c = wave; 4 * c < lmax; c += 4) {
+        double v3[3];
+        gram_wave<R>(X, ld, p0, p1, 4 * c, lmax, r, lane, v3);
+        if ((lane & 7) == 0) {
+            const int vb = gram_vbase(lane);
+            for (int k = 0; k < 3; ++k) out[c * 24 + vb + k] = v3[k];
+        }
+    }
+}
+
 // Residual row pass, one workgroup per kSaTile column points.
 template <typename R>
 __global__ void __launch_bounds__(256)
     sa_row_kernel(Geometry g, GreenParams<R> gp, const AcaBlk *__restrict__ blks,
                   const SaState *__restrict__ state, const SaTask *__restrict__ tasks,
                   cplx<R> *__restrict__ fac, const uint8_t *__restrict__ flags,
-                  Best2 *__restrict__ bests, const SaBlk *__restrict__ sab, double nu2) {
+                  Best2 *__restrict__ bests, const SaBlk *__restrict__ sab, double nu2,
+                  double *__restrict__ parts) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     cplx<R> *piv = reinterpret_cast<cplx<R> *>(smem_raw);
     __shared__ Best2 sh_best[4];
@@ -838,36 +864,7 @@ __global__ void __launch_bounds__(256)
                      ldv, r, !used_j[j], nu2, best);
     best = block_best2(best, sh_best);
     if (tid == 0) bests[sab[tk.s].rowt0 + tk.t] = best;
-}
-
-// Gram partials of one point slice: wave w takes the column chunks w, w + 4,
-// ...; SIDE 0 is V against its three new columns (l < r + 3), SIDE 1 is U
-// against its p new columns (l < r + p).
-template <typename R, int SIDE>
-__global__ void __launch_bounds__(256)
-    sa_gram_kernel(const AcaBlk *__restrict__ blks, const SaState *__restrict__ state,
-                   const SaTask *__restrict__ tasks, const cplx<R> *__restrict__ fac,
-                   double *__restrict__ parts, const SaBlk *__restrict__ sab) {
-    const SaTask tk = tasks[blockIdx.x];
-    const SaState st = state[tk.s];
-    if (!sa_running(st)) return;
-    const AcaBlk b = blks[tk.s];
-    const SaBlk sb = sab[tk.s];
-    const int npts = SIDE == 0 ? b.n : b.m;
-    const int64_t ld = 3 * (int64_t)npts;
-    const cplx<R> *X = fac + (SIDE == 0 ? b.voff : b.uoff);
-    const int lmax = st.r + (SIDE == 0 ? 3 : st.p);
-    const int p0 = tk.t * kSaSlice, p1 = min(npts, p0 + kSaSlice);
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    double *out = parts + (SIDE == 0 ? sb.vgoff : sb.ugoff) + (int64_t)tk.t * sb.nchunk * 24;
-    for (int c = wave; 4 * c < lmax; c += 4) {
-        double v3[3];
-        gram_wave<R>(X, ld, p0, p1, 4 * c, lmax, st.r, lane, v3);
-        if ((lane & 7) == 0) {
-            const int vb = gram_vbase(lane);
-            for (int k = 0; k < 3; ++k) out[c * 24 + vb + k] = v3[k];
-        }
-    }
+    sa_gram_slice<R, 0>(b, sab[tk.s], r, 0, tk.t, fac, parts);
 }
 
 // Sum of value v of chunk c over the slices of a Gram (slice order).
@@ -1091,7 +1088,8 @@ __global__ void __launch_bounds__(256)
     sa_col_kernel(Geometry g, GreenParams<R> gp, const AcaBlk *__restrict__ blks,
                   const SaState *__restrict__ state, const SaTask *__restrict__ tasks,
                   cplx<R> *__restrict__ fac, const uint8_t *__restrict__ flags,
-                  Best2 *__restrict__ bests, const SaBlk *__restrict__ sab, double nu2) {
+                  Best2 *__restrict__ bests, const SaBlk *__restrict__ sab, double nu2,
+                  double *__restrict__ parts) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     cplx<R> *piv = reinterpret_cast<cplx<R> *>(smem_raw);
     __shared__ Best2 sh_best[4];
@@ -1125,6 +1123,7 @@ __global__ void __launch_bounds__(256)
                      U, ldu, r, p, sh_T, !used_i[i], nu2, best);
     best = block_best2(best, sh_best);
     if (tid == 0) bests[sab[tk.s].colt0 + tk.t] = best;
+    sa_gram_slice<R, 1>(b, sab[tk.s], r, p, tk.t, fac, parts);
 }
 
 // Step end, one workgroup per block: next row pivot, the norm recurrence and
@@ -1231,7 +1230,7 @@ static void run_aca_split(const Geometry &g, const GreenParams<R> &gp, const Aca
                           AcaOut *d_out, double eps, double tau_piv, double nu2, hipStream_t st) {
     if (nblk == 0) return;
     std::vector<SaBlk> sab(nblk);
-    std::vector<SaTask> rowt, colt, vgt, ugt;
+    std::vector<SaTask> rowt, colt;
     int64_t cvlen = 0, plen = 0;
     int32_t maxb = 3, maxsteps = 1;
     for (size_t q = 0; q < nblk; ++q) {
@@ -1249,8 +1248,6 @@ static void run_aca_split(const Geometry &g, const GreenParams<R> &gp, const Aca
         for (int t = 0; t * kSaTile < b.n; ++t) rowt.push_back({(int32_t)q, t});
         s.colt0 = (int32_t)colt.size();
         for (int t = 0; t * kSaTile < b.m; ++t) colt.push_back({(int32_t)q, t});
-        for (int t = 0; t < nvs; ++t) vgt.push_back({(int32_t)q, t});
-        for (int t = 0; t < nus; ++t) ugt.push_back({(int32_t)q, t});
         s.pad = 0;
         maxb = std::max(maxb, b.budget);
         // every step adds a term or marks a row used
@@ -1258,7 +1255,7 @@ static void run_aca_split(const Geometry &g, const GreenParams<R> &gp, const Aca
     }
     // column-pass bests follow the row-pass bests
     for (auto &sb : sab) sb.colt0 += (int32_t)rowt.size();
-    DeviceBuf d_sab, d_row, d_col, d_vg, d_ug, d_state, d_cv, d_parts, d_bests, d_run;
+    DeviceBuf d_sab, d_row, d_col, d_state, d_cv, d_parts, d_bests, d_run;
     auto put = [&](DeviceBuf &d, const auto &v) {
         using E = typename std::decay_t<decltype(v)>::value_type;
         d.alloc(std::max<size_t>(v.size(), 1) * sizeof(E));
@@ -1269,8 +1266,6 @@ static void run_aca_split(const Geometry &g, const GreenParams<R> &gp, const Aca
     put(d_sab, sab);
     put(d_row, rowt);
     put(d_col, colt);
-    put(d_vg, vgt);
-    put(d_ug, ugt);
     d_state.alloc(nblk * sizeof(SaState));
     d_cv.alloc(std::max<int64_t>(cvlen, 1) * sizeof(cplx<double>));
     d_parts.alloc(std::max<int64_t>(plen, 1) * sizeof(double));
@@ -1285,10 +1280,7 @@ static void run_aca_split(const Geometry &g, const GreenParams<R> &gp, const Aca
     for (int step = 0; step < maxsteps && running > 0; ++step) {
         hipLaunchKernelGGL(sa_row_kernel<R>, dim3((unsigned)rowt.size()), dim3(256), lds, st, g,
                            gp, d_blk, d_state.as<SaState>(), d_row.as<SaTask>(), scratch, flags,
-                           bests, d_sab.as<SaBlk>(), nu2);
-        hipLaunchKernelGGL((sa_gram_kernel<R, 0>), dim3((unsigned)vgt.size()), dim3(256), 0, st,
-                           d_blk, d_state.as<SaState>(), d_vg.as<SaTask>(), scratch,
-                           d_parts.as<double>(), d_sab.as<SaBlk>());
+                           bests, d_sab.as<SaBlk>(), nu2, d_parts.as<double>());
         hipLaunchKernelGGL(sa_pivot_kernel<R>, dim3((unsigned)nblk), dim3(256), 0, st, g, gp,
                            d_blk, d_state.as<SaState>(), bests, d_parts.as<double>(),
                            d_cv.as<cplx<double>>(), scratch, flags, d_sab.as<SaBlk>(), d_out,
@@ -1297,10 +1289,7 @@ static void run_aca_split(const Geometry &g, const GreenParams<R> &gp, const Aca
                            d_blk, d_state.as<SaState>(), d_row.as<SaTask>(), scratch);
         hipLaunchKernelGGL(sa_col_kernel<R>, dim3((unsigned)colt.size()), dim3(256), lds, st, g,
                            gp, d_blk, d_state.as<SaState>(), d_col.as<SaTask>(), scratch, flags,
-                           bests, d_sab.as<SaBlk>(), nu2);
-        hipLaunchKernelGGL((sa_gram_kernel<R, 1>), dim3((unsigned)ugt.size()), dim3(256), 0, st,
-                           d_blk, d_state.as<SaState>(), d_ug.as<SaTask>(), scratch,
-                           d_parts.as<double>(), d_sab.as<SaBlk>());
+                           bests, d_sab.as<SaBlk>(), nu2, d_parts.as<double>());
         HM_HIP_CHECK(hipMemsetAsync(d_run.p, 0, sizeof(int), st));
         hipLaunchKernelGGL(sa_step_kernel<R>, dim3((unsigned)nblk), dim3(256), 0, st, d_blk,
                            d_state.as<SaState>(), bests, d_parts.as<double>(),
