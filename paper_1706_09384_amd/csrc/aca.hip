@@ -749,8 +749,9 @@ __global__ void __launch_bounds__(NT)
 // ---------------------------------------------------------------------------
 // Split form of the same greedy loop for blocks with many points: one ACA step
 // of all such blocks is a sequence of launches over many workgroups (residual
-// row, V Gram, pivot, V update, residual column, U Gram, step end), so that a
-// block with tens of thousands of rows is not confined to one CU.  Each step
+// row with its V Gram partials, pivot, V update, residual column with its U
+// Gram partials, step end), so that a block with tens of thousands of rows is
+// not confined to one CU.  Each step
 // takes the same decisions in the same order as the one-workgroup kernel; the
 // Gram columns are summed over fixed point slices (the order depends only on
 // the block), so a block gets the same factors whichever blocks share its
