@@ -453,18 +453,21 @@ __global__ void __launch_bounds__(NT)
     cplx<R> *V = fac + b.voff;
     uint8_t *used_i = flags + b.foff;
     uint8_t *used_j = used_i + m;
-    for (int k = tid; k < m + n; k += NT) used_i[k] = 0;
+    const bool resume = b.r0 > 0;
+    if (!resume)
+        for (int k = tid; k < m + n; k += NT) used_i[k] = 0;
     if (tid == 0) {
-        sh_ctl[0] = 0;
+        sh_ctl[0] = resume ? b.ih0 : 0;
         sh_ctl[5] = 0;
-        sh_norm2 = 0.0;
+        sh_norm2 = resume ? b.norm0 : 0.0;
     }
     __syncthreads();
 
     const bool isT = gp.kind == 1;
-    int r = 0, steps = 0, fallbacks = 0, status = 0;
+    int r = resume ? b.r0 : 0, steps = resume ? b.steps0 : 0;
+    int fallbacks = resume ? b.fallbacks0 : 0, status = 0;
     const int cap = min(m, n);
-    double norm2 = 0.0;
+    double norm2 = resume ? b.norm0 : 0.0;
     while (true) {
         if (steps >= cap) {
             status = 2;
@@ -742,6 +745,8 @@ __global__ void __launch_bounds__(NT)
         o.fallbacks = fallbacks;
         o.steps = steps;
         o.norm2 = norm2;
+        o.ih = sh_ctl[0];
+        o.pad = 0;
         outs[blockIdx.x] = o;
     }
 }
@@ -789,6 +794,8 @@ __device__ inline void sa_output(const SaState &st, AcaOut *o) {
     r.fallbacks = st.fallbacks;
     r.steps = st.steps;
     r.norm2 = st.norm2;
+    r.ih = st.ih;
+    r.pad = 0;
     *o = r;
 }
 
@@ -797,11 +804,21 @@ __global__ void __launch_bounds__(256)
     sa_init_kernel(const AcaBlk *__restrict__ blks, SaState *__restrict__ state,
                    uint8_t *__restrict__ flags, AcaOut *__restrict__ outs) {
     const AcaBlk b = blks[blockIdx.x];
+    const bool resume = b.r0 > 0;
     uint8_t *f = flags + b.foff;
-    for (int k = threadIdx.x; k < b.m + b.n; k += blockDim.x) f[k] = 0;
+    if (!resume)
+        for (int k = threadIdx.x; k < b.m + b.n; k += blockDim.x) f[k] = 0;
     if (threadIdx.x == 0) {
         SaState st{};
-        st.status = b.budget < 3 ? 1 : -1;
+        if (resume) {
+            st.r = b.r0;
+            st.steps = b.steps0;
+            st.fallbacks = b.fallbacks0;
+            st.ih = b.ih0;
+            st.norm2 = b.norm0;
+        }
+        // the checks the one-workgroup loop makes before a step
+        st.status = st.steps >= min(b.m, b.n) ? 2 : (st.r + 3 > b.budget ? 1 : -1);
         state[blockIdx.x] = st;
         if (st.status >= 0) sa_output(st, outs + blockIdx.x);
     }

@@ -528,6 +528,18 @@ void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vect
         1, std::min<int64_t>(nlr, ceil_div(total_need * (int64_t)sizeof(cplx<R>), cap_bytes)));
     std::vector<int32_t> aca_rank(nlr, 0), final_rank(nlr, 0);
     std::vector<int64_t> aca_u(nlr), aca_v(nlr), fu(nlr), fv(nlr);
+    // A block that uses up its budget continues later from where it stopped:
+    // its factor columns and used flags wait in a holding buffer, its loop
+    // state here.  The continued run takes the same steps as one run with the
+    // larger budget would.
+    struct Resume {
+        int32_t r = 0, steps = 0, fallbacks = 0, ih = 0;
+        double norm2 = 0.0;
+        const cplx<R> *u = nullptr, *v = nullptr;
+        const uint8_t *f = nullptr;
+    };
+    std::vector<Resume> resume(nlr);
+    std::vector<std::unique_ptr<DeviceBuf>> holding;
     std::vector<std::unique_ptr<DeviceBuf>> chunk_out;
     std::vector<int64_t> chunk_base, chunk_len;
     int64_t lr_entries = 0, t_len = 0;
@@ -590,6 +602,14 @@ void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vect
                 a.foff = flg;
                 flg += a.m + a.n;
                 maxb = std::max(maxb, a.budget);
+                const Resume &rs = resume[k];
+                if (rs.r > 0) {
+                    a.r0 = rs.r;
+                    a.steps0 = rs.steps;
+                    a.fallbacks0 = rs.fallbacks;
+                    a.ih0 = rs.ih;
+                    a.norm0 = rs.norm2;
+                }
             }
             if (pass_scratch.empty() && !last) S.aca_scratch_bytes += fac * (int64_t)sizeof(cplx<R>);
             L.scratch = std::make_unique<DeviceBuf>();
@@ -598,6 +618,20 @@ void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vect
             L.d_out = std::make_unique<DeviceBuf>();
             L.scratch->alloc(std::max<int64_t>(fac, 1) * sizeof(cplx<R>));
             L.flags->alloc(std::max<int64_t>(flg, 1));
+            // resumed blocks: earlier columns and flags into the new buffers
+            for (size_t q = 0; q < todo.size(); ++q) {
+                const AcaBlk &a = L.ab[q];
+                if (a.r0 <= 0) continue;
+                const Resume &rs = resume[todo[q]];
+                HM_HIP_CHECK(hipMemcpyAsync(L.scratch->template as<cplx<R>>() + a.uoff, rs.u,
+                                            3 * (size_t)a.m * a.r0 * sizeof(cplx<R>),
+                                            hipMemcpyDeviceToDevice, s));
+                HM_HIP_CHECK(hipMemcpyAsync(L.scratch->template as<cplx<R>>() + a.voff, rs.v,
+                                            3 * (size_t)a.n * a.r0 * sizeof(cplx<R>),
+                                            hipMemcpyDeviceToDevice, s));
+                HM_HIP_CHECK(hipMemcpyAsync(L.flags->template as<uint8_t>() + a.foff, rs.f,
+                                            (size_t)(a.m + a.n), hipMemcpyDeviceToDevice, s));
+            }
             upload(*L.d_ab, L.ab, s);
             L.d_out->alloc(L.ab.size() * sizeof(AcaOut));
             run_aca<R>(g, gp, L.ab, static_cast<AcaBlk *>(L.d_ab->p),
@@ -617,6 +651,46 @@ void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vect
             std::vector<int64_t> next;
             const int32_t pass = (int32_t)pass_scratch.size();
             pass_members.emplace_back();
+            // blocks that continue later keep their columns and flags
+            {
+                int64_t hf = 0, hb = 0;
+                for (size_t q = 0; q < L.todo.size(); ++q)
+                    if (res[q].status == 1 && budget[L.todo[q]] < budget_cap) {
+                        hf += 3 * (int64_t)(L.ab[q].m + L.ab[q].n) * res[q].rank;
+                        hb += L.ab[q].m + L.ab[q].n;
+                    }
+                if (hb > 0) {
+                    auto hfac = std::make_unique<DeviceBuf>(), hflg = std::make_unique<DeviceBuf>();
+                    hfac->alloc(std::max<int64_t>(hf, 1) * sizeof(cplx<R>));
+                    hflg->alloc(hb);
+                    int64_t of = 0, ob = 0;
+                    for (size_t q = 0; q < L.todo.size(); ++q) {
+                        const int64_t k = L.todo[q];
+                        if (!(res[q].status == 1 && budget[k] < budget_cap)) continue;
+                        const AcaBlk &a = L.ab[q];
+                        const int32_t rk = res[q].rank;
+                        cplx<R> *hu = hfac->template as<cplx<R>>() + of;
+                        cplx<R> *hv = hu + 3 * (int64_t)a.m * rk;
+                        uint8_t *hg = hflg->template as<uint8_t>() + ob;
+                        HM_HIP_CHECK(hipMemcpyAsync(hu, L.scratch->template as<cplx<R>>() + a.uoff,
+                                                    3 * (size_t)a.m * rk * sizeof(cplx<R>),
+                                                    hipMemcpyDeviceToDevice, L.s));
+                        HM_HIP_CHECK(hipMemcpyAsync(hv, L.scratch->template as<cplx<R>>() + a.voff,
+                                                    3 * (size_t)a.n * rk * sizeof(cplx<R>),
+                                                    hipMemcpyDeviceToDevice, L.s));
+                        HM_HIP_CHECK(hipMemcpyAsync(hg, L.flags->template as<uint8_t>() + a.foff,
+                                                    (size_t)(a.m + a.n), hipMemcpyDeviceToDevice,
+                                                    L.s));
+                        resume[k] = {rk, res[q].steps, res[q].fallbacks, res[q].ih, res[q].norm2,
+                                     hu, hv, hg};
+                        of += 3 * (int64_t)(a.m + a.n) * rk;
+                        ob += a.m + a.n;
+                    }
+                    HM_HIP_CHECK(hipStreamSynchronize(L.s));
+                    holding.push_back(std::move(hfac));
+                    holding.push_back(std::move(hflg));
+                }
+            }
             for (size_t q = 0; q < L.todo.size(); ++q) {
                 const int64_t k = L.todo[q];
                 if (res[q].status == 1 && budget[k] < budget_cap) {

@@ -86,7 +86,12 @@ struct AcaBlk {
     int64_t foff;         // offset of the used-flag bytes (m + n)
     int32_t rb, m, cb, n;
     int32_t budget;       // column budget
-    int32_t pad;
+    // r0 > 0: the block resumes a run that stopped at its budget; its first
+    // r0 factor columns and its used flags are already in place, and the
+    // run's step count, fallbacks, next row pivot and ||B_k||_F^2 follow.
+    int32_t r0;
+    int32_t steps0, fallbacks0, ih0, pad;
+    double norm0;
 };
 
 struct AcaOut {
@@ -95,6 +100,8 @@ struct AcaOut {
     int32_t fallbacks;
     int32_t steps;
     double norm2;         // recursive ||B_k||_F^2
+    int32_t ih;           // next row pivot (meaningful for status 1)
+    int32_t pad;
 };
 
 // Recompression work description.

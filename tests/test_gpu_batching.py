@@ -149,3 +149,39 @@ def test_chunked_assembly_is_bit_identical(hm, prec):
     say("chunks", s0["aca_chunks"], s1["aca_chunks"])
     assert s0["aca_chunks"] == 1 and s1["aca_chunks"] > 4
     same_blocks(H0, H1)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_overflow_resume_is_bit_identical(hm, prec):
+    """A block that outgrows its first column budget continues from where it
+    stopped with a larger one: with a first budget of 12 (many blocks resume
+    several times, on the split and the one-workgroup path) the factors equal
+    those of a build whose first budget is never exceeded."""
+    import torch
+    say(f"case overflow resume prec={prec}")
+    w = W.small_sphere(12000, omega=19.4, leaf=32, eps=1e-4)
+    X, _ = w.points()
+    H0 = hm.build_workload(w, X=X, prec=prec, rank_budget=600)
+    H1 = hm.build_workload(w, X=X, prec=prec, rank_budget=12)
+    s0, s1 = H0.info(), H1.info()
+    say("overflow", s0["n_overflow"], s1["n_overflow"], "max ACA rank", s0["max_rank_aca"])
+    assert s0["n_overflow"] == 0 and s1["n_overflow"] > 100
+    b0, r0, a0 = H0.export_blocklist()
+    b1, r1, a1 = H1.export_blocklist()
+    assert np.array_equal(b0, b1) and np.array_equal(r0, r1) and np.array_equal(a0, a1)
+    nx, ny = H0.export_tree(0)[1], H0.export_tree(1)[1]
+    pts = (nx[b0[:, 0], 1] - nx[b0[:, 0], 0]) + (ny[b0[:, 1], 1] - ny[b0[:, 1], 0])
+    lowrank = np.flatnonzero(b0[:, 2] == 1)
+    big = lowrank[pts[lowrank] >= 1500]
+    resumed = lowrank[a0[lowrank] > 12]
+    say("split blocks", big.size, "resumed blocks", resumed.size)
+    assert big.size > 0 and np.all(a0[big] > 12)
+    rng = np.random.default_rng(5)
+    pick = np.concatenate([big, rng.choice(resumed, min(200, resumed.size), replace=False)])
+    for k in pick:
+        d0 = H0.export_block(int(k), b0, r0, nx, ny)
+        d1 = H1.export_block(int(k), b1, r1, nx, ny)
+        assert all(np.array_equal(u, v) for u, v in zip(d0, d1)), int(k)
+    dt = H0.complex_dtype
+    x = torch.from_numpy(W.complex_normal(3 * w.n_points, 1, seed=9)[:, 0]).cuda().to(dt)
+    assert torch.equal(H0.matvec(x), H1.matvec(x))
