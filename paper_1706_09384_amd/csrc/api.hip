@@ -5,6 +5,8 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <exception>
+#include <future>
 #include <mutex>
 #include <numeric>
 #include <string>
@@ -539,6 +541,7 @@ void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vect
         const uint8_t *f = nullptr;
     };
     std::vector<Resume> resume(nlr);
+    std::vector<uint8_t> reran(nlr, 0);   // the first budget did not suffice
     std::vector<std::unique_ptr<DeviceBuf>> holding;
     std::vector<std::unique_ptr<DeviceBuf>> chunk_out;
     std::vector<int64_t> chunk_base, chunk_len;
@@ -695,12 +698,13 @@ void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vect
                 const int64_t k = L.todo[q];
                 if (res[q].status == 1 && budget[k] < budget_cap) {
                     ++overflow;
+                    reran[k] = 1;
                     budget[k] = std::min({3 * std::min(lm[k], ln[k]), 2 * budget[k], budget_cap});
                     next.push_back(k);
                     continue;
                 }
                 if (res[q].status == 1) ++capped;
-                if (pass == 0 && !last && from_model[k]) ++hits;
+                if (!reran[k] && from_model[k]) ++hits;
                 aca_rank[k] = res[q].rank;
                 aca_u[k] = L.ab[q].uoff;
                 aca_v[k] = L.ab[q].voff;
@@ -756,15 +760,49 @@ void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vect
         };
         hipStream_t aca_side = p.unbatched ? st : side_stream(1);
         {
-            AcaLaunch first = launch(members, st);
-            std::vector<int64_t> next = finish(first);
+            // Pass 0.  The blocks with many points run the split ACA, whose
+            // steps the host drives; they go to a worker thread and their own
+            // stream, so that the other blocks (one ACA launch) are finished
+            // and recompressed meanwhile, as pass 0, and the split blocks
+            // become pass 1.
+            std::vector<int64_t> big, small;
+            for (int64_t k : members)
+                (lm[k] + ln[k] >= kAcaBigPoints ? big : small).push_back(k);
+            std::vector<int64_t> next;
+            size_t ps0 = 0;
+            if (!p.unbatched && !big.empty() && !small.empty()) {
+                int dev = 0;
+                HM_HIP_CHECK(hipGetDevice(&dev));
+                auto split = std::async(std::launch::async, [&, dev]() {
+                    HM_HIP_CHECK(hipSetDevice(dev));
+                    return launch(big, aca_side);
+                });
+                std::exception_ptr err;
+                try {
+                    AcaLaunch first = launch(small, st);
+                    next = finish(first);
+                    recompress_pass(0);
+                } catch (...) {
+                    err = std::current_exception();
+                }
+                // the worker uses this scope's state: wait for it before
+                // anything unwinds (get() rethrows its own error)
+                AcaLaunch second = split.get();
+                if (err) std::rethrow_exception(err);
+                const std::vector<int64_t> n2 = finish(second);
+                next.insert(next.end(), n2.begin(), n2.end());
+                ps0 = 1;
+            } else {
+                AcaLaunch first = launch(members, st);
+                next = finish(first);
+            }
             if (defer) {
                 deferred.insert(deferred.end(), next.begin(), next.end());
                 next.clear();
             }
             t_aca += now_s() - tc;
             tc = now_s();
-            for (size_t ps = 0;; ++ps) {
+            for (size_t ps = ps0;; ++ps) {
                 const bool more = !next.empty();
                 AcaLaunch rerun;
                 if (more) rerun = launch(next, aca_side);   // runs beside ...
