@@ -765,12 +765,19 @@ void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vect
             // stream, so that the other blocks (one ACA launch) are finished
             // and recompressed meanwhile, as pass 0, and the split blocks
             // become pass 1.
+            // This pays off once the split blocks hold some 200,000 points
+            // together (a 20k-point sphere has 370,000); with fewer, the
+            // second recompression round costs more than the overlap saves.
             std::vector<int64_t> big, small;
-            for (int64_t k : members)
-                (lm[k] + ln[k] >= kAcaBigPoints ? big : small).push_back(k);
+            int64_t big_points = 0;
+            for (int64_t k : members) {
+                const bool b = lm[k] + ln[k] >= kAcaBigPoints;
+                (b ? big : small).push_back(k);
+                if (b) big_points += lm[k] + ln[k];
+            }
             std::vector<int64_t> next;
             size_t ps0 = 0;
-            if (!p.unbatched && !big.empty() && !small.empty()) {
+            if (!p.unbatched && big_points >= 200000 && !small.empty()) {
                 int dev = 0;
                 HM_HIP_CHECK(hipGetDevice(&dev));
                 auto split = std::async(std::launch::async, [&, dev]() {

@@ -151,15 +151,18 @@ def test_chunked_assembly_is_bit_identical(hm, prec):
     same_blocks(H0, H1)
 
 
-@pytest.mark.parametrize("prec", [0, 1])
-def test_overflow_resume_is_bit_identical(hm, prec):
+@pytest.mark.parametrize("which,prec", [("sphere12k", 0), ("sphere12k", 1), ("sphere20k", 1)])
+def test_overflow_resume_is_bit_identical(hm, which, prec):
     """A block that outgrows its first column budget continues from where it
     stopped with a larger one: with a first budget of 12 (many blocks resume
     several times, on the split and the one-workgroup path) the factors equal
-    those of a build whose first budget is never exceeded."""
+    those of a build whose first budget is never exceeded.  On the 20k sphere
+    the split blocks hold enough points for their ACA to run beside the other
+    blocks' recompression."""
     import torch
-    say(f"case overflow resume prec={prec}")
-    w = W.small_sphere(12000, omega=19.4, leaf=32, eps=1e-4)
+    say(f"case overflow resume {which} prec={prec}")
+    w = (W.small_sphere(12000, omega=19.4, leaf=32, eps=1e-4) if which == "sphere12k"
+         else W.precision_sphere_20k(1e-4))
     X, _ = w.points()
     H0 = hm.build_workload(w, X=X, prec=prec, rank_budget=600)
     H1 = hm.build_workload(w, X=X, prec=prec, rank_budget=12)
