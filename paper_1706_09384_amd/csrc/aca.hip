@@ -305,29 +305,14 @@ __device__ inline void gram_wave(const cplx<R> *X, int64_t ld, int p0, int p1, i
         for (int o = 4; o > 0; o >>= 1) out[k] += __shfl_xor(out[k], o, 64);
 }
 
-// Residual row entries of column point j (local index; pj in cluster order):
-// the 3x3 block K = A(i^, j) - U(i^, :) V(j, :)^* with the pivot row of U
-// staged in piv (3 x r, row a at piv + a r), written into the next three
-// columns of V as conj(K); an unused j is offered as a column pivot.
+// Residual-row terms l0 <= l < l1 of column point j: K -= U(i^, l) V(j, l)^*
+// with the pivot row of U staged in piv (3 x r, row a at piv + a r) and vrow
+// = V + 3 j (column-major, leading dimension ldv).
 template <typename R>
-__device__ inline void row_point(const Geometry &g, const GreenParams<R> &gp, bool isT, double xi0,
-                                 double xi1, double xi2, int pj, int j, const cplx<R> *piv,
-                                 cplx<R> *V, int64_t ldv, int r, bool unused, double nu2,
-                                 Best2 &best) {
-    cplx<R> K[9];
-    R nx = 0, ny = 0, nz = 0;
-    if (isT) {
-        nx = R(g.n[0][pj]);
-        ny = R(g.n[1][pj]);
-        nz = R(g.n[2][pj]);
-    }
-    green_block<R>(gp, xi0 - g.y[0][pj], xi1 - g.y[1][pj], xi2 - g.y[2][pj], nx, ny, nz, K);
-    double a2 = 0.0;   // |A(i, j)|_F^2 before the update: scale of the rounding noise
-#pragma unroll
-    for (int e = 0; e < 9; ++e) a2 += (double)abs2(K[e]);
-    const cplx<R> *vrow = V + 3 * j;
-    int l = 0;
-    for (; l + 4 <= r; l += 4) {
+__device__ inline void row_terms(cplx<R> (&K)[9], const cplx<R> *piv, const cplx<R> *vrow,
+                                 int64_t ldv, int r, int l0, int l1) {
+    int l = l0;
+    for (; l + 4 <= l1; l += 4) {
         cplx<R> vv[4][3];
 #pragma unroll
         for (int u = 0; u < 4; ++u)
@@ -342,7 +327,7 @@ __device__ inline void row_point(const Geometry &g, const GreenParams<R> &gp, bo
                 for (int be = 0; be < 3; ++be) fms_conj(K[3 * a + be], uu, vv[u][be]);
             }
     }
-    for (; l < r; ++l) {
+    for (; l < l1; ++l) {
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             const cplx<R> uu = piv[a * r + l];
@@ -350,6 +335,14 @@ __device__ inline void row_point(const Geometry &g, const GreenParams<R> &gp, bo
             for (int be = 0; be < 3; ++be) fms_conj(K[3 * a + be], uu, vrow[l * ldv + be]);
         }
     }
+}
+
+// The finished residual block K of column point j: written into the next
+// three columns of V as conj(K); an unused j is offered as a column pivot
+// (a2 = |A(i^, j)|_F^2, the scale of the rounding noise).
+template <typename R>
+__device__ inline void row_store(const cplx<R> (&K)[9], cplx<R> *V, int64_t ldv, int j, int r,
+                                 bool unused, double nu2, double a2, Best2 &best) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         cplx<R> *vn = V + (r + a) * ldv + 3 * j;
@@ -366,24 +359,44 @@ __device__ inline void row_point(const Geometry &g, const GreenParams<R> &gp, bo
     }
 }
 
-// Residual column entries of row point i (local index; pii in cluster order):
-// K = A(i, j^) - U(i, :) V(j^, :)^* with the pivot row of V staged in piv
-// (3 x r); an unused i is offered as the next row pivot, and the new U rows
-// 3i + a get K T (T: M^-1 or Z_p Sigma_p^-1; columns c >= p are zero).
+// Kernel block A(i^, j) of column point pj and its squared Frobenius norm.
 template <typename R>
-__device__ inline void col_point(const Geometry &g, const GreenParams<R> &gp, int pii, double yj0,
-                                 double yj1, double yj2, R njx, R njy, R njz, int i,
-                                 const cplx<R> *piv, cplx<R> *U, int64_t ldu, int r, int p,
-                                 const cplx<double> *T, bool unused, double nu2, Best2 &best) {
-    cplx<R> K[9];
-    green_block<R>(gp, g.x[0][pii] - yj0, g.x[1][pii] - yj1, g.x[2][pii] - yj2, njx, njy, njz,
-                   K);
+__device__ inline double row_kernel_block(const Geometry &g, const GreenParams<R> &gp, bool isT,
+                                          double xi0, double xi1, double xi2, int pj,
+                                          cplx<R> (&K)[9]) {
+    R nx = 0, ny = 0, nz = 0;
+    if (isT) {
+        nx = R(g.n[0][pj]);
+        ny = R(g.n[1][pj]);
+        nz = R(g.n[2][pj]);
+    }
+    green_block<R>(gp, xi0 - g.y[0][pj], xi1 - g.y[1][pj], xi2 - g.y[2][pj], nx, ny, nz, K);
     double a2 = 0.0;
 #pragma unroll
     for (int e = 0; e < 9; ++e) a2 += (double)abs2(K[e]);
-    const cplx<R> *urow = U + 3 * i;
-    int l = 0;
-    for (; l + 4 <= r; l += 4) {
+    return a2;
+}
+
+// Residual row entries of column point j (local index; pj in cluster order):
+// the 3x3 block K = A(i^, j) - U(i^, :) V(j, :)^*, stored by row_store.
+template <typename R>
+__device__ inline void row_point(const Geometry &g, const GreenParams<R> &gp, bool isT, double xi0,
+                                 double xi1, double xi2, int pj, int j, const cplx<R> *piv,
+                                 cplx<R> *V, int64_t ldv, int r, bool unused, double nu2,
+                                 Best2 &best) {
+    cplx<R> K[9];
+    const double a2 = row_kernel_block<R>(g, gp, isT, xi0, xi1, xi2, pj, K);
+    row_terms<R>(K, piv, V + 3 * j, ldv, r, 0, r);
+    row_store<R>(K, V, ldv, j, r, unused, nu2, a2, best);
+}
+
+// Residual-column terms l0 <= l < l1 of row point i: K -= U(i, l) V(j^, l)^*
+// with the pivot row of V staged in piv (3 x r) and urow = U + 3 i.
+template <typename R>
+__device__ inline void col_terms(cplx<R> (&K)[9], const cplx<R> *piv, const cplx<R> *urow,
+                                 int64_t ldu, int r, int l0, int l1) {
+    int l = l0;
+    for (; l + 4 <= l1; l += 4) {
         cplx<R> uu[4][3];
 #pragma unroll
         for (int u = 0; u < 4; ++u)
@@ -398,7 +411,7 @@ __device__ inline void col_point(const Geometry &g, const GreenParams<R> &gp, in
                 for (int a = 0; a < 3; ++a) fms_conj(K[3 * a + be], uu[u][a], v);
             }
     }
-    for (; l < r; ++l) {
+    for (; l < l1; ++l) {
 #pragma unroll
         for (int be = 0; be < 3; ++be) {
             const cplx<R> v = piv[be * r + l];
@@ -406,6 +419,15 @@ __device__ inline void col_point(const Geometry &g, const GreenParams<R> &gp, in
             for (int a = 0; a < 3; ++a) fms_conj(K[3 * a + be], urow[l * ldu + a], v);
         }
     }
+}
+
+// The finished residual block K of row point i: an unused i is offered as
+// the next row pivot, and the new U rows 3i + a get K T (T: M^-1 or
+// Z_p Sigma_p^-1; columns c >= p are zero).
+template <typename R>
+__device__ inline void col_store(const cplx<R> (&K)[9], cplx<R> *U, int64_t ldu, int i, int r,
+                                 int p, const cplx<double> *T, bool unused, double nu2, double a2,
+                                 Best2 &best) {
     if (unused) {
         cplx<double> Md[9];
 #pragma unroll
@@ -424,6 +446,32 @@ __device__ inline void col_point(const Geometry &g, const GreenParams<R> &gp, in
             U[(r + c) * ldu + 3 * i + a] = cvt<R>(c < p ? s : cplx<double>{0, 0});
         }
     }
+}
+
+// Kernel block A(i, j^) of row point pii and its squared Frobenius norm.
+template <typename R>
+__device__ inline double col_kernel_block(const Geometry &g, const GreenParams<R> &gp, int pii,
+                                          double yj0, double yj1, double yj2, R njx, R njy,
+                                          R njz, cplx<R> (&K)[9]) {
+    green_block<R>(gp, g.x[0][pii] - yj0, g.x[1][pii] - yj1, g.x[2][pii] - yj2, njx, njy, njz,
+                   K);
+    double a2 = 0.0;
+#pragma unroll
+    for (int e = 0; e < 9; ++e) a2 += (double)abs2(K[e]);
+    return a2;
+}
+
+// Residual column entries of row point i (local index; pii in cluster order):
+// K = A(i, j^) - U(i, :) V(j^, :)^*, stored by col_store.
+template <typename R>
+__device__ inline void col_point(const Geometry &g, const GreenParams<R> &gp, int pii, double yj0,
+                                 double yj1, double yj2, R njx, R njy, R njz, int i,
+                                 const cplx<R> *piv, cplx<R> *U, int64_t ldu, int r, int p,
+                                 const cplx<double> *T, bool unused, double nu2, Best2 &best) {
+    cplx<R> K[9];
+    const double a2 = col_kernel_block<R>(g, gp, pii, yj0, yj1, yj2, njx, njy, njz, K);
+    col_terms<R>(K, piv, U + 3 * i, ldu, r, 0, r);
+    col_store<R>(K, U, ldu, i, r, p, T, unused, nu2, a2, best);
 }
 
 template <typename R, int NT>
@@ -746,7 +794,7 @@ __global__ void __launch_bounds__(NT)
         o.steps = steps;
         o.norm2 = norm2;
         o.ih = sh_ctl[0];
-        o.pad = 0;
+        o.pend = 0;
         outs[blockIdx.x] = o;
     }
 }
@@ -754,21 +802,28 @@ __global__ void __launch_bounds__(NT)
 // ---------------------------------------------------------------------------
 // Split form of the same greedy loop for blocks with many points: one ACA step
 // of all such blocks is a sequence of launches over many workgroups (residual
-// row with its V Gram partials, pivot, V update, residual column with its U
-// Gram partials, step end), so that a block with tens of thousands of rows is
-// not confined to one CU.  Each step
-// takes the same decisions in the same order as the one-workgroup kernel; the
-// Gram columns are summed over fixed point slices (the order depends only on
-// the block), so a block gets the same factors whichever blocks share its
-// launches.
+// row, pivot, V update, residual column, step end), so that a block with tens
+// of thousands of rows is not confined to one CU.
+//
+// The residual passes read every factor column once, and the Gram columns of
+// the norm recurrence come from the same loads: each pass sums, besides the
+// residual, the Gram of all its columns against the columns of the previous
+// step's term (final by then).  The stopping test of a term therefore runs in
+// the step after it; when it says stop, that step's new term is dropped, so
+// the factors and decisions are those of testing at once.  Gram partials are
+// kept per 64-point slice and summed in slice order (an order that depends
+// only on the block), so a block gets the same factors whichever blocks
+// share its launches.
 constexpr int kSaTile = 256;     // points per workgroup of the residual passes
-constexpr int kSaSlice = kSaTile; // points per Gram slice: the residual tile's points
+constexpr int kSaSlice = 64;     // points per Gram slice: one wave of a residual tile
 constexpr int kSaSync = 4;       // steps queued between readbacks of the running count
 
 struct SaState {
     int32_t r, steps, status, fallbacks;   // status -1 while running, then as AcaOut
     int32_t ih, jh, mode, p;
-    int32_t skip, pad0, pad1, pad2;        // skip: this step found a zero residual row
+    int32_t skip, pq, pad1, pad2;          // skip: this step found a zero residual row;
+                                           // pq: columns r - pq .. r - 1 of the last term, whose
+                                           // stopping test runs with the next step
     double norm2, anorm;
     cplx<double> T[9], W[9];
 };
@@ -795,7 +850,7 @@ __device__ inline void sa_output(const SaState &st, AcaOut *o) {
     r.steps = st.steps;
     r.norm2 = st.norm2;
     r.ih = st.ih;
-    r.pad = 0;
+    r.pend = st.pq;
     *o = r;
 }
 
@@ -815,6 +870,7 @@ __global__ void __launch_bounds__(256)
             st.steps = b.steps0;
             st.fallbacks = b.fallbacks0;
             st.ih = b.ih0;
+            st.pq = b.pend0;
             st.norm2 = b.norm0;
         }
         // the checks the one-workgroup loop makes before a step
@@ -824,32 +880,50 @@ __global__ void __launch_bounds__(256)
     }
 }
 
-// Gram partials of one point slice (the points of residual tile t): wave w
-// takes the column chunks w, w + 4, ...; SIDE 0 is V against its three new
-// columns (l < r + 3), SIDE 1 is U against its p new columns (l < r + p).
-// Called by the residual kernels after the new columns are written (their
-// last barrier makes them visible to the whole workgroup).
-template <typename R, int SIDE>
-__device__ inline void sa_gram_slice(const AcaBlk &b, const SaBlk &sb, int r, int p, int t,
-                                     const cplx<R> *__restrict__ fac, double *__restrict__ parts) {
-    const int npts = SIDE == 0 ? b.n : b.m;
-    const int64_t ld = 3 * (int64_t)npts;
-    const cplx<R> *X = fac + (SIDE == 0 ? b.voff : b.uoff);
-    const int lmax = r + (SIDE == 0 ? 3 : p);
-    const int p0 = t * kSaSlice, p1 = min(npts, p0 + kSaSlice);
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    double *out = parts + (SIDE == 0 ? sb.vgoff : sb.ugoff) + (int64_t)t * sb.nchunk * 24;
-    for (int c = wave; 4 * c < lmax; c += 4) {
-        double v3[3];
-        gram_wave<R>(X, ld, p0, p1, 4 * c, lmax, r, lane, v3);
-        if ((lane & 7) == 0) {
-            const int vb = gram_vbase(lane);
-            for (int k = 0; k < 3; ++k) out[c * 24 + vb + k] = v3[k];
-        }
+// Sums v over the wave (entry 6 u + 2 c + {0: re, 1: im}: column u of a
+// four-column chunk against column c of the previous term) by recursive
+// halving, as the Gram of the one-workgroup kernel does, and writes the 24
+// sums to out.
+__device__ inline void sa_wave_put(const double (&v)[24], int lane, double *out) {
+    double h12[12], h6[6], o3[3];
+    halve<24>(v, h12, 32, (lane & 32) != 0);
+    halve<12>(h12, h6, 16, (lane & 16) != 0);
+    halve<6>(h6, o3, 8, (lane & 8) != 0);
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int o = 4; o > 0; o >>= 1) o3[k] += __shfl_xor(o3[k], o, 64);
+    if ((lane & 7) == 0) {
+        const int vb = gram_vbase(lane);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) out[vb + k] = o3[k];
     }
 }
 
-// Residual row pass, one workgroup per kSaTile column points.
+// Gram entries of one point: acc(u, c) = sum_k conj(x[u][k]) y[c][k] for the
+// four columns x[u] of a chunk against the q <= 3 columns y[c] (products and
+// the three-term sums in R, as in the one-workgroup kernel).
+template <typename R>
+__device__ inline void sa_gram_point(const cplx<R> (&x)[4][3], const cplx<R> (&y)[3][3],
+                                     double (&acc)[24]) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            R re = 0, im = 0;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const cplx<R> o = x[u][k], n = y[c][k];
+                re += o.re * n.re + o.im * n.im;
+                im += o.re * n.im - o.im * n.re;
+            }
+            acc[6 * u + 2 * c] = double(re);
+            acc[6 * u + 2 * c + 1] = double(im);
+        }
+}
+
+// Residual row pass, one workgroup per kSaTile column points.  Wave w of tile
+// t owns Gram slice 4 t + w: V(:, l)^* V(:, r - pq + c) for l < r, c < pq.
 template <typename R>
 __global__ void __launch_bounds__(256)
     sa_row_kernel(Geometry g, GreenParams<R> gp, const AcaBlk *__restrict__ blks,
@@ -864,7 +938,9 @@ __global__ void __launch_bounds__(256)
     const SaState st = state[tk.s];
     if (!sa_running(st)) return;
     const AcaBlk b = blks[tk.s];
-    const int r = st.r, ih = st.ih, tid = threadIdx.x;
+    const SaBlk sb = sab[tk.s];
+    const int r = st.r, ih = st.ih, pq = st.pq, tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
     const int64_t ldu = 3 * (int64_t)b.m, ldv = 3 * (int64_t)b.n;
     const cplx<R> *U = fac + b.uoff;
     cplx<R> *V = fac + b.voff;
@@ -874,15 +950,77 @@ __global__ void __launch_bounds__(256)
         piv[a * r + l] = U[l * ldu + 3 * ih + a];
     }
     __syncthreads();
-    const int pi = b.rb + ih;
-    Best2 best = {-1.0, INT_MAX, -1.0, INT_MAX};
     const int j = tk.t * kSaTile + tid;
-    if (j < b.n)
-        row_point<R>(g, gp, gp.kind == 1, g.x[0][pi], g.x[1][pi], g.x[2][pi], b.cb + j, j, piv, V,
-                     ldv, r, !used_j[j], nu2, best);
+    const bool in = j < b.n;
+    const int slice = tk.t * (kSaTile / kSaSlice) + wave;
+    const bool gram = pq > 0 && slice * kSaSlice < b.n;   // uniform over the wave
+    cplx<R> K[9];
+    double a2 = 0.0;
+    if (in) {
+        const int pi = b.rb + ih;
+        a2 = row_kernel_block<R>(g, gp, gp.kind == 1, g.x[0][pi], g.x[1][pi], g.x[2][pi],
+                                 b.cb + j, K);
+    } else {
+#pragma unroll
+        for (int e = 0; e < 9; ++e) K[e] = {R(0), R(0)};
+    }
+    const cplx<R> *vrow = V + 3 * (int64_t)(in ? j : 0);
+    // the previous term's columns at this point
+    cplx<R> pv[3][3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int be = 0; be < 3; ++be)
+            pv[c][be] = (in && c < pq) ? vrow[(r - pq + c) * ldv + be] : cplx<R>{R(0), R(0)};
+    double *out = parts + sb.vgoff + (int64_t)slice * sb.nchunk * 24;
+    int l = 0;
+    for (; l + 4 <= r; l += 4) {
+        cplx<R> vv[4][3];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int be = 0; be < 3; ++be)
+                vv[u][be] = in ? vrow[(l + u) * ldv + be] : cplx<R>{R(0), R(0)};
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const cplx<R> uu = piv[a * r + l + u];
+#pragma unroll
+                for (int be = 0; be < 3; ++be) fms_conj(K[3 * a + be], uu, vv[u][be]);
+            }
+        if (gram) {
+            double acc[24];
+            sa_gram_point<R>(vv, pv, acc);
+            sa_wave_put(acc, lane, out + (l / 4) * 24);
+        }
+    }
+    if (l < r) {   // last chunk, r - l < 4 columns
+        cplx<R> vv[4][3];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int be = 0; be < 3; ++be)
+                vv[u][be] = (in && l + u < r) ? vrow[(l + u) * ldv + be] : cplx<R>{R(0), R(0)};
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (l + u < r)
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const cplx<R> uu = piv[a * r + l + u];
+#pragma unroll
+                    for (int be = 0; be < 3; ++be) fms_conj(K[3 * a + be], uu, vv[u][be]);
+                }
+        if (gram) {
+            double acc[24];
+            sa_gram_point<R>(vv, pv, acc);
+            sa_wave_put(acc, lane, out + (l / 4) * 24);
+        }
+    }
+    Best2 best = {-1.0, INT_MAX, -1.0, INT_MAX};
+    if (in) row_store<R>(K, V, ldv, j, r, !used_j[j], nu2, a2, best);
     best = block_best2(best, sh_best);
-    if (tid == 0) bests[sab[tk.s].rowt0 + tk.t] = best;
-    sa_gram_slice<R, 0>(b, sab[tk.s], r, 0, tk.t, fac, parts);
+    if (tid == 0) bests[sb.rowt0 + tk.t] = best;
 }
 
 // Sum of value v of chunk c over the slices of a Gram (slice order).
@@ -903,10 +1041,8 @@ __global__ void __launch_bounds__(256)
                     const SaBlk *__restrict__ sab, AcaOut *__restrict__ outs, double tau_piv,
                     double nu2) {
     __shared__ Best2 sh_best[4];
-    __shared__ cplx<double> sh_M[9], sh_W[9];
-    __shared__ double sh_out[24];
+    __shared__ cplx<double> sh_M[9];
     __shared__ double sh_anorm;
-    __shared__ int sh_mode, sh_p;
     const int s = blockIdx.x, tid = threadIdx.x;
     SaState st = state[s];
     if (!sa_running(st)) return;
@@ -957,10 +1093,11 @@ __global__ void __launch_bounds__(256)
     }
     const bool degenerate = best.s3 <= tau_piv * tau_piv * best.fro;
     const int jh = degenerate ? best.ifro : best.i3;
-    // V Gram columns cv[l][c] = V[:, l]^* Vraw[:, r + c], l < r + 3
+    // V Gram columns of the previous term: cv[l][c] = V[:, l]^* V[:, r - pq + c],
+    // l < r, c < pq
     cplx<double> *cv = cvall + sb.cvoff;
     const int nsl = (n + kSaSlice - 1) / kSaSlice;
-    for (int q = tid; q < 6 * (r + 3); q += 256) {
+    for (int q = tid; q < 6 * r && st.pq > 0; q += 256) {
         // double q of cv is value 6 (l % 4) + q % 6 of chunk l / 4, l = q / 6
         const int l = q / 6;
         reinterpret_cast<double *>(cv)[q] =
@@ -1043,34 +1180,9 @@ __global__ void __launch_bounds__(256)
             st.p = p;
             ++st.fallbacks;
         }
-        for (int e = 0; e < 9; ++e) sh_W[e] = st.W[e];
-        sh_mode = st.mode;
-        sh_p = st.p;
         st.jh = jh;
         st.anorm = sh_anorm;
         state[s] = st;
-    }
-    __syncthreads();
-    if (sh_mode == 1) {
-        // cv[l][:] <- cv[l][:] W for old columns; the new-new block becomes W^* G W
-        for (int l = tid; l < r + 3; l += 256) {
-            cplx<double> row[3] = {cv[3 * l], cv[3 * l + 1], cv[3 * l + 2]};
-            for (int c = 0; c < 3; ++c) {
-                cplx<double> t = {0, 0};
-                for (int a = 0; a < 3; ++a) t = t + row[a] * sh_W[3 * a + c];
-                cv[3 * l + c] = t;
-            }
-        }
-        __syncthreads();
-        if (tid < 9) {
-            const int a = tid / 3, c = tid % 3;
-            cplx<double> t = {0, 0};
-            for (int k = 0; k < 3; ++k) t = t + cmul(sh_W[3 * k + a], cv[3 * (r + k) + c]);
-            sh_out[2 * tid] = t.re;
-            sh_out[2 * tid + 1] = t.im;
-        }
-        __syncthreads();
-        if (tid < 9) cv[3 * (r + tid / 3) + tid % 3] = {sh_out[2 * tid], sh_out[2 * tid + 1]};
     }
 }
 
@@ -1100,7 +1212,9 @@ __global__ void __launch_bounds__(256)
         }
 }
 
-// Residual column pass and U_new, one workgroup per kSaTile row points.
+// Residual column pass and U_new, one workgroup per kSaTile row points.  Wave
+// w of tile t owns Gram slice 4 t + w: U(:, l)^* U(:, r - pq + c) for l < r,
+// c < pq.
 template <typename R>
 __global__ void __launch_bounds__(256)
     sa_col_kernel(Geometry g, GreenParams<R> gp, const AcaBlk *__restrict__ blks,
@@ -1116,7 +1230,9 @@ __global__ void __launch_bounds__(256)
     const SaState &gst = state[tk.s];
     if (!sa_running(gst)) return;
     const AcaBlk b = blks[tk.s];
-    const int r = gst.r, jh = gst.jh, p = gst.p, tid = threadIdx.x;
+    const SaBlk sb = sab[tk.s];
+    const int r = gst.r, jh = gst.jh, p = gst.p, pq = gst.pq, tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
     const int64_t ldu = 3 * (int64_t)b.m, ldv = 3 * (int64_t)b.n;
     cplx<R> *U = fac + b.uoff;
     const cplx<R> *V = fac + b.voff;
@@ -1127,21 +1243,82 @@ __global__ void __launch_bounds__(256)
     }
     if (tid < 9) sh_T[tid] = gst.T[tid];
     __syncthreads();
-    const int pj = b.cb + jh;
-    R njx = 0, njy = 0, njz = 0;
-    if (gp.kind == 1) {
-        njx = R(g.n[0][pj]);
-        njy = R(g.n[1][pj]);
-        njz = R(g.n[2][pj]);
+    const int i = tk.t * kSaTile + tid;
+    const bool in = i < b.m;
+    const int slice = tk.t * (kSaTile / kSaSlice) + wave;
+    const bool gram = pq > 0 && slice * kSaSlice < b.m;   // uniform over the wave
+    cplx<R> K[9];
+    double a2 = 0.0;
+    if (in) {
+        const int pj = b.cb + jh;
+        R njx = 0, njy = 0, njz = 0;
+        if (gp.kind == 1) {
+            njx = R(g.n[0][pj]);
+            njy = R(g.n[1][pj]);
+            njz = R(g.n[2][pj]);
+        }
+        a2 = col_kernel_block<R>(g, gp, b.rb + i, g.y[0][pj], g.y[1][pj], g.y[2][pj], njx, njy,
+                                 njz, K);
+    } else {
+#pragma unroll
+        for (int e = 0; e < 9; ++e) K[e] = {R(0), R(0)};
+    }
+    const cplx<R> *urow = U + 3 * (int64_t)(in ? i : 0);
+    cplx<R> pu[3][3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            pu[c][a] = (in && c < pq) ? urow[(r - pq + c) * ldu + a] : cplx<R>{R(0), R(0)};
+    double *out = parts + sb.ugoff + (int64_t)slice * sb.nchunk * 24;
+    int l = 0;
+    for (; l + 4 <= r; l += 4) {
+        cplx<R> uu[4][3];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+                uu[u][a] = in ? urow[(l + u) * ldu + a] : cplx<R>{R(0), R(0)};
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int be = 0; be < 3; ++be) {
+                const cplx<R> v = piv[be * r + l + u];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) fms_conj(K[3 * a + be], uu[u][a], v);
+            }
+        if (gram) {
+            double acc[24];
+            sa_gram_point<R>(uu, pu, acc);
+            sa_wave_put(acc, lane, out + (l / 4) * 24);
+        }
+    }
+    if (l < r) {   // last chunk, r - l < 4 columns
+        cplx<R> uu[4][3];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+                uu[u][a] = (in && l + u < r) ? urow[(l + u) * ldu + a] : cplx<R>{R(0), R(0)};
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (l + u < r)
+#pragma unroll
+                for (int be = 0; be < 3; ++be) {
+                    const cplx<R> v = piv[be * r + l + u];
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) fms_conj(K[3 * a + be], uu[u][a], v);
+                }
+        if (gram) {
+            double acc[24];
+            sa_gram_point<R>(uu, pu, acc);
+            sa_wave_put(acc, lane, out + (l / 4) * 24);
+        }
     }
     Best2 best = {-1.0, INT_MAX, -1.0, INT_MAX};
-    const int i = tk.t * kSaTile + tid;
-    if (i < b.m)
-        col_point<R>(g, gp, b.rb + i, g.y[0][pj], g.y[1][pj], g.y[2][pj], njx, njy, njz, i, piv,
-                     U, ldu, r, p, sh_T, !used_i[i], nu2, best);
+    if (in) col_store<R>(K, U, ldu, i, r, p, sh_T, !used_i[i], nu2, a2, best);
     best = block_best2(best, sh_best);
-    if (tid == 0) bests[sab[tk.s].colt0 + tk.t] = best;
-    sa_gram_slice<R, 1>(b, sab[tk.s], r, p, tk.t, fac, parts);
+    if (tid == 0) bests[sb.colt0 + tk.t] = best;
 }
 
 // Step end, one workgroup per block: next row pivot, the norm recurrence and
@@ -1188,17 +1365,20 @@ __global__ void __launch_bounds__(256)
     int next_i = -1;
     if (best.ifro != INT_MAX)
         next_i = (best.s3 <= tau_piv * tau_piv * best.fro) ? best.ifro : best.i3;
-    // cross = 2 Re sum_{l < r, c < p} cu conj(cv), fresh = Re sum_{l >= r, c < p} ...
+    // Stopping test of the previous term (columns r - pq .. r - 1), from the
+    // Gram columns of both passes of this step:
+    // cross = 2 Re sum_{l < r - pq, c < pq} cu conj(cv), fresh = the rest
+    const int pq = st.pq;
     const cplx<double> *cv = cvall + sb.cvoff;
     const int nsl = (m + kSaSlice - 1) / kSaSlice;
     double cross = 0.0, fresh = 0.0;
-    for (int q = tid; q < 6 * (r + p); q += 256) {
+    for (int q = tid; q < 6 * r && pq > 0; q += 256) {
         const int l = q / 6, c = (q % 6) >> 1;
-        if (c >= p) continue;
+        if (c >= pq) continue;
         const double u = sa_gram_sum(parts + sb.ugoff, nsl, sb.nchunk, l / 4, 6 * (l % 4) + q % 6);
         const cplx<double> w = cv[3 * l + c];
         const double t = u * ((q & 1) ? w.im : w.re);
-        if (l < r)
+        if (l < r - pq)
             cross += 2.0 * t;
         else
             fresh += t;
@@ -1219,19 +1399,30 @@ __global__ void __launch_bounds__(256)
             cross += sh_sum[2 * w];
             fresh += sh_sum[2 * w + 1];
         }
-        st.norm2 += cross + fresh;
-        const bool stop = (fresh <= eps * eps * st.norm2) || next_i < 0;
-        st.r = r + p;
-        ++st.steps;
+        bool stop_prev = false;
+        if (pq > 0) {
+            st.norm2 += cross + fresh;
+            stop_prev = fresh <= eps * eps * st.norm2;
+        }
         const int cap = min(b.m, b.n);
-        if (stop) {
+        if (stop_prev) {
+            // the previous term met the test: this step's term is dropped
+            if (st.mode == 1) --st.fallbacks;
+            st.pq = 0;
             st.status = (st.steps >= cap) ? 2 : 0;
         } else {
-            st.ih = next_i;
-            if (st.steps >= cap)
-                st.status = 2;
-            else if (st.r + 3 > b.budget)
-                st.status = 1;
+            st.r = r + p;
+            ++st.steps;
+            st.pq = p;
+            if (next_i < 0) {
+                st.status = (st.steps >= cap) ? 2 : 0;
+            } else {
+                st.ih = next_i;
+                if (st.steps >= cap)
+                    st.status = 2;
+                else if (st.r + 3 > b.budget)
+                    st.status = 1;
+            }
         }
         if (st.status >= 0)
             sa_output(st, outs + s);

@@ -535,7 +535,7 @@ void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vect
     // state here.  The continued run takes the same steps as one run with the
     // larger budget would.
     struct Resume {
-        int32_t r = 0, steps = 0, fallbacks = 0, ih = 0;
+        int32_t r = 0, steps = 0, fallbacks = 0, ih = 0, pend = 0;
         double norm2 = 0.0;
         const cplx<R> *u = nullptr, *v = nullptr;
         const uint8_t *f = nullptr;
@@ -611,6 +611,7 @@ void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vect
                     a.steps0 = rs.steps;
                     a.fallbacks0 = rs.fallbacks;
                     a.ih0 = rs.ih;
+                    a.pend0 = rs.pend;
                     a.norm0 = rs.norm2;
                 }
             }
@@ -684,8 +685,8 @@ void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vect
                         HM_HIP_CHECK(hipMemcpyAsync(hg, L.flags->template as<uint8_t>() + a.foff,
                                                     (size_t)(a.m + a.n), hipMemcpyDeviceToDevice,
                                                     L.s));
-                        resume[k] = {rk, res[q].steps, res[q].fallbacks, res[q].ih, res[q].norm2,
-                                     hu, hv, hg};
+                        resume[k] = {rk, res[q].steps, res[q].fallbacks, res[q].ih, res[q].pend,
+                                     res[q].norm2, hu, hv, hg};
                         of += 3 * (int64_t)(a.m + a.n) * rk;
                         ob += a.m + a.n;
                     }

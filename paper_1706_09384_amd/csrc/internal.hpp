@@ -88,9 +88,11 @@ struct AcaBlk {
     int32_t budget;       // column budget
     // r0 > 0: the block resumes a run that stopped at its budget; its first
     // r0 factor columns and its used flags are already in place, and the
-    // run's step count, fallbacks, next row pivot and ||B_k||_F^2 follow.
+    // run's step count, fallbacks, next row pivot, the column count of its
+    // last term whose stopping test is still open (split ACA) and
+    // ||B_k||_F^2 follow.
     int32_t r0;
-    int32_t steps0, fallbacks0, ih0, pad;
+    int32_t steps0, fallbacks0, ih0, pend0;
     double norm0;
 };
 
@@ -101,7 +103,7 @@ struct AcaOut {
     int32_t steps;
     double norm2;         // recursive ||B_k||_F^2
     int32_t ih;           // next row pivot (meaningful for status 1)
-    int32_t pad;
+    int32_t pend;         // columns of the last term whose stopping test is open (status 1)
 };
 
 // Recompression work description.
