@@ -1023,11 +1023,40 @@ __global__ void __launch_bounds__(256)
     if (tid == 0) bests[sb.rowt0 + tk.t] = best;
 }
 
-// Sum of value v of chunk c over the slices of a Gram (slice order).
-__device__ inline double sa_gram_sum(const double *parts, int nslice, int nchunk, int c, int v) {
+// Gram columns of the open term, summed over the slices: out (doubles) value
+// q < 6 r is the sum of value 6 (l % 4) + q % 6 of chunk l / 4, l = q / 6,
+// over the slices of the block (SIDE 0: V, after the row pass; SIDE 1: U,
+// after the column pass).  One workgroup per block and 64 values; wave w sums
+// the slices w, w + 4, ..., and the four partial sums are added in wave order.
+template <int SIDE>
+__global__ void __launch_bounds__(256)
+    sa_gsum_kernel(const AcaBlk *__restrict__ blks, const SaState *__restrict__ state,
+                   const SaBlk *__restrict__ sab, const double *__restrict__ parts,
+                   cplx<double> *__restrict__ outall, int ngroups) {
+    __shared__ double sh[4][64];
+    const int s = blockIdx.x / ngroups, q0 = (blockIdx.x % ngroups) * 64;
+    const SaState st = state[s];
+    if (!sa_running(st) || st.pq == 0 || q0 >= 6 * st.r) return;   // uniform
+    const AcaBlk b = blks[s];
+    const SaBlk sb = sab[s];
+    const int npts = SIDE == 0 ? b.n : b.m;
+    const int nsl = (npts + kSaSlice - 1) / kSaSlice;
+    const int tv = threadIdx.x & 63, ts = threadIdx.x >> 6;
+    const int q = q0 + tv;
+    const bool has = q < 6 * st.r;
     double t = 0.0;
-    for (int sl = 0; sl < nslice; ++sl) t += parts[((int64_t)sl * nchunk + c) * 24 + v];
-    return t;
+    if (has) {
+        const int l = q / 6;
+        const double *src = parts + (SIDE == 0 ? sb.vgoff : sb.ugoff) + (l / 4) * 24 +
+                            6 * (l % 4) + q % 6;
+        const int64_t stride = (int64_t)sb.nchunk * 24;
+        for (int sl = ts; sl < nsl; sl += 4) t += src[sl * stride];
+    }
+    sh[ts][tv] = t;
+    __syncthreads();
+    if (ts == 0 && has)
+        reinterpret_cast<double *>(outall + sb.cvoff)[q] =
+            ((sh[0][tv] + sh[1][tv]) + sh[2][tv]) + sh[3][tv];
 }
 
 // Column pivot of the step, one workgroup per block: the row pass's best
@@ -1093,16 +1122,6 @@ __global__ void __launch_bounds__(256)
     }
     const bool degenerate = best.s3 <= tau_piv * tau_piv * best.fro;
     const int jh = degenerate ? best.ifro : best.i3;
-    // V Gram columns of the previous term: cv[l][c] = V[:, l]^* V[:, r - pq + c],
-    // l < r, c < pq
-    cplx<double> *cv = cvall + sb.cvoff;
-    const int nsl = (n + kSaSlice - 1) / kSaSlice;
-    for (int q = tid; q < 6 * r && st.pq > 0; q += 256) {
-        // double q of cv is value 6 (l % 4) + q % 6 of chunk l / 4, l = q / 6
-        const int l = q / 6;
-        reinterpret_cast<double *>(cv)[q] =
-            sa_gram_sum(parts + sb.vgoff, nsl, sb.nchunk, l / 4, 6 * (l % 4) + q % 6);
-    }
     if (tid == 0) {
         for (int a = 0; a < 3; ++a)
             for (int be = 0; be < 3; ++be)
@@ -1327,7 +1346,8 @@ template <typename R>
 __global__ void __launch_bounds__(256)
     sa_step_kernel(const AcaBlk *__restrict__ blks, SaState *__restrict__ state,
                    const Best2 *__restrict__ bests, const double *__restrict__ parts,
-                   const cplx<double> *__restrict__ cvall, const SaBlk *__restrict__ sab,
+                   const cplx<double> *__restrict__ cvall,
+                   const cplx<double> *__restrict__ cuall, const SaBlk *__restrict__ sab,
                    AcaOut *__restrict__ outs, double eps, double tau_piv,
                    int *__restrict__ running) {
     __shared__ Best2 sh_best[4];
@@ -1370,12 +1390,12 @@ __global__ void __launch_bounds__(256)
     // cross = 2 Re sum_{l < r - pq, c < pq} cu conj(cv), fresh = the rest
     const int pq = st.pq;
     const cplx<double> *cv = cvall + sb.cvoff;
-    const int nsl = (m + kSaSlice - 1) / kSaSlice;
+    const double *cu = reinterpret_cast<const double *>(cuall + sb.cvoff);
     double cross = 0.0, fresh = 0.0;
     for (int q = tid; q < 6 * r && pq > 0; q += 256) {
         const int l = q / 6, c = (q % 6) >> 1;
         if (c >= pq) continue;
-        const double u = sa_gram_sum(parts + sb.ugoff, nsl, sb.nchunk, l / 4, 6 * (l % 4) + q % 6);
+        const double u = cu[q];
         const cplx<double> w = cv[3 * l + c];
         const double t = u * ((q & 1) ? w.im : w.re);
         if (l < r - pq)
@@ -1464,7 +1484,7 @@ static void run_aca_split(const Geometry &g, const GreenParams<R> &gp, const Aca
     }
     // column-pass bests follow the row-pass bests
     for (auto &sb : sab) sb.colt0 += (int32_t)rowt.size();
-    DeviceBuf d_sab, d_row, d_col, d_state, d_cv, d_parts, d_bests, d_run;
+    DeviceBuf d_sab, d_row, d_col, d_state, d_cv, d_cu, d_parts, d_bests, d_run;
     auto put = [&](DeviceBuf &d, const auto &v) {
         using E = typename std::decay_t<decltype(v)>::value_type;
         d.alloc(std::max<size_t>(v.size(), 1) * sizeof(E));
@@ -1477,6 +1497,8 @@ static void run_aca_split(const Geometry &g, const GreenParams<R> &gp, const Aca
     put(d_col, colt);
     d_state.alloc(nblk * sizeof(SaState));
     d_cv.alloc(std::max<int64_t>(cvlen, 1) * sizeof(cplx<double>));
+    d_cu.alloc(std::max<int64_t>(cvlen, 1) * sizeof(cplx<double>));
+    const int ngroups = (6 * maxb + 63) / 64;   // 64 Gram values per summing workgroup
     d_parts.alloc(std::max<int64_t>(plen, 1) * sizeof(double));
     d_bests.alloc((rowt.size() + colt.size()) * sizeof(Best2));
     d_run.alloc(sizeof(int));
@@ -1499,11 +1521,17 @@ static void run_aca_split(const Geometry &g, const GreenParams<R> &gp, const Aca
         hipLaunchKernelGGL(sa_col_kernel<R>, dim3((unsigned)colt.size()), dim3(256), lds, st, g,
                            gp, d_blk, d_state.as<SaState>(), d_col.as<SaTask>(), scratch, flags,
                            bests, d_sab.as<SaBlk>(), nu2, d_parts.as<double>());
+        hipLaunchKernelGGL(sa_gsum_kernel<0>, dim3((unsigned)(nblk * ngroups)), dim3(256), 0, st,
+                           d_blk, d_state.as<SaState>(), d_sab.as<SaBlk>(), d_parts.as<double>(),
+                           d_cv.as<cplx<double>>(), ngroups);
+        hipLaunchKernelGGL(sa_gsum_kernel<1>, dim3((unsigned)(nblk * ngroups)), dim3(256), 0, st,
+                           d_blk, d_state.as<SaState>(), d_sab.as<SaBlk>(), d_parts.as<double>(),
+                           d_cu.as<cplx<double>>(), ngroups);
         HM_HIP_CHECK(hipMemsetAsync(d_run.p, 0, sizeof(int), st));
         hipLaunchKernelGGL(sa_step_kernel<R>, dim3((unsigned)nblk), dim3(256), 0, st, d_blk,
                            d_state.as<SaState>(), bests, d_parts.as<double>(),
-                           d_cv.as<cplx<double>>(), d_sab.as<SaBlk>(), d_out, eps, tau_piv,
-                           d_run.as<int>());
+                           d_cv.as<cplx<double>>(), d_cu.as<cplx<double>>(), d_sab.as<SaBlk>(),
+                           d_out, eps, tau_piv, d_run.as<int>());
         HM_HIP_CHECK(hipGetLastError());
         // the running count is read every kSaSync steps; a block that stops
         // in between makes the following launches exit at once
