@@ -802,8 +802,8 @@ __global__ void __launch_bounds__(NT)
 // ---------------------------------------------------------------------------
 // Split form of the same greedy loop for blocks with many points: one ACA step
 // of all such blocks is a sequence of launches over many workgroups (residual
-// row, pivot, V update, residual column, step end), so that a block with tens
-// of thousands of rows is not confined to one CU.
+// row, pivot, V update, residual column, Gram sums, step end), so that a block
+// with tens of thousands of rows is not confined to one CU.
 //
 // The residual passes read every factor column once, and the Gram columns of
 // the norm recurrence come from the same loads: each pass sums, besides the
@@ -1065,7 +1065,6 @@ template <typename R>
 __global__ void __launch_bounds__(256)
     sa_pivot_kernel(Geometry g, GreenParams<R> gp, const AcaBlk *__restrict__ blks,
                     SaState *__restrict__ state, const Best2 *__restrict__ bests,
-                    const double *__restrict__ parts, cplx<double> *__restrict__ cvall,
                     cplx<R> *__restrict__ fac, uint8_t *__restrict__ flags,
                     const SaBlk *__restrict__ sab, AcaOut *__restrict__ outs, double tau_piv,
                     double nu2) {
@@ -1345,8 +1344,7 @@ __global__ void __launch_bounds__(256)
 template <typename R>
 __global__ void __launch_bounds__(256)
     sa_step_kernel(const AcaBlk *__restrict__ blks, SaState *__restrict__ state,
-                   const Best2 *__restrict__ bests, const double *__restrict__ parts,
-                   const cplx<double> *__restrict__ cvall,
+                   const Best2 *__restrict__ bests, const cplx<double> *__restrict__ cvall,
                    const cplx<double> *__restrict__ cuall, const SaBlk *__restrict__ sab,
                    AcaOut *__restrict__ outs, double eps, double tau_piv,
                    int *__restrict__ running) {
@@ -1513,9 +1511,8 @@ static void run_aca_split(const Geometry &g, const GreenParams<R> &gp, const Aca
                            gp, d_blk, d_state.as<SaState>(), d_row.as<SaTask>(), scratch, flags,
                            bests, d_sab.as<SaBlk>(), nu2, d_parts.as<double>());
         hipLaunchKernelGGL(sa_pivot_kernel<R>, dim3((unsigned)nblk), dim3(256), 0, st, g, gp,
-                           d_blk, d_state.as<SaState>(), bests, d_parts.as<double>(),
-                           d_cv.as<cplx<double>>(), scratch, flags, d_sab.as<SaBlk>(), d_out,
-                           tau_piv, nu2);
+                           d_blk, d_state.as<SaState>(), bests, scratch, flags, d_sab.as<SaBlk>(),
+                           d_out, tau_piv, nu2);
         hipLaunchKernelGGL(sa_vfix_kernel<R>, dim3((unsigned)rowt.size()), dim3(256), 0, st,
                            d_blk, d_state.as<SaState>(), d_row.as<SaTask>(), scratch);
         hipLaunchKernelGGL(sa_col_kernel<R>, dim3((unsigned)colt.size()), dim3(256), lds, st, g,
@@ -1529,9 +1526,9 @@ static void run_aca_split(const Geometry &g, const GreenParams<R> &gp, const Aca
                            d_cu.as<cplx<double>>(), ngroups);
         HM_HIP_CHECK(hipMemsetAsync(d_run.p, 0, sizeof(int), st));
         hipLaunchKernelGGL(sa_step_kernel<R>, dim3((unsigned)nblk), dim3(256), 0, st, d_blk,
-                           d_state.as<SaState>(), bests, d_parts.as<double>(),
-                           d_cv.as<cplx<double>>(), d_cu.as<cplx<double>>(), d_sab.as<SaBlk>(),
-                           d_out, eps, tau_piv, d_run.as<int>());
+                           d_state.as<SaState>(), bests, d_cv.as<cplx<double>>(),
+                           d_cu.as<cplx<double>>(), d_sab.as<SaBlk>(), d_out, eps, tau_piv,
+                           d_run.as<int>());
         HM_HIP_CHECK(hipGetLastError());
         // the running count is read every kSaSync steps; a block that stops
         // in between makes the following launches exit at once
