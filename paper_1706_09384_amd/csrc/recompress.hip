@@ -68,14 +68,25 @@ __global__ void __launch_bounds__(256) gram_mfma_kernel(const RcBlk *__restrict_
     const cplx<R> *xa = X + (int64_t)(va ? ca : 0) * rows;
     const cplx<R> *xc = X + (int64_t)(vc ? cc : 0) * rows;
     mf64x4 gr = {0, 0, 0, 0}, gi = {0, 0, 0, 0};
+    // the next slab's operands are loaded while the current slab's products run
+    cplx<R> na[4], nb[4];
+    auto fetch = [&](int64_t q0) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int64_t q = q0 + 4 * g + s;
+            na[s] = (va && q < rows) ? xa[q] : cplx<R>{R(0), R(0)};
+            nb[s] = (vc && q < rows) ? xc[q] : cplx<R>{R(0), R(0)};
+        }
+    };
+    fetch(0);
     for (int64_t q0 = 0; q0 < rows; q0 += 16) {
         cplx<double> A[4], B[4];
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
-            const int64_t q = q0 + 4 * g + s;
-            A[s] = (va && q < rows) ? cvt<double>(xa[q]) : cplx<double>{0, 0};
-            B[s] = (vc && q < rows) ? cvt<double>(xc[q]) : cplx<double>{0, 0};
+            A[s] = cvt<double>(na[s]);
+            B[s] = cvt<double>(nb[s]);
         }
+        if (q0 + 16 < rows) fetch(q0 + 16);
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
             gr = __builtin_amdgcn_mfma_f64_16x16x4f64(A[s].re, B[s].re, gr, 0, 0, 0);
