@@ -175,10 +175,15 @@ typedef struct {
     int64_t storage_bytes;             /* dense + low-rank bytes as stored */
     int32_t max_rank_aca, max_rank;    /* largest ACA rank, largest rank after recompression */
     int64_t sum_rank_aca, sum_rank;
-    int32_t n_overflow;                /* blocks re-run because they outgrew their first budget */
+    int32_t n_overflow;                /* budget continuations: a block that outgrows its column
+                                          budget continues from where it stopped with a larger one
+                                          (counted once per continuation), plus blocks that reached
+                                          the budget cap and keep their capped factors */
     int32_t n_fallback;                /* ACA steps that used the singular-pivot fallback */
     int32_t n_model_hits;              /* blocks whose predicted budget sufficed */
-    double t_tree, t_upload, t_nearfield, t_aca, t_recompress, t_plan, t_total; /* seconds */
+    double t_tree, t_upload, t_nearfield, t_aca, t_recompress, t_plan, t_total; /* seconds; the
+                                          recompression of the blocks with few points can run inside
+                                          t_aca, beside the ACA of the blocks with many points */
     int64_t matvec_bytes;              /* algorithmic bytes of one 1-RHS matvec */
     int64_t aca_scratch_bytes;         /* first-pass ACA factor scratch, summed over chunks */
     int32_t aca_chunks;                /* chunks the admissible blocks were assembled in */
