@@ -821,9 +821,10 @@ constexpr int kSaSync = 4;       // steps queued between readbacks of the runnin
 struct SaState {
     int32_t r, steps, status, fallbacks;   // status -1 while running, then as AcaOut
     int32_t ih, jh, mode, p;
-    int32_t skip, pq, pad1, pad2;          // skip: this step found a zero residual row;
+    int32_t skip, pq, vfix, pad2;          // skip: this step found a zero residual row;
                                            // pq: columns r - pq .. r - 1 of the last term, whose
-                                           // stopping test runs with the next step
+                                           // stopping test runs with the next step; vfix: that
+                                           // term's V columns still await R_row^* W_p
     double norm2, anorm;
     cplx<double> T[9], W[9];
 };
@@ -922,6 +923,24 @@ __device__ inline void sa_gram_point(const cplx<R> (&x)[4][3], const cplx<R> (&y
         }
 }
 
+// V_new = R_row^* W_p for a term whose pivot fell back to the pseudo-inverse:
+// the raw columns r0 .. r0 + 2 of point j become the p fixed columns (the
+// rest zero).  Each point's rows are fixed by the thread that owns the point.
+template <typename R>
+__device__ inline void sa_fix_point(cplx<R> *V, int64_t ldv, int j, int r0, int p,
+                                    const cplx<double> *W) {
+    cplx<double> v[3][3];
+    for (int a = 0; a < 3; ++a)
+        for (int be = 0; be < 3; ++be) v[a][be] = cvt<double>(V[(r0 + a) * ldv + 3 * j + be]);
+    for (int c = 0; c < 3; ++c)
+        for (int be = 0; be < 3; ++be) {
+            cplx<double> t = {0, 0};
+            if (c < p)
+                for (int a = 0; a < 3; ++a) t = t + v[a][be] * W[3 * a + c];
+            V[(r0 + c) * ldv + 3 * j + be] = cvt<R>(t);
+        }
+}
+
 // Residual row pass, one workgroup per kSaTile column points.  Wave w of tile
 // t owns Gram slice 4 t + w: V(:, l)^* V(:, r - pq + c) for l < r, c < pq.
 template <typename R>
@@ -964,6 +983,9 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
         for (int e = 0; e < 9; ++e) K[e] = {R(0), R(0)};
     }
+    // a fallback pivot of the previous step: its V columns get R_row^* W_p
+    // here, before they are read (this thread owns point j's rows)
+    if (st.vfix && in) sa_fix_point<R>(V, ldv, j, r - pq, pq, st.W);
     const cplx<R> *vrow = V + 3 * (int64_t)(in ? j : 0);
     // the previous term's columns at this point
     cplx<R> pv[3][3];
@@ -1074,6 +1096,7 @@ __global__ void __launch_bounds__(256)
     const int s = blockIdx.x, tid = threadIdx.x;
     SaState st = state[s];
     if (!sa_running(st)) return;
+    st.vfix = 0;   // this step's row pass fixed the previous term's columns
     const AcaBlk b = blks[s];
     const SaBlk sb = sab[s];
     const int r = st.r, ih = st.ih, m = b.m, n = b.n;
@@ -1200,34 +1223,24 @@ __global__ void __launch_bounds__(256)
         }
         st.jh = jh;
         st.anorm = sh_anorm;
+        st.vfix = st.mode == 1 ? 1 : 0;
         state[s] = st;
     }
 }
 
-// V_new = R_row^* W_p for blocks whose pivot fell back to the pseudo-inverse.
+// The V fix of a block whose last term is still unfixed when its loop ends
+// (the next row pass fixes it otherwise).
 template <typename R>
 __global__ void __launch_bounds__(256)
     sa_vfix_kernel(const AcaBlk *__restrict__ blks, const SaState *__restrict__ state,
                    const SaTask *__restrict__ tasks, cplx<R> *__restrict__ fac) {
     const SaTask tk = tasks[blockIdx.x];
     const SaState st = state[tk.s];
-    if (!sa_running(st) || st.mode != 1) return;
+    if (!st.vfix) return;
     const AcaBlk b = blks[tk.s];
     const int j = tk.t * kSaTile + threadIdx.x;
     if (j >= b.n) return;
-    const int r = st.r, p = st.p;
-    const int64_t ldv = 3 * (int64_t)b.n;
-    cplx<R> *V = fac + b.voff;
-    cplx<double> v[3][3];
-    for (int a = 0; a < 3; ++a)
-        for (int be = 0; be < 3; ++be) v[a][be] = cvt<double>(V[(r + a) * ldv + 3 * j + be]);
-    for (int c = 0; c < 3; ++c)
-        for (int be = 0; be < 3; ++be) {
-            cplx<double> t = {0, 0};
-            if (c < p)
-                for (int a = 0; a < 3; ++a) t = t + v[a][be] * st.W[3 * a + c];
-            V[(r + c) * ldv + 3 * j + be] = cvt<R>(t);
-        }
+    sa_fix_point<R>(fac + b.voff, 3 * (int64_t)b.n, j, st.r - st.pq, st.pq, st.W);
 }
 
 // Residual column pass and U_new, one workgroup per kSaTile row points.  Wave
@@ -1427,6 +1440,7 @@ __global__ void __launch_bounds__(256)
             // the previous term met the test: this step's term is dropped
             if (st.mode == 1) --st.fallbacks;
             st.pq = 0;
+            st.vfix = 0;
             st.status = (st.steps >= cap) ? 2 : 0;
         } else {
             st.r = r + p;
@@ -1513,8 +1527,6 @@ static void run_aca_split(const Geometry &g, const GreenParams<R> &gp, const Aca
         hipLaunchKernelGGL(sa_pivot_kernel<R>, dim3((unsigned)nblk), dim3(256), 0, st, g, gp,
                            d_blk, d_state.as<SaState>(), bests, scratch, flags, d_sab.as<SaBlk>(),
                            d_out, tau_piv, nu2);
-        hipLaunchKernelGGL(sa_vfix_kernel<R>, dim3((unsigned)rowt.size()), dim3(256), 0, st,
-                           d_blk, d_state.as<SaState>(), d_row.as<SaTask>(), scratch);
         hipLaunchKernelGGL(sa_col_kernel<R>, dim3((unsigned)colt.size()), dim3(256), lds, st, g,
                            gp, d_blk, d_state.as<SaState>(), d_col.as<SaTask>(), scratch, flags,
                            bests, d_sab.as<SaBlk>(), nu2, d_parts.as<double>());
@@ -1538,6 +1550,9 @@ static void run_aca_split(const Geometry &g, const GreenParams<R> &gp, const Aca
         }
     }
     if (running > 0) throw StatusError(HM_ERR_STATE, "split ACA did not finish");
+    hipLaunchKernelGGL(sa_vfix_kernel<R>, dim3((unsigned)rowt.size()), dim3(256), 0, st, d_blk,
+                       d_state.as<SaState>(), d_row.as<SaTask>(), scratch);
+    HM_HIP_CHECK(hipGetLastError());
 }
 
 template <typename R>
