@@ -3,11 +3,12 @@
 //
 // Each block product is a small complex GEMM: a dense tile times X_sigma, and
 // for a low-rank block T = V^* X_sigma followed by U T.  A complex product
-// C += A B splits into four real ones,
-//   Re C += Re A Re B - Im A Im B,   Im C += Re A Im B + Im A Re B,
+// C += A B takes three real ones (Gauss):
+//   P1 += Re A Re B,  P2 += Im A Im B,  P3 += (Re A + Im A)(Re B + Im B),
+//   Re C = P1 - P2,   Im C = P3 - P1 - P2,
 // each issued as v_mfma_f32_16x16x4_f32 steps: 16 output rows x 16 columns,
 // 4 values of the contraction index per step.  One wave owns 16 output rows
-// and all 64 columns (4 column blocks x real/imaginary = 8 accumulator tiles).
+// and all 64 columns (4 column blocks x 3 products = 12 accumulator tiles).
 //
 // Operand layout of one 16x16x4 step (CDNA): lane l supplies A[l % 16][l / 16]
 // and B[l / 16][l % 16]; the 4 accumulator values of lane l are the rows
@@ -38,19 +39,21 @@ __device__ inline v4f mfma16(float a, float b, v4f c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-// acc[0..3]: real parts of column blocks 0..3, acc[4..7]: imaginary parts.
-__device__ inline void mr_step(v4f (&acc)[8], float ar, float ai, const float2 (&x)[4]) {
-    const float nai = -ai;
+// acc[cb], acc[4 + cb], acc[8 + cb]: P1, P2, P3 of column block cb.
+__device__ inline void mr_step(v4f (&acc)[12], float ar, float ai, const float2 (&x)[4]) {
+    const float as = ar + ai;
 #pragma unroll
     for (int cb = 0; cb < 4; ++cb) {
         acc[cb] = mfma16(ar, x[cb].x, acc[cb]);
-        acc[4 + cb] = mfma16(ar, x[cb].y, acc[4 + cb]);
+        acc[4 + cb] = mfma16(ai, x[cb].y, acc[4 + cb]);
+        acc[8 + cb] = mfma16(as, x[cb].x + x[cb].y, acc[8 + cb]);
     }
-#pragma unroll
-    for (int cb = 0; cb < 4; ++cb) {
-        acc[cb] = mfma16(nai, x[cb].y, acc[cb]);
-        acc[4 + cb] = mfma16(ai, x[cb].x, acc[4 + cb]);
-    }
+}
+
+// Entry (v, cb) of the product from the three accumulators.
+__device__ inline float2 mr_out(const v4f (&acc)[12], int cb, int v) {
+    const float p1 = acc[cb][v], p2 = acc[4 + cb][v];
+    return make_float2(p1 - p2, acc[8 + cb][v] - p1 - p2);
 }
 
 // acc += op(A)[rows, 0..K) * B[0..K, 0..64): A element (i, k) at a[k * ld + i]
@@ -58,7 +61,7 @@ __device__ inline void mr_step(v4f (&acc)[8], float ar, float ai, const float2 (
 // complex columns.  Loads of the next step are issued before the current
 // step's matrix instructions.
 template <bool CONJ>
-__device__ inline void mr_panel(v4f (&acc)[8], const float2 *__restrict__ a, int64_t ld, int i,
+__device__ inline void mr_panel(v4f (&acc)[12], const float2 *__restrict__ a, int64_t ld, int i,
                                 bool iv, const float2 *__restrict__ b, int32_t K, int lane) {
     const int kq = lane >> 4, cl = lane & 15;
     const float2 zero = make_float2(0.f, 0.f);
@@ -110,9 +113,9 @@ __global__ void __launch_bounds__(256) mr_project_kernel(const MrProjItem *__res
     if (w >= nitems) return;   // whole waves only; no barriers below
     const MrProjItem it = items[w];
     const LowRankBlk b = lblk[it.blk];
-    v4f acc[8];
+    v4f acc[12];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) acc[q] = v4f{0.f, 0.f, 0.f, 0.f};
+    for (int q = 0; q < 12; ++q) acc[q] = v4f{0.f, 0.f, 0.f, 0.f};
     // A(i, k) = conj(V(k0 + k, j0 + i)); V row-major with row stride ldv
     const int j = it.j0 + (lane & 15);
     mr_panel<true>(acc, fac + b.voff + (int64_t)it.k0 * b.ldv + it.j0, b.ldv, lane & 15, j < b.r,
@@ -125,7 +128,7 @@ __global__ void __launch_bounds__(256) mr_project_kernel(const MrProjItem *__res
                                   : tpart + ((int64_t)it.slot * 16 + row) * 64;
 #pragma unroll
         for (int cb = 0; cb < 4; ++cb)
-            dst[16 * cb + (lane & 15)] = make_float2(acc[cb][v], acc[4 + cb][v]);
+            dst[16 * cb + (lane & 15)] = mr_out(acc, cb, v);
     }
 }
 
@@ -163,9 +166,9 @@ __global__ void __launch_bounds__(256) mr_accum_kernel(
     const int32_t rows = 3 * L.m;
     const int i = it.row0 + (lane & 15);
     const bool iv = i < rows;
-    v4f acc[8];
+    v4f acc[12];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) acc[q] = v4f{0.f, 0.f, 0.f, 0.f};
+    for (int q = 0; q < 12; ++q) acc[q] = v4f{0.f, 0.f, 0.f, 0.f};
     for (int32_t ti = L.tbeg; ti < L.tend; ++ti) {
         const Task tk = tasks[ti];
         if (tk.kind == 0) {
@@ -187,7 +190,7 @@ __global__ void __launch_bounds__(256) mr_accum_kernel(
 #pragma unroll
         for (int cb = 0; cb < 4; ++cb) {
             const int c = 16 * cb + (lane & 15);
-            if (c < ncols) dst[c] = make_float2(acc[cb][v], acc[4 + cb][v]);
+            if (c < ncols) dst[c] = mr_out(acc, cb, v);
         }
     }
 }
