@@ -46,7 +46,8 @@ typedef double mf64x4 __attribute__((ext_vector_type(4)));
 // per 16 x 16 quarter; the 4-deep contraction steps take the rows of a
 // 16-row slab as q0 + 4 (l / 16) + s, s = 0..3, so that every lane reads
 // four consecutive rows of its column.  Re G = Xr^T Xr + Xi^T Xi and
-// Im G = Xr^T Xi - Xi^T Xr, products of the FP32 entries exact in FP64.
+// Im G = Xr^T Xi - Xi^T Xr, from three real products (products of the FP32
+// entries and their sums exact or nearly so in FP64).
 template <typename R>
 __global__ void __launch_bounds__(256) gram_mfma_kernel(const RcBlk *__restrict__ blks,
                                                         const GramItem *__restrict__ items,
@@ -67,7 +68,10 @@ __global__ void __launch_bounds__(256) gram_mfma_kernel(const RcBlk *__restrict_
     const bool va = ca < r, vc = cc < r;
     const cplx<R> *xa = X + (int64_t)(va ? ca : 0) * rows;
     const cplx<R> *xc = X + (int64_t)(vc ? cc : 0) * rows;
-    mf64x4 gr = {0, 0, 0, 0}, gi = {0, 0, 0, 0};
+    // conj(a) b as three real products (Gauss): P1 = Re a Re b,
+    // P2 = -Im a Im b, P3 = (Re a - Im a)(Re b + Im b); Re G = P1 - P2,
+    // Im G = P3 - P1 - P2
+    mf64x4 p1 = {0, 0, 0, 0}, p2 = {0, 0, 0, 0}, p3 = {0, 0, 0, 0};
     // the next slab's operands are loaded while the current slab's products run
     cplx<R> na[4], nb[4];
     auto fetch = [&](int64_t q0) {
@@ -89,18 +93,19 @@ __global__ void __launch_bounds__(256) gram_mfma_kernel(const RcBlk *__restrict_
         if (q0 + 16 < rows) fetch(q0 + 16);
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
-            gr = __builtin_amdgcn_mfma_f64_16x16x4f64(A[s].re, B[s].re, gr, 0, 0, 0);
-            gr = __builtin_amdgcn_mfma_f64_16x16x4f64(A[s].im, B[s].im, gr, 0, 0, 0);
-            gi = __builtin_amdgcn_mfma_f64_16x16x4f64(A[s].re, B[s].im, gi, 0, 0, 0);
-            gi = __builtin_amdgcn_mfma_f64_16x16x4f64(-A[s].im, B[s].re, gi, 0, 0, 0);
+            p1 = __builtin_amdgcn_mfma_f64_16x16x4f64(A[s].re, B[s].re, p1, 0, 0, 0);
+            p2 = __builtin_amdgcn_mfma_f64_16x16x4f64(-A[s].im, B[s].im, p2, 0, 0, 0);
+            p3 = __builtin_amdgcn_mfma_f64_16x16x4f64(A[s].re - A[s].im, B[s].re + B[s].im, p3, 0,
+                                                     0, 0);
         }
     }
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
         const int a = abase + 4 * e + g, c = cc;
         if (a < r && c < r && a <= c) {
-            G[a + (int64_t)c * r] = {gr[e], gi[e]};
-            G[c + (int64_t)a * r] = {gr[e], -gi[e]};
+            const double gr = p1[e] - p2[e], gi = a == c ? 0.0 : p3[e] - p1[e] - p2[e];
+            G[a + (int64_t)c * r] = {gr, gi};
+            G[c + (int64_t)a * r] = {gr, -gi};
         }
     }
 }
@@ -379,8 +384,8 @@ __device__ void jacobi_svd(cplx<double> *M, cplx<double> *J, int r, cplx<double>
 
 // C(i, j) = sum_k A(i, k) B(k, j) (complex FP64) on the matrix cores: one
 // wave per 16 x 16 output tile, the workgroup's waves taking the tiles in
-// turn; each 4-deep contraction step is four v_mfma_f64_16x16x4f64 (real and
-// imaginary parts).  Element accessors fa(i, k), fb(k, j), sink fc(i, j, v);
+// turn; each 4-deep contraction step is three v_mfma_f64_16x16x4f64 (three
+// real products per complex one).  Element accessors fa(i, k), fb(k, j), sink fc(i, j, v);
 // the accessors are only called inside the bounds.  Ends with a barrier.
 template <typename FA, typename FB, typename FC>
 __device__ void mfma_gemm(int mC, int nC, int K, FA fa, FB fb, FC fc) {
@@ -390,20 +395,21 @@ __device__ void mfma_gemm(int mC, int nC, int K, FA fa, FB fb, FC fc) {
     for (int t = wave; t < tm * tn; t += nw) {
         const int i0 = (t % tm) << 4, j0 = (t / tm) << 4;
         const int ia = i0 + (lane & 15), jb = j0 + (lane & 15);
-        mf64x4 cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
+        // three real products (Gauss): P1 = Re a Re b, P2 = Im a Im b,
+        // P3 = (Re a + Im a)(Re b + Im b); Re = P1 - P2, Im = P3 - P1 - P2
+        mf64x4 p1 = {0, 0, 0, 0}, p2 = {0, 0, 0, 0}, p3 = {0, 0, 0, 0};
         for (int k0 = 0; k0 < K; k0 += 4) {
             const int k = k0 + g;
             const cplx<double> a = (ia < mC && k < K) ? fa(ia, k) : cplx<double>{0, 0};
             const cplx<double> b = (k < K && jb < nC) ? fb(k, jb) : cplx<double>{0, 0};
-            cr = __builtin_amdgcn_mfma_f64_16x16x4f64(a.re, b.re, cr, 0, 0, 0);
-            cr = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.im, b.im, cr, 0, 0, 0);
-            ci = __builtin_amdgcn_mfma_f64_16x16x4f64(a.re, b.im, ci, 0, 0, 0);
-            ci = __builtin_amdgcn_mfma_f64_16x16x4f64(a.im, b.re, ci, 0, 0, 0);
+            p1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a.re, b.re, p1, 0, 0, 0);
+            p2 = __builtin_amdgcn_mfma_f64_16x16x4f64(a.im, b.im, p2, 0, 0, 0);
+            p3 = __builtin_amdgcn_mfma_f64_16x16x4f64(a.re + a.im, b.re + b.im, p3, 0, 0, 0);
         }
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             const int i = i0 + 4 * e + g;
-            if (i < mC && jb < nC) fc(i, jb, cplx<double>{cr[e], ci[e]});
+            if (i < mC && jb < nC) fc(i, jb, cplx<double>{p1[e] - p2[e], p3[e] - p1[e] - p2[e]});
         }
     }
     __syncthreads();
