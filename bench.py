@@ -399,9 +399,9 @@ def main():
     }
     if not args.no_gmres:
         tg = time.perf_counter()
-        x, inf = H.gmres(bd, tol=1e-8, restart=200, maxit=12000, check=False)
+        x, inf = H.gmres(bd, tol=1e-8, restart=400, maxit=12000, check=False)
         torch.cuda.synchronize()
-        out["gmres"] = {"tol": 1e-8, "s": round(time.perf_counter() - tg, 3), **inf}
+        out["gmres"] = {"tol": 1e-8, "restart": 400, "s": round(time.perf_counter() - tg, 3), **inf}
         log(f"[bench] gmres {out['gmres']}")
     H.close()
     if not args.no_fp64:
