@@ -46,9 +46,11 @@ def check_tree(orc, P, t, leaf):
             assert t.begin[l] == b and t.end[l] == t.begin[r] and t.end[r] == e
             assert t.depth[l] == t.depth[v] + 1 == t.depth[r]
             assert l == v + 1                       # pre-order, left first
-            # The split separates the children along one axis of the parent box.
+            # The split is at the midpoint of the parent box's longest side
+            # (lowest axis on ties): left < (lo + hi) * 0.5 <= right.
             ax = int(np.argmax(t.hi[v] - t.lo[v]))
-            assert t.hi[l][ax] < t.lo[r][ax] or t.hi[l][ax] <= t.lo[r][ax]
+            mid = (t.lo[v][ax] + t.hi[v][ax]) * 0.5
+            assert t.hi[l][ax] < mid <= t.lo[r][ax]
 
 
 @pytest.mark.parametrize("n,leaf", [(1000, 32), (4000, 16), (777, 5)])
