@@ -110,9 +110,9 @@ typedef struct hm_matrix hm_matrix;   /* opaque; owns all device memory it alloc
  * Memory: the admissible blocks are compressed in chunks (dealt round-robin
  * in longest-ACA-first order); a chunk holds about aca_scratch_mb of
  * first-pass ACA factors, and its recompressed factors are final before the
- * next chunk starts.  Peak device
- * memory is then about the near field + twice the compressed factors + the
- * chunk scratch.
+ * next chunk starts.  Each chunk's factors stay in their own buffer, so peak
+ * device memory is about the near field + the compressed factors + one
+ * chunk's scratch.
  */
 hm_status hm_build(const double *x, int64_t nx, const double *y, int64_t ny, const double *normals,
                    const hm_params *p, void *stream, hm_matrix **out);
@@ -132,8 +132,13 @@ hm_status hm_matvec(const hm_matrix *A, const void *x, void *y, int32_t nrhs, vo
 
 /*
  * r = b - A_H x evaluated with FP64 arithmetic from the stored factors
- * (complex64 or complex128 storage), the outer residual of iterative
- * refinement.  b, x, r: device complex128, (3n, nrhs).  Asynchronous.
+ * (complex64 or complex128 storage): the residual of the linear system
+ * eq. syst_a with the H-matrix product of Section 3.1, used as the outer
+ * residual of iterative refinement and to confirm GMRES convergence.
+ *   b, x, r  device complex128, (3 nx, nrhs) / (3 ny, nrhs) / (3 nx, nrhs),
+ *            row-major as in hm_matvec; r must not overlap b or x.
+ * Asynchronous on stream.  HM_ERR_ARG for nrhs < 1 or NULL pointers,
+ * HM_ERR_STATE for a plan-only matrix.
  */
 hm_status hm_residual(const hm_matrix *A, const void *b, const void *x, void *r, int32_t nrhs,
                       void *stream);
@@ -148,7 +153,10 @@ typedef struct {
 } hm_gmres_info;
 
 /*
- * Solve A_H x = b by restarted GMRES(restart), x0 = 0, no preconditioner.
+ * Solve A_H x = b, the system eq. syst_a with the H-matrix operator, by
+ * restarted GMRES(restart), the iterative solver of Section 1 whose cost is
+ * dominated by the H-matrix-vector products of Section 3.1; x0 = 0, no
+ * preconditioner (the paper leaves preconditioning open).
  * Each of the nrhs columns is an independent GMRES run; all columns share
  * one multi-right-hand-side H-matvec per iteration.  Complex128 operators
  * iterate in FP64 until the recursive residual is below tol, then confirm
@@ -177,8 +185,7 @@ typedef struct {
     int64_t sum_rank_aca, sum_rank;
     int32_t n_overflow;                /* budget continuations: a block that outgrows its column
                                           budget continues from where it stopped with a larger one
-                                          (counted once per continuation), plus blocks that reached
-                                          the budget cap and keep their capped factors */
+                                          (counted once per continuation) */
     int32_t n_fallback;                /* ACA steps that used the singular-pivot fallback */
     int32_t n_model_hits;              /* blocks whose predicted budget sufficed */
     double t_tree, t_upload, t_nearfield, t_aca, t_recompress, t_plan, t_total; /* seconds; the
@@ -188,6 +195,10 @@ typedef struct {
     int64_t aca_scratch_bytes;         /* first-pass ACA factor scratch, summed over chunks */
     int32_t aca_chunks;                /* chunks the admissible blocks were assembled in */
     int32_t acc_waves, proj_rows;      /* 1-RHS matvec launch shape (hm_autotune may change it) */
+    int32_t n_capped;                  /* admissible blocks whose ACA reached the rank cap (639
+                                          columns for complex128, 852 for complex64) before its
+                                          stopping test held: they keep the capped factors, which
+                                          miss eps; 0 on every workload the library is tested on */
 } hm_stats;
 
 hm_status hm_info(const hm_matrix *A, hm_stats *s);

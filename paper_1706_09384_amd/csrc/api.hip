@@ -225,6 +225,7 @@ static void build_project_plan(hm_matrix *M, int32_t chunk, hipStream_t st) {
     M->n_ptasks = (int32_t)ptasks.size();
     M->n_preduce = (int32_t)preduce.size();
     M->proj_rows = chunk;
+    M->proj_slots = nslots;
     upload(M->d_ptasks, ptasks, st);
     upload(M->d_preduce, preduce, st);
     M->tpart.alloc(std::max<int64_t>(nslots, 1) * 64 * sizeof(cplx<double>));
@@ -497,7 +498,7 @@ void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vect
     // The ACA kernel keeps the pivot row (3 x budget, compute type) and the V
     // Gram column (budget x 3, complex FP64) in LDS: cap the budget so that
     // both fit in 64 KiB.  A block still unconverged at the cap keeps its
-    // capped-rank approximation (counted in hm_stats.n_overflow as well).
+    // capped-rank approximation (counted in hm_stats.n_capped).
     const int32_t budget_cap =
         (int32_t)((60 * 1024) / (3 * (sizeof(cplx<R>) + sizeof(cplx<double>)))) / 3 * 3;
     for (auto &bg : budget) bg = std::min(bg, budget_cap);
@@ -543,8 +544,7 @@ void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vect
     std::vector<Resume> resume(nlr);
     std::vector<uint8_t> reran(nlr, 0);   // the first budget did not suffice
     std::vector<std::unique_ptr<DeviceBuf>> holding;
-    std::vector<std::unique_ptr<DeviceBuf>> chunk_out;
-    std::vector<int64_t> chunk_base, chunk_len;
+    int32_t n_chunks_done = 0;
     int64_t lr_entries = 0, t_len = 0;
     double t_aca = 0.0, t_rc = 0.0;
     S.aca_scratch_bytes = 0;
@@ -577,7 +577,11 @@ void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vect
             std::vector<AcaBlk> ab;
             std::unique_ptr<DeviceBuf> scratch, flags, d_ab, d_out;
             hipStream_t s = nullptr;
+            int64_t scratch_bytes = 0;
         };
+        // launch() may run on a worker thread beside the main thread's
+        // launch(): it writes only its own AcaLaunch and reads per-block state
+        // of its own blocks; shared totals are added by the main thread.
         auto launch = [&](std::vector<int64_t> todo, hipStream_t s) {
             AcaLaunch L;
             // blocks with many points first (they run in the split form), each
@@ -615,7 +619,7 @@ void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vect
                     a.norm0 = rs.norm2;
                 }
             }
-            if (pass_scratch.empty() && !last) S.aca_scratch_bytes += fac * (int64_t)sizeof(cplx<R>);
+            L.scratch_bytes = fac * (int64_t)sizeof(cplx<R>);
             L.scratch = std::make_unique<DeviceBuf>();
             L.flags = std::make_unique<DeviceBuf>();
             L.d_ab = std::make_unique<DeviceBuf>();
@@ -786,8 +790,10 @@ void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vect
                     return launch(big, aca_side);
                 });
                 std::exception_ptr err;
+                int64_t first_bytes = 0;
                 try {
                     AcaLaunch first = launch(small, st);
+                    first_bytes = first.scratch_bytes;
                     next = finish(first);
                     recompress_pass(0);
                 } catch (...) {
@@ -797,11 +803,13 @@ void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vect
                 // anything unwinds (get() rethrows its own error)
                 AcaLaunch second = split.get();
                 if (err) std::rethrow_exception(err);
+                if (!last) S.aca_scratch_bytes += first_bytes + second.scratch_bytes;
                 const std::vector<int64_t> n2 = finish(second);
                 next.insert(next.end(), n2.begin(), n2.end());
                 ps0 = 1;
             } else {
                 AcaLaunch first = launch(members, st);
+                if (!last) S.aca_scratch_bytes += first.scratch_bytes;
                 next = finish(first);
             }
             if (defer) {
@@ -823,18 +831,29 @@ void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vect
         // ---- the chunk's final factors, in pass order ------------------------------
         std::vector<int64_t> held;   // blocks whose factors this chunk computed
         for (const auto &pm : pass_members) held.insert(held.end(), pm.begin(), pm.end());
+        // The chunk's factors stay in their own buffer (no second copy into
+        // one slab); every block's offsets are taken from the first chunk's
+        // buffer, the base pointer of the matvec kernels.  Allocations are
+        // 256-byte aligned, so the distance between two buffers is a whole
+        // (and, for complex64, even) number of elements.
         int64_t len = 0;
         for (int64_t k : held) {
             const Block &B = M->blocks[lr_ids[k]];
-            fu[k] = lr_entries + len;
+            fu[k] = len;
             len += (int64_t)padded_rows(rowpad, tx.begin[B.row], lm[k]) * final_rank[k];
-            fv[k] = lr_entries + len;
+            fv[k] = len;
             len += 3 * (int64_t)ln[k] * even_up(final_rank[k]);
             len += (kSegRows - len % kSegRows) % kSegRows;   // next U on a segment boundary
         }
         auto out = std::make_unique<DeviceBuf>();
         out->alloc((len + 2) * sizeof(cplx<R>));
         HM_HIP_CHECK(hipMemsetAsync(out->p, 0, (len + 2) * sizeof(cplx<R>), st));
+        if (!M->lr_base) M->lr_base = out->p;
+        const std::ptrdiff_t gap =
+            static_cast<const char *>(out->p) - static_cast<const char *>(M->lr_base);
+        if (gap % (std::ptrdiff_t)(kSegRows * sizeof(cplx<R>)) != 0)
+            throw HipError("factor buffer misaligned against the first chunk", hipErrorInvalidValue);
+        const int64_t delta = (int64_t)(gap / (std::ptrdiff_t)sizeof(cplx<R>));
         for (size_t ps = 0; ps < np; ++ps) {
             auto &mem = pass_members[ps];
             if (mem.empty()) continue;
@@ -842,8 +861,8 @@ void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vect
             std::vector<int32_t> kp(mem.size());
             for (size_t q = 0; q < mem.size(); ++q) {
                 kp[q] = final_rank[mem[q]];
-                ou[q] = fu[mem[q]] - lr_entries;
-                ov[q] = fv[mem[q]] - lr_entries;
+                ou[q] = fu[mem[q]];
+                ov[q] = fv[mem[q]];
             }
             DeviceBuf d_ou, d_ov;
             upload(d_ou, ou, st);
@@ -867,35 +886,18 @@ void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vect
             pass_work[ps].reset();
             pass_scratch[ps].reset();
         }
-        chunk_out.push_back(std::move(out));
-        chunk_base.push_back(lr_entries);
-        chunk_len.push_back(len);
-        lr_entries += len;
-        t_rc += now_s() - tc;
-    }
-    // ---- one slab for all low-rank factors ------------------------------------
-    {
-        const double tc = now_s();
-        if (chunk_out.size() == 1) {
-            std::swap(M->lowrank.p, chunk_out[0]->p);
-            std::swap(M->lowrank.bytes, chunk_out[0]->bytes);
-            std::swap(M->lowrank.dev, chunk_out[0]->dev);
-        } else {
-            M->lowrank.alloc((lr_entries + 2) * sizeof(cplx<R>));
-            for (size_t c = 0; c < chunk_out.size(); ++c)
-                if (chunk_len[c] > 0)
-                    HM_HIP_CHECK(hipMemcpyAsync(M->lowrank.as<cplx<R>>() + chunk_base[c],
-                                                chunk_out[c]->p, chunk_len[c] * sizeof(cplx<R>),
-                                                hipMemcpyDeviceToDevice, st));
-            HM_HIP_CHECK(hipMemsetAsync(M->lowrank.as<cplx<R>>() + lr_entries, 0,
-                                        2 * sizeof(cplx<R>), st));
-            HM_HIP_CHECK(hipStreamSynchronize(st));
+        for (int64_t k : held) {
+            fu[k] += delta;
+            fv[k] += delta;
         }
-        chunk_out.clear();
+        M->lowrank.push_back(std::move(out));
+        lr_entries += len;
+        ++n_chunks_done;
         t_rc += now_s() - tc;
     }
-    S.aca_chunks = (int32_t)chunk_base.size();
-    S.n_overflow = overflow + capped;
+    S.aca_chunks = n_chunks_done;
+    S.n_overflow = overflow;
+    S.n_capped = capped;
     if (capped)
         std::fprintf(stderr, "hmat: %d admissible blocks reached the ACA rank cap %d\n", capped,
                      budget_cap);
@@ -1342,9 +1344,9 @@ extern "C" hm_status hm_export_block(const hm_matrix *A, int64_t b, void *host_b
         if (r > 0) {
             const int64_t ldu = padded_rows(rowpad, rb, (int32_t)m), ldv = even_up((int32_t)r);
             std::vector<char> tu(ldu * r * es), tv(3 * n * ldv * es);
-            HM_HIP_CHECK(hipMemcpy(tu.data(), static_cast<char *>(A->lowrank.p) + A->off_a[b] * es,
+            HM_HIP_CHECK(hipMemcpy(tu.data(), static_cast<char *>(A->lr_base) + A->off_a[b] * es,
                                    tu.size(), hipMemcpyDeviceToHost));
-            HM_HIP_CHECK(hipMemcpy(tv.data(), static_cast<char *>(A->lowrank.p) + A->off_v[b] * es,
+            HM_HIP_CHECK(hipMemcpy(tv.data(), static_cast<char *>(A->lr_base) + A->off_v[b] * es,
                                    tv.size(), hipMemcpyDeviceToHost));
             for (int64_t c = 0; c < r; ++c)
                 for (int64_t row = 0; row < 3 * m; ++row)

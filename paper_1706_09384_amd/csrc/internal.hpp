@@ -166,12 +166,19 @@ struct hm_matrix {
     hm::DeviceBuf geo;        // 9 SoA float64 arrays (x, y, n)
     hm::DeviceBuf perm_x, perm_y;
     hm::DeviceBuf dense;      // dense slab
-    hm::DeviceBuf lowrank;    // U and V factors
+    // U and V factors, one buffer per assembly chunk; every LowRankBlk offset
+    // counts complex elements from lr_base (the first chunk's buffer), so the
+    // offsets of later chunks may be negative or span the gap between buffers
+    std::vector<std::unique_ptr<hm::DeviceBuf>> lowrank;
+    void *lr_base = nullptr;
+    template <typename T>
+    T *factors() const { return static_cast<T *>(lr_base); }
     hm::DeviceBuf d_dblk, d_lblk, d_tasks, d_leaves, d_ptasks, d_preduce, tpart;
     int32_t n_dblk = 0, n_lblk = 0, n_leaves = 0, n_ptasks = 0, n_preduce = 0;
     int32_t max_leaf = 1;     // largest leaf row cluster (points)
     int32_t acc_waves = 8;    // waves per workgroup of the 1-RHS accumulation (4, 8, 16)
     int32_t proj_rows = hm::kProjRows;   // row chunk of the 1-RHS projection items
+    int32_t proj_slots = 0;   // partial-sum slots (64 entries each) of the projection plan
     hm::DeviceBuf d_rowpad;   // int32[nx + 1]: padding rows before each position
     std::vector<int32_t> rowpad;
     int64_t t_len = 0;        // sum of ranks

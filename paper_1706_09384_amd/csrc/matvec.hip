@@ -361,12 +361,12 @@ __global__ void __launch_bounds__(64 * NW) accum_kernel(
 }
 
 template <typename S, typename A>
-static void launch_project(const hm_matrix *M, const cplx<A> *xc, cplx<A> *tb, hipStream_t st) {
+static void launch_project(const hm_matrix *M, const cplx<A> *xc, cplx<A> *tb, cplx<A> *tp,
+                           hipStream_t st) {
     if (M->n_ptasks == 0) return;
-    auto *tp = M->tpart.as<cplx<A>>();
     hipLaunchKernelGGL((project_kernel<S, A>), dim3((unsigned)ceil_div(M->n_ptasks, 4)), dim3(256),
                        0, st, M->d_lblk.as<LowRankBlk>(), M->d_ptasks.as<ProjTask>(),
-                       M->n_ptasks, M->lowrank.as<cplx<S>>(), xc, tb, tp);
+                       M->n_ptasks, M->factors<cplx<S>>(), xc, tb, tp);
     HM_HIP_CHECK(hipGetLastError());
     if (M->n_preduce > 0) {
         hipLaunchKernelGGL((project_reduce_kernel<A>), dim3((unsigned)ceil_div(M->n_preduce, 4)),
@@ -382,7 +382,7 @@ static void launch_accum_nw(const hm_matrix *M, const cplx<A> *xc, const cplx<A>
     hipLaunchKernelGGL((accum_kernel<S, A, OUT, RPL, NW>), dim3(M->n_leaves), dim3(64 * NW), 0, st,
                        M->d_leaves.as<LeafRow>(), M->d_tasks.as<Task>(),
                        M->d_dblk.as<DenseBlk>(), M->d_lblk.as<LowRankBlk>(),
-                       M->dense.as<cplx<S>>(), M->lowrank.as<cplx<S>>(), xc, tb,
+                       M->dense.as<cplx<S>>(), M->factors<cplx<S>>(), xc, tb,
                        M->perm_x.as<int32_t>(), y, ldy, col, b);
     HM_HIP_CHECK(hipGetLastError());
 }
@@ -412,12 +412,13 @@ static void launch_accum(const hm_matrix *M, const cplx<A> *xc, const cplx<A> *t
     }
 }
 
+// The three launches of one column with explicit workspaces: xc (3 ny
+// entries), tb (sum of ranks) and tp (proj_slots x 64 partial sums).
 template <typename S, typename A>
-void launch_matvec_col(const hm_matrix *M, const void *x, int64_t ldx, int32_t col, void *y,
-                       int64_t ldy, const double *b, hipStream_t st) {
+static void launch_matvec_col_ws(const hm_matrix *M, const void *x, int64_t ldx, int32_t col,
+                                 void *y, int64_t ldy, const double *b, hipStream_t st,
+                                 cplx<A> *xc, cplx<A> *tb, cplx<A> *tp) {
     const int64_t ny = M->ny;
-    auto *xc = M->ws_xc.as<cplx<A>>();
-    auto *tb = M->ws_t.as<cplx<A>>();
     const auto *perm_y = M->p.same ? M->perm_x.as<int32_t>() : M->perm_y.as<int32_t>();
     // The FP64 residual (b != nullptr) takes a complex128 x whatever the storage type.
     if (b == nullptr)
@@ -427,11 +428,18 @@ void launch_matvec_col(const hm_matrix *M, const void *x, int64_t ldx, int32_t c
         hipLaunchKernelGGL((gather_kernel<double, A>), dim3(ceil_div(3 * ny, 256)), dim3(256), 0,
                            st, static_cast<const cplx<double> *>(x), ldx, col, perm_y, ny, xc);
     HM_HIP_CHECK(hipGetLastError());
-    launch_project<S, A>(M, xc, tb, st);
+    launch_project<S, A>(M, xc, tb, tp, st);
     if (b == nullptr)
         launch_accum<S, A, 0>(M, xc, tb, y, ldy, col, nullptr, st);
     else
         launch_accum<S, A, 1>(M, xc, tb, y, ldy, col, b, st);
+}
+
+template <typename S, typename A>
+void launch_matvec_col(const hm_matrix *M, const void *x, int64_t ldx, int32_t col, void *y,
+                       int64_t ldy, const double *b, hipStream_t st) {
+    launch_matvec_col_ws<S, A>(M, x, ldx, col, y, ldy, b, st, M->ws_xc.as<cplx<A>>(),
+                               M->ws_t.as<cplx<A>>(), M->tpart.as<cplx<A>>());
 }
 
 // Same three launches with HIP events between them; adds each kernel's
@@ -449,7 +457,7 @@ void profile_matvec_col(const hm_matrix *M, const void *x, void *y, hipStream_t 
     hipLaunchKernelGGL((gather_kernel<S, A>), dim3(ceil_div(3 * ny, 256)), dim3(256), 0, st,
                        static_cast<const cplx<S> *>(x), 1, 0, perm_y, ny, xc);
     HM_HIP_CHECK(hipEventRecord(ev[1], st));
-    launch_project<S, A>(M, xc, tb, st);
+    launch_project<S, A>(M, xc, tb, M->tpart.as<cplx<A>>(), st);
     HM_HIP_CHECK(hipEventRecord(ev[2], st));
     launch_accum<S, A, 0>(M, xc, tb, y, 1, 0, nullptr, st);
     HM_HIP_CHECK(hipEventRecord(ev[3], st));

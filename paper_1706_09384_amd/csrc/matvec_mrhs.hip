@@ -213,7 +213,7 @@ void launch_matvec_mrhs(const hm_matrix *M, const void *x, int64_t ldx, int32_t 
     auto *x64 = M->ws_x64.as<float2>();
     auto *t64 = M->ws_t64.as<float2>();
     auto *tp = M->ws_tp64.as<float2>();
-    const auto *fac = M->lowrank.as<float2>();
+    const auto *fac = M->factors<float2>();
     if (ev) HM_HIP_CHECK(hipEventRecord(ev[0], st));
     hipLaunchKernelGGL(mr_gather_kernel, dim3((unsigned)ceil_div(3 * M->ny * 64, 256)), dim3(256), 0,
                        st, static_cast<const float2 *>(x), ldx, col0, ncols, perm_y, M->ny, x64);

@@ -73,6 +73,7 @@ class Stats(ctypes.Structure):
         ("matvec_bytes", ctypes.c_int64),
         ("aca_scratch_bytes", ctypes.c_int64), ("aca_chunks", ctypes.c_int32),
         ("acc_waves", ctypes.c_int32), ("proj_rows", ctypes.c_int32),
+        ("n_capped", ctypes.c_int32),
     ]
 
     def as_dict(self):
