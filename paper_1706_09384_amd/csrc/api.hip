@@ -114,9 +114,17 @@ void DeviceBuf::reset() {
 void DeviceBuf::alloc(size_t b) {
     reset();
     if (b == 0) return;
+    // Failure injection for tests: with HM_FAULT_ALLOC=k the k-th device
+    // allocation of this thread fails, counted from the last time the
+    // variable's value changed.
     const char *inj = std::getenv("HM_FAULT_ALLOC");
     if (inj) {
         static thread_local long counter = 0;
+        static thread_local std::string seen;
+        if (seen != inj) {
+            seen = inj;
+            counter = 0;
+        }
         if (++counter == std::atol(inj)) throw StatusError(HM_ERR_ALLOC, "injected allocation failure");
     }
     HM_HIP_CHECK(hipGetDevice(&dev));

@@ -180,6 +180,8 @@ class HMatrix:
 
     def __init__(self, handle, params):
         self._h = handle
+        # kept on the instance: at interpreter exit the module globals may be gone
+        self._destroy = LIB.hm_destroy
         self.params = params
         self.prec = params.prec
         s = self.info()
@@ -189,9 +191,10 @@ class HMatrix:
         self.close()
 
     def close(self):
-        if getattr(self, "_h", None):
-            LIB.hm_destroy(self._h)
+        h = getattr(self, "_h", None)
+        if h:
             self._h = None
+            self._destroy(h)
 
     @property
     def complex_dtype(self):

@@ -126,6 +126,7 @@ def test_cube100k_T_sampled_rows(hm, orc, leaf):
     s = H.info()
     say({k: s[k] for k in ("n_lowrank", "max_rank_aca", "max_rank", "n_fallback", "n_overflow",
                            "t_total", "acc_waves", "proj_rows")})
+    assert s["n_capped"] == 0   # every block met its stopping test below the rank cap
     b = w.rhs()
     y = H.matvec(torch.from_numpy(b[:, 0]).cuda().to(torch.complex64)).cpu().numpy()
     rows = np.random.default_rng(0).choice(w.n_points, 256, replace=False)
@@ -190,7 +191,12 @@ def test_overflow_resume_is_bit_identical(hm, which, prec):
     big = lowrank[pts[lowrank] >= 1500]
     resumed = lowrank[a0[lowrank] > 12]
     say("split blocks", big.size, "resumed blocks", resumed.size)
-    assert big.size > 0 and np.any(a0[big] > 12)
+    assert big.size > 0
+    if which == "cube12k_T":
+        # coplanar cube faces: some split blocks converge within the first 12 columns
+        assert np.any(a0[big] > 12)
+    else:
+        assert np.all(a0[big] > 12)
     rng = np.random.default_rng(5)
     pick = np.concatenate([big, rng.choice(resumed, min(200, resumed.size), replace=False)])
     for k in pick:

@@ -6,8 +6,14 @@ Gates, per right-hand side column c (relative 2-norm):
   (both FP32 accumulations of the same stored factors, different order);
 * panel product vs the oracle's re-application of the exported operator to
   the complex64-rounded input: <= 1e-5;
-* panel product vs the dense oracle product: <= 5 eps.
+* panel product vs the dense oracle product: <= 5 eps + C64_FLOOR.
+
+C64_FLOOR is the complex64 allowance: the all-dense (eta = 0) product of a
+complex64 operator, which has no approximation error at all, already differs
+from the FP64 oracle by up to 2e-6 (float32 kernel evaluation, storage and
+accumulation); the gate adds 1.5 times that floor to 5 eps.
 """
+C64_FLOOR = 3e-6
 import sys
 
 import numpy as np
@@ -98,7 +104,7 @@ def test_panels_sphere1k(hm, orc, sphere1k, nrhs):
     say(f"case multirhs sphere1k nrhs={nrhs}")
     H = hm.build_workload(w, X=X, prec=1)
     B = W.complex_normal(3 * w.n_points, nrhs, seed=7)
-    check_panels(hm, orc, H, A, B, w.eps, 5 * w.eps)
+    check_panels(hm, orc, H, A, B, w.eps, 5 * w.eps + C64_FLOOR)
 
 
 @pytest.mark.parametrize("kernel,n,leaf,omega", [(1, 513, 5, 9.0), (0, 97, 7, 0.5), (1, 300, 40, 3.0)])
@@ -111,7 +117,7 @@ def test_panels_small_ragged(hm, orc, kernel, n, leaf, omega):
     A = orc.dense(pb)
     H = hm.build_workload(w, X=X, N=N, prec=1)
     B = W.complex_normal(3 * n, 24, seed=8)
-    check_panels(hm, orc, H, A, B, w.eps, 6e-5)
+    check_panels(hm, orc, H, A, B, w.eps, 5 * w.eps + C64_FLOOR)
 
 
 def test_panels_two_clouds(hm, orc):
@@ -122,7 +128,7 @@ def test_panels_two_clouds(hm, orc):
     A = orc.dense(pb)
     H = hm.build(to_dev(X), to_dev(Y), kernel=0, omega=4.0, leaf=16, eps=1e-5, prec=1)
     B = W.complex_normal(900, 16, seed=9)
-    check_panels(hm, orc, H, A, B, 1e-5, 5e-5)
+    check_panels(hm, orc, H, A, B, 1e-5, 5e-5 + C64_FLOOR)
 
 
 def test_panels_single_point(hm, orc):
@@ -133,7 +139,7 @@ def test_panels_single_point(hm, orc):
     A = orc.dense(pb)
     H = hm.build_workload(w, X=X, prec=1)
     B = W.complex_normal(3, 9, seed=10)
-    check_panels(hm, orc, H, A, B, 1e-4, 1e-6)
+    check_panels(hm, orc, H, A, B, 1e-4, C64_FLOOR)
 
 
 @pytest.mark.parametrize("nrhs", [4, 12])
@@ -166,6 +172,7 @@ def test_sphere200k_T_64rhs_sampled_rows(hm, orc):
     s = H.info()
     say({k: s[k] for k in ("n_lowrank", "max_rank", "n_overflow", "n_fallback", "storage_bytes",
                            "t_total")})
+    assert s["n_capped"] == 0   # every block met its stopping test below the rank cap
     B = w.rhs()
     assert B.shape == (3 * w.n_points, 64)
     Y = H.matvec(to_dev(B, torch.complex64)).cpu().numpy().astype(np.complex128)

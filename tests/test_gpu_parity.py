@@ -7,7 +7,13 @@ Gates (relative 2-norm errors e = |y_H - y|/|y|):
   equals the GPU product: complex128 <= 1e-12, complex64 <= 1e-5;
 * GMRES: FP64 residual of the exported operator <= tol, and on the small
   case the solution equals the LU solution of the densified operator.
+
+Complex64 operators are held to 5 eps + C64_FLOOR against the FP64 oracle:
+the all-dense (eta = 0) complex64 product, which carries no approximation
+error, already differs from the oracle by up to 2e-6 (float32 kernel
+evaluation, storage and accumulation), and C64_FLOOR is 1.5 times that.
 """
+C64_FLOOR = 3e-6
 import math
 import sys
 
@@ -153,7 +159,8 @@ def test_sphere1k_gmres_c128(hm, orc, sphere1k):
     Ad = orc.densify(blocks, tx, ty)
     xs, rcond = orc.lu_solve(Ad, b[:, 0])
     kappa = 1.0 / rcond
-    assert rel(x, xs) <= 1e-6 * max(1.0, kappa / 1e3) * 10            # G2
+    say("G2: |x - x*|/|x*| =", rel(x, xs), "kappa estimate", kappa)
+    assert rel(x, xs) <= 1e-6 * max(1.0, kappa / 1e3)                 # G2
     # reported: backward error against the exact dense operator ~ eps
     xl, _ = orc.lu_solve(A, b[:, 0])
     say("backward error vs dense", np.linalg.norm(A @ x - b[:, 0]) / np.linalg.norm(b),
@@ -196,9 +203,10 @@ def test_small_ragged_cases(hm, orc, kernel, n, leaf, omega):
     pb = orc.Problem.from_workload(w, X, N)
     A = orc.dense(pb)
     b = W.complex_normal(3 * n, 2, seed=1)
-    for prec, tol in [(0, 5e-5), (1, 6e-5)]:
+    for prec, tol in [(0, 5 * w.eps), (1, 5 * w.eps + C64_FLOOR)]:
         H = hm.build_workload(w, X=X, N=N, prec=prec)
         y = H.matvec(to_dev(b, H.complex_dtype)).cpu().numpy().astype(np.complex128)
+        say(f"  prec={prec} e = {rel(y, A @ b):.3e} gate {tol:.2e}")
         assert rel(y, A @ b) <= tol, (prec, rel(y, A @ b))
 
 
@@ -258,7 +266,9 @@ def test_coplanar_T_uses_pivot_fallback(hm, orc):
     ref = orc.matvec_rows(pb, b, rows)
     y = H.matvec(to_dev(b)).cpu().numpy()
     idx = (3 * rows[:, None] + np.arange(3)).ravel()
-    assert rel(y[idx], ref) <= 5 * w.eps * 4     # T: the paper reports ~20 eps for T
+    e = rel(y[idx], ref)
+    say("sampled e =", e, "gate", 5 * w.eps)
+    assert e <= 5 * w.eps
 
 
 def test_build_is_deterministic(hm, sphere1k):
@@ -287,6 +297,7 @@ def test_sphere20k_sampled_rows(hm, orc, eps):
     s = H.info()
     say({k: s[k] for k in ("n_lowrank", "max_rank_aca", "max_rank", "n_overflow", "storage_bytes",
                            "t_total", "t_aca", "t_recompress")})
+    assert s["n_capped"] == 0   # every block met its stopping test below the rank cap
     b = w.rhs()
     y = H.matvec(to_dev(b, H.complex_dtype)).cpu().numpy().astype(np.complex128)
     rows = np.random.default_rng(0).choice(w.n_points, 512, replace=False)
@@ -298,7 +309,7 @@ def test_sphere20k_sampled_rows(hm, orc, eps):
     assert e <= 5 * eps
 
 
-@pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 3e-6)])
+@pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, C64_FLOOR)])
 def test_leaf_one_point(hm, orc, prec, tol):
     """Leaves of one point (3-row segments, all padded): with eta = 0 everything is a 3x3
     dense tile; with eta = 3 the low-rank blocks span many padded segments."""
@@ -342,7 +353,7 @@ def test_single_admissible_block(hm, orc, kernel):
         s = H.info()
         assert s["n_blocks"] == 1 and s["n_lowrank"] == 1
         y = H.matvec(to_dev(b, H.complex_dtype)).cpu().numpy().astype(np.complex128)
-        assert rel(y, A @ b) <= 5e-6 + (3e-6 if prec else 0), (prec, rel(y, A @ b))
+        assert rel(y, A @ b) <= 5e-6 + (C64_FLOOR if prec else 0), (prec, rel(y, A @ b))
 
 
 def test_many_rhs_ragged_panels(hm, orc, sphere1k):
@@ -381,3 +392,4 @@ def test_split_aca_complex128_sampled_rows(hm, orc):
     e = rel(y[idx], ref)
     say("sampled e =", e)
     assert e <= 5 * w.eps
+

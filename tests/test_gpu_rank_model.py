@@ -190,6 +190,7 @@ def test_spheroid50k_with_model_sampled_rows(hm, samples):
     s = H.info()
     say({k: s[k] for k in ("n_lowrank", "n_model_hits", "n_overflow", "aca_scratch_bytes", "t_aca",
                            "t_total")})
+    assert s["n_capped"] == 0   # every block met its stopping test below the rank cap
     assert s["n_model_hits"] > 0.9 * s["n_lowrank"]
     b = w.rhs()
     y = H.matvec(torch.from_numpy(b).cuda().to(torch.complex64)).cpu().numpy().astype(np.complex128)
