@@ -131,6 +131,30 @@ hm_status hm_build(const double *x, int64_t nx, const double *y, int64_t ny, con
 hm_status hm_matvec(const hm_matrix *A, const void *x, void *y, int32_t nrhs, void *stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * product as hm_matvec, y = A_H x, with its work vectors (x in cluster order,
+ * the projections t = V^* x, the projection partial sums) taken from a fixed
+ * 64 MiB device array that the library holds on each GPU it runs on until
+ * the process ends, instead of the matrix's own workspaces.  It calls no
+ * hipMalloc, hipFree or allocating library routine.
+ *   x, y   as in hm_matvec (device, operator's complex type, row-major
+ *          (3 ny, nrhs) / (3 nx, nrhs)); columns are applied one at a time
+ *          with the one-column kernels (never the 64-column matrix-core
+ *          panels), so for those columns the result equals hm_matvec's
+ *          bit for bit.
+ * HM_ERR_ARG when 3 ny + sum(rank) + 64 * (projection slots) complex
+ * entries (each part rounded up to 256 bytes) exceed the 64 MiB, that is
+ * 8,388,608 complex64 or 4,194,304 complex128 entries, for NULL pointers or
+ * nrhs < 1;
+ * HM_ERR_STATE for a plan-only matrix.  Every entry of the array is written
+ * before it is read within one call.  All calls on one GPU share its array:
+ * calls that overlap on one GPU (any matrices, any streams) race.
+ * Asynchronous on stream.
+ */
+hm_status hm_matvec_noalloc(const hm_matrix *A, const void *x, void *y, int32_t nrhs, void *stream);
+
+/*
  * r = b - A_H x evaluated with FP64 arithmetic from the stored factors
  * (complex64 or complex128 storage): the residual of the linear system
  * eq. syst_a with the H-matrix product of Section 3.1, used as the outer

@@ -19,6 +19,7 @@
 //            subtracted from b for the FP64 residual).
 // S is the storage real type, A the accumulation real type.
 #include <algorithm>
+#include <mutex>
 
 #include "internal.hpp"
 
@@ -481,4 +482,71 @@ template void launch_matvec_col<double, double>(const hm_matrix *, const void *,
 template void launch_matvec_col<float, double>(const hm_matrix *, const void *, int64_t, int32_t,
                                                void *, int64_t, const double *, hipStream_t);
 
+// ---- allocation-free product -------------------------------------------------
+// The workspaces of hm_matvec_noalloc live in one fixed device array per GPU.
+// In host code `scratch` names a host-side stand-in, not device memory: only
+// the address from hipGetSymbolAddress (kept per device below) reaches kernels.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+void *g_scratch_dev[64] = {};
+
+// Device address of this GPU's `scratch`, looked up once per device with the
+// device current.
+unsigned char *scratch_address() {
+    int dev = 0;
+    HM_HIP_CHECK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) throw StatusError(HM_ERR_HIP, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        HM_HIP_CHECK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) throw StatusError(HM_ERR_HIP, "hipGetSymbolAddress returned NULL for the scratch");
+        g_scratch_dev[dev] = p;
+    }
+    return static_cast<unsigned char *>(g_scratch_dev[dev]);
+}
+
+size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+template <typename S>
+void matvec_noalloc_cols(const hm_matrix *M, const void *x, void *y, int32_t nrhs,
+                         hipStream_t st) {
+    using A = S;
+    const size_t sa = sizeof(cplx<A>);
+    const size_t bx = align256(3 * (size_t)M->ny * sa);
+    const size_t bt = align256((size_t)std::max<int64_t>(M->t_len, 1) * sa);
+    const size_t bp = align256((size_t)std::max(M->proj_slots, 1) * kWave * sa);
+    if (bx + bt + bp > kScratchBytes)
+        throw StatusError(HM_ERR_ARG, "hm_matvec_noalloc needs " + std::to_string(bx + bt + bp) +
+                                          " bytes of scratch, more than its fixed " +
+                                          std::to_string(kScratchBytes));
+    unsigned char *base = scratch_address();
+    auto *xc = reinterpret_cast<cplx<A> *>(base);
+    auto *tb = reinterpret_cast<cplx<A> *>(base + bx);
+    auto *tp = reinterpret_cast<cplx<A> *>(base + bx + bt);
+    for (int32_t c = 0; c < nrhs; ++c)
+        launch_matvec_col_ws<S, A>(M, x, nrhs, c, y, nrhs, nullptr, st, xc, tb, tp);
+}
+}  // namespace
+
 }  // namespace hm
+
+using namespace hm;
+
+extern "C" hm_status hm_matvec_noalloc(const hm_matrix *A, const void *x, void *y, int32_t nrhs,
+                                       void *stream) {
+    HM_API_BEGIN
+    if (!A || !x || !y) throw StatusError(HM_ERR_ARG, "NULL argument");
+    if (nrhs < 1) throw StatusError(HM_ERR_ARG, "nrhs must be >= 1");
+    if (A->plan_only) throw StatusError(HM_ERR_STATE, "matrix was built with plan_only");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (A->p.prec == HM_C64)
+        matvec_noalloc_cols<float>(A, x, y, nrhs, st);
+    else
+        matvec_noalloc_cols<double>(A, x, y, nrhs, st);
+    return HM_OK;
+    HM_API_END
+}

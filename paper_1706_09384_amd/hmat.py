@@ -99,6 +99,7 @@ def _load():
         "hm_params_default": ([P], i32),
         "hm_build": ([P, i64, P, i64, P, P, P, P], i32),
         "hm_matvec": ([P, P, P, i32, P], i32),
+        "hm_matvec_noalloc": ([P, P, P, i32, P], i32),
         "hm_residual": ([P, P, P, P, i32, P], i32),
         "hm_gmres": ([P, P, P, i32, d, i32, i32, P, P], i32),
         "hm_info": ([P, P], i32),
@@ -124,7 +125,7 @@ def _load():
 
 
 LIB = _load()
-EXPORTED = ["hm_params_default", "hm_build", "hm_matvec", "hm_residual", "hm_gmres", "hm_info",
+EXPORTED = ["hm_params_default", "hm_build", "hm_matvec", "hm_matvec_noalloc", "hm_residual", "hm_gmres", "hm_info",
             "hm_profile_matvec", "hm_profile_matvec_multi", "hm_autotune",
             "hm_export_tree", "hm_export_blocklist", "hm_export_block", "hm_destroy",
             "hm_release_cache",
@@ -216,6 +217,16 @@ class HMatrix:
             y = torch.empty((3 * self.nx, X.shape[1]), dtype=X.dtype, device=X.device)
         _check(LIB.hm_matvec(self._h, _ptr(X), _ptr(y), X.shape[1], _stream(stream)))
         return y.reshape(-1) if vec else y
+
+    def matvec_noalloc(self, x, y, stream=None):
+        """hm_matvec_noalloc: y = A_H x into the caller's y, with the library's fixed
+        device scratch (no allocation inside the call)."""
+        X = x.reshape(x.shape[0], -1)
+        Y = y.reshape(y.shape[0], -1)
+        assert X.is_contiguous() and Y.is_contiguous() and X.dtype == self.complex_dtype
+        assert Y.dtype == X.dtype and X.shape[0] == 3 * self.ny and Y.shape == (3 * self.nx, X.shape[1])
+        _check(LIB.hm_matvec_noalloc(self._h, _ptr(X), _ptr(Y), X.shape[1], _stream(stream)))
+        return y
 
     def residual(self, b, x, r=None, stream=None):
         """r = b - A_H x in FP64 (complex128 tensors)."""
