@@ -528,29 +528,46 @@ __global__ void __launch_bounds__(NT) factor_kernel(const RcBlk *__restrict__ bl
         __syncthreads();
         return sh_i[1];
     };
+    // Right singular vectors.  L = M0^* P S^-1 from the unrotated core M0 is
+    // cheap, but a left vector P_c that the sweeps left at angle tau (their
+    // orthogonality tolerance) to P_1 puts an error of tau s_1 / s_c into
+    // L_c, and the product U' V'^* inherits tau s_1^2 / s_c: 3e-10 relative
+    // at eps = 1e-4.  That is far below the rounding of complex64 storage,
+    // but not of complex128, so complex128 always accumulates the rotations
+    // in J (L = J, error of order tau s_c), and complex64 only when a kept
+    // singular value is far below s_1.
+    constexpr bool kAlwaysJ = sizeof(R) == 8;
+    auto identity_J = [&]() {
+        for (int64_t q = tid; q < (int64_t)r * r; q += NT)
+            J[q] = (q % r == q / r) ? cplx<double>{1, 0} : cplx<double>{0, 0};
+        __syncthreads();
+    };
     if (PHASE == 1) {
         form_core(M);
+        if (kAlwaysJ) identity_J();
         const double t = jacobi_tiny(M, r);
         if (tid == 0) tiny[blockIdx.x] = t;
         return;
     }
     if (PHASE == 0) {
         form_core(M);
-        jacobi_svd<false>(M, nullptr, r, lds, lds_elems, &sh_i[0]);
+        if (kAlwaysJ) {
+            identity_J();
+            jacobi_svd<true>(M, J, r, lds, lds_elems, &sh_i[0]);
+        } else {
+            jacobi_svd<false>(M, nullptr, r, lds, lds_elems, &sh_i[0]);
+        }
     }
     int keep = rank_and_keep();
-    // Right singular vectors: L = M0^* P S^-1 from the unrotated core M0 has an
-    // error of order u s_1 / s_c, harmless unless a kept singular value is far
-    // below s_1; then the sweeps are redone accumulating the rotations in J.
-    const bool useJ = keep > 0 && sv[idx[keep - 1]] < 1e-6 * sv[idx[0]];
-    if (useJ) {
+    const bool useJ = kAlwaysJ || (keep > 0 && sv[idx[keep - 1]] < 1e-6 * sv[idx[0]]);
+    if (useJ && !kAlwaysJ) {
         form_core(M);
         for (int64_t q = tid; q < (int64_t)r * r; q += NT)
             J[q] = (q % r == q / r) ? cplx<double>{1, 0} : cplx<double>{0, 0};
         __syncthreads();
         jacobi_svd<true>(M, J, r, lds, lds_elems, &sh_i[0]);
         keep = rank_and_keep();
-    } else {
+    } else if (!useJ) {
         form_core(J);   // J slot holds M0
         // L[:, c] = M0^* (M J)[:, idx_c] / s_c^2
         mfma_gemm(
@@ -589,6 +606,9 @@ struct JacTask {
     int32_t slot, bi, bj, pad;
 };
 
+// WITHJ: the rotations also go to J (slot 3), as in the one-workgroup sweep
+// with J (the column blocks are then half as wide).
+template <bool WITHJ>
 __global__ void __launch_bounds__(1024) jacobi_round_kernel(const RcBlk *__restrict__ blks,
                                                             const int32_t *__restrict__ order,
                                                             const JacTask *__restrict__ tasks,
@@ -605,8 +625,10 @@ __global__ void __launch_bounds__(1024) jacobi_round_kernel(const RcBlk *__restr
     const RcBlk b = blks[order[t.slot]];
     const int r = b.r;
     cplx<double> *M = work + b.goff + rc_slot(r, 2);
+    cplx<double> *J = work + b.goff + rc_slot(r, 3);
     const double tol = fmax(1e-14, 4.0 * r * 1.1e-16);
-    const int bw = jacobi_bw(r, lds_elems, 1);
+    const int bw = jacobi_bw(r, lds_elems, WITHJ ? 2 : 1);
+    cplx<double> *ldj = lds + 2 * (int64_t)bw * r;
     const int c0 = t.bi * bw, n0 = min(bw, r - c0);
     const int c1 = t.bj * bw, n1 = min(bw, r - c1);
     const int nc = n0 + n1;
@@ -614,13 +636,15 @@ __global__ void __launch_bounds__(1024) jacobi_round_kernel(const RcBlk *__restr
         const int cc = (int)(q / r), i = (int)(q % r);
         const int col = cc < n0 ? c0 + cc : c1 + (cc - n0);
         lds[q] = M[(int64_t)col * r + i];
+        if constexpr (WITHJ) ldj[q] = J[(int64_t)col * r + i];
     }
     __syncthreads();
-    const bool any = lds_sweep<false>(lds, nullptr, nc, r, tol, tiny[t.slot], &sh_flag);
+    const bool any = lds_sweep<WITHJ>(lds, ldj, nc, r, tol, tiny[t.slot], &sh_flag);
     for (int64_t q = threadIdx.x; q < (int64_t)nc * r; q += blockDim.x) {
         const int cc = (int)(q / r), i = (int)(q % r);
         const int col = cc < n0 ? c0 + cc : c1 + (cc - n0);
         M[(int64_t)col * r + i] = lds[q];
+        if constexpr (WITHJ) J[(int64_t)col * r + i] = ldj[q];
     }
     if (any && threadIdx.x == 0) rotated[t.slot] = 1;
 }
@@ -703,7 +727,7 @@ static void split_jacobi(const std::vector<RcBlk> &blk, const std::vector<int32_
     for (int s = 0; s < nbig; ++s) {
         const int r = blk[order[q0 + s]].r;
         if (r == 0) continue;
-        const int bw = jacobi_bw(r, lds_elems, 1);
+        const int bw = jacobi_bw(r, lds_elems, sizeof(R) == 8 ? 2 : 1);
         const int nb = (r + bw - 1) / bw;
         const int ne = (nb + 1) & ~1;
         if ((int)rounds.size() < ne - 1) rounds.resize(ne - 1);
@@ -731,7 +755,8 @@ static void split_jacobi(const std::vector<RcBlk> &blk, const std::vector<int32_
             HM_HIP_CHECK(hipMemsetAsync(d_rot.p, 0, nbig * sizeof(int32_t), st));
             for (size_t t = 0; t < rounds.size(); ++t)
                 if (!rounds[t].empty())
-                    hipLaunchKernelGGL(jacobi_round_kernel, dim3((unsigned)rounds[t].size()),
+                    hipLaunchKernelGGL(jacobi_round_kernel<sizeof(R) == 8>,
+                                       dim3((unsigned)rounds[t].size()),
                                        dim3(1024), bytes, st, d_blk, d_order + q0,
                                        d_tasks.as<JacTask>() + t0[t], W, d_tiny.as<double>(),
                                        d_active.as<int32_t>(), d_rot.as<int32_t>(), lds_elems);
@@ -803,7 +828,8 @@ void run_recompress(const std::vector<RcBlk> &blk, RcBlk *d_blk, const cplx<R> *
                                    (const void *)factor_kernel<R, 1024, 0>,
                                    (const void *)factor_kernel<R, 1024, 1>,
                                    (const void *)factor_kernel<R, 1024, 2>,
-                                   (const void *)jacobi_round_kernel};
+                                   (const void *)jacobi_round_kernel<false>,
+                                   (const void *)jacobi_round_kernel<true>};
             for (const void *k : kerns)
                 HM_HIP_CHECK(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize,
                                                  max_lds));
@@ -841,8 +867,9 @@ void run_recompress(const std::vector<RcBlk> &blk, RcBlk *d_blk, const cplx<R> *
         const int lo = cls > 0 ? classes[cls - 1] : -1;
         size_t q1 = q0;
         while (q1 < order.size() && blk[order[q1]].r > lo) ++q1;
+        // complex128 sweeps carry J beside M (twice the LDS for in-LDS sweeps)
         const int64_t need = (int64_t)rmax * rmax * (int64_t)sizeof(cplx<double>);
-        const int64_t bytes = std::min<int64_t>(need, max_lds);
+        const int64_t bytes = std::min<int64_t>(sizeof(R) == 8 ? 2 * need : need, max_lds);
         const int64_t lds_elems = bytes / (int64_t)sizeof(cplx<double>);
         // ranks above 64 leave room for one workgroup per CU (LDS): give it
         // 1024 threads (more lanes per Jacobi pair and per Cholesky column)

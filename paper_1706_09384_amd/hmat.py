@@ -93,6 +93,10 @@ def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
                           "(the HIP path has no fallback)")
+    # torch carries its own HIP runtime library: it is loaded before this
+    # library's, because with the opposite load order the library's HIP calls
+    # have reported no device on the MI355X boxes
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     P, i32, i64, d = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
     sig = {

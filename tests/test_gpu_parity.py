@@ -393,3 +393,66 @@ def test_split_aca_complex128_sampled_rows(hm, orc):
     say("sampled e =", e)
     assert e <= 5 * w.eps
 
+
+def _lowrank_fro(A, B):
+    """|A B^*|_F without forming the product: |R_A R_B^*|_F from thin QRs."""
+    if A.shape[1] == 0:
+        return 0.0
+    return float(np.linalg.norm(np.linalg.qr(A, mode="r") @ np.linalg.qr(B, mode="r").conj().T))
+
+
+def _recompression_parity(hm, orc, w, X, pick_limit, seed):
+    """Per-block recompression against the oracle (QR + truncated SVD, Section 3.2):
+    the ACA factors of a build with recompression off go through oracle.recompress,
+    and its rank and U'V'^* must equal the GPU's recompressed block.  Both builds
+    run the same deterministic ACA, so the inputs are identical."""
+    H0 = hm.build_workload(w, X=X, prec=0, recompress=False)
+    H1 = hm.build_workload(w, X=X, prec=0)
+    b0, r0, a0 = H0.export_blocklist()
+    b1, r1, a1 = H1.export_blocklist()
+    assert np.array_equal(b0, b1) and np.array_equal(a0, a1) and np.array_equal(r0, a0)
+    nx, ny = H0.export_tree(0)[1], H0.export_tree(1)[1]
+    lowrank = np.flatnonzero(b0[:, 2] == 1)
+    order = lowrank[np.argsort(-a0[lowrank], kind="stable")]
+    rng = np.random.default_rng(seed)
+    rest = order[pick_limit // 2:]
+    pick = np.concatenate([order[:pick_limit // 2],
+                           rng.choice(rest, min(pick_limit // 2, rest.size), replace=False)])
+    worst, mism = 0.0, 0
+    for k in pick:
+        U, V = H0.export_block(int(k), b0, r0, nx, ny)
+        Ug, Vg = H1.export_block(int(k), b1, r1, nx, ny)
+        Uo, Vo, S = orc.recompress(U, V, w.eps)
+        nrm = _lowrank_fro(U, V)
+        if Uo.shape[1] != Ug.shape[1]:
+            # only a singular value at the truncation threshold may round either way
+            tot = float(np.sum(S ** 2))
+            tails = [float(np.sum(S[r:] ** 2)) for r in (Ug.shape[1], Uo.shape[1])]
+            thr = w.eps ** 2 * tot
+            assert all(abs(t - thr) <= 1e-9 * thr for t in tails), (int(k), Ug.shape, Uo.shape)
+            mism += 1
+            continue
+        e = _lowrank_fro(np.hstack([Ug, -Uo]), np.hstack([Vg, Vo])) / nrm
+        worst = max(worst, e)
+    say(f"recompression parity: {pick.size} blocks, max ACA rank {int(a0[pick].max())}, "
+        f"max rel diff {worst:.3e}, threshold ties {mism}")
+    assert mism <= max(1, pick.size // 100)
+    return worst
+
+
+@pytest.mark.parametrize("eps", [1e-4, 1e-8])
+def test_recompression_matches_oracle_per_block(hm, orc, sphere1k, eps):
+    w, X, pb, A, b = sphere1k
+    say(f"case recompression per block sphere1k eps={eps}")
+    w = W.Workload(w.name, w.n_points, w.kernel, omega=w.omega, eps=eps, leaf=w.leaf,
+                   self_re=w.self_re, geometry=w.geometry)
+    assert _recompression_parity(hm, orc, w, X, 300, 1) <= 1e-12
+
+
+def test_recompression_matches_oracle_split_blocks(hm, orc):
+    """Large blocks: split ACA, rank classes above 64 (1024-thread workgroups)
+    and above 100 (cross-workgroup Jacobi rounds)."""
+    w = W.small_sphere(12000, omega=19.4, leaf=32, eps=1e-6)
+    say("case recompression per block sphere12k eps=1e-6")
+    X, _ = w.points()
+    assert _recompression_parity(hm, orc, w, X, 40, 2) <= 1e-12
