@@ -456,6 +456,61 @@ def sphere20k_leg(hmat, W, orc, do_gmres=True):
     return out
 
 
+def sweep_leg(hmat, W, orc, max_points=400000, max_points_t=260000, kernels=(0, 1),
+              fixed_omega=14.0):
+    """Frequency sweeps of the paper's Section 8 on Fibonacci spheres (complex64, eps 1e-4,
+    leaf 32): at the fixed density of Table table_corr (omega grows with sqrt(N_c)) and at
+    the fixed frequency omega = 14 of Section 7.2.  Per point: maximum ACA and recompressed
+    rank, storage, compression rate (stored entries / (3 N_c)^2), assembly seconds and the
+    sampled-row error against the oracle."""
+    import torch
+    res = {"fixed_density": [], "fixed_frequency": []}
+    series = [(n, w_) for n, w_ in W.fixed_density_series() if n <= max_points]
+    fixed = [(n, fixed_omega) for n, _ in series if n <= 100000]
+    for key, pts in (("fixed_density", series), ("fixed_frequency", fixed)):
+        for kernel in kernels:
+            for n, om in pts:
+                if kernel == 1 and n > max_points_t:
+                    continue
+                w = W.sweep_sphere(n, om, kernel=kernel)
+                X, N = w.points()
+                tb = time.perf_counter()
+                H = hmat.build_workload(w, X=X, N=N, prec=hmat.C64)
+                torch.cuda.synchronize()
+                tbuild = time.perf_counter() - tb
+                s = H.info()
+                b = w.rhs()
+                y = H.matvec(torch.from_numpy(b[:, 0]).cuda().to(torch.complex64))
+                rows = np.random.default_rng(7).choice(n, 32, replace=False)
+                ref = orc.matvec_rows(orc.Problem.from_workload(w, X, N), b, rows)
+                idx = (3 * rows[:, None] + np.arange(3)).ravel()
+                yy = y.cpu().numpy().astype(np.complex128)[idx]
+                err = float(np.linalg.norm(yy - ref[:, 0]) / np.linalg.norm(ref[:, 0]))
+                ent = s["dense_entries"] + s["lowrank_entries"]
+                rec = {"kernel": "U" if kernel == 0 else "T", "N_c": n, "dofs": 3 * n, "omega": om,
+                       "max_rank_aca": s["max_rank_aca"], "max_rank": s["max_rank"],
+                       "storage_bytes": s["storage_bytes"],
+                       "compression_rate": round(ent / (3.0 * n) ** 2, 5),
+                       "assembly_s": round(tbuild, 3), "err_vs_oracle_sampled": err,
+                       "n_capped": s["n_capped"]}
+                res[key].append(rec)
+                log(f"[bench] sweep {key} {rec}")
+                H.close()
+                hmat.release_cache()
+    # fitted exponents of the maximum recompressed rank (least squares in log-log)
+    fits = {}
+    for kern in ("U", "T"):
+        pts = [r for r in res["fixed_density"] if r["kernel"] == kern]
+        if len(pts) >= 3:
+            lw = np.log([r["omega"] for r in pts])
+            ln_ = np.log([r["dofs"] for r in pts])
+            lr = np.log([r["max_rank"] for r in pts])
+            fits[kern] = {"rank_vs_omega": round(float(np.polyfit(lw, lr, 1)[0]), 3),
+                          "rank_vs_dofs": round(float(np.polyfit(ln_, lr, 1)[0]), 3)}
+    res["fitted_exponents_fixed_density"] = fits
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -468,6 +523,8 @@ def main():
     ap.add_argument("--no-multirhs", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-batching", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--sweep-only", action="store_true", help="run the frequency sweeps alone")
     ap.add_argument("--counters", action="store_true",
                     help="profiling mode: one headline build, the autotuner, 10 matvecs, then a "
                          "256 MiB device copy (x3) whose known byte count calibrates FETCH_SIZE / "
@@ -480,6 +537,11 @@ def main():
 
     import torch
     from paper_1706_09384_amd import hmat, workloads as W
+
+    if args.sweep_only:
+        import oracle as orc
+        print(json.dumps({"sweep": sweep_leg(hmat, W, orc)}), flush=True)
+        return
 
     w = W.multirhs_sphere_200k()
     X, N = w.points()
@@ -622,6 +684,9 @@ def main():
         out["learned"] = learned_leg(hmat, W, orc)
     if not args.no_batching:
         out["batching"] = batching_leg(hmat, W, orc)
+    if not args.no_sweep:
+        # up to 163,543 points here; --sweep-only runs the whole table
+        out["sweep"] = sweep_leg(hmat, W, orc, max_points=170000, max_points_t=170000)
     print(json.dumps(out), flush=True)
 
 

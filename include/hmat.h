@@ -83,8 +83,8 @@ typedef struct {
     int32_t unbatched;     /* 1: assembly launches its kernels once per block (the
                               comparison baseline of the batched default) */
     int32_t aca_scratch_mb;/* cap on the first-pass ACA factor scratch of one chunk of
-                              admissible blocks, MiB; 0 = half of the free device
-                              memory (see hm_build) */
+                              admissible blocks, MiB; 0 = 40% of the device memory
+                              free when the chunk starts (see hm_build) */
     int32_t reserved[5];
 } hm_params;
 
@@ -219,10 +219,10 @@ typedef struct {
     int64_t aca_scratch_bytes;         /* first-pass ACA factor scratch, summed over chunks */
     int32_t aca_chunks;                /* chunks the admissible blocks were assembled in */
     int32_t acc_waves, proj_rows;      /* 1-RHS matvec launch shape (hm_autotune may change it) */
-    int32_t n_capped;                  /* admissible blocks whose ACA reached the rank cap (639
-                                          columns for complex128, 852 for complex64) before its
+    int32_t n_capped;                  /* admissible blocks whose ACA reached the rank cap (852
+                                          columns in complex64, 639 in complex128) before its
                                           stopping test held: they keep the capped factors, which
-                                          miss eps; 0 on every workload the library is tested on */
+                                          may miss eps; 0 on every workload of the test suite */
 } hm_stats;
 
 hm_status hm_info(const hm_matrix *A, hm_stats *s);

@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstring>
 #include <exception>
+#include <atomic>
 #include <future>
 #include <mutex>
 #include <numeric>
@@ -35,6 +36,7 @@ struct CachedBlock {
 };
 std::mutex g_cache_mu;
 std::vector<CachedBlock> g_cache;
+std::atomic<int64_t> g_live_bytes{0};   // device bytes held by live DeviceBufs
 constexpr size_t kCacheMin = size_t(32) << 20;
 
 // Smallest cached block on `dev` holding b bytes and at most twice b.
@@ -95,6 +97,7 @@ hipStream_t side_stream(int which) {
 
 void DeviceBuf::reset() {
     if (!p) return;
+    g_live_bytes -= (int64_t)bytes;
     if (bytes >= kCacheMin) {
         // as hipFree would: no queued work may still use the memory
         int cur = 0;
@@ -128,7 +131,10 @@ void DeviceBuf::alloc(size_t b) {
         if (++counter == std::atol(inj)) throw StatusError(HM_ERR_ALLOC, "injected allocation failure");
     }
     HM_HIP_CHECK(hipGetDevice(&dev));
-    if (b >= kCacheMin / 2 && cache_take(b, dev, &p, &bytes)) return;
+    if (b >= kCacheMin / 2 && cache_take(b, dev, &p, &bytes)) {
+        g_live_bytes += (int64_t)bytes;
+        return;
+    }
     hipError_t e = hipMalloc(&p, b);
     if (e == hipErrorOutOfMemory) {
         // give the cached blocks back and try once more
@@ -140,9 +146,12 @@ void DeviceBuf::alloc(size_t b) {
         p = nullptr;
         (void)hipGetLastError();
         throw StatusError(HM_ERR_ALLOC, "hipMalloc of " + std::to_string(b) + " bytes failed: " +
-                                            hipGetErrorString(e));
+                                            hipGetErrorString(e) + " (the library holds " +
+                                            std::to_string(g_live_bytes.load()) +
+                                            " bytes in live buffers)");
     }
     bytes = b;
+    g_live_bytes += (int64_t)b;
 }
 
 size_t elem_bytes(int prec) { return prec == HM_C64 ? 8 : 16; }
@@ -503,13 +512,19 @@ void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vect
         }
     }
     int32_t overflow = 0, fallbacks = 0, capped = 0, hits = 0;
-    // The ACA kernel keeps the pivot row (3 x budget, compute type) and the V
-    // Gram column (budget x 3, complex FP64) in LDS: cap the budget so that
-    // both fit in 64 KiB.  A block still unconverged at the cap keeps its
-    // capped-rank approximation (counted in hm_stats.n_capped).
+    // The one-workgroup ACA kernel keeps the pivot row (3 x budget, compute
+    // type) and the V Gram column (budget x 3, complex FP64) in LDS: the
+    // budget is capped so that both fit in 60 KiB (852 columns in complex64,
+    // 639 in complex128).  The split form would allow three times as many
+    // (only its pivot row is in LDS), but the blocks that reach the cap are
+    // ones whose ACA stagnates: on the 254,546-point T sphere at kappa_s = 84
+    // they ran on to 2,559 columns for a recompressed rank of 515 and took
+    // 85 s, so the split form keeps the same cap.  A block still unconverged
+    // at the cap keeps its capped-rank approximation (hm_stats.n_capped).
     const int32_t budget_cap =
         (int32_t)((60 * 1024) / (3 * (sizeof(cplx<R>) + sizeof(cplx<double>)))) / 3 * 3;
-    for (auto &bg : budget) bg = std::min(bg, budget_cap);
+    auto cap_of = [&](int64_t) { return budget_cap; };
+    for (int64_t k = 0; k < nlr; ++k) budget[k] = std::min(budget[k], cap_of(k));
     // Longest first: ACA step k costs O(k (m + n)), a block about budget^2 (m + n).
     auto lpt = [&](int64_t a, int64_t b) {
         return (int64_t)(lm[a] + ln[a]) * budget[a] * budget[a] >
@@ -519,24 +534,24 @@ void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vect
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), lpt);
     // The admissible blocks are processed in chunks whose first-pass factor
-    // scratch stays about under a cap (default: half of the free device
-    // memory, counting the library's cached blocks as free): a chunk's ACA, recompression and final factors are done, and
-    // its scratch released, before the next chunk starts.  Blocks are dealt
-    // to the chunks round-robin in the longest-first order, so that every
-    // chunk has the same mix of long and short blocks.
-    int64_t cap_bytes = (int64_t)p.aca_scratch_mb << 20;
-    if (cap_bytes <= 0) {
+    // scratch stays about under a cap: a chunk's ACA, recompression and final
+    // factors are done, and its scratch released, before the next chunk
+    // starts.  The default cap is 40% of the device memory free when the
+    // chunk starts (the library's cached blocks count as free), so that the
+    // factors kept from earlier chunks shrink later ones.  The blocks not yet
+    // compressed are dealt round-robin in the longest-first order, so that
+    // every chunk has the same mix of long and short blocks.
+    auto chunk_cap = [&]() -> int64_t {
+        if (p.aca_scratch_mb > 0) return (int64_t)p.aca_scratch_mb << 20;
         size_t fr = 0, tot = 0;
         int dev = 0;
         HM_HIP_CHECK(hipMemGetInfo(&fr, &tot));
         HM_HIP_CHECK(hipGetDevice(&dev));
-        // the library's own cached blocks count as available
-        cap_bytes = std::max<int64_t>(int64_t(1) << 30, (int64_t)((fr + cache_bytes(dev)) / 2));
-    }
-    int64_t total_need = 0;
-    for (int64_t k = 0; k < nlr; ++k) total_need += 3 * (int64_t)(lm[k] + ln[k]) * budget[k];
-    const int64_t nchunks = std::max<int64_t>(
-        1, std::min<int64_t>(nlr, ceil_div(total_need * (int64_t)sizeof(cplx<R>), cap_bytes)));
+        return std::max<int64_t>(int64_t(1) << 30, (int64_t)((fr + cache_bytes(dev)) / 5 * 2));
+    };
+    auto first_need = [&](int64_t k) {
+        return 3 * (int64_t)(lm[k] + ln[k]) * budget[k] * (int64_t)sizeof(cplx<R>);
+    };
     std::vector<int32_t> aca_rank(nlr, 0), final_rank(nlr, 0);
     std::vector<int64_t> aca_u(nlr), aca_v(nlr), fu(nlr), fv(nlr);
     // A block that uses up its budget continues later from where it stopped:
@@ -551,7 +566,14 @@ void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vect
     };
     std::vector<Resume> resume(nlr);
     std::vector<uint8_t> reran(nlr, 0);   // the first budget did not suffice
-    std::vector<std::unique_ptr<DeviceBuf>> holding;
+    // Holding buffers, released once every block they hold has continued
+    // (used_gen catches up with the generation the block was held in).
+    struct Held {
+        std::unique_ptr<DeviceBuf> fac, flg;
+        std::vector<std::pair<int64_t, int32_t>> blocks;   // (block, generation)
+    };
+    std::vector<Held> holding;
+    std::vector<int32_t> hold_gen(nlr, 0), used_gen(nlr, 0);
     int32_t n_chunks_done = 0;
     int64_t lr_entries = 0, t_len = 0;
     double t_aca = 0.0, t_rc = 0.0;
@@ -560,17 +582,32 @@ void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vect
     // collected from every chunk and compressed together in one last chunk,
     // so that their long re-runs and large recompressions overlap each other
     // instead of ending every chunk.
+    // The deferred blocks form the final phase, chunked by the same cap (their
+    // budgets have grown); blocks that outgrow a budget there continue at once.
     std::vector<int64_t> deferred;
-    for (int64_t ch = 0; ch <= nchunks; ++ch) {
-        const bool last = ch == nchunks;
-        std::vector<int64_t> members;
-        if (!last) {
-            for (int64_t q = ch; q < nlr; q += nchunks) members.push_back(order[q]);
-        } else {
-            if (deferred.empty()) break;
-            members.swap(deferred);
+    std::vector<int64_t> remaining = order;
+    bool chunked = false, last = false;
+    for (;;) {
+        if (remaining.empty()) {
+            if (last || deferred.empty()) break;
+            last = true;
+            remaining.swap(deferred);
+            std::stable_sort(remaining.begin(), remaining.end(), lpt);
         }
-        const bool defer = !last && nchunks > 1;
+        std::vector<int64_t> members;
+        {
+            int64_t need = 0;
+            for (int64_t k : remaining) need += first_need(k);
+            const int64_t stride =
+                std::max<int64_t>(1, std::min<int64_t>((int64_t)remaining.size(),
+                                                       ceil_div(need, chunk_cap())));
+            chunked = chunked || stride > 1;
+            std::vector<int64_t> rest;
+            for (size_t q = 0; q < remaining.size(); ++q)
+                (q % stride == 0 ? members : rest).push_back(remaining[q]);
+            remaining.swap(rest);
+        }
+        const bool defer = !last && chunked;
         double tc = now_s();
         // ---- vector ACA passes of the chunk, pipelined with recompression ------
         // Pass 0 runs every block of the chunk; blocks that use up their budget
@@ -578,8 +615,6 @@ void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vect
         // its own stream while pass p is recompressed.
         std::vector<std::unique_ptr<DeviceBuf>> pass_scratch;
         std::vector<std::vector<int64_t>> pass_members;
-        std::vector<std::unique_ptr<DeviceBuf>> pass_work, pass_newrank, pass_drc;
-        std::vector<std::vector<RcBlk>> pass_rc;
         struct AcaLaunch {
             std::vector<int64_t> todo;
             std::vector<AcaBlk> ab;
@@ -616,7 +651,8 @@ void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vect
                 fac += 3 * (int64_t)a.n * a.budget;
                 a.foff = flg;
                 flg += a.m + a.n;
-                maxb = std::max(maxb, a.budget);
+                // LDS of the one-workgroup kernel (split blocks size their own)
+                if (a.m + a.n < kAcaBigPoints) maxb = std::max(maxb, a.budget);
                 const Resume &rs = resume[k];
                 if (rs.r > 0) {
                     a.r0 = rs.r;
@@ -645,6 +681,7 @@ void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vect
                 HM_HIP_CHECK(hipMemcpyAsync(L.scratch->template as<cplx<R>>() + a.voff, rs.v,
                                             3 * (size_t)a.n * a.r0 * sizeof(cplx<R>),
                                             hipMemcpyDeviceToDevice, s));
+                used_gen[todo[q]] = hold_gen[todo[q]];
                 HM_HIP_CHECK(hipMemcpyAsync(L.flags->template as<uint8_t>() + a.foff, rs.f,
                                             (size_t)(a.m + a.n), hipMemcpyDeviceToDevice, s));
             }
@@ -671,18 +708,19 @@ void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vect
             {
                 int64_t hf = 0, hb = 0;
                 for (size_t q = 0; q < L.todo.size(); ++q)
-                    if (res[q].status == 1 && budget[L.todo[q]] < budget_cap) {
+                    if (res[q].status == 1 && budget[L.todo[q]] < cap_of(L.todo[q])) {
                         hf += 3 * (int64_t)(L.ab[q].m + L.ab[q].n) * res[q].rank;
                         hb += L.ab[q].m + L.ab[q].n;
                     }
                 if (hb > 0) {
+                    Held hd;
                     auto hfac = std::make_unique<DeviceBuf>(), hflg = std::make_unique<DeviceBuf>();
                     hfac->alloc(std::max<int64_t>(hf, 1) * sizeof(cplx<R>));
                     hflg->alloc(hb);
                     int64_t of = 0, ob = 0;
                     for (size_t q = 0; q < L.todo.size(); ++q) {
                         const int64_t k = L.todo[q];
-                        if (!(res[q].status == 1 && budget[k] < budget_cap)) continue;
+                        if (!(res[q].status == 1 && budget[k] < cap_of(k))) continue;
                         const AcaBlk &a = L.ab[q];
                         const int32_t rk = res[q].rank;
                         cplx<R> *hu = hfac->template as<cplx<R>>() + of;
@@ -699,20 +737,22 @@ void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vect
                                                     L.s));
                         resume[k] = {rk, res[q].steps, res[q].fallbacks, res[q].ih, res[q].pend,
                                      res[q].norm2, hu, hv, hg};
+                        hd.blocks.emplace_back(k, ++hold_gen[k]);
                         of += 3 * (int64_t)(a.m + a.n) * rk;
                         ob += a.m + a.n;
                     }
                     HM_HIP_CHECK(hipStreamSynchronize(L.s));
-                    holding.push_back(std::move(hfac));
-                    holding.push_back(std::move(hflg));
+                    hd.fac = std::move(hfac);
+                    hd.flg = std::move(hflg);
+                    holding.push_back(std::move(hd));
                 }
             }
             for (size_t q = 0; q < L.todo.size(); ++q) {
                 const int64_t k = L.todo[q];
-                if (res[q].status == 1 && budget[k] < budget_cap) {
+                if (res[q].status == 1 && budget[k] < cap_of(k)) {
                     ++overflow;
                     reran[k] = 1;
-                    budget[k] = std::min({3 * std::min(lm[k], ln[k]), 2 * budget[k], budget_cap});
+                    budget[k] = std::min({3 * std::min(lm[k], ln[k]), 2 * budget[k], cap_of(k)});
                     next.push_back(k);
                     continue;
                 }
@@ -730,46 +770,106 @@ void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vect
             L.d_out.reset();
             return next;
         };
-        // Recompression of pass ps on the build stream.
-        auto recompress_pass = [&](size_t ps) {
-            pass_work.emplace_back();
-            pass_newrank.emplace_back();
-            pass_drc.emplace_back();
-            pass_rc.emplace_back();
-            auto &mem = pass_members[ps];
-            auto &rc = pass_rc[ps];
-            int64_t goff = 0;
-            for (int64_t k : mem) {
-                RcBlk c;
-                c.uoff = aca_u[k];
-                c.voff = aca_v[k];
-                c.m = lm[k];
-                c.rb = tx.begin[M->blocks[lr_ids[k]].row];
-                c.n = ln[k];
-                c.r = aca_rank[k];
-                c.goff = goff;
-                // slot 6 holds r^2 + 2r entries (see the recompression work layout)
-                goff += 8 * (int64_t)c.r * c.r + 2 * (int64_t)c.r;
-                rc.push_back(c);
-            }
-            pass_drc[ps] = std::make_unique<DeviceBuf>();
-            upload(*pass_drc[ps], rc, st);
-            pass_newrank[ps] = std::make_unique<DeviceBuf>();
-            pass_newrank[ps]->alloc(std::max<size_t>(rc.size(), 1) * sizeof(int32_t));
-            if (p.recompress && !rc.empty()) {
-                pass_work[ps] = std::make_unique<DeviceBuf>();
-                pass_work[ps]->alloc(std::max<int64_t>(goff, 1) * sizeof(cplx<double>));
-                run_recompress<R>(rc, pass_drc[ps]->as<RcBlk>(), pass_scratch[ps]->as<cplx<R>>(),
-                                  pass_work[ps]->as<double>(), pass_newrank[ps]->as<int32_t>(),
-                                  p.eps, 0, st, p.unbatched != 0);
-                std::vector<int32_t> nr(rc.size());
-                HM_HIP_CHECK(hipMemcpyAsync(nr.data(), pass_newrank[ps]->p,
-                                            nr.size() * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        // Recompression of pass ps on the build stream, and the final factors
+        // of its blocks.  The blocks go in groups whose FP64 recompression
+        // work (8 r^2 + 2r complex doubles per block) stays under a cap; each
+        // group's factors are written to a buffer of their own at once, and
+        // the pass's ACA scratch is released at the end.  Every block's factor
+        // offsets count from the first buffer (M->lr_base), the base pointer
+        // of the matvec kernels; allocations are 256-byte aligned, so the
+        // distance between two buffers is a whole (for complex64, even)
+        // number of elements.
+        auto compress_emit = [&](size_t ps) {
+            const auto &mem = pass_members[ps];
+            const int64_t work_cap =
+                std::max<int64_t>(int64_t(1) << 30, chunk_cap() / 4) / (int64_t)sizeof(cplx<double>);
+            size_t q0 = 0;
+            while (q0 < mem.size()) {
+                std::vector<RcBlk> rc;
+                int64_t goff = 0;
+                size_t q1 = q0;
+                for (; q1 < mem.size(); ++q1) {
+                    const int64_t k = mem[q1];
+                    const int64_t wk = 8 * (int64_t)aca_rank[k] * aca_rank[k] + 2 * (int64_t)aca_rank[k];
+                    if (q1 > q0 && goff + wk > work_cap) break;
+                    RcBlk c;
+                    c.uoff = aca_u[k];
+                    c.voff = aca_v[k];
+                    c.m = lm[k];
+                    c.rb = tx.begin[M->blocks[lr_ids[k]].row];
+                    c.n = ln[k];
+                    c.r = aca_rank[k];
+                    c.goff = goff;
+                    goff += wk;
+                    rc.push_back(c);
+                }
+                DeviceBuf d_rc, d_newrank, work;
+                upload(d_rc, rc, st);
+                d_newrank.alloc(rc.size() * sizeof(int32_t));
+                if (p.recompress) {
+                    work.alloc(std::max<int64_t>(goff, 1) * sizeof(cplx<double>));
+                    run_recompress<R>(rc, d_rc.as<RcBlk>(), pass_scratch[ps]->as<cplx<R>>(),
+                                      work.as<double>(), d_newrank.as<int32_t>(), p.eps, 0, st,
+                                      p.unbatched != 0);
+                    std::vector<int32_t> nr(rc.size());
+                    HM_HIP_CHECK(hipMemcpyAsync(nr.data(), d_newrank.p, nr.size() * sizeof(int32_t),
+                                                hipMemcpyDeviceToHost, st));
+                    HM_HIP_CHECK(hipStreamSynchronize(st));
+                    for (size_t q = q0; q < q1; ++q) final_rank[mem[q]] = nr[q - q0];
+                } else {
+                    for (size_t q = q0; q < q1; ++q) final_rank[mem[q]] = aca_rank[mem[q]];
+                }
+                // this group's final factors
+                int64_t len = 0;
+                std::vector<int64_t> ou(rc.size()), ov(rc.size());
+                std::vector<int32_t> kp(rc.size());
+                for (size_t q = q0; q < q1; ++q) {
+                    const int64_t k = mem[q];
+                    const Block &B = M->blocks[lr_ids[k]];
+                    kp[q - q0] = final_rank[k];
+                    ou[q - q0] = len;
+                    len += (int64_t)padded_rows(rowpad, tx.begin[B.row], lm[k]) * final_rank[k];
+                    ov[q - q0] = len;
+                    len += 3 * (int64_t)ln[k] * even_up(final_rank[k]);
+                    len += (kSegRows - len % kSegRows) % kSegRows;   // next U on a segment boundary
+                }
+                auto out = std::make_unique<DeviceBuf>();
+                out->alloc((len + 2) * sizeof(cplx<R>));
+                HM_HIP_CHECK(hipMemsetAsync(out->p, 0, (len + 2) * sizeof(cplx<R>), st));
+                if (!M->lr_base) M->lr_base = out->p;
+                const std::ptrdiff_t gap =
+                    static_cast<const char *>(out->p) - static_cast<const char *>(M->lr_base);
+                if (gap % (std::ptrdiff_t)(kSegRows * sizeof(cplx<R>)) != 0)
+                    throw HipError("factor buffer misaligned against the first one",
+                                   hipErrorInvalidValue);
+                const int64_t delta = (int64_t)(gap / (std::ptrdiff_t)sizeof(cplx<R>));
+                DeviceBuf d_ou, d_ov;
+                upload(d_ou, ou, st);
+                upload(d_ov, ov, st);
+                if (p.recompress) {
+                    run_recompress_apply<R>(rc, d_rc.as<RcBlk>(), pass_scratch[ps]->as<cplx<R>>(),
+                                            work.as<double>(), d_ou.as<int64_t>(),
+                                            d_ov.as<int64_t>(), d_newrank.as<int32_t>(),
+                                            out->as<cplx<R>>(), kp, M->d_rowpad.as<int32_t>(), st,
+                                            p.unbatched != 0);
+                } else {
+                    hipLaunchKernelGGL(copy_factors_kernel<R>, dim3(64, (unsigned)rc.size()),
+                                       dim3(256), 0, st, d_rc.as<RcBlk>(),
+                                       pass_scratch[ps]->as<cplx<R>>(), d_ou.as<int64_t>(),
+                                       d_ov.as<int64_t>(), out->as<cplx<R>>(),
+                                       M->d_rowpad.as<int32_t>());
+                    HM_HIP_CHECK(hipGetLastError());
+                }
                 HM_HIP_CHECK(hipStreamSynchronize(st));
-                for (size_t q = 0; q < mem.size(); ++q) final_rank[mem[q]] = nr[q];
-            } else {
-                for (size_t q = 0; q < mem.size(); ++q) final_rank[mem[q]] = aca_rank[mem[q]];
+                for (size_t q = q0; q < q1; ++q) {
+                    fu[mem[q]] = delta + ou[q - q0];
+                    fv[mem[q]] = delta + ov[q - q0];
+                }
+                M->lowrank.push_back(std::move(out));
+                lr_entries += len;
+                q0 = q1;
             }
+            pass_scratch[ps].reset();
         };
         hipStream_t aca_side = p.unbatched ? st : side_stream(1);
         {
@@ -803,7 +903,7 @@ void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vect
                     AcaLaunch first = launch(small, st);
                     first_bytes = first.scratch_bytes;
                     next = finish(first);
-                    recompress_pass(0);
+                    compress_emit(0);
                 } catch (...) {
                     err = std::current_exception();
                 }
@@ -830,77 +930,20 @@ void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vect
                 const bool more = !next.empty();
                 AcaLaunch rerun;
                 if (more) rerun = launch(next, aca_side);   // runs beside ...
-                recompress_pass(ps);                        // ... this recompression
+                compress_emit(ps);                          // ... this recompression
                 if (!more) break;
                 next = finish(rerun);
             }
         }
-        const size_t np = pass_scratch.size();
-        // ---- the chunk's final factors, in pass order ------------------------------
-        std::vector<int64_t> held;   // blocks whose factors this chunk computed
-        for (const auto &pm : pass_members) held.insert(held.end(), pm.begin(), pm.end());
-        // The chunk's factors stay in their own buffer (no second copy into
-        // one slab); every block's offsets are taken from the first chunk's
-        // buffer, the base pointer of the matvec kernels.  Allocations are
-        // 256-byte aligned, so the distance between two buffers is a whole
-        // (and, for complex64, even) number of elements.
-        int64_t len = 0;
-        for (int64_t k : held) {
-            const Block &B = M->blocks[lr_ids[k]];
-            fu[k] = len;
-            len += (int64_t)padded_rows(rowpad, tx.begin[B.row], lm[k]) * final_rank[k];
-            fv[k] = len;
-            len += 3 * (int64_t)ln[k] * even_up(final_rank[k]);
-            len += (kSegRows - len % kSegRows) % kSegRows;   // next U on a segment boundary
-        }
-        auto out = std::make_unique<DeviceBuf>();
-        out->alloc((len + 2) * sizeof(cplx<R>));
-        HM_HIP_CHECK(hipMemsetAsync(out->p, 0, (len + 2) * sizeof(cplx<R>), st));
-        if (!M->lr_base) M->lr_base = out->p;
-        const std::ptrdiff_t gap =
-            static_cast<const char *>(out->p) - static_cast<const char *>(M->lr_base);
-        if (gap % (std::ptrdiff_t)(kSegRows * sizeof(cplx<R>)) != 0)
-            throw HipError("factor buffer misaligned against the first chunk", hipErrorInvalidValue);
-        const int64_t delta = (int64_t)(gap / (std::ptrdiff_t)sizeof(cplx<R>));
-        for (size_t ps = 0; ps < np; ++ps) {
-            auto &mem = pass_members[ps];
-            if (mem.empty()) continue;
-            std::vector<int64_t> ou(mem.size()), ov(mem.size());
-            std::vector<int32_t> kp(mem.size());
-            for (size_t q = 0; q < mem.size(); ++q) {
-                kp[q] = final_rank[mem[q]];
-                ou[q] = fu[mem[q]];
-                ov[q] = fv[mem[q]];
-            }
-            DeviceBuf d_ou, d_ov;
-            upload(d_ou, ou, st);
-            upload(d_ov, ov, st);
-            if (p.recompress) {
-                run_recompress_apply<R>(pass_rc[ps], pass_drc[ps]->as<RcBlk>(),
-                                        pass_scratch[ps]->as<cplx<R>>(),
-                                        pass_work[ps]->as<double>(), d_ou.as<int64_t>(),
-                                        d_ov.as<int64_t>(), pass_newrank[ps]->as<int32_t>(),
-                                        out->as<cplx<R>>(), kp, M->d_rowpad.as<int32_t>(), st,
-                                        p.unbatched != 0);
-            } else {
-                hipLaunchKernelGGL(copy_factors_kernel<R>, dim3(64, (unsigned)mem.size()),
-                                   dim3(256), 0, st, pass_drc[ps]->as<RcBlk>(),
-                                   pass_scratch[ps]->as<cplx<R>>(), d_ou.as<int64_t>(),
-                                   d_ov.as<int64_t>(), out->as<cplx<R>>(),
-                                   M->d_rowpad.as<int32_t>());
-                HM_HIP_CHECK(hipGetLastError());
-            }
-            HM_HIP_CHECK(hipStreamSynchronize(st));
-            pass_work[ps].reset();
-            pass_scratch[ps].reset();
-        }
-        for (int64_t k : held) {
-            fu[k] += delta;
-            fv[k] += delta;
-        }
-        M->lowrank.push_back(std::move(out));
-        lr_entries += len;
         ++n_chunks_done;
+        // holding buffers whose blocks have all continued (their copies are done)
+        holding.erase(std::remove_if(holding.begin(), holding.end(),
+                                     [&](const Held &h) {
+                                         for (const auto &bg : h.blocks)
+                                             if (used_gen[bg.first] < bg.second) return false;
+                                         return true;
+                                     }),
+                      holding.end());
         t_rc += now_s() - tc;
     }
     S.aca_chunks = n_chunks_done;

@@ -206,6 +206,27 @@ def small_sphere(n: int, kernel: int = KERNEL_U, omega: float = 5.6, leaf: int =
                     self_re=self_re, geometry="sphere")
 
 
+# Fixed density of points per S-wavelength (the paper's Section 8, Table table_corr):
+# (DOFs N = 3 x mesh vertices, circular frequency omega) of its sphere meshes.
+TABLE_CORR = [(7686, 8.25), (30726, 16.5), (122886, 33.0), (183099, 40.0), (490629, 66.0),
+              (763638, 84.0), (985818, 92.0)]
+
+
+def fixed_density_series() -> list:
+    """(points, omega) pairs of the fixed-density sweep: N_c = N / 3 points at the
+    paper's frequencies (10 points per S-wavelength on its meshes)."""
+    return [(n // 3, w) for n, w in TABLE_CORR]
+
+
+def sweep_sphere(n: int, omega: float, kernel: int = KERNEL_U, eps: float = 1e-4,
+                 leaf: int = 32) -> Workload:
+    """Fibonacci sphere of the frequency sweeps: unit sphere, material of Section 7.1,
+    self blocks by the density rule of the other workloads."""
+    w = small_sphere(n, kernel=kernel, omega=omega, leaf=leaf, eps=eps)
+    w.name = f"sphere{n}_{'U' if kernel == KERNEL_U else 'T'}_w{omega:g}"
+    return w
+
+
 ALL = {
     "sphere1k": plain_sphere_1k,
     "sphere20k": precision_sphere_20k,

@@ -13,6 +13,7 @@ mutation of the oracle that the test catches:
 * rank-model features, sparsity constant and storage count computed by hand.
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -205,3 +206,22 @@ def test_sparsity_constant_and_storage_by_hand(orc):
     assert orc.sparsity_constant(blocks[:3], 4, 4) == 3
     sizes = [(orc.DENSE, 2, 3, 0), (orc.LOWRANK, 4, 5, 6), (orc.LOWRANK, 7, 1, 0)]
     assert orc.storage_entries(sizes) == 9 * 2 * 3 + 3 * 6 * (4 + 5)
+
+
+def test_sweep_recipe_matches_table_corr():
+    """The fixed-density sweep uses the paper's (N, omega) pairs (Section 8, Table
+    table_corr), and its reading of n_lambda_s holds: the unit sphere's diameter 2
+    spans D omega / (2 pi) S-wavelengths (kappa_s = omega with mu = rho = 1)."""
+    import json
+    import math
+    from paper_1706_09384_amd import workloads as W
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_table_corr.json")))
+    assert [n for n, _ in W.TABLE_CORR] == g["N"]
+    assert [w for _, w in W.TABLE_CORR] == [float(x) for x in g["omega"]]
+    for (n, w), nl in zip(W.TABLE_CORR, g["n_lambda_s"]):
+        assert n % 3 == 0
+        assert abs(2.0 * w / (2.0 * math.pi) - nl) <= 0.06 * nl
+    # about ten mesh points per S-wavelength at every row: h = sqrt(4 pi / N_c)
+    for n_c, w in W.fixed_density_series():
+        ppw = (2.0 * math.pi / w) / math.sqrt(4.0 * math.pi / n_c)
+        assert 10.0 <= ppw <= 11.5
