@@ -85,11 +85,22 @@ typedef struct {
     int32_t aca_scratch_mb;/* cap on the first-pass ACA factor scratch of one chunk of
                               admissible blocks, MiB; 0 = 40% of the device memory
                               free when the chunk starts (see hm_build) */
-    int32_t reserved[5];
+    int32_t rsvd;          /* 1: T-kernel admissible blocks whose 3x3 sub-blocks are all
+                              singular by construction (both clusters in one coordinate
+                              plane x_a = c, every column normal +-e_a: the planar
+                              pattern of Section 2.3) are compressed by the randomized
+                              range finder (the remark closing Section 2.3) instead of
+                              the vector ACA with its singular-pivot fallback; the
+                              range keeps |A - Q Q^* A|_F <= (eps/2)|A|_F and the
+                              recompression truncates to eps (default 1: with the
+                              fallback, single coplanar blocks of a cube missed eps by
+                              up to 1,200 times); 0: vector ACA for every block */
+    int32_t reserved[4];
 } hm_params;
 
 /* Fill p with the defaults: U kernel, complex128, w = 1, lambda = 2, mu = rho = 1,
- * eta = 3, eps = 1e-4, leaf = 32, same = 1, everything else 0 / NULL. */
+ * eta = 3, eps = 1e-4, leaf = 32, same = 1, recompress = 1, rsvd = 1, everything
+ * else 0 / NULL. */
 hm_status hm_params_default(hm_params *p);
 
 typedef struct hm_matrix hm_matrix;   /* opaque; owns all device memory it allocates */
@@ -223,6 +234,9 @@ typedef struct {
                                           columns in complex64, 639 in complex128) before its
                                           stopping test held: they keep the capped factors, which
                                           may miss eps; 0 on every workload of the test suite */
+    int32_t n_rsvd;                    /* admissible blocks compressed by the randomized range
+                                          finder (params.rsvd); their rank_aca is the number of
+                                          samples */
 } hm_stats;
 
 hm_status hm_info(const hm_matrix *A, hm_stats *s);

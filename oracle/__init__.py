@@ -19,6 +19,10 @@ Contents, each following the paper (arXiv 1706.09384):
   stagnation stopping test eq. stop_part.
 * ``recompress`` -- QR of both factors then a truncated SVD of R_U R_V^*
   (Section 3.2, recompression paragraph).
+* ``randomized_svd`` / ``aca_plus`` -- the two alternatives Section 2.3 names for
+  blocks whose 3x3 sub-blocks are all singular, with the counter-based
+  SplitMix64 generator (``splitmix64``, ``gaussian_test_matrix``) for the
+  randomized test matrix.
 * ``hmatvec`` -- the leaf-level H-matrix-vector product of Section 3.1.
 * ``gmres`` -- a textbook restarted GMRES on an explicit operator.
 * ``mlp_*`` -- FP64 reference of the 6-64-64-1 rank-predictor network.
@@ -439,6 +443,209 @@ def vector_aca(A: np.ndarray, eps: float, tau_piv: float = 1e-8, max_rank=None) 
     if steps == cap:
         converged = True
     return ACAResult(U, V, U.shape[1], steps, rows, cols, fallbacks, norm2, converged)
+
+
+# --------------------------------------------------------------------------
+# Robust alternatives for blocks whose 3x3 sub-blocks are all singular
+# (remark closing Section 2.3): randomized SVD and ACA+ (Section 2.3)
+# --------------------------------------------------------------------------
+
+_M64 = (1 << 64) - 1
+
+
+def splitmix64(counters, seed: int = 0) -> np.ndarray:
+    """Counter-based SplitMix64 (Steele, Lea and Flood, OOPSLA 2014): output i is the
+    SplitMix64 mixing function applied to seed + (i + 1) * 0x9E3779B97F4A7C15, i.e. the
+    (i + 1)-th output of the sequential generator started from state `seed`.  uint64."""
+    c = np.asarray(counters, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = np.uint64(seed & _M64) + (c + np.uint64(1)) * np.uint64(0x9E3779B97F4A7C15)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        z = z ^ (z >> np.uint64(31))
+    return z
+
+
+def gaussian_test_matrix(rows: int, cols: int, seed: int = 0) -> np.ndarray:
+    """Complex standard normal test matrix Omega (rows x cols) for the randomized range
+    finder: entry (r, c) takes the uniforms u1, u2 = 53-bit fractions of SplitMix64
+    outputs 2 (r cols + c) and 2 (r cols + c) + 1, and by the Box-Muller transform
+    g = sqrt(-2 ln(1 - u1)) (cos 2 pi u2 + i sin 2 pi u2) / sqrt(2)."""
+    idx = np.arange(rows * cols, dtype=np.uint64)
+    x1 = splitmix64(2 * idx, seed)
+    x2 = splitmix64(2 * idx + np.uint64(1), seed)
+    u1 = (x1 >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+    u2 = (x2 >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+    g = np.sqrt(-2.0 * np.log1p(-u1)) / math.sqrt(2.0)
+    return (g * np.exp(2j * math.pi * u2)).reshape(rows, cols)
+
+
+@dataclass
+class RSVDResult:
+    U: np.ndarray
+    V: np.ndarray
+    rank: int
+    samples: int          # columns of the last test matrix
+    range_err2: float     # |A - Q Q^* A|_F^2 of the accepted range
+
+
+def randomized_svd(A: np.ndarray, eps: float, k0: int = 24, seed: int = 0) -> RSVDResult:
+    """Randomized low-rank approximation (Liberty, Woolfe, Martinsson, Rokhlin and
+    Tygert 2007): the range finder Y = A Omega, Q = orth(Y), B = Q^* A, then the
+    truncated SVD of B.  Omega is the SplitMix64 Gaussian test matrix above.
+
+    Readings (the paper only names the method):
+    * the number of samples starts at k0 and doubles until the range error
+      |A - Q Q^* A|_F^2 = |A|_F^2 - |B|_F^2 (exact for orthonormal Q) is at most
+      (eps / 2)^2 |A|_F^2, or the samples reach the block's smaller dimension;
+    * the truncation then keeps the Frobenius tail of B's singular values under
+      what is left of the budget, eps^2 |A|_F^2 - range error, so that
+      |A - U V^*|_F <= eps |A|_F (the two errors are orthogonal);
+    * factors split S^(1/2) on both sides, B = Q^* A written as U = Q P_r S_r^(1/2),
+      V = L_r S_r^(1/2) with B = P S L^*."""
+    A = np.asarray(A, dtype=np.complex128)
+    m3, n3 = A.shape
+    nA2 = float(np.sum(np.abs(A) ** 2))
+    if nA2 == 0.0:
+        z = np.zeros((m3, 0), np.complex128)
+        return RSVDResult(z, np.zeros((n3, 0), np.complex128), 0, 0, 0.0)
+    kmax = min(m3, n3)
+    k = min(k0, kmax)
+    while True:
+        Om = gaussian_test_matrix(n3, k, seed)
+        Q, _ = np.linalg.qr(A @ Om)
+        B = Q.conj().T @ A
+        err2 = max(nA2 - float(np.sum(np.abs(B) ** 2)), 0.0)
+        if err2 <= 0.25 * eps * eps * nA2 or k >= kmax:
+            break
+        k = min(2 * k, kmax)
+    P, S, Lh = np.linalg.svd(B, full_matrices=False)
+    budget = max(eps * eps * nA2 - err2, 0.0)
+    tail = np.concatenate([np.cumsum((S[::-1]) ** 2)[::-1], [0.0]])
+    r = next(i for i in range(S.size + 1) if tail[i] <= budget)
+    sq = np.sqrt(S[:r])
+    return RSVDResult((Q @ P[:, :r]) * sq, Lh.conj().T[:, :r] * sq, r, k, err2)
+
+
+def aca_plus(A: np.ndarray, eps: float, max_rank=None) -> ACAResult:
+    """Scalar partially pivoted ACA+ (Boerm and Grasedyck; the variant Section 2.3
+    mentions): besides the current residual it keeps a reference row and a reference
+    column of the residual and starts each step from the larger of their largest
+    entries, so that decoupled groups of unknowns are found as well.
+
+    Readings (the algorithm is only cited by the paper):
+    * the reference row starts at row 0 and the reference column at column 0; a
+      reference that a step uses as its pivot, or whose residual has become
+      negligible (largest entry on the unused indices <= eps times the RMS entry of
+      the current approximation), moves to the next unused index in order whose
+      residual is not negligible;
+    * with r_ref and c_ref the residual reference row and column, a step takes
+      j* = argmax |r_ref| and i* = argmax |c_ref| over unused indices; if
+      |r_ref(j*)| >= |c_ref(i*)| it computes the residual column j*, takes the row
+      pivot i = argmax over unused rows of that column and the residual row i;
+      otherwise the mirror image;
+    * rank-1 update u = residual column / pivot, v = conj(residual row); the
+      approximation stops when the newest term meets eq. stop_part,
+      |u||v| <= eps |S_k|_F (norm recurrence), and neither reference can move to a
+      row or column with a residual that is not negligible.
+    Returns an ACAResult (steps = rank; no vector pivots, fallbacks = 0)."""
+    A = np.asarray(A, dtype=np.complex128)
+    mm, nn = A.shape
+    cap = min(mm, nn) if max_rank is None else min(mm, nn, max_rank)
+    U = np.zeros((mm, 0), np.complex128)
+    V = np.zeros((nn, 0), np.complex128)
+    used_i = np.zeros(mm, bool)
+    used_j = np.zeros(nn, bool)
+    norm2 = 0.0
+    rows, cols = [], []
+    converged = False
+
+    def res_row(i):
+        return A[i, :] - U[i, :] @ V.conj().T
+
+    def res_col(j):
+        return A[:, j] - U @ V[j, :].conj()
+
+    def tiny():
+        return eps * math.sqrt(max(norm2, 0.0) / (mm * nn))
+
+    def live_row(i, r):
+        return i >= 0 and not used_i[i] and np.abs(np.where(used_j, 0.0, r)).max(initial=0.0) > tiny()
+
+    def live_col(j, c):
+        return j >= 0 and not used_j[j] and np.abs(np.where(used_i, 0.0, c)).max(initial=0.0) > tiny()
+
+    def advance_row(i, r):
+        if live_row(i, r):
+            return i, r
+        for k in range(mm):
+            q = (max(i, 0) + 1 + k) % mm
+            if used_i[q]:
+                continue
+            rq = res_row(q)
+            if live_row(q, rq):
+                return q, rq
+        return -1, None
+
+    def advance_col(j, c):
+        if live_col(j, c):
+            return j, c
+        for k in range(nn):
+            q = (max(j, 0) + 1 + k) % nn
+            if used_j[q]:
+                continue
+            cq = res_col(q)
+            if live_col(q, cq):
+                return q, cq
+        return -1, None
+
+    i_ref, j_ref = 0, 0
+    r_ref, c_ref = res_row(0), res_col(0)
+    while U.shape[1] < cap:
+        i_ref, r_ref = advance_row(i_ref, r_ref)
+        j_ref, c_ref = advance_col(j_ref, c_ref)
+        if i_ref < 0 and j_ref < 0:
+            converged = True
+            break
+        rr = np.where(used_j, 0.0, np.abs(r_ref)) if i_ref >= 0 else np.zeros(nn)
+        cc = np.where(used_i, 0.0, np.abs(c_ref)) if j_ref >= 0 else np.zeros(mm)
+        js, is_ = int(np.argmax(rr)), int(np.argmax(cc))
+        if rr[js] >= cc[is_]:
+            col = res_col(js)
+            i = int(np.argmax(np.where(used_i, -1.0, np.abs(col))))
+            row = res_row(i)
+            j = js
+        else:
+            row = res_row(is_)
+            j = int(np.argmax(np.where(used_j, -1.0, np.abs(row))))
+            col = res_col(j)
+            i = is_
+        piv = row[j]
+        used_i[i] = True
+        used_j[j] = True
+        rows.append(i); cols.append(j)
+        if piv == 0.0:
+            continue
+        un = (col / piv)[:, None]
+        vn = row.conj()[:, None]
+        nu2 = float(np.sum(np.abs(un) ** 2) * np.sum(np.abs(vn) ** 2))
+        cross = 0.0
+        if U.shape[1]:
+            cross = 2.0 * float(np.real(np.sum((U.conj().T @ un) * (vn.conj().T @ V).T)))
+        norm2 += cross + nu2
+        U = np.concatenate([U, un], axis=1)
+        V = np.concatenate([V, vn], axis=1)
+        if i_ref >= 0:
+            r_ref = r_ref - un[i_ref, 0] * vn[:, 0].conj()
+        if j_ref >= 0:
+            c_ref = c_ref - un[:, 0] * np.conj(vn[j_ref, 0])
+        if math.sqrt(nu2) <= eps * math.sqrt(max(norm2, 0.0)):
+            i_ref, r_ref = advance_row(i_ref, r_ref if i_ref >= 0 else np.zeros(nn))
+            j_ref, c_ref = advance_col(j_ref, c_ref if j_ref >= 0 else np.zeros(mm))
+            if i_ref < 0 and j_ref < 0:
+                converged = True
+                break
+    return ACAResult(U, V, U.shape[1], U.shape[1], rows, cols, 0, norm2, converged)
 
 
 def truncation_rank(S: np.ndarray, eps: float) -> int:

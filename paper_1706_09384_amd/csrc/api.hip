@@ -262,6 +262,7 @@ extern "C" hm_status hm_params_default(hm_params *p) {
     p->leaf = 32;
     p->same = 1;
     p->recompress = 1;
+    p->rsvd = 1;
     return HM_OK;
 }
 
@@ -533,6 +534,36 @@ void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vect
     std::vector<int64_t> order(nlr);
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), lpt);
+    // Blocks for the randomized range finder (params.rsvd): T kernel, both
+    // clusters in one coordinate plane x_a = c (flat boxes at the same c) and
+    // every column normal +-e_a, so that every 3x3 sub-block has the planar
+    // pattern of Section 2.3 and is singular.
+    std::vector<int64_t> rs_order;
+    if (p.rsvd && p.kernel == HM_KERNEL_T && nlr > 0) {
+        std::vector<uint8_t> nmask(ty.nodes(), 0);
+        for (int32_t v = 0; v < ty.nodes(); ++v) {
+            uint8_t mk = 7;
+            for (int32_t q = ty.begin[v]; q < ty.end[v] && mk; ++q) {
+                const double *nv = &Nrm[3 * (int64_t)ty.perm[q]];
+                for (int a = 0; a < 3; ++a)
+                    if (std::fabs(nv[a]) != 1.0 || nv[(a + 1) % 3] != 0.0 || nv[(a + 2) % 3] != 0.0)
+                        mk &= (uint8_t)~(1u << a);
+            }
+            nmask[v] = mk;
+        }
+        std::vector<int64_t> rest;
+        for (int64_t k : order) {
+            const Block &B = M->blocks[lr_ids[k]];
+            bool planar = false;
+            for (int a = 0; a < 3 && !planar; ++a) {
+                const double c = tx.lo[3 * B.row + a];
+                planar = ((nmask[B.col] >> a) & 1) && tx.hi[3 * B.row + a] == c &&
+                         ty.lo[3 * B.col + a] == c && ty.hi[3 * B.col + a] == c;
+            }
+            (planar ? rs_order : rest).push_back(k);
+        }
+        order.swap(rest);
+    }
     // The admissible blocks are processed in chunks whose first-pass factor
     // scratch stays about under a cap: a chunk's ACA, recompression and final
     // factors are done, and its scratch released, before the next chunk
@@ -587,15 +618,35 @@ void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vect
     std::vector<int64_t> deferred;
     std::vector<int64_t> remaining = order;
     bool chunked = false, last = false;
+    int32_t n_rsvd = 0;
     for (;;) {
-        if (remaining.empty()) {
+        // randomized range finder batches first: dense blocks plus FP64 samples
+        // under half the chunk cap
+        std::vector<int64_t> rs_members;
+        if (!rs_order.empty()) {
+            const int64_t cap = std::max<int64_t>(int64_t(1) << 30, chunk_cap() / 2);
+            int64_t used = 0;
+            size_t q = 0;
+            for (; q < rs_order.size(); ++q) {
+                const int64_t k = rs_order[q];
+                const int64_t need = 9 * (int64_t)lm[k] * ln[k] * (int64_t)sizeof(cplx<R>) +
+                                     3 * (int64_t)(lm[k] + ln[k]) * 2 * kRsMaxK * 16;
+                if (q > 0 && used + need > cap) break;
+                used += need;
+                rs_members.push_back(k);
+            }
+            rs_order.erase(rs_order.begin(), rs_order.begin() + (std::ptrdiff_t)q);
+        } else if (remaining.empty()) {
             if (last || deferred.empty()) break;
             last = true;
             remaining.swap(deferred);
             std::stable_sort(remaining.begin(), remaining.end(), lpt);
         }
         std::vector<int64_t> members;
-        {
+        const bool rs_chunk = !rs_members.empty();
+        if (rs_chunk) {
+            members.swap(rs_members);
+        } else {
             int64_t need = 0;
             for (int64_t k : remaining) need += first_need(k);
             const int64_t stride =
@@ -872,7 +923,31 @@ void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vect
             pass_scratch[ps].reset();
         };
         hipStream_t aca_side = p.unbatched ? st : side_stream(1);
-        {
+        if (rs_chunk) {
+            // randomized range finder, then the usual recompression to eps
+            std::vector<RsIn> in(members.size());
+            for (size_t q = 0; q < members.size(); ++q) {
+                const Block &B = M->blocks[lr_ids[members[q]]];
+                in[q].rb = tx.begin[B.row];
+                in[q].m = lm[members[q]];
+                in[q].cb = ty.begin[B.col];
+                in[q].n = ln[members[q]];
+            }
+            std::unique_ptr<DeviceBuf> fac;
+            run_rsvd<R>(g, gp, in, p.eps, 24, 0, fac, st);
+            pass_scratch.push_back(std::move(fac));
+            pass_members.push_back(members);
+            for (size_t q = 0; q < members.size(); ++q) {
+                const int64_t k = members[q];
+                aca_rank[k] = in[q].k;
+                aca_u[k] = in[q].uoff;
+                aca_v[k] = in[q].voff;
+            }
+            n_rsvd += (int32_t)members.size();
+            t_aca += now_s() - tc;
+            tc = now_s();
+            compress_emit(0);
+        } else {
             // Pass 0.  The blocks with many points run the split ACA, whose
             // steps the host drives; they go to a worker thread and their own
             // stream, so that the other blocks (one ACA launch) are finished
@@ -949,6 +1024,7 @@ void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vect
     S.aca_chunks = n_chunks_done;
     S.n_overflow = overflow;
     S.n_capped = capped;
+    S.n_rsvd = n_rsvd;
     if (capped)
         std::fprintf(stderr, "hmat: %d admissible blocks reached the ACA rank cap %d\n", capped,
                      budget_cap);

@@ -106,6 +106,27 @@ struct AcaOut {
     int32_t pend;         // columns of the last term whose stopping test is open (status 1)
 };
 
+// Randomized range finder (rsvd.hip) for admissible blocks whose 3x3
+// sub-blocks are all singular.  RsIn: one block on the host (input rb, m, cb,
+// n; output k, factor offsets and the FP64 norms); RsBlk: its device
+// descriptor for one attempt; RsTask: 64 rows of a product.
+constexpr int32_t kRsMaxK = 256;   // largest number of samples per block
+struct RsIn {
+    int32_t rb, m, cb, n;
+    int64_t aoff = 0;          // dense block in the batch's dense scratch
+    int32_t k = 0, buf = -1;   // accepted samples; attempt buffer holding them
+    int64_t uoff = 0, voff = 0;   // factors in the returned scratch (ACA layout)
+    double norm2 = 0, range_err2 = 0;   // |A|_F^2 and |A - Q Q^* A|_F^2
+};
+struct RsBlk {
+    int64_t aoff, omoff, yoff, boff, uoff, voff;
+    int32_t m, n, k, pad;
+};
+struct RsTask {
+    int32_t blk, row0, pad0, pad1;
+};
+
+
 // Recompression work description.
 struct RcBlk {
     int64_t uoff, voff;   // ACA factors (scratch slab)
@@ -255,6 +276,12 @@ void run_aca(const Geometry &g, const GreenParams<R> &gp, const std::vector<AcaB
              AcaBlk *d_blk, cplx<R> *scratchU, uint8_t *flags, AcaOut *d_out, double eps,
              double tau_piv, int32_t max_budget, hipStream_t st, bool unbatched,
              hipStream_t aux);
+
+// Randomized range finder for the blocks blk (see rsvd.hip); factors receives
+// the ACA-layout factor scratch (U = Q: 3m x k, V = B^*: 3n x k).
+template <typename R>
+void run_rsvd(const Geometry &g, const GreenParams<R> &gp, std::vector<RsIn> &blk, double eps,
+              int k0, uint64_t seed, std::unique_ptr<DeviceBuf> &factors, hipStream_t st);
 
 // Recompression of ACA factors in place into compact output.
 template <typename R>

@@ -48,7 +48,8 @@ class Params(ctypes.Structure):
         ("rank_model", ctypes.c_void_p),
         ("matvec_graph", ctypes.c_int32), ("unbatched", ctypes.c_int32),
         ("aca_scratch_mb", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 5),
+        ("rsvd", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 4),
     ]
 
 
@@ -73,7 +74,7 @@ class Stats(ctypes.Structure):
         ("matvec_bytes", ctypes.c_int64),
         ("aca_scratch_bytes", ctypes.c_int64), ("aca_chunks", ctypes.c_int32),
         ("acc_waves", ctypes.c_int32), ("proj_rows", ctypes.c_int32),
-        ("n_capped", ctypes.c_int32),
+        ("n_capped", ctypes.c_int32), ("n_rsvd", ctypes.c_int32),
     ]
 
     def as_dict(self):
@@ -160,7 +161,7 @@ def _ptr(t):
 def make_params(kernel=KERNEL_U, prec=C128, omega=1.0, lam=2.0, mu=1.0, rho=1.0, eta=3.0,
                 eps=1e-4, leaf=32, same=True, self_re=0.0, self_im=0.0, points_on_host=False,
                 plan_only=False, rank_budget=0, recompress=True, tau_piv=0.0, rank_model=None,
-                matvec_graph=False, unbatched=False, aca_scratch_mb=0):
+                matvec_graph=False, unbatched=False, aca_scratch_mb=0, rsvd=True):
     p = Params()
     _check(LIB.hm_params_default(ctypes.byref(p)))
     p.kernel, p.prec = int(kernel), int(prec)
@@ -171,6 +172,7 @@ def make_params(kernel=KERNEL_U, prec=C128, omega=1.0, lam=2.0, mu=1.0, rho=1.0,
     p.rank_budget, p.recompress, p.tau_piv = int(rank_budget), int(bool(recompress)), float(tau_piv)
     p.matvec_graph, p.unbatched = int(bool(matvec_graph)), int(bool(unbatched))
     p.aca_scratch_mb = int(aca_scratch_mb)
+    p.rsvd = int(bool(rsvd))
     p._model_keepalive = None
     if rank_model is not None:
         w = np.ascontiguousarray(rank_model, dtype=np.float32)
