@@ -183,3 +183,29 @@ def test_sphere200k_T_64rhs_sampled_rows(hm, orc):
     e = colrel(Y[idx], ref)
     say("sampled e max", e.max())
     assert e.max() <= 5 * w.eps
+
+
+def test_lockstep_gmres_T_sphere_64rhs(hm, orc):
+    """The 200k T sphere's recipe (T kernel, n = x, leaf 64, eps 1e-4, 64 right-hand
+    sides, FP64 refinement to 1e-8) scaled to the largest size whose unpreconditioned
+    GMRES converges in a test's time: 20,000 points with kappa_s = 56 sqrt(20000 / 200000)
+    = 17.7.  Every column reaches 1e-8 in FP64 against A_H, and the sampled rows of the
+    oracle's exact operator give a backward error of order eps."""
+    import math
+    import torch
+    n = 20000
+    ks = 56.0 * math.sqrt(n / 200000)
+    w = W.small_sphere(n, kernel=1, omega=ks, leaf=64, eps=1e-4)
+    say(f"case lockstep GMRES T sphere n={n} kappa_s={ks:.2f} 64 RHS")
+    X, N = w.points()
+    H = hm.build_workload(w, X=X, N=N, prec=1)
+    B = W.complex_normal(3 * n, 64, seed=0)
+    x, info = H.gmres(to_dev(B), tol=1e-8, restart=30, maxit=4000)
+    say("gmres", info)
+    assert info["converged"] == 64 and info["relres"] <= 1e-8
+    rows = np.random.default_rng(4).choice(n, 24, replace=False)
+    Ax = orc.matvec_rows(orc.Problem.from_workload(w, X, N), x.cpu().numpy(), rows)
+    idx = (3 * rows[:, None] + np.arange(3)).ravel()
+    be = np.linalg.norm(B[idx] - Ax, axis=0) / np.linalg.norm(B[idx], axis=0)
+    say(f"backward error vs the exact operator on sampled rows: max {be.max():.2e}")
+    assert be.max() <= 10 * w.eps
