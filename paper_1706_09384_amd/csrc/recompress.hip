@@ -37,77 +37,122 @@ struct GramItem {
     int32_t blk, which, ta, tc;   // which 0 = U, 1 = V; ta <= tc tile indices
 };
 
-constexpr int kGT = 32;   // output tile
-
+constexpr int kGT = 64;   // output tile: 64 x 64 per workgroup, 32 x 32 per wave
+constexpr int kGS = 16;   // rows of X staged in LDS per contraction slab
 
 // G_X = X^* X on the FP64 matrix cores (v_mfma_f64_16x16x4f64: lane l holds
 // A[l % 16][l / 16] and B[l / 16][l % 16], and accumulator element e is
-// C[4e + l / 16][l % 16]).  One workgroup per 32 x 32 output tile, one wave
-// per 16 x 16 quarter; the 4-deep contraction steps take the rows of a
-// 16-row slab as q0 + 4 (l / 16) + s, s = 0..3, so that every lane reads
-// four consecutive rows of its column.  Re G = Xr^T Xr + Xi^T Xi and
-// Im G = Xr^T Xi - Xi^T Xr, from three real products (products of the FP32
-// entries and their sums exact or nearly so in FP64).
+// C[4e + l / 16][l % 16]).  One workgroup per 64 x 64 output tile (upper
+// triangle of tiles); the four waves take its 32 x 32 quadrants, and a wave
+// skips the 16 x 16 sub-tiles that lie outside the matrix or wholly below the
+// diagonal.  The contraction runs over slabs of 16 rows of the two 64-column
+// panels, staged in LDS and converted to FP64 once, so that every factor entry
+// is read from memory once per tile instead of once per wave; the next slab
+// is loaded into registers while the current one is multiplied.
+// Re G = Xr^T Xr + Xi^T Xi and Im G = Xr^T Xi - Xi^T Xr, from three real
+// products.
 template <typename R>
 __global__ void __launch_bounds__(256) gram_mfma_kernel(const RcBlk *__restrict__ blks,
                                                         const GramItem *__restrict__ items,
                                                         const cplx<R> *__restrict__ fac,
                                                         cplx<double> *__restrict__ work) {
+    __shared__ cplx<double> sa[kGS][kGT + 1], sc[kGS][kGT + 1];
     const GramItem it = items[blockIdx.x];
     const RcBlk b = blks[it.blk];
     const int r = b.r;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int ia = wave & 1, ic = wave >> 1;
-    const int abase = it.ta * kGT + 16 * ia, cbase = it.tc * kGT + 16 * ic;
-    // quarters entirely outside the matrix or below the diagonal add nothing
-    if (abase >= r || cbase >= r || abase > cbase + 15) return;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int wa = wave & 1, wc = wave >> 1, g = lane >> 4, l16 = lane & 15;
     const int64_t rows = 3 * (int64_t)(it.which == 0 ? b.m : b.n);
     const cplx<R> *X = fac + (it.which == 0 ? b.uoff : b.voff);
     cplx<double> *G = work + b.goff + rc_slot(r, it.which);
-    const int ca = abase + (lane & 15), cc = cbase + (lane & 15), g = lane >> 4;
-    const bool va = ca < r, vc = cc < r;
-    const cplx<R> *xa = X + (int64_t)(va ? ca : 0) * rows;
-    const cplx<R> *xc = X + (int64_t)(vc ? cc : 0) * rows;
+    const int a0 = it.ta * kGT, c0 = it.tc * kGT;
+    const bool diag = it.ta == it.tc;
+    bool act[2][2];
+    bool any = false;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int ab = a0 + 32 * wa + 16 * i, cb = c0 + 32 * wc + 16 * j;
+            act[i][j] = ab < r && cb < r && ab <= cb + 15;
+            any = any || act[i][j];
+        }
     // conj(a) b as three real products (Gauss): P1 = Re a Re b,
     // P2 = -Im a Im b, P3 = (Re a - Im a)(Re b + Im b); Re G = P1 - P2,
     // Im G = P3 - P1 - P2
-    mf64x4 p1 = {0, 0, 0, 0}, p2 = {0, 0, 0, 0}, p3 = {0, 0, 0, 0};
-    // the next slab's operands are loaded while the current slab's products run
-    cplx<R> na[4], nb[4];
+    mf64x4 p1[2][2], p2[2][2], p3[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) p1[i][j] = p2[i][j] = p3[i][j] = mf64x4{0, 0, 0, 0};
+    cplx<double>(*scp)[kGT + 1] = diag ? sa : sc;
+    // staging: entry tid + 256 s of a slab is (row (tid + 256 s) % 16, column
+    // (tid + 256 s) / 16), so that 16 lanes read 16 consecutive rows of a column
+    constexpr int kPer = kGS * kGT / 256;
+    cplx<R> na[kPer], nc[kPer];
     auto fetch = [&](int64_t q0) {
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            const int64_t q = q0 + 4 * g + s;
-            na[s] = (va && q < rows) ? xa[q] : cplx<R>{R(0), R(0)};
-            nb[s] = (vc && q < rows) ? xc[q] : cplx<R>{R(0), R(0)};
+        for (int s = 0; s < kPer; ++s) {
+            const int e = tid + 256 * s, col = e / kGS;
+            const int64_t q = q0 + e % kGS;
+            na[s] = (a0 + col < r && q < rows) ? X[(int64_t)(a0 + col) * rows + q]
+                                               : cplx<R>{R(0), R(0)};
+            if (!diag)
+                nc[s] = (c0 + col < r && q < rows) ? X[(int64_t)(c0 + col) * rows + q]
+                                                   : cplx<R>{R(0), R(0)};
         }
     };
     fetch(0);
-    for (int64_t q0 = 0; q0 < rows; q0 += 16) {
-        cplx<double> A[4], B[4];
+    for (int64_t q0 = 0; q0 < rows; q0 += kGS) {
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            A[s] = cvt<double>(na[s]);
-            B[s] = cvt<double>(nb[s]);
+        for (int s = 0; s < kPer; ++s) {
+            const int e = tid + 256 * s, col = e / kGS, row = e % kGS;
+            sa[row][col] = cvt<double>(na[s]);
+            if (!diag) sc[row][col] = cvt<double>(nc[s]);
         }
-        if (q0 + 16 < rows) fetch(q0 + 16);
+        if (q0 + kGS < rows) fetch(q0 + kGS);
+        __syncthreads();
+        if (any) {
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            p1 = __builtin_amdgcn_mfma_f64_16x16x4f64(A[s].re, B[s].re, p1, 0, 0, 0);
-            p2 = __builtin_amdgcn_mfma_f64_16x16x4f64(-A[s].im, B[s].im, p2, 0, 0, 0);
-            p3 = __builtin_amdgcn_mfma_f64_16x16x4f64(A[s].re - A[s].im, B[s].re + B[s].im, p3, 0,
-                                                     0, 0);
+            for (int s4 = 0; s4 < kGS; s4 += 4) {
+                cplx<double> A[2], B[2];
+#pragma unroll
+                for (int t = 0; t < 2; ++t) {
+                    A[t] = sa[s4 + g][32 * wa + 16 * t + l16];
+                    B[t] = scp[s4 + g][32 * wc + 16 * t + l16];
+                }
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j)
+                        if (act[i][j]) {
+                            p1[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(A[i].re, B[j].re,
+                                                                            p1[i][j], 0, 0, 0);
+                            p2[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-A[i].im, B[j].im,
+                                                                            p2[i][j], 0, 0, 0);
+                            p3[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                                A[i].re - A[i].im, B[j].re + B[j].im, p3[i][j], 0, 0, 0);
+                        }
+            }
         }
+        __syncthreads();
     }
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        const int a = abase + 4 * e + g, c = cc;
-        if (a < r && c < r && a <= c) {
-            const double gr = p1[e] - p2[e], gi = a == c ? 0.0 : p3[e] - p1[e] - p2[e];
-            G[a + (int64_t)c * r] = {gr, gi};
-            G[c + (int64_t)a * r] = {gr, -gi};
-        }
-    }
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+            if (act[i][j])
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int a = a0 + 32 * wa + 16 * i + 4 * e + g;
+                    const int c = c0 + 32 * wc + 16 * j + l16;
+                    if (a < r && c < r && a <= c) {
+                        const double gr = p1[i][j][e] - p2[i][j][e];
+                        const double gi = a == c ? 0.0 : p3[i][j][e] - p1[i][j][e] - p2[i][j][e];
+                        G[a + (int64_t)c * r] = {gr, gi};
+                        G[c + (int64_t)a * r] = {gr, -gi};
+                    }
+                }
 }
 
 __device__ inline double wave_sumd(double v) {
@@ -621,14 +666,101 @@ inline int rr_slot_host(int pos, int round, int n) {
 }
 
 // U' = U W_U (3m x keep), V' = V W_V (3n x keep) into the compact slab, one
-// workgroup per (block, factor, 128-row chunk): a tiled product with the
-// factor rows converted to FP64 and the result rounded to the storage type.
+// workgroup per (block, factor, 64 rows, 64 output columns).  Wave w owns rows
+// 16w .. 16w + 15 of the chunk and every 16-column output tile that holds
+// kept columns; its A operand comes straight from the factor (each entry read
+// once, the next 16-deep slab loaded into registers while the current one is
+// multiplied), and the 16 x 64 slab of W is staged in LDS for the four waves.
+// The result is rounded to the storage type.
 struct ApplyTask {
-    int32_t blk, which, row0, pad;
+    int32_t blk, which, row0, col0;
 };
 
+// The product for NT output tiles of 16 columns (NT = 1 .. 4), so that no
+// multiply-accumulate sits under a per-tile condition.
+template <typename R, int NT>
+__device__ void apply_tiles(const RcBlk &b, const ApplyTask &tk, int keep, const cplx<R> *X,
+                            const cplx<double> *T, cplx<R> *Y, const int32_t *rowpad,
+                            cplx<double> (*sw)[65]) {
+    constexpr int kS = 16;
+    const int r = b.r;
+    const int which = tk.which;
+    const int64_t rows = 3 * (int64_t)(which == 0 ? b.m : b.n);
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int g = lane >> 4, l16 = lane & 15;
+    const int col0 = tk.col0;
+    const int64_t myrow = (int64_t)tk.row0 + 16 * wave + l16;
+    const bool live = (int64_t)tk.row0 + 16 * wave < rows;
+    const bool rv = myrow < rows;
+    // (Re, Im) of a b as three real products: P1 = Re a Re b, P2 = Im a Im b,
+    // P3 = (Re a + Im a)(Re b + Im b); Re = P1 - P2, Im = P3 - P1 - P2
+    mf64x4 p1[NT], p2[NT], p3[NT];
+#pragma unroll
+    for (int j = 0; j < NT; ++j) p1[j] = p2[j] = p3[j] = mf64x4{0, 0, 0, 0};
+    // next slab: this lane's A entries (row myrow, k = k0 + 4s + g) and its
+    // share of the W slab (entry tid + 256 s: k (tid + 256 s) % 16, column
+    // (tid + 256 s) / 16)
+    cplx<R> nx[4];
+    cplx<double> nw[4];
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int k = k0 + 4 * s + g;
+            nx[s] = (rv && k < r) ? X[(int64_t)k * rows + myrow] : cplx<R>{R(0), R(0)};
+            const int e = tid + 256 * s, col = e / kS, kk = k0 + e % kS;
+            nw[s] = (kk < r && col0 + col < keep) ? T[kk + (int64_t)(col0 + col) * r]
+                                                  : cplx<double>{0, 0};
+        }
+    };
+    fetch(0);
+    for (int k0 = 0; k0 < r; k0 += kS) {
+        cplx<double> A[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            A[s] = cvt<double>(nx[s]);
+            const int e = tid + 256 * s;
+            sw[e % kS][e / kS] = nw[s];
+        }
+        if (k0 + kS < r) fetch(k0 + kS);
+        __syncthreads();
+        if (live) {
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                for (int j = 0; j < NT; ++j) {
+                    const cplx<double> B = sw[4 * s + g][16 * j + l16];
+                    p1[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(A[s].re, B.re, p1[j], 0, 0, 0);
+                    p2[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(A[s].im, B.im, p2[j], 0, 0, 0);
+                    p3[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(A[s].re + A[s].im, B.re + B.im,
+                                                                 p3[j], 0, 0, 0);
+                }
+        }
+        __syncthreads();
+    }
+    if (!live) return;
+    // U' column-major with the padded leaf-segment rows; V' row-major with an
+    // even row stride.
+    const int64_t ldu = padded_rows(rowpad, b.rb, b.m);
+    const int64_t ldv = even_up(keep);
+#pragma unroll
+    for (int j = 0; j < NT; ++j)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int64_t row = (int64_t)tk.row0 + 16 * wave + 4 * e + g;
+            const int c = col0 + 16 * j + l16;
+            if (row < rows && c < keep) {
+                const cplx<double> v = {p1[j][e] - p2[j][e], p3[j][e] - p1[j][e] - p2[j][e]};
+                const int64_t o = which == 0 ? (int64_t)c * ldu + padded_row(rowpad, b.rb,
+                                                                             (int32_t)(row / 3),
+                                                                             (int)(row % 3))
+                                             : row * ldv + c;
+                Y[o] = cvt<R>(v);
+            }
+        }
+}
+
 template <typename R>
-__global__ void __launch_bounds__(256) apply_kernel(const RcBlk *__restrict__ blks,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) apply_kernel(const RcBlk *__restrict__ blks,
                                                     const ApplyTask *__restrict__ tasks,
                                                     const cplx<R> *__restrict__ fac,
                                                     const cplx<double> *__restrict__ work,
@@ -637,32 +769,20 @@ __global__ void __launch_bounds__(256) apply_kernel(const RcBlk *__restrict__ bl
                                                     const int64_t *__restrict__ outv,
                                                     cplx<R> *__restrict__ out,
                                                     const int32_t *__restrict__ rowpad) {
+    __shared__ cplx<double> sw[16][65];
     const ApplyTask tk = tasks[blockIdx.x];
     const int bi = tk.blk;
     const RcBlk b = blks[bi];
-    const int r = b.r, keep = newrank[bi];
-    const cplx<double> *W = work + b.goff;
-    const int which = tk.which;
-    const int64_t rows = 3 * (int64_t)(which == 0 ? b.m : b.n);
-    const int nrow = (int)min<int64_t>(128, rows - tk.row0);
-    const cplx<R> *X = fac + (which == 0 ? b.uoff : b.voff);
-    const cplx<double> *T = W + rc_slot(r, which == 0 ? 4 : 5);
-    cplx<R> *Y = out + (which == 0 ? outu[bi] : outv[bi]);
-    // U' column-major with the padded leaf-segment rows; V' row-major with an
-    // even row stride.
-    const int64_t ldu = padded_rows(rowpad, b.rb, b.m);
-    const int64_t ldv = even_up(keep);
-    const int64_t row0 = tk.row0;
-    mfma_gemm(
-        nrow, keep, r, [&](int i, int k) { return cvt<double>(X[(int64_t)k * rows + row0 + i]); },
-        [&](int k, int c) { return T[k + (int64_t)c * r]; },
-        [&](int i, int c, cplx<double> v) {
-            const int64_t row = row0 + i;
-            const int64_t o =
-                which == 0 ? (int64_t)c * ldu + padded_row(rowpad, b.rb, (int32_t)(row / 3), (int)(row % 3))
-                           : row * ldv + c;
-            Y[o] = cvt<R>(v);
-        });
+    const int keep = newrank[bi];
+    const cplx<R> *X = fac + (tk.which == 0 ? b.uoff : b.voff);
+    const cplx<double> *T = work + b.goff + rc_slot(b.r, tk.which == 0 ? 4 : 5);
+    cplx<R> *Y = out + (tk.which == 0 ? outu[bi] : outv[bi]);
+    switch (min(4, (keep - tk.col0 + 15) >> 4)) {
+    case 1: apply_tiles<R, 1>(b, tk, keep, X, T, Y, rowpad, sw); break;
+    case 2: apply_tiles<R, 2>(b, tk, keep, X, T, Y, rowpad, sw); break;
+    case 3: apply_tiles<R, 3>(b, tk, keep, X, T, Y, rowpad, sw); break;
+    default: apply_tiles<R, 4>(b, tk, keep, X, T, Y, rowpad, sw); break;
+    }
 }
 
 // Factorisation of the blocks order[q0, q1) whose r x r core exceeds the LDS:
@@ -885,7 +1005,8 @@ void run_recompress_apply(const std::vector<RcBlk> &blk, RcBlk *d_blk, const cpl
         if (keep[i] != 0)
             for (int w = 0; w < 2; ++w) {
                 const int32_t rows = 3 * (w == 0 ? blk[i].m : blk[i].n);
-                for (int32_t r0 = 0; r0 < rows; r0 += 128) tasks.push_back({i, w, r0, 0});
+                for (int32_t r0 = 0; r0 < rows; r0 += 64)
+                    for (int32_t c0 = 0; c0 < keep[i]; c0 += 64) tasks.push_back({i, w, r0, c0});
             }
         task0[i + 1] = (int64_t)tasks.size();
     }
