@@ -25,6 +25,9 @@ Contents, each following the paper (arXiv 1706.09384):
   randomized test matrix.
 * ``hmatvec`` -- the leaf-level H-matrix-vector product of Section 3.1.
 * ``gmres`` -- a textbook restarted GMRES on an explicit operator.
+* ``hlu`` (module) -- the H-LU factorisation and solve of Section 3.2 over the
+  F / R / H block formats with eps_LU recompression, and the certification
+  estimator of Section 3.3.
 * ``mlp_*`` -- FP64 reference of the 6-64-64-1 rank-predictor network.
 
 Readings of the paper where it is silent or ambiguous are listed in the
@@ -46,6 +49,9 @@ KERNEL_U = 0
 KERNEL_T = 1
 DENSE = 0
 LOWRANK = 1
+
+
+from . import hlu  # noqa: E402  (H-LU of Section 3.2; pure numpy)
 
 
 def _lib():
