@@ -309,6 +309,94 @@ hm_status hm_export_block(const hm_matrix *A, int64_t block, void *host_buf);
 
 void hm_destroy(hm_matrix *A);
 
+/* ---------------------------------------------------------------------
+ * H-LU direct solver (Section 3.2) and its certification (Section 3.3).
+ * ------------------------------------------------------------------- */
+typedef struct hm_lu hm_lu;   /* opaque; owns the factors' device memory */
+
+typedef struct {
+    double t_import;          /* seconds: copy of A_H into the factor blocks */
+    double t_factor;          /* seconds: the recursive factorisation (synchronous) */
+    int64_t storage_entries;  /* complex entries of L_H and U_H: m n per dense block,
+                                 (m + n) k per low-rank block */
+    int64_t device_bytes;     /* device memory held by the factors and their workspaces */
+    int32_t max_rank;         /* largest rank of a low-rank factor block */
+    int32_t n_nodes;          /* blocks of the block cluster tree (leaves and inner) */
+    int32_t n_diag;           /* dense diagonal leaves factorised */
+    int32_t n_recompressed;   /* low-rank blocks recompressed at eps_LU */
+    int32_t n_batches;        /* batches those recompressions ran in */
+    int32_t n_gemm;           /* matrix-core GEMM launches */
+    double gemm_flops;        /* their flops, 8 per complex multiply-add */
+} hm_lu_stats;
+
+/*
+ * Factorise A_H = L_H U_H (Section 3.2): the recursive 2 x 2 block LU over
+ * the block cluster tree, steps (1) A11 = L11 U11, (2) U12 = L11^-1 A12,
+ * (3) L21 = A21 U11^-1, (4) A22 - L21 U12 = L22 U22, every block in the
+ * dense, low-rank or subdivided format, without pivoting.  Sums that reach a
+ * low-rank block are recompressed (QR of both factors, truncated SVD of
+ * R_U R_V^*) at eps_lu, keeping the singular values whose Frobenius tail
+ * exceeds eps_lu times the total.  Dense diagonal leaves are eliminated
+ * without pivoting.  Arithmetic is complex128 whatever A's precision.
+ *   A       an assembled square operator (params.same = 1); read only, and
+ *           not needed by the factors afterwards
+ *   eps_lu  >= 0; values below 1e-13 act as 1e-13 (singular values at the
+ *           rounding level of a block are never kept), so eps_lu = 0 gives
+ *           the LU of A_H up to that floor
+ *   out     receives the factors; free with hm_lu_destroy
+ * Synchronous on stream.  HM_ERR_ARG for bad arguments or same = 0,
+ * HM_ERR_STATE for a plan-only matrix, HM_ERR_NOCONV if a diagonal leaf
+ * meets a zero pivot, HM_ERR_ALLOC when device memory runs out.
+ */
+hm_status hm_lu_factor(const hm_matrix *A, double eps_lu, void *stream, hm_lu **out);
+
+/*
+ * x0 = U_H^-1 L_H^-1 b: block forward then backward substitution over the
+ * block tree (Section 3.2, direct solver).
+ *   b, x  device complex128, row-major (3N, nrhs), original point order;
+ *         b and x may not overlap
+ * Asynchronous on stream.  HM_ERR_ARG for NULL pointers or nrhs < 1.
+ */
+hm_status hm_lu_solve(hm_lu *F, const void *b, void *x, int32_t nrhs, void *stream);
+
+hm_status hm_lu_get_stats(const hm_lu *F, hm_lu_stats *s);
+
+/*
+ * The factors as one dense matrix, L_H strictly below the diagonal (unit
+ * diagonal implied) and U_H on and above it, 3N x 3N column-major complex128
+ * in cluster order (row 3p + a is point perm[p], component a), to a host
+ * buffer.  For checks on small problems: HM_ERR_ARG when 3N > 20000.
+ */
+hm_status hm_lu_export_dense(hm_lu *F, void *host_buf);
+
+void hm_lu_destroy(hm_lu *F);
+
+/*
+ * delta_H,F = |A_H - A|_F and |A|_F (Section 3.3): every stored block is
+ * compared with the kernel re-evaluated in FP64 at its point pairs (dense
+ * tiles entry by entry, low-rank blocks through their factors).
+ * Synchronous on stream.  HM_ERR_STATE for a plan-only matrix.
+ */
+hm_status hm_frob_error(const hm_matrix *A, void *stream, double *diff_fro, double *a_fro);
+
+typedef struct {
+    double delta;      /* |b - A_H x0|_2 (FP64 residual with the H-matvec) */
+    double delta_h;    /* the delta_H passed in */
+    double b_norm, x0_norm;
+    double estimate;   /* I = (delta + delta_H |x0|) / |b|, eq. est_direct */
+} hm_lu_estimate_t;
+
+/*
+ * The estimator of eq. est_direct for one right-hand side:
+ * |b - A x0| / |b| <= (delta + delta_H |x0|) / |b| with delta = |b - A_H x0|.
+ *   b, x0    device complex128 vectors (3N), original point order
+ *   delta_h  |A_H - A| in a norm that bounds the 2-norm (hm_frob_error's
+ *            diff_fro)
+ * Synchronous on stream.
+ */
+hm_status hm_lu_estimate(const hm_matrix *A, const void *b, const void *x0, double delta_h,
+                         void *stream, hm_lu_estimate_t *est);
+
 /*
  * Return the library's cached device memory to the driver.  Buffers of
  * 32 MiB or more that the library releases (build temporaries, destroyed

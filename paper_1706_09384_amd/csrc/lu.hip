@@ -1,0 +1,776 @@
+// H-LU factorisation and solve (Section 3.2) and the quantities of the
+// certification estimator (Section 3.3, eq. est_direct), complex128.
+//
+// The factorisation runs the recursive 2 x 2 block LU over the block
+// cluster tree on the host, as a sequence of device operations on one
+// stream: every block of the factors is dense (F, column-major), low-rank
+// (R, U W with W = V^*, both column-major) or subdivided (H).  The device
+// work is
+//   * dense diagonal leaves: elimination without pivoting plus the inverses
+//     of both triangular factors, in one workgroup (lu_getrf_inv_kernel);
+//   * every product (block substitutions against a diagonal leaf are
+//     products with its inverse factors, low-rank products, dense updates):
+//     a strided complex FP64 matrix-core GEMM (lu_gemm_kernel);
+//   * sums into a low-rank block are kept exactly as extra factor columns
+//     and recompressed at eps_LU, in batches over all the blocks that one
+//     block substitution is about to read, with the assembly's
+//     QR + truncated SVD kernels.
+// Device memory comes from two arenas: one for the factors and the pending
+// low-rank pieces (freed with the object), one stack for temporaries
+// (released in stream order).
+#include <algorithm>
+#include <chrono>
+#include <memory>
+#include <vector>
+
+#include "green.hpp"
+#include "internal.hpp"
+#include "lu_core.hpp"
+#include "mfma_gemm.hpp"
+
+namespace hm {
+
+using Z = cplx<double>;
+using lu::DMat;
+using lu::LuNode;
+using lu::need;
+
+namespace {
+
+__host__ __device__ inline Z zdiv(Z a, Z b) {
+    const double d = b.re * b.re + b.im * b.im;
+    return {(a.re * b.re + a.im * b.im) / d, (a.im * b.re - a.re * b.im) / d};
+}
+
+// ------------------------------------------------------------------ kernels
+
+// C = alpha A B (+ C when beta), element (i, j) of X at X[i rs + j cs]:
+// 64 x 64 output tiles per workgroup, the four waves on its 32 x 32
+// quadrants (2 x 2 tiles of v_mfma_f64_16x16x4f64 each), 16-deep slabs of A
+// and B staged in LDS along whichever index is contiguous in memory.
+struct GemmArgs {
+    const Z *A;
+    int64_t ars, acs;
+    const Z *B;
+    int64_t brs, bcs;
+    Z *C;
+    int64_t crs, ccs;
+    int32_t m, n, k;
+    Z alpha;
+    int32_t beta;
+};
+
+__global__ void __launch_bounds__(256) lu_gemm_kernel(GemmArgs g) {
+    constexpr int kT = 64, kS = 16;
+    __shared__ Z sa[kS][kT + 1], sb[kS][kT + 1];
+    const int i0 = blockIdx.x * kT, j0 = blockIdx.y * kT;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int wa = wave & 1, wb = wave >> 1, gq = lane >> 4, l16 = lane & 15;
+    // three real products per complex one: P1 = Re a Re b, P2 = Im a Im b,
+    // P3 = (Re a + Im a)(Re b + Im b); Re = P1 - P2, Im = P3 - P1 - P2
+    mf64x4 p1[2][2], p2[2][2], p3[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) p1[i][j] = p2[i][j] = p3[i][j] = mf64x4{0, 0, 0, 0};
+    const bool a_rows = g.ars == 1, b_rows = g.brs == 1;
+    for (int k0 = 0; k0 < g.k; k0 += kS) {
+        for (int e = tid; e < kS * kT; e += 256) {
+            int i, kk;
+            if (a_rows) { i = e % kT; kk = e / kT; } else { kk = e % kS; i = e / kS; }
+            sa[kk][i] = (i0 + i < g.m && k0 + kk < g.k)
+                            ? g.A[(int64_t)(i0 + i) * g.ars + (int64_t)(k0 + kk) * g.acs]
+                            : Z{0, 0};
+            int j, k2;
+            if (b_rows) { k2 = e % kS; j = e / kS; } else { j = e % kT; k2 = e / kT; }
+            sb[k2][j] = (k0 + k2 < g.k && j0 + j < g.n)
+                            ? g.B[(int64_t)(k0 + k2) * g.brs + (int64_t)(j0 + j) * g.bcs]
+                            : Z{0, 0};
+        }
+        __syncthreads();
+#pragma unroll
+        for (int s4 = 0; s4 < kS; s4 += 4) {
+            Z A[2], B[2];
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                A[t] = sa[s4 + gq][32 * wa + 16 * t + l16];
+                B[t] = sb[s4 + gq][32 * wb + 16 * t + l16];
+            }
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    p1[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(A[i].re, B[j].re, p1[i][j], 0, 0, 0);
+                    p2[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(A[i].im, B[j].im, p2[i][j], 0, 0, 0);
+                    p3[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(A[i].re + A[i].im,
+                                                                    B[j].re + B[j].im, p3[i][j], 0, 0, 0);
+                }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int row = i0 + 32 * wa + 16 * i + 4 * e + gq;
+                const int col = j0 + 32 * wb + 16 * j + l16;
+                if (row < g.m && col < g.n) {
+                    const Z v = {p1[i][j][e] - p2[i][j][e], p3[i][j][e] - p1[i][j][e] - p2[i][j][e]};
+                    Z *c = g.C + (int64_t)row * g.crs + (int64_t)col * g.ccs;
+                    const Z r = g.alpha * v;
+                    *c = g.beta ? *c + r : r;
+                }
+            }
+}
+
+// dst(i, j) = [dst(i, j) +] alpha op(src(i, j)), op = conj when cj.
+__global__ void lu_copy_kernel(Z *dst, int64_t drs, int64_t dcs, const Z *src, int64_t srs,
+                               int64_t scs, int32_t m, int32_t n, Z alpha, int32_t cj,
+                               int32_t acc) {
+    const int64_t tot = (int64_t)m * n;
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < tot;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = q % m, j = q / m;
+        Z v = src[i * srs + j * scs];
+        if (cj) v = conj(v);
+        v = alpha * v;
+        Z *d = dst + i * drs + j * dcs;
+        *d = acc ? *d + v : v;
+    }
+}
+
+// dst(i, j) = (i == j ? diag : 0).
+__global__ void lu_fill_kernel(Z *dst, int64_t drs, int64_t dcs, int32_t m, int32_t n, Z diag) {
+    const int64_t tot = (int64_t)m * n;
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < tot;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = q % m, j = q / m;
+        dst[i * drs + j * dcs] = i == j ? diag : Z{0, 0};
+    }
+}
+
+// Dense tile of the H-matrix (padded leaf-segment rows, storage type S) to a
+// plain column-major complex128 array of 3m rows.
+template <typename S>
+__global__ void lu_import_dense_kernel(const cplx<S> *__restrict__ src, int64_t ld,
+                                       const int32_t *__restrict__ rowpad, int32_t rb, int32_t m,
+                                       int32_t ncols, Z *__restrict__ dst) {
+    const int64_t rows = 3 * (int64_t)m, tot = rows * ncols;
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < tot;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t row = q % rows, c = q / rows;
+        dst[q] = cvt<double>(src[c * ld + padded_row(rowpad, rb, (int32_t)(row / 3), (int)(row % 3))]);
+    }
+}
+
+// Low-rank block U V^* of the H-matrix (U padded column-major, V row-major)
+// to U (3m x r) and W = V^* (r x 3n), column-major complex128.
+template <typename S>
+__global__ void lu_import_lr_kernel(const cplx<S> *__restrict__ U, int64_t ldu,
+                                    const cplx<S> *__restrict__ V, int64_t ldv,
+                                    const int32_t *__restrict__ rowpad, int32_t rb, int32_t m,
+                                    int32_t n, int32_t r, Z *__restrict__ Uo, Z *__restrict__ Wo) {
+    const int64_t mr = 3 * (int64_t)m, nr = 3 * (int64_t)n;
+    const int64_t tot = (mr + nr) * r;
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < tot;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        if (q < mr * r) {
+            const int64_t row = q % mr, c = q / mr;
+            Uo[q] = cvt<double>(U[c * ldu + padded_row(rowpad, rb, (int32_t)(row / 3), (int)(row % 3))]);
+        } else {
+            const int64_t e = q - mr * r;
+            const int64_t c = e % r, j = e / r;
+            Wo[e] = conj(cvt<double>(V[j * ldv + c]));
+        }
+    }
+}
+
+// In place: A (n x n, column-major) = L \ U by elimination without pivoting
+// (unit lower L), then Linv = L^-1 and Uinv = U^-1 by substitution, one
+// column per thread.  One workgroup.
+__global__ void __launch_bounds__(1024) lu_getrf_inv_kernel(Z *__restrict__ A, Z *__restrict__ Linv,
+                                                            Z *__restrict__ Uinv, int32_t n,
+                                                            int32_t *__restrict__ zero_pivot) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    for (int k = 0; k < n; ++k) {
+        const Z piv = A[k + (int64_t)k * n];
+        if (piv.re == 0.0 && piv.im == 0.0) {
+            if (tid == 0) atomicAdd(zero_pivot, 1);
+            return;   // uniform: every thread read the same pivot
+        }
+        const Z inv = zdiv(Z{1, 0}, piv);
+        for (int i = k + 1 + tid; i < n; i += nt) A[i + (int64_t)k * n] = A[i + (int64_t)k * n] * inv;
+        __syncthreads();
+        const int rem = n - k - 1;
+        for (int q = tid; q < rem * rem; q += nt) {
+            const int i = k + 1 + q % rem, j = k + 1 + q / rem;
+            const Z l = A[i + (int64_t)k * n], u = A[k + (int64_t)j * n];
+            Z &a = A[i + (int64_t)j * n];
+            a = a - l * u;
+        }
+        __syncthreads();
+    }
+    for (int j = tid; j < n; j += nt) {
+        Z *x = Linv + (int64_t)j * n;
+        for (int i = 0; i < j; ++i) x[i] = Z{0, 0};
+        x[j] = Z{1, 0};
+        for (int i = j + 1; i < n; ++i) {
+            Z s = {0, 0};
+            for (int k = j; k < i; ++k) fma_(s, A[i + (int64_t)k * n], x[k]);
+            x[i] = Z{-s.re, -s.im};
+        }
+        Z *y = Uinv + (int64_t)j * n;
+        for (int i = j + 1; i < n; ++i) y[i] = Z{0, 0};
+        for (int i = j; i >= 0; --i) {
+            Z s = i == j ? Z{1, 0} : Z{0, 0};
+            for (int k = i + 1; k <= j; ++k) s = s - A[i + (int64_t)k * n] * y[k];
+            y[i] = zdiv(s, A[i + (int64_t)i * n]);
+        }
+    }
+}
+
+// b (original point order, row-major (3N, nrhs)) -> X (cluster order,
+// column-major 3N x nrhs), and back.
+__global__ void lu_gather_kernel(const Z *__restrict__ b, const int32_t *__restrict__ perm,
+                                 int64_t dofs, int32_t nrhs, Z *__restrict__ X) {
+    const int64_t tot = dofs * nrhs;
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < tot;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = q % dofs, c = q / dofs;
+        X[q] = b[(3 * (int64_t)perm[i / 3] + i % 3) * nrhs + c];
+    }
+}
+
+__global__ void lu_scatter_kernel(const Z *__restrict__ X, const int32_t *__restrict__ perm,
+                                  int64_t dofs, int32_t nrhs, Z *__restrict__ x) {
+    const int64_t tot = dofs * nrhs;
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < tot;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = q % dofs, c = q / dofs;
+        x[(3 * (int64_t)perm[i / 3] + i % 3) * nrhs + c] = X[q];
+    }
+}
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+unsigned grid_for(int64_t tot) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(tot, 256), 65536)); }
+
+// ------------------------------------------------------------------ memory
+
+// Bump allocator over device chunks; mark / release give stack discipline
+// for temporaries (reuse is safe in stream order: a later kernel on the same
+// stream runs after every kernel that used the memory before).
+struct Arena {
+    std::vector<std::unique_ptr<DeviceBuf>> chunks;
+    std::vector<size_t> caps;
+    int cur = -1;
+    size_t used = 0;
+    size_t chunk_bytes;
+    size_t total = 0;
+    explicit Arena(size_t cb) : chunk_bytes(cb) {}
+    struct Mark {
+        int cur;
+        size_t used;
+    };
+    Mark mark() const { return {cur, used}; }
+    void release(Mark m) {
+        cur = m.cur;
+        used = m.used;
+    }
+    Z *alloc(int64_t elems) {
+        const size_t b = std::max<size_t>(256, ((size_t)std::max<int64_t>(elems, 1) * sizeof(Z) + 255) & ~size_t(255));
+        if (cur >= 0 && used + b <= caps[cur]) {
+            Z *p = reinterpret_cast<Z *>(static_cast<char *>(chunks[cur]->p) + used);
+            used += b;
+            return p;
+        }
+        for (int c = cur + 1; c < (int)chunks.size(); ++c)
+            if (caps[c] >= b) {
+                cur = c;
+                used = b;
+                return chunks[c]->as<Z>();
+            }
+        auto buf = std::make_unique<DeviceBuf>();
+        const size_t cb = std::max(chunk_bytes, b);
+        buf->alloc(cb);
+        total += cb;
+        chunks.push_back(std::move(buf));
+        caps.push_back(cb);
+        cur = (int)chunks.size() - 1;
+        used = b;
+        return chunks.back()->as<Z>();
+    }
+    Z *base() const { return chunks.empty() ? nullptr : chunks[0]->as<Z>(); }
+};
+
+}  // namespace
+}  // namespace hm
+
+struct hm_lu {
+    double eps = 0;
+    int64_t dofs = 0;
+    std::vector<hm::lu::LuNode> nodes;
+    hm::Arena keep{size_t(1) << 28};
+    hm::Arena tmp{size_t(1) << 28};
+    hm::DeviceBuf d_perm, d_zero_rowpad, d_flag;
+    hm_lu_stats stats{};
+    hipStream_t st = nullptr;
+};
+
+namespace hm {
+namespace {
+
+// The H-LU's arithmetic on the device: kernels of this file, and the
+// assembly's QR + truncated SVD for the eps_LU recompressions.
+struct GpuBackend {
+    hm_lu &F;
+    hipStream_t st;
+    using Mark = Arena::Mark;
+
+    Z *keep_alloc(int64_t n) { return F.keep.alloc(n); }
+    Z *tmp_alloc(int64_t n) { return F.tmp.alloc(n); }
+    Mark tmp_mark() { return F.tmp.mark(); }
+    void tmp_release(Mark m) { F.tmp.release(m); }
+    hm_lu_stats &stats() { return F.stats; }
+
+    void gemm(DMat C, DMat A, DMat B, Z alpha, bool beta) {
+        GemmArgs g{A.p, A.rs, A.cs, B.p, B.rs, B.cs, C.p, C.rs, C.cs, C.m, C.n, A.n, alpha, beta ? 1 : 0};
+        hipLaunchKernelGGL(lu_gemm_kernel, dim3((unsigned)ceil_div(C.m, 64), (unsigned)ceil_div(C.n, 64)),
+                           dim3(256), 0, st, g);
+        HM_HIP_CHECK(hipGetLastError());
+    }
+    void copy(DMat dst, DMat src, Z alpha, bool cj, bool acc) {
+        hipLaunchKernelGGL(lu_copy_kernel, dim3(grid_for((int64_t)dst.m * dst.n)), dim3(256), 0, st,
+                           dst.p, dst.rs, dst.cs, src.p, src.rs, src.cs, dst.m, dst.n, alpha,
+                           cj ? 1 : 0, acc ? 1 : 0);
+        HM_HIP_CHECK(hipGetLastError());
+    }
+    void fill(DMat dst, Z diag) {
+        hipLaunchKernelGGL(lu_fill_kernel, dim3(grid_for((int64_t)dst.m * dst.n)), dim3(256), 0, st,
+                           dst.p, dst.rs, dst.cs, dst.m, dst.n, diag);
+        HM_HIP_CHECK(hipGetLastError());
+    }
+    void getrf_inv(Z *D, Z *Linv, Z *Uinv, int32_t n) {
+        hipLaunchKernelGGL(lu_getrf_inv_kernel, dim3(1), dim3(1024), 0, st, D, Linv, Uinv, n,
+                           F.d_flag.as<int32_t>());
+        HM_HIP_CHECK(hipGetLastError());
+    }
+    // Every item through run_recompress / run_recompress_apply (offsets
+    // counted from the first factor chunk; a zero row padding makes the U'
+    // output plain column-major).
+    void truncate(std::vector<lu::RcItem> &items, double eps_lu) {
+        // The update matrices scale column c by s_c^-1/2 and s_c^-3/2: a
+        // singular value at the rounding level of the core is noise, and
+        // keeping it inflates the factors by orders of magnitude per
+        // recompression until they overflow.  Tolerances below kEpsFloor act
+        // as kEpsFloor.
+        constexpr double kEpsFloor = 1e-13;
+        const double eps = std::max(eps_lu, kEpsFloor);
+        Z *base = F.keep.base();
+        std::vector<RcBlk> rc;
+        int64_t goff = 0;
+        for (const lu::RcItem &it : items) {
+            RcBlk b;
+            b.uoff = it.U - base;
+            b.voff = it.V - base;
+            b.goff = goff;
+            b.m = it.m / 3;
+            b.n = it.n / 3;
+            b.r = it.K;
+            b.rb = 0;
+            goff += 8 * (int64_t)it.K * it.K + 2 * (int64_t)it.K;
+            rc.push_back(b);
+        }
+        DeviceBuf d_rc, d_newrank, d_ou, d_ov;
+        d_rc.alloc(rc.size() * sizeof(RcBlk));
+        HM_HIP_CHECK(hipMemcpyAsync(d_rc.p, rc.data(), rc.size() * sizeof(RcBlk), hipMemcpyHostToDevice, st));
+        d_newrank.alloc(rc.size() * sizeof(int32_t));
+        Z *work = F.tmp.alloc(goff);
+        run_recompress<double>(rc, d_rc.as<RcBlk>(), base, reinterpret_cast<double *>(work),
+                               d_newrank.as<int32_t>(), eps, 0, st, false);
+        std::vector<int32_t> keep(rc.size());
+        HM_HIP_CHECK(hipMemcpyAsync(keep.data(), d_newrank.p, keep.size() * sizeof(int32_t),
+                                    hipMemcpyDeviceToHost, st));
+        HM_HIP_CHECK(hipStreamSynchronize(st));
+        std::vector<int64_t> ou(rc.size(), 0), ov(rc.size(), 0);
+        for (size_t i = 0; i < items.size(); ++i) {
+            lu::RcItem &it = items[i];
+            need(keep[i] >= 0 && keep[i] <= it.K, "H-LU: recompressed rank out of range");
+            it.keep = keep[i];
+            if (!it.keep) continue;
+            it.Uout = F.keep.alloc((int64_t)it.m * it.keep);
+            it.Vrow = F.tmp.alloc((int64_t)it.n * lu::even(it.keep));
+            ou[i] = it.Uout - base;
+            ov[i] = it.Vrow - base;
+        }
+        d_ou.alloc(ou.size() * sizeof(int64_t));
+        d_ov.alloc(ov.size() * sizeof(int64_t));
+        HM_HIP_CHECK(hipMemcpyAsync(d_ou.p, ou.data(), ou.size() * sizeof(int64_t), hipMemcpyHostToDevice, st));
+        HM_HIP_CHECK(hipMemcpyAsync(d_ov.p, ov.data(), ov.size() * sizeof(int64_t), hipMemcpyHostToDevice, st));
+        run_recompress_apply<double>(rc, d_rc.as<RcBlk>(), base, reinterpret_cast<const double *>(work),
+                                     d_ou.as<int64_t>(), d_ov.as<int64_t>(), d_newrank.as<int32_t>(),
+                                     base, keep, F.d_zero_rowpad.as<int32_t>(), st, false);
+        // the host vectors and buffers above outlive their copies and kernels
+        HM_HIP_CHECK(hipStreamSynchronize(st));
+    }
+};
+
+using GpuCore = lu::Core<GpuBackend>;
+
+template <typename S>
+void import_leaves(hm_lu &F, const hm_matrix *A, const std::vector<std::pair<int, int64_t>> &leaves,
+                   const std::vector<int32_t> &leaf_block, hipStream_t st) {
+    const cplx<S> *dense = A->dense.as<cplx<S>>();
+    const cplx<S> *fac = A->factors<cplx<S>>();
+    const int32_t *rp = A->d_rowpad.as<int32_t>();
+    for (const auto &pr : leaves) {
+        LuNode &X = F.nodes[pr.first];
+        const int32_t b = leaf_block[pr.second];
+        const Block &B = A->blocks[b];
+        const int32_t slot = A->block_slot[b];
+        if (B.kind == BLOCK_DENSE) {
+            const DenseBlk &d = A->h_dblk[slot];
+            X.kind = lu::FMT_F;
+            X.D = F.keep.alloc((int64_t)X.m * X.n);
+            hipLaunchKernelGGL(lu_import_dense_kernel<S>, dim3(grid_for((int64_t)X.m * X.n)), dim3(256),
+                               0, st, dense + d.off, (int64_t)d.ld, rp, d.rb, d.m, 3 * d.n, X.D);
+        } else {
+            const LowRankBlk &L = A->h_lblk[slot];
+            X.kind = lu::FMT_R;
+            X.k = L.r;
+            if (L.r > 0) {
+                X.U = F.keep.alloc((int64_t)X.m * L.r);
+                X.W = F.keep.alloc((int64_t)L.r * X.n);
+                hipLaunchKernelGGL(lu_import_lr_kernel<S>,
+                                   dim3(grid_for((int64_t)(X.m + X.n) * L.r)), dim3(256), 0, st,
+                                   fac + L.uoff, (int64_t)L.ldu, fac + L.voff, (int64_t)L.ldv, rp,
+                                   L.rb, L.m, L.n, L.r, X.U, X.W);
+            }
+        }
+        HM_HIP_CHECK(hipGetLastError());
+    }
+}
+
+// ---------------------------------------------- |A_H - A|_F and |A|_F
+// One thread per point pair (p, q) of a block: the 3 x 3 kernel block is
+// evaluated in FP64 and compared with the stored one (dense tile, or the
+// rows of U and V for a low-rank block).  Partial sums per workgroup.
+struct FrobTask {
+    int32_t slot, kind, p0, np;   // block (dense or low-rank slot), pairs p0 .. p0 + np
+};
+
+template <typename S>
+__global__ void __launch_bounds__(256) frob_kernel(Geometry g, GreenParams<double> gp,
+                                                   const FrobTask *__restrict__ tasks,
+                                                   const DenseBlk *__restrict__ dblk,
+                                                   const LowRankBlk *__restrict__ lblk,
+                                                   const cplx<S> *__restrict__ dense,
+                                                   const cplx<S> *__restrict__ fac,
+                                                   const int32_t *__restrict__ rowpad,
+                                                   double self_re, double self_im,
+                                                   double *__restrict__ part) {
+    const FrobTask tk = tasks[blockIdx.x];
+    double sd = 0, sa = 0;
+    for (int32_t e = threadIdx.x; e < tk.np; e += blockDim.x) {
+        const int32_t pq = tk.p0 + e;
+        int32_t rb, cb, m;
+        if (tk.kind == 0) {
+            rb = dblk[tk.slot].rb;
+            cb = dblk[tk.slot].cb;
+            m = dblk[tk.slot].m;
+        } else {
+            rb = lblk[tk.slot].rb;
+            cb = lblk[tk.slot].cb;
+            m = lblk[tk.slot].m;
+        }
+        const int32_t i = pq % m, j = pq / m;
+        const int32_t pi = rb + i, pj = cb + j;
+        cplx<double> K[9];
+        if (g.same && pi == pj) {
+#pragma unroll
+            for (int a = 0; a < 9; ++a) K[a] = {0, 0};
+            K[0] = K[4] = K[8] = {self_re, self_im};
+        } else {
+            const double dx = g.x[0][pi] - g.y[0][pj];
+            const double dy = g.x[1][pi] - g.y[1][pj];
+            const double dz = g.x[2][pi] - g.y[2][pj];
+            double nx = 0, ny = 0, nz = 0;
+            if (gp.kind == 1) {
+                nx = g.n[0][pj];
+                ny = g.n[1][pj];
+                nz = g.n[2][pj];
+            }
+            green_block<double>(gp, dx, dy, dz, nx, ny, nz, K);
+        }
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int bcol = 0; bcol < 3; ++bcol) {
+                cplx<double> h;
+                if (tk.kind == 0) {
+                    const DenseBlk &d = dblk[tk.slot];
+                    h = cvt<double>(dense[d.off + (3 * (int64_t)j + bcol) * d.ld +
+                                          padded_row(rowpad, rb, i, a)]);
+                } else {
+                    const LowRankBlk &L = lblk[tk.slot];
+                    const cplx<S> *u = fac + L.uoff + padded_row(rowpad, rb, i, a);
+                    const cplx<S> *v = fac + L.voff + (3 * (int64_t)j + bcol) * L.ldv;
+                    h = {0, 0};
+                    for (int c = 0; c < L.r; ++c) {
+                        const cplx<double> uu = cvt<double>(u[(int64_t)c * L.ldu]);
+                        const cplx<double> vv = cvt<double>(v[c]);
+                        h = h + mulc(uu, vv);
+                    }
+                }
+                const cplx<double> k = K[3 * a + bcol];
+                sd += abs2(h - k);
+                sa += abs2(k);
+            }
+    }
+    __shared__ double red[2][4];
+    sd = wave_sum(sd);
+    sa = wave_sum(sa);
+    if ((threadIdx.x & 63) == 0) {
+        red[0][threadIdx.x >> 6] = sd;
+        red[1][threadIdx.x >> 6] = sa;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = 0, b = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+            a += red[0][w];
+            b += red[1][w];
+        }
+        part[2 * blockIdx.x] = a;
+        part[2 * blockIdx.x + 1] = b;
+    }
+}
+
+__global__ void norm2_kernel(const Z *__restrict__ x, int64_t n, double *__restrict__ part) {
+    double s = 0;
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n;
+         q += (int64_t)gridDim.x * blockDim.x)
+        s += abs2(x[q]);
+    __shared__ double red[4];
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+double device_norm(const Z *x, int64_t n, hipStream_t st) {
+    const unsigned nb = 1024;
+    DeviceBuf part;
+    part.alloc(nb * sizeof(double));
+    hipLaunchKernelGGL(norm2_kernel, dim3(nb), dim3(256), 0, st, x, n, part.as<double>());
+    HM_HIP_CHECK(hipGetLastError());
+    std::vector<double> h(nb);
+    HM_HIP_CHECK(hipMemcpyAsync(h.data(), part.p, nb * sizeof(double), hipMemcpyDeviceToHost, st));
+    HM_HIP_CHECK(hipStreamSynchronize(st));
+    double s = 0;
+    for (double v : h) s += v;
+    return std::sqrt(s);
+}
+
+}  // namespace
+}  // namespace hm
+
+using namespace hm;
+
+extern "C" hm_status hm_lu_factor(const hm_matrix *A, double eps_lu, void *stream, hm_lu **out) {
+    HM_API_BEGIN
+    need(A != nullptr && out != nullptr, "NULL argument");
+    need(eps_lu >= 0.0, "eps_lu must be >= 0");
+    if (A->plan_only) throw StatusError(HM_ERR_STATE, "matrix was built with plan_only");
+    need(A->p.same != 0, "the H-LU needs a square operator on one point cloud (same = 1)");
+    *out = nullptr;
+    const auto t0 = std::chrono::steady_clock::now();
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    auto F = std::make_unique<hm_lu>();
+    F->eps = eps_lu;
+    F->st = st;
+    const ClusterTree &tr = A->rowtree();
+    F->dofs = 3 * A->nx;
+    // leaf blocks keyed by (row node, col node)
+    std::vector<std::pair<int64_t, int32_t>> key;
+    for (size_t b = 0; b < A->blocks.size(); ++b)
+        key.push_back({(int64_t)A->blocks[b].row * tr.nodes() + A->blocks[b].col, (int32_t)b});
+    std::sort(key.begin(), key.end());
+    std::vector<int64_t> leaf_of(key.size());
+    std::vector<int32_t> leaf_block(key.size());
+    for (size_t i = 0; i < key.size(); ++i) {
+        leaf_of[i] = key[i].first;
+        leaf_block[i] = key[i].second;
+    }
+    std::vector<std::pair<int, int64_t>> leaves;
+    const lu::TreeView tv{tr.begin.data(), tr.end.data(), tr.left.data(), tr.right.data(), tr.nodes()};
+    lu::build_node(F->nodes, tv, leaf_of, 0, 0, leaves);
+    need(leaves.size() == A->blocks.size(), "internal: block list and tree disagree");
+    {
+        std::vector<int32_t> zero(A->nx + 1, 0);
+        F->d_zero_rowpad.alloc(zero.size() * sizeof(int32_t));
+        HM_HIP_CHECK(hipMemcpyAsync(F->d_zero_rowpad.p, zero.data(), zero.size() * sizeof(int32_t),
+                                    hipMemcpyHostToDevice, st));
+        F->d_perm.alloc(tr.perm.size() * sizeof(int32_t));
+        HM_HIP_CHECK(hipMemcpyAsync(F->d_perm.p, tr.perm.data(), tr.perm.size() * sizeof(int32_t),
+                                    hipMemcpyHostToDevice, st));
+        F->d_flag.alloc(sizeof(int32_t));
+        HM_HIP_CHECK(hipMemsetAsync(F->d_flag.p, 0, sizeof(int32_t), st));
+        HM_HIP_CHECK(hipStreamSynchronize(st));
+    }
+    if (A->p.prec == HM_C64)
+        import_leaves<float>(*F, A, leaves, leaf_block, st);
+    else
+        import_leaves<double>(*F, A, leaves, leaf_block, st);
+    HM_HIP_CHECK(hipStreamSynchronize(st));
+    const auto t1 = std::chrono::steady_clock::now();
+    GpuBackend be{*F, st};
+    GpuCore c(be, F->nodes, eps_lu);
+    c.hlu(0);
+    int32_t zp = 0;
+    HM_HIP_CHECK(hipMemcpyAsync(&zp, F->d_flag.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HM_HIP_CHECK(hipStreamSynchronize(st));
+    if (zp) throw StatusError(HM_ERR_NOCONV, "zero pivot in a diagonal leaf (elimination without pivoting)");
+    const auto t2 = std::chrono::steady_clock::now();
+    c.tally(0);
+    F->stats.t_import = std::chrono::duration<double>(t1 - t0).count();
+    F->stats.t_factor = std::chrono::duration<double>(t2 - t1).count();
+    F->stats.device_bytes = (int64_t)(F->keep.total + F->tmp.total);
+    F->stats.n_nodes = (int32_t)F->nodes.size();
+    *out = F.release();
+    return HM_OK;
+    HM_API_END
+}
+
+extern "C" hm_status hm_lu_solve(hm_lu *F, const void *b, void *x, int32_t nrhs, void *stream) {
+    HM_API_BEGIN
+    need(F != nullptr && b != nullptr && x != nullptr, "NULL argument");
+    need(nrhs >= 1, "nrhs must be >= 1");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    GpuBackend be{*F, st};
+    GpuCore c(be, F->nodes, F->eps);
+    const auto mk = F->tmp.mark();
+    DMat X = c.tmpmat((int32_t)F->dofs, nrhs, false);
+    const int64_t tot = F->dofs * nrhs;
+    hipLaunchKernelGGL(lu_gather_kernel, dim3(grid_for(tot)), dim3(256), 0, st,
+                       static_cast<const Z *>(b), F->d_perm.as<int32_t>(), F->dofs, nrhs, X.p);
+    HM_HIP_CHECK(hipGetLastError());
+    c.lower_solve(0, X);
+    c.upper_solve_left(0, X);
+    hipLaunchKernelGGL(lu_scatter_kernel, dim3(grid_for(tot)), dim3(256), 0, st, X.p,
+                       F->d_perm.as<int32_t>(), F->dofs, nrhs, static_cast<Z *>(x));
+    HM_HIP_CHECK(hipGetLastError());
+    F->tmp.release(mk);
+    return HM_OK;
+    HM_API_END
+}
+
+extern "C" hm_status hm_lu_get_stats(const hm_lu *F, hm_lu_stats *s) {
+    HM_API_BEGIN
+    need(F != nullptr && s != nullptr, "NULL argument");
+    *s = F->stats;
+    return HM_OK;
+    HM_API_END
+}
+
+extern "C" hm_status hm_lu_export_dense(hm_lu *F, void *host_buf) {
+    HM_API_BEGIN
+    need(F != nullptr && host_buf != nullptr, "NULL argument");
+    need(F->dofs <= 20000, "hm_lu_export_dense is for small problems (3N <= 20000)");
+    hipStream_t st = F->st;
+    GpuBackend be{*F, st};
+    GpuCore c(be, F->nodes, F->eps);
+    const auto mk = F->tmp.mark();
+    DMat D = c.tmpmat((int32_t)F->dofs, (int32_t)F->dofs, false);
+    c.densify(0, D);
+    HM_HIP_CHECK(hipMemcpyAsync(host_buf, D.p, (size_t)F->dofs * F->dofs * sizeof(Z),
+                                hipMemcpyDeviceToHost, st));
+    HM_HIP_CHECK(hipStreamSynchronize(st));
+    F->tmp.release(mk);
+    return HM_OK;
+    HM_API_END
+}
+
+extern "C" void hm_lu_destroy(hm_lu *F) { delete F; }
+
+extern "C" hm_status hm_frob_error(const hm_matrix *A, void *stream, double *diff_fro,
+                                   double *a_fro) {
+    HM_API_BEGIN
+    need(A != nullptr && diff_fro != nullptr && a_fro != nullptr, "NULL argument");
+    if (A->plan_only) throw StatusError(HM_ERR_STATE, "matrix was built with plan_only");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    constexpr int32_t kPairs = 2048;
+    std::vector<FrobTask> tasks;
+    for (size_t i = 0; i < A->h_dblk.size(); ++i) {
+        const int32_t np = A->h_dblk[i].m * A->h_dblk[i].n;
+        for (int32_t p0 = 0; p0 < np; p0 += kPairs) tasks.push_back({(int32_t)i, 0, p0, std::min(kPairs, np - p0)});
+    }
+    for (size_t i = 0; i < A->h_lblk.size(); ++i) {
+        const int32_t np = A->h_lblk[i].m * A->h_lblk[i].n;
+        for (int32_t p0 = 0; p0 < np; p0 += kPairs) tasks.push_back({(int32_t)i, 1, p0, std::min(kPairs, np - p0)});
+    }
+    DeviceBuf d_tasks, d_d, d_l, part;
+    auto up = [&](DeviceBuf &buf, const void *src, size_t bytes) {
+        buf.alloc(std::max<size_t>(bytes, 16));
+        if (bytes) HM_HIP_CHECK(hipMemcpyAsync(buf.p, src, bytes, hipMemcpyHostToDevice, st));
+    };
+    up(d_tasks, tasks.data(), tasks.size() * sizeof(FrobTask));
+    up(d_d, A->h_dblk.data(), A->h_dblk.size() * sizeof(DenseBlk));
+    up(d_l, A->h_lblk.data(), A->h_lblk.size() * sizeof(LowRankBlk));
+    part.alloc(std::max<size_t>(tasks.size(), 1) * 2 * sizeof(double));
+    const GreenParams<double> gp =
+        make_green_params<double>(A->p.kernel, A->p.omega, A->p.lambda, A->p.mu, A->p.rho);
+    if (!tasks.empty()) {
+        if (A->p.prec == HM_C64)
+            hipLaunchKernelGGL(frob_kernel<float>, dim3((unsigned)tasks.size()), dim3(256), 0, st,
+                               A->geometry(), gp, d_tasks.as<FrobTask>(), d_d.as<DenseBlk>(),
+                               d_l.as<LowRankBlk>(), A->dense.as<cplx<float>>(),
+                               A->factors<cplx<float>>(), A->d_rowpad.as<int32_t>(), A->p.self_re,
+                               A->p.self_im, part.as<double>());
+        else
+            hipLaunchKernelGGL(frob_kernel<double>, dim3((unsigned)tasks.size()), dim3(256), 0, st,
+                               A->geometry(), gp, d_tasks.as<FrobTask>(), d_d.as<DenseBlk>(),
+                               d_l.as<LowRankBlk>(), A->dense.as<cplx<double>>(),
+                               A->factors<cplx<double>>(), A->d_rowpad.as<int32_t>(), A->p.self_re,
+                               A->p.self_im, part.as<double>());
+        HM_HIP_CHECK(hipGetLastError());
+    }
+    std::vector<double> h(2 * tasks.size());
+    if (!h.empty())
+        HM_HIP_CHECK(hipMemcpyAsync(h.data(), part.p, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HM_HIP_CHECK(hipStreamSynchronize(st));
+    double sd = 0, sa = 0;
+    for (size_t i = 0; i < tasks.size(); ++i) {
+        sd += h[2 * i];
+        sa += h[2 * i + 1];
+    }
+    *diff_fro = std::sqrt(sd);
+    *a_fro = std::sqrt(sa);
+    return HM_OK;
+    HM_API_END
+}
+
+extern "C" hm_status hm_lu_estimate(const hm_matrix *A, const void *b, const void *x0,
+                                    double delta_h, void *stream, hm_lu_estimate_t *est) {
+    HM_API_BEGIN
+    need(A != nullptr && b != nullptr && x0 != nullptr && est != nullptr, "NULL argument");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int64_t n = 3 * A->nx;
+    DeviceBuf r;
+    r.alloc(n * sizeof(Z));
+    const hm_status s = hm_residual(A, b, x0, r.p, 1, stream);
+    if (s != HM_OK) return s;
+    est->delta = device_norm(r.as<Z>(), n, st);
+    est->b_norm = device_norm(static_cast<const Z *>(b), n, st);
+    est->x0_norm = device_norm(static_cast<const Z *>(x0), n, st);
+    est->delta_h = delta_h;
+    est->estimate = (est->delta + delta_h * est->x0_norm) / est->b_norm;
+    return HM_OK;
+    HM_API_END
+}

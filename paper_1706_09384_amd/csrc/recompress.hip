@@ -509,11 +509,14 @@ __global__ void __launch_bounds__(NT) factor_kernel(const RcBlk *__restrict__ bl
             if (lane == 0) sv[c] = sqrt(s);
         }
         __syncthreads();
+        // a non-finite value ranks last, so that idx is a permutation
+        // whatever the input (NaN compares false both ways)
+        auto key = [](double x) { return x <= 1.7976931348623157e308 ? x : -1.0; };
         for (int c = tid; c < r; c += NT) {
-            const double v = sv[c];
+            const double v = key(sv[c]);
             int pos = 0;
             for (int k = 0; k < r; ++k) {
-                const double w = sv[k];
+                const double w = key(sv[k]);
                 if (w > v || (w == v && k < c)) ++pos;
             }
             idx[pos] = c;

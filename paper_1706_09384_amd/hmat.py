@@ -81,6 +81,27 @@ class Stats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class LuStats(ctypes.Structure):
+    _fields_ = [("t_import", ctypes.c_double), ("t_factor", ctypes.c_double),
+                ("storage_entries", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
+                ("max_rank", ctypes.c_int32), ("n_nodes", ctypes.c_int32),
+                ("n_diag", ctypes.c_int32), ("n_recompressed", ctypes.c_int32),
+                ("n_batches", ctypes.c_int32), ("n_gemm", ctypes.c_int32),
+                ("gemm_flops", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class LuEstimate(ctypes.Structure):
+    _fields_ = [("delta", ctypes.c_double), ("delta_h", ctypes.c_double),
+                ("b_norm", ctypes.c_double), ("x0_norm", ctypes.c_double),
+                ("estimate", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class GmresInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("restarts", ctypes.c_int32),
                 ("refinements", ctypes.c_int32), ("converged", ctypes.c_int32),
@@ -121,6 +142,13 @@ def _load():
         "hm_rank_model_train": ([P, P, i64, P, i32, i32, ctypes.c_float, ctypes.c_uint64, P, P], i32),
         "hm_rank_model_predict": ([P, P, P, i64, P], i32),
         "hm_rank_model_grad": ([P, P, P, i64, P, P, P], i32),
+        "hm_lu_factor": ([P, d, P, P], i32),
+        "hm_lu_solve": ([P, P, P, i32, P], i32),
+        "hm_lu_get_stats": ([P, P], i32),
+        "hm_lu_export_dense": ([P, P], i32),
+        "hm_lu_destroy": ([P], None),
+        "hm_frob_error": ([P, P, P, P], i32),
+        "hm_lu_estimate": ([P, P, P, d, P, P], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -135,7 +163,8 @@ EXPORTED = ["hm_params_default", "hm_build", "hm_matvec", "hm_matvec_noalloc", "
             "hm_export_tree", "hm_export_blocklist", "hm_export_block", "hm_destroy",
             "hm_release_cache",
             "hm_last_error", "hm_rank_samples", "hm_rank_model_train", "hm_rank_model_predict",
-            "hm_rank_model_grad"]
+            "hm_rank_model_grad", "hm_lu_factor", "hm_lu_solve", "hm_lu_get_stats",
+            "hm_lu_export_dense", "hm_lu_destroy", "hm_frob_error", "hm_lu_estimate"]
 
 
 def _check(rc):
@@ -180,6 +209,46 @@ def make_params(kernel=KERNEL_U, prec=C128, omega=1.0, lam=2.0, mu=1.0, rho=1.0,
         p.rank_model = w.ctypes.data
         p._model_keepalive = w
     return p
+
+
+class HLU:
+    """Owning handle of H-LU factors (hm_lu*)."""
+
+    def __init__(self, handle, dofs):
+        self._h = handle
+        self._destroy = LIB.hm_lu_destroy
+        self.dofs = dofs
+
+    def __del__(self):
+        self.close()
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h:
+            self._h = None
+            self._destroy(h)
+
+    def stats(self) -> dict:
+        s = LuStats()
+        _check(LIB.hm_lu_get_stats(self._h, ctypes.byref(s)))
+        return s.as_dict()
+
+    def solve(self, b, x=None, stream=None):
+        """x0 = U_H^-1 L_H^-1 b; b a complex128 cuda tensor (3N,) or (3N, nrhs)."""
+        import torch
+        vec = b.dim() == 1
+        B = b.reshape(b.shape[0], -1).contiguous()
+        assert B.dtype == torch.complex128 and B.is_cuda and B.shape[0] == self.dofs
+        if x is None:
+            x = torch.empty_like(B)
+        _check(LIB.hm_lu_solve(self._h, _ptr(B), _ptr(x), B.shape[1], _stream(stream)))
+        return x.reshape(-1) if vec else x
+
+    def export_dense(self) -> np.ndarray:
+        """L_H (strictly lower, unit diagonal implied) and U_H packed, cluster order."""
+        out = np.zeros((self.dofs, self.dofs), dtype=np.complex128, order="F")
+        _check(LIB.hm_lu_export_dense(self._h, out.ctypes.data_as(ctypes.c_void_p)))
+        return out
 
 
 class HMatrix:
@@ -245,6 +314,27 @@ class HMatrix:
             r = torch.empty_like(B)
         _check(LIB.hm_residual(self._h, _ptr(B), _ptr(X), _ptr(r), B.shape[1], _stream(stream)))
         return r.reshape(-1) if vec else r
+
+    def lu(self, eps_lu, stream=None) -> "HLU":
+        """H-LU factors of this operator at eps_LU (hm_lu_factor)."""
+        h = ctypes.c_void_p()
+        _check(LIB.hm_lu_factor(self._h, float(eps_lu), _stream(stream), ctypes.byref(h)))
+        return HLU(h.value, 3 * self.nx)
+
+    def frob_error(self, stream=None):
+        """(|A_H - A|_F, |A|_F) (hm_frob_error)."""
+        d, a = ctypes.c_double(), ctypes.c_double()
+        _check(LIB.hm_frob_error(self._h, _stream(stream), ctypes.byref(d), ctypes.byref(a)))
+        return d.value, a.value
+
+    def lu_estimate(self, b, x0, delta_h, stream=None) -> dict:
+        """Estimator of eq. est_direct for one right-hand side (hm_lu_estimate)."""
+        import torch
+        assert b.dtype == torch.complex128 and x0.dtype == torch.complex128
+        e = LuEstimate()
+        _check(LIB.hm_lu_estimate(self._h, _ptr(b.contiguous()), _ptr(x0.contiguous()),
+                                  float(delta_h), _stream(stream), ctypes.byref(e)))
+        return e.as_dict()
 
     def gmres(self, b, tol=1e-6, restart=50, maxit=2000, stream=None, check=True):
         """Solve A_H x = b (complex128 cuda tensors); returns (x, info dict)."""

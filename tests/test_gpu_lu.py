@@ -1,0 +1,176 @@
+"""H-LU direct solver (Section 3.2) and certification estimator (Section 3.3) on the GPU.
+
+* eps_LU = 0: the GPU factors are unit-lower / upper triangular with
+  L U = A_H up to the resolution of the recompression (its Cholesky-QR
+  resolves a block's singular values down to about 3e-7 of its column
+  norms, the square root of its pivot tolerance), so |L U - A_H| / |A_H|
+  <= 2e-6, and the solve agrees with a dense solve with A_H.
+* eps_LU = 1e-4, 1e-6 (the paper's settings): |L U - A_H| / |A_H| tracks
+  eps_LU, as for the oracle.
+* Against the oracle: the GPU solution and the oracle's H-LU solution (each
+  from its own A_H) agree to the accuracy both approximate A^-1 b, and the
+  GPU's |A_H - A|_F equals the one computed from the oracle's dense A.
+* The estimator bounds the true residual |b - A x0| / |b|.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1706_09384_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def hm():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1706_09384_amd import hmat
+    return hmat
+
+
+def dense_from_exports(H):
+    """A_H as one dense matrix in cluster order, from the exported blocks."""
+    b, r, _ = H.export_blocklist()
+    nodes = H.export_tree(0)[1]
+    n = 3 * H.nx
+    D = np.zeros((n, n), dtype=np.complex128)
+    for k in range(b.shape[0]):
+        t, s, kind = b[k]
+        r0, r1 = 3 * nodes[t, 0], 3 * nodes[t, 1]
+        c0, c1 = 3 * nodes[s, 0], 3 * nodes[s, 1]
+        d = H.export_block(k, b, r, nodes, nodes)
+        D[r0:r1, c0:c1] = d if kind == 0 else d[0] @ d[1].conj().T
+    return D
+
+
+def cluster_dofs(H):
+    perm = H.export_tree(0)[0]
+    return (3 * perm[:, None] + np.arange(3)).ravel()
+
+
+@pytest.fixture(scope="module")
+def sphere1k(hm, orc):
+    w = W.plain_sphere_1k()
+    X, _ = w.points()
+    H = hm.build_workload(w, X=X, prec=0)
+    A = orc.dense(orc.Problem.from_workload(w, X))
+    return w, X, H, A
+
+
+def test_exact_lu_is_the_unpivoted_lu_of_A_H(hm, sphere1k):
+    import torch
+    w, X, H, A = sphere1k
+    say("case lu exact sphere1k")
+    F = H.lu(0.0)
+    st = F.stats()
+    say(st)
+    assert st["n_recompressed"] > 0 and st["n_diag"] > 0
+    P = F.export_dense()
+    L = np.tril(P, -1) + np.eye(P.shape[0])
+    U = np.triu(P)
+    AH = dense_from_exports(H)
+    e = np.linalg.norm(L @ U - AH) / np.linalg.norm(AH)
+    say("|LU - A_H| / |A_H|", e)
+    assert e <= 2e-6
+    b = w.rhs()[:, 0]
+    x = F.solve(torch.from_numpy(b).cuda()).cpu().numpy()
+    dof = cluster_dofs(H)
+    xd = np.empty_like(b)
+    xd[dof] = np.linalg.solve(AH, b[dof])
+    ex = np.linalg.norm(x - xd) / np.linalg.norm(xd)
+    say("|x - A_H^-1 b| / |x|", ex)
+    assert ex <= 1e-4
+
+
+@pytest.mark.parametrize("eps_lu", [1e-4, 1e-6])
+def test_truncated_lu_error_tracks_eps(hm, sphere1k, eps_lu):
+    w, X, H, A = sphere1k
+    say(f"case lu eps {eps_lu}")
+    F = H.lu(eps_lu)
+    P = F.export_dense()
+    L = np.tril(P, -1) + np.eye(P.shape[0])
+    AH = dense_from_exports(H)
+    e = np.linalg.norm(L @ np.triu(P) - AH) / np.linalg.norm(AH)
+    say("|LU - A_H| / |A_H|", e, F.stats())
+    assert 1e-3 * eps_lu <= e <= 2 * eps_lu + 1e-6
+
+
+def test_frobenius_error_matches_dense_difference(hm, sphere1k):
+    w, X, H, A = sphere1k
+    say("case frob sphere1k")
+    d, a = H.frob_error()
+    dof = cluster_dofs(H)
+    Ac = A[np.ix_(dof, dof)]
+    AH = dense_from_exports(H)
+    d_ref, a_ref = np.linalg.norm(AH - Ac), np.linalg.norm(Ac)
+    say("GPU", d, a, "dense", d_ref, a_ref)
+    assert abs(a - a_ref) <= 1e-12 * a_ref
+    assert abs(d - d_ref) <= 1e-6 * d_ref
+    assert d / a <= 5 * w.eps
+
+
+@pytest.mark.parametrize("eps", [1e-4, 1e-6])
+def test_solution_and_estimator_against_oracle(hm, orc, eps):
+    """GPU and oracle H-LU from their own A_H at eps_ACA = eps_LU = eps: both
+    solutions within the estimator of the dense solution, and the GPU
+    estimator bounds its true residual."""
+    import torch
+    sys.path.insert(0, __file__.rsplit("/", 1)[0])
+    from test_oracle_hlu import svd_leaves
+    w = W.small_sphere(1000, leaf=32, eps=eps)
+    say(f"case lu vs oracle eps {eps}")
+    X, _ = w.points()
+    H = hm.build_workload(w, X=X, prec=0)
+    F = H.lu(eps)
+    b = w.rhs()[:, 0]
+    bt = torch.from_numpy(b).cuda()
+    x = F.solve(bt)
+    dh, _ = H.frob_error()
+    est = H.lu_estimate(bt, x, dh)
+    x = x.cpu().numpy()
+    pb = orc.Problem.from_workload(w, X)
+    A = orc.dense(pb)
+    res = np.linalg.norm(b - A @ x) / np.linalg.norm(b)
+    say("estimate", est, "true residual", res)
+    assert res <= est["estimate"]
+    assert est["delta"] / est["b_norm"] <= 10 * eps
+    xd, _ = orc.lu_solve(A, b)
+    # oracle H-LU on its own A_H
+    t = orc.cluster_tree(X, w.leaf)
+    blocks = orc.block_tree(t, t, w.eta)
+    root = orc.hlu.build(t, svd_leaves(orc, t, blocks, A, eps))
+    orc.hlu.hlu(root, eps)
+    dof = (3 * t.perm[:, None] + np.arange(3)).ravel()
+    xo = np.empty_like(b)
+    xo[dof] = orc.hlu.hlu_solve(root, b[dof])
+    eg = np.linalg.norm(x - xd) / np.linalg.norm(xd)
+    eo = np.linalg.norm(xo - xd) / np.linalg.norm(xd)
+    say("|x_gpu - x| / |x|", eg, "|x_oracle - x| / |x|", eo,
+        "|x_gpu - x_oracle| / |x|", np.linalg.norm(x - xo) / np.linalg.norm(xd))
+    assert eg <= 100 * eps and eo <= 100 * eps
+    assert np.linalg.norm(x - xo) <= 100 * eps * np.linalg.norm(xd)
+
+
+def test_t_kernel_and_complex64_operator(hm):
+    """The T kernel on a cube surface (coplanar faces), operator stored in
+    complex64: the factorisation runs in complex128 and, at eps_LU = 0,
+    reproduces the stored operator to the recompression's resolution."""
+    say("case lu T cube c64")
+    P, Nrm = W.cube_surface(1200, seed=3)
+    w = W.Workload("cube1200", 1200, 1, omega=1.1547, eps=1e-4, leaf=32,
+                   self_re=W._t_self(W.CUBE_AREA, 1200), geometry="cube")
+    H = hm.build_workload(w, X=P, N=Nrm, prec=1)
+    F = H.lu(0.0)
+    Pk = F.export_dense()
+    L = np.tril(Pk, -1) + np.eye(Pk.shape[0])
+    AH = dense_from_exports(H).astype(np.complex128)
+    e = np.linalg.norm(L @ np.triu(Pk) - AH) / np.linalg.norm(AH)
+    say("|LU - A_H| / |A_H|", e, F.stats())
+    assert e <= 2e-6
