@@ -533,6 +533,64 @@ def sweep_leg(hmat, W, orc, max_points=400000, max_points_t=260000, kernels=(0, 
     return res
 
 
+def hlu_leg(hmat, W, large=False):
+    """H-LU direct solver (Section 3.2) and its certification (Section 3.3) on Fibonacci
+    spheres with the DOF counts of Table error_freq_single (642, 2562 and, with
+    --hlu-large, 10242 points), omega = 3, U kernel, complex128, eps_ACA = eps_LU.
+    Per row the table's columns: the estimator I(delta_H,F, delta) of eq. est_direct with
+    the absolute |A_H - A|_F (a rigorous bound), the true residual |b - A x0| / |b| (A
+    applied exactly as an all-dense operator), delta_H,F absolute and relative,
+    |x0| / |b| and delta / |b|; plus factorisation and solve times, storage of the
+    factors and, for comparison, GMRES on A_H to the same tolerance."""
+    import torch
+    rows = []
+    cases = [(642, 1e-4), (642, 1e-6), (2562, 1e-4), (2562, 1e-6)]
+    if large:
+        cases += [(10242, 1e-4), (10242, 1e-6)]
+    for n, eps in cases:
+        w = W.small_sphere(n, omega=3.0, leaf=32, eps=eps)
+        X, _ = w.points()
+        tb = time.perf_counter()
+        H = hmat.build_workload(w, X=X, prec=hmat.C128)
+        torch.cuda.synchronize()
+        t_build = time.perf_counter() - tb
+        F = H.lu(eps)
+        st = F.stats()
+        b = torch.from_numpy(w.rhs()[:, 0]).cuda()
+        x = F.solve(b)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            x = F.solve(b)
+        torch.cuda.synchronize()
+        t_solve = (time.perf_counter() - t0) / 3
+        dh, af = H.frob_error()
+        est = H.lu_estimate(b, x, dh)
+        Hd = hmat.build_workload(w, X=X, prec=hmat.C128, eta=0.0)
+        res = float(torch.linalg.vector_norm(Hd.residual(b, x))) / est["b_norm"]
+        Hd.close()
+        tg = time.perf_counter()
+        xg, info = H.gmres(b, tol=eps, restart=100, maxit=5000, check=False)
+        torch.cuda.synchronize()
+        t_gmres = time.perf_counter() - tg
+        rec = {"N_c": n, "dofs": 3 * n, "omega": 3.0, "eps": eps,
+               "I_estimate": est["estimate"], "residual_true": res,
+               "delta_HF_abs": dh, "delta_HF_rel": dh / af,
+               "x0_over_b": est["x0_norm"] / est["b_norm"], "delta_over_b": est["delta"] / est["b_norm"],
+               "assembly_s": round(t_build, 3), "factor_s": round(st["t_factor"], 3),
+               "solve_ms": round(t_solve * 1e3, 2),
+               "factor_storage_rate": round(st["storage_entries"] / (3.0 * n) ** 2, 4),
+               "max_rank_factors": st["max_rank"], "recompressed_blocks": st["n_recompressed"],
+               "gemm_launches": st["n_gemm"], "gmres_s": round(t_gmres, 3),
+               "gmres_iters": info["iters"], "gmres_relres": info["relres"]}
+        rows.append(rec)
+        log(f"[bench] hlu {rec}")
+        F.close()
+        H.close()
+        hmat.release_cache()
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -547,6 +605,9 @@ def main():
     ap.add_argument("--no-batching", action="store_true")
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--sweep-only", action="store_true", help="run the frequency sweeps alone")
+    ap.add_argument("--no-hlu", action="store_true")
+    ap.add_argument("--hlu-only", action="store_true", help="run the H-LU leg alone")
+    ap.add_argument("--hlu-large", action="store_true", help="add 10242 points to the H-LU leg")
     ap.add_argument("--counters", action="store_true",
                     help="profiling mode: one headline build, the autotuner, 10 matvecs, then a "
                          "256 MiB device copy (x3) whose known byte count calibrates FETCH_SIZE / "
@@ -563,6 +624,9 @@ def main():
     if args.sweep_only:
         import oracle as orc
         print(json.dumps({"sweep": sweep_leg(hmat, W, orc)}), flush=True)
+        return
+    if args.hlu_only:
+        print(json.dumps({"hlu": hlu_leg(hmat, W, large=args.hlu_large)}), flush=True)
         return
 
     w = W.multirhs_sphere_200k()
@@ -709,6 +773,8 @@ def main():
     if not args.no_sweep:
         # up to 163,543 points here; --sweep-only runs the whole table
         out["sweep"] = sweep_leg(hmat, W, orc, max_points=170000, max_points_t=170000)
+    if not args.no_hlu:
+        out["hlu"] = hlu_leg(hmat, W, large=args.hlu_large)
     print(json.dumps(out), flush=True)
 
 
