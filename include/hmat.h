@@ -325,8 +325,11 @@ typedef struct {
     int32_t n_diag;           /* dense diagonal leaves factorised */
     int32_t n_recompressed;   /* low-rank blocks recompressed at eps_LU */
     int32_t n_batches;        /* batches those recompressions ran in */
-    int32_t n_gemm;           /* matrix-core GEMM launches */
+    int32_t n_gemm;           /* matrix-core GEMM launches of the recursion */
     double gemm_flops;        /* their flops, 8 per complex multiply-add */
+    int32_t n_sampled;        /* recompressions whose stacked factors (more than 64 columns)
+                                 went through the randomized range finder first */
+    int32_t reserved;
 } hm_lu_stats;
 
 /*
@@ -336,7 +339,9 @@ typedef struct {
  * dense, low-rank or subdivided format, without pivoting.  Sums that reach a
  * low-rank block are recompressed (QR of both factors, truncated SVD of
  * R_U R_V^*) at eps_lu, keeping the singular values whose Frobenius tail
- * exceeds eps_lu times the total.  Dense diagonal leaves are eliminated
+ * exceeds eps_lu times the total; when the stacked factors hold more than 64
+ * columns and eps_lu >= 1e-6, a randomized range finder (Liberty et al. 2007,
+ * range error at most eps_lu / 2 in the Frobenius norm) reduces them first.  Dense diagonal leaves are eliminated
  * without pivoting.  Arithmetic is complex128 whatever A's precision.
  *   A       an assembled square operator (params.same = 1); read only, and
  *           not needed by the factors afterwards

@@ -127,6 +127,11 @@ struct RsTask {
 };
 
 
+// In place Q = orth(Y) for every descriptor (Y at base + yoff, 3m x k
+// column-major, k <= kRsMaxK): classical Gram-Schmidt with one
+// reorthogonalisation, dependent columns set to zero; one workgroup each.
+void launch_orth(const RsBlk *d_blk, int32_t nblk, cplx<double> *base, hipStream_t st);
+
 // Recompression work description.
 struct RcBlk {
     int64_t uoff, voff;   // ACA factors (scratch slab)

@@ -27,6 +27,7 @@
 #include "internal.hpp"
 #include "lu_core.hpp"
 #include "mfma_gemm.hpp"
+#include "rng.hpp"
 
 namespace hm {
 
@@ -58,6 +59,7 @@ struct GemmArgs {
     int32_t m, n, k;
     Z alpha;
     int32_t beta;
+    int32_t conja, conjb;   // use conj(A) / conj(B) entries
 };
 
 __global__ void __launch_bounds__(256) lu_gemm_kernel(GemmArgs g) {
@@ -78,14 +80,18 @@ __global__ void __launch_bounds__(256) lu_gemm_kernel(GemmArgs g) {
         for (int e = tid; e < kS * kT; e += 256) {
             int i, kk;
             if (a_rows) { i = e % kT; kk = e / kT; } else { kk = e % kS; i = e / kS; }
-            sa[kk][i] = (i0 + i < g.m && k0 + kk < g.k)
-                            ? g.A[(int64_t)(i0 + i) * g.ars + (int64_t)(k0 + kk) * g.acs]
-                            : Z{0, 0};
+            Z av = (i0 + i < g.m && k0 + kk < g.k)
+                       ? g.A[(int64_t)(i0 + i) * g.ars + (int64_t)(k0 + kk) * g.acs]
+                       : Z{0, 0};
+            if (g.conja) av.im = -av.im;
+            sa[kk][i] = av;
             int j, k2;
             if (b_rows) { k2 = e % kS; j = e / kS; } else { j = e % kT; k2 = e / kT; }
-            sb[k2][j] = (k0 + k2 < g.k && j0 + j < g.n)
-                            ? g.B[(int64_t)(k0 + k2) * g.brs + (int64_t)(j0 + j) * g.bcs]
-                            : Z{0, 0};
+            Z bv = (k0 + k2 < g.k && j0 + j < g.n)
+                       ? g.B[(int64_t)(k0 + k2) * g.brs + (int64_t)(j0 + j) * g.bcs]
+                       : Z{0, 0};
+            if (g.conjb) bv.im = -bv.im;
+            sb[k2][j] = bv;
         }
         __syncthreads();
 #pragma unroll
@@ -149,6 +155,40 @@ __global__ void lu_fill_kernel(Z *dst, int64_t drs, int64_t dcs, int32_t m, int3
         const int64_t i = q % m, j = q / m;
         dst[i * drs + j * dcs] = i == j ? diag : Z{0, 0};
     }
+}
+
+// om[e] = gauss_at(seed, e), e < count.
+__global__ void lu_gauss_kernel(Z *__restrict__ om, int64_t count, uint64_t seed) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < count;
+         e += (int64_t)gridDim.x * blockDim.x)
+        om[e] = gauss_at(seed, (uint64_t)e);
+}
+
+// Per item: Re sum_e a[e] conj(b[e]) over `count` entries, one workgroup each.
+struct DotItem {
+    const Z *a, *b;
+    int64_t count;
+};
+
+__device__ inline double wave_sum_lu(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__global__ void __launch_bounds__(256) lu_dot_kernel(const DotItem *__restrict__ items,
+                                                     double *__restrict__ out) {
+    const DotItem it = items[blockIdx.x];
+    double s = 0;
+    for (int64_t e = threadIdx.x; e < it.count; e += 256) {
+        const Z x = it.a[e], y = it.b[e];
+        s += x.re * y.re + x.im * y.im;
+    }
+    __shared__ double red[4];
+    s = wave_sum_lu(s);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) out[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
 // Dense tile of the H-matrix (padded leaf-segment rows, storage type S) to a
@@ -321,6 +361,7 @@ struct hm_lu {
     hm::DeviceBuf d_perm, d_zero_rowpad, d_flag;
     hm_lu_stats stats{};
     hipStream_t st = nullptr;
+    uint64_t rng_calls = 0;   // counter of the range finder's Gaussian draws
 };
 
 namespace hm {
@@ -339,11 +380,120 @@ struct GpuBackend {
     void tmp_release(Mark m) { F.tmp.release(m); }
     hm_lu_stats &stats() { return F.stats; }
 
-    void gemm(DMat C, DMat A, DMat B, Z alpha, bool beta) {
-        GemmArgs g{A.p, A.rs, A.cs, B.p, B.rs, B.cs, C.p, C.rs, C.cs, C.m, C.n, A.n, alpha, beta ? 1 : 0};
+    void gemm(DMat C, DMat A, DMat B, Z alpha, bool beta) { gemm_c(C, A, false, B, false, alpha, beta); }
+    // C = alpha op(A) op(B) (+ C), op = conj when the flag is set
+    void gemm_c(DMat C, DMat A, bool ca, DMat B, bool cb, Z alpha, bool beta) {
+        need(A.m == C.m && B.n == C.n && A.n == B.m, "H-LU: product shapes");
+        if (C.m == 0 || C.n == 0) return;
+        GemmArgs g{A.p, A.rs, A.cs, B.p, B.rs, B.cs, C.p, C.rs, C.cs, C.m, C.n, A.n, alpha,
+                   beta ? 1 : 0, ca ? 1 : 0, cb ? 1 : 0};
         hipLaunchKernelGGL(lu_gemm_kernel, dim3((unsigned)ceil_div(C.m, 64), (unsigned)ceil_div(C.n, 64)),
                            dim3(256), 0, st, g);
         HM_HIP_CHECK(hipGetLastError());
+    }
+    // Re sum a conj(b) per item (synchronous)
+    std::vector<double> dots(const std::vector<DotItem> &items) {
+        std::vector<double> out(items.size());
+        if (items.empty()) return out;
+        DeviceBuf d_items, d_out;
+        d_items.alloc(items.size() * sizeof(DotItem));
+        d_out.alloc(items.size() * sizeof(double));
+        HM_HIP_CHECK(hipMemcpyAsync(d_items.p, items.data(), items.size() * sizeof(DotItem),
+                                    hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL(lu_dot_kernel, dim3((unsigned)items.size()), dim3(256), 0, st,
+                           d_items.as<DotItem>(), d_out.as<double>());
+        HM_HIP_CHECK(hipGetLastError());
+        HM_HIP_CHECK(hipMemcpyAsync(out.data(), d_out.p, out.size() * sizeof(double),
+                                    hipMemcpyDeviceToHost, st));
+        HM_HIP_CHECK(hipStreamSynchronize(st));
+        return out;
+    }
+    // Randomized range finder (Liberty, Woolfe, Martinsson, Rokhlin and Tygert
+    // 2007) in front of the recompression of wide stacks: for B = U V^* with
+    // K > kRandMinK columns, Y = B Omega (s complex Gaussian columns), Q =
+    // orth(Y), Z = B^* Q, accepted when |B|_F^2 - |Z|_F^2 = |B - Q Q^* B|_F^2
+    // <= (eps / 2)^2 |B|_F^2 (s doubles otherwise, up to kRsMaxK and below K);
+    // an accepted item continues as (Q, Z) with s columns.  The recompression
+    // then truncates at eps as before; the Jacobi core shrinks from K to s.
+    static constexpr int32_t kRandMinK = 64;
+    void range_finder(std::vector<lu::RcItem> &items, double eps) {
+        std::vector<size_t> act;
+        for (size_t i = 0; i < items.size(); ++i)
+            if (items[i].K > kRandMinK) act.push_back(i);
+        if (act.empty()) return;
+        const auto cm_ = [](Z *p, int32_t m, int32_t n) { return lu::cm(p, m, n, std::max(m, 1)); };
+        const auto adj = [](DMat X) { return DMat{X.p, X.cs, X.rs, X.n, X.m}; };   // X^T (use with conj)
+        // |B|_F^2 = sum_ij (U^* U)_ij conj((V^* V)_ij)
+        std::vector<DotItem> di;
+        for (size_t a : act) {
+            const lu::RcItem &it = items[a];
+            DMat U = cm_(it.U, it.m, it.K), V = cm_(it.V, it.n, it.K);
+            DMat GU = cm_(F.tmp.alloc((int64_t)it.K * it.K), it.K, it.K);
+            DMat GV = cm_(F.tmp.alloc((int64_t)it.K * it.K), it.K, it.K);
+            gemm_c(GU, adj(U), true, U, false, Z{1, 0}, false);
+            gemm_c(GV, adj(V), true, V, false, Z{1, 0}, false);
+            di.push_back({GU.p, GV.p, (int64_t)it.K * it.K});
+        }
+        const std::vector<double> nb = dots(di);
+        std::vector<int32_t> s(act.size());
+        for (size_t a = 0; a < act.size(); ++a) s[a] = std::min(items[act[a]].K, kRandMinK);
+        std::vector<size_t> live(act.size());
+        for (size_t a = 0; a < act.size(); ++a) live[a] = a;
+        Z *base = F.keep.base();
+        while (!live.empty()) {
+            std::vector<DMat> Q(live.size()), Zm(live.size());
+            std::vector<RsBlk> ob(live.size());
+            for (size_t l = 0; l < live.size(); ++l) {
+                const lu::RcItem &it = items[act[live[l]]];
+                const int32_t k = s[live[l]];
+                DMat U = cm_(it.U, it.m, it.K), V = cm_(it.V, it.n, it.K);
+                DMat Om = cm_(F.tmp.alloc((int64_t)it.n * k), it.n, k);
+                hipLaunchKernelGGL(lu_gauss_kernel, dim3(grid_for((int64_t)it.n * k)), dim3(256), 0, st, Om.p,
+                                   (int64_t)it.n * k, 0x9E3779B97F4A7C15ull * (++F.rng_calls));
+                HM_HIP_CHECK(hipGetLastError());
+                DMat T = cm_(F.tmp.alloc((int64_t)it.K * k), it.K, k);
+                gemm_c(T, adj(V), true, Om, false, Z{1, 0}, false);       // V^* Omega
+                Q[l] = cm_(F.tmp.alloc((int64_t)it.m * k), it.m, k);
+                gemm_c(Q[l], U, false, T, false, Z{1, 0}, false);         // Y = U V^* Omega
+                RsBlk d{};
+                d.yoff = Q[l].p - base;
+                d.m = it.m / 3;
+                d.k = k;
+                ob[l] = d;
+            }
+            DeviceBuf d_ob;
+            d_ob.alloc(ob.size() * sizeof(RsBlk));
+            HM_HIP_CHECK(hipMemcpyAsync(d_ob.p, ob.data(), ob.size() * sizeof(RsBlk), hipMemcpyHostToDevice, st));
+            launch_orth(d_ob.as<RsBlk>(), (int32_t)ob.size(), base, st);
+            std::vector<DotItem> dz;
+            for (size_t l = 0; l < live.size(); ++l) {
+                const lu::RcItem &it = items[act[live[l]]];
+                const int32_t k = s[live[l]];
+                DMat U = cm_(it.U, it.m, it.K), V = cm_(it.V, it.n, it.K);
+                DMat P = cm_(F.tmp.alloc((int64_t)it.K * k), it.K, k);
+                gemm_c(P, adj(U), true, Q[l], false, Z{1, 0}, false);      // U^* Q
+                Zm[l] = cm_(F.tmp.alloc((int64_t)it.n * k), it.n, k);
+                gemm_c(Zm[l], V, false, P, false, Z{1, 0}, false);         // Z = V U^* Q = B^* Q
+                dz.push_back({Zm[l].p, Zm[l].p, (int64_t)it.n * k});
+            }
+            const std::vector<double> nz = dots(dz);   // synchronizes: ob outlives its copy
+            std::vector<size_t> next;
+            for (size_t l = 0; l < live.size(); ++l) {
+                const size_t a = live[l];
+                lu::RcItem &it = items[act[a]];
+                const int32_t k = s[a];
+                if (nb[a] - nz[l] <= 0.25 * eps * eps * nb[a]) {
+                    it.U = Q[l].p;
+                    it.V = Zm[l].p;
+                    it.K = k;
+                    ++F.stats.n_sampled;
+                } else if (2 * k < it.K && 2 * k <= kRsMaxK) {
+                    s[a] = 2 * k;
+                    next.push_back(a);
+                }
+            }
+            live.swap(next);
+        }
     }
     void copy(DMat dst, DMat src, Z alpha, bool cj, bool acc) {
         hipLaunchKernelGGL(lu_copy_kernel, dim3(grid_for((int64_t)dst.m * dst.n)), dim3(256), 0, st,
@@ -372,6 +522,9 @@ struct GpuBackend {
         // as kEpsFloor.
         constexpr double kEpsFloor = 1e-13;
         const double eps = std::max(eps_lu, kEpsFloor);
+        // |B|_F^2 - |Z|_F^2 certifies the sampled range only where eps^2 stays
+        // well above the rounding of |B|_F^2
+        if (eps >= 1e-6) range_finder(items, eps);
         Z *base = F.keep.base();
         std::vector<RcBlk> rc;
         int64_t goff = 0;

@@ -16,31 +16,16 @@
 
 #include "internal.hpp"
 #include "mfma_gemm.hpp"
+#include "rng.hpp"
 
 namespace hm {
 
-__device__ inline uint64_t splitmix64_at(uint64_t seed, uint64_t i) {
-    uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ull;
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-    return z ^ (z >> 31);
-}
-
-// Omega (rows x k, row-major): entry e = r k + c is
-// sqrt(-2 ln(1 - u1)) e^{2 pi i u2} / sqrt(2) with u1, u2 the 53-bit fractions of
-// SplitMix64 outputs 2e and 2e + 1.
+// Omega (rows x k, row-major): entry e = r k + c is gauss_at(seed, e).
 __global__ void rs_omega_kernel(cplx<double> *__restrict__ om, int64_t rows, int k,
                                 uint64_t seed) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= rows * k) return;
-    const uint64_t x1 = splitmix64_at(seed, 2 * (uint64_t)e);
-    const uint64_t x2 = splitmix64_at(seed, 2 * (uint64_t)e + 1);
-    const double u1 = (double)(x1 >> 11) * 0x1.0p-53;
-    const double u2 = (double)(x2 >> 11) * 0x1.0p-53;
-    const double g = sqrt(-2.0 * log1p(-u1)) * 0.70710678118654752;
-    double s, c;
-    sincospi(2.0 * u2, &s, &c);
-    om[e] = {g * c, g * s};
+    om[e] = gauss_at(seed, (uint64_t)e);
 }
 
 __device__ inline double block_sum256(double v, double *sh) {
@@ -347,6 +332,12 @@ void run_rsvd(const Geometry &g, const GreenParams<R> &gp, std::vector<RsIn> &bl
         HM_HIP_CHECK(hipGetLastError());
         HM_HIP_CHECK(hipStreamSynchronize(st));
     }
+}
+
+void launch_orth(const RsBlk *d_blk, int32_t nblk, cplx<double> *base, hipStream_t st) {
+    if (nblk <= 0) return;
+    hipLaunchKernelGGL(rs_orth_kernel, dim3((unsigned)nblk), dim3(256), 0, st, d_blk, base);
+    HM_HIP_CHECK(hipGetLastError());
 }
 
 template void run_rsvd<float>(const Geometry &, const GreenParams<float> &, std::vector<RsIn> &,

@@ -87,7 +87,8 @@ class LuStats(ctypes.Structure):
                 ("max_rank", ctypes.c_int32), ("n_nodes", ctypes.c_int32),
                 ("n_diag", ctypes.c_int32), ("n_recompressed", ctypes.c_int32),
                 ("n_batches", ctypes.c_int32), ("n_gemm", ctypes.c_int32),
-                ("gemm_flops", ctypes.c_double)]
+                ("gemm_flops", ctypes.c_double), ("n_sampled", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
