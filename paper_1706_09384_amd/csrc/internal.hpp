@@ -129,8 +129,10 @@ struct RsTask {
 
 // In place Q = orth(Y) for every descriptor (Y at base + yoff, 3m x k
 // column-major, k <= kRsMaxK): classical Gram-Schmidt with one
-// reorthogonalisation, dependent columns set to zero; one workgroup each.
-void launch_orth(const RsBlk *d_blk, int32_t nblk, cplx<double> *base, hipStream_t st);
+// reorthogonalisation, dependent columns set to zero; one workgroup each
+// (1024 threads when wide, for calls with few descriptors, else 256).
+void launch_orth(const RsBlk *d_blk, int32_t nblk, cplx<double> *base, hipStream_t st,
+                 bool wide = false);
 
 // Recompression work description.
 struct RcBlk {
@@ -292,7 +294,7 @@ void run_rsvd(const Geometry &g, const GreenParams<R> &gp, std::vector<RsIn> &bl
 template <typename R>
 void run_recompress(const std::vector<RcBlk> &blk, RcBlk *d_blk, const cplx<R> *acaslab,
                     double *work, int32_t *d_newrank, double eps, int32_t rmax, hipStream_t st,
-                    bool unbatched);
+                    bool unbatched, bool wide_small = false);
 
 template <typename R>
 void run_recompress_apply(const std::vector<RcBlk> &blk, RcBlk *d_blk, const cplx<R> *acaslab,

@@ -60,6 +60,8 @@ struct GemmArgs {
     Z alpha;
     int32_t beta;
     int32_t conja, conjb;   // use conj(A) / conj(B) entries
+    int32_t kchunk;         // split-K: slice z of the grid sums k in [z kchunk, (z + 1) kchunk)
+    int64_t zstride;        // and writes its partial product at C + z zstride
 };
 
 __global__ void __launch_bounds__(256) lu_gemm_kernel(GemmArgs g) {
@@ -76,18 +78,19 @@ __global__ void __launch_bounds__(256) lu_gemm_kernel(GemmArgs g) {
 #pragma unroll
         for (int j = 0; j < 2; ++j) p1[i][j] = p2[i][j] = p3[i][j] = mf64x4{0, 0, 0, 0};
     const bool a_rows = g.ars == 1, b_rows = g.brs == 1;
-    for (int k0 = 0; k0 < g.k; k0 += kS) {
+    const int kb = blockIdx.z * g.kchunk, ke = min(g.k, kb + g.kchunk);
+    for (int k0 = kb; k0 < ke; k0 += kS) {
         for (int e = tid; e < kS * kT; e += 256) {
             int i, kk;
             if (a_rows) { i = e % kT; kk = e / kT; } else { kk = e % kS; i = e / kS; }
-            Z av = (i0 + i < g.m && k0 + kk < g.k)
+            Z av = (i0 + i < g.m && k0 + kk < ke)
                        ? g.A[(int64_t)(i0 + i) * g.ars + (int64_t)(k0 + kk) * g.acs]
                        : Z{0, 0};
             if (g.conja) av.im = -av.im;
             sa[kk][i] = av;
             int j, k2;
             if (b_rows) { k2 = e % kS; j = e / kS; } else { j = e % kT; k2 = e / kT; }
-            Z bv = (k0 + k2 < g.k && j0 + j < g.n)
+            Z bv = (k0 + k2 < ke && j0 + j < g.n)
                        ? g.B[(int64_t)(k0 + k2) * g.brs + (int64_t)(j0 + j) * g.bcs]
                        : Z{0, 0};
             if (g.conjb) bv.im = -bv.im;
@@ -124,7 +127,7 @@ __global__ void __launch_bounds__(256) lu_gemm_kernel(GemmArgs g) {
                 const int col = j0 + 32 * wb + 16 * j + l16;
                 if (row < g.m && col < g.n) {
                     const Z v = {p1[i][j][e] - p2[i][j][e], p3[i][j][e] - p1[i][j][e] - p2[i][j][e]};
-                    Z *c = g.C + (int64_t)row * g.crs + (int64_t)col * g.ccs;
+                    Z *c = g.C + blockIdx.z * g.zstride + (int64_t)row * g.crs + (int64_t)col * g.ccs;
                     const Z r = g.alpha * v;
                     *c = g.beta ? *c + r : r;
                 }
@@ -143,6 +146,20 @@ __global__ void lu_copy_kernel(Z *dst, int64_t drs, int64_t dcs, const Z *src, i
         if (cj) v = conj(v);
         v = alpha * v;
         Z *d = dst + i * drs + j * dcs;
+        *d = acc ? *d + v : v;
+    }
+}
+
+// C(i, j) = [C(i, j) +] sum_z P_z(i, j), the split-K partials (m x n,
+// column-major, z = 0 .. nz - 1 in order).
+__global__ void lu_ksum_kernel(Z *dst, int64_t drs, int64_t dcs, const Z *__restrict__ P, int32_t m,
+                               int32_t n, int32_t nz, int32_t acc) {
+    const int64_t tot = (int64_t)m * n;
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < tot;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        Z v = {0, 0};
+        for (int z = 0; z < nz; ++z) v = v + P[z * tot + q];
+        Z *d = dst + (q % m) * drs + (q / m) * dcs;
         *d = acc ? *d + v : v;
     }
 }
@@ -385,11 +402,35 @@ struct GpuBackend {
     void gemm_c(DMat C, DMat A, bool ca, DMat B, bool cb, Z alpha, bool beta) {
         need(A.m == C.m && B.n == C.n && A.n == B.m, "H-LU: product shapes");
         if (C.m == 0 || C.n == 0) return;
-        GemmArgs g{A.p, A.rs, A.cs, B.p, B.rs, B.cs, C.p, C.rs, C.cs, C.m, C.n, A.n, alpha,
-                   beta ? 1 : 0, ca ? 1 : 0, cb ? 1 : 0};
-        hipLaunchKernelGGL(lu_gemm_kernel, dim3((unsigned)ceil_div(C.m, 64), (unsigned)ceil_div(C.n, 64)),
+        const int64_t tiles = ceil_div(C.m, 64) * ceil_div(C.n, 64);
+        // few output tiles over a long inner dimension: split the inner
+        // dimension over the grid's z slices into partial products summed in
+        // slice order afterwards (deterministic)
+        int32_t nz = 1;
+        if (tiles < 64 && A.n >= 1024)
+            nz = (int32_t)std::min<int64_t>({A.n / 256, std::max<int64_t>(1, 256 / tiles), 64});
+        if (nz <= 1) {
+            GemmArgs g{A.p, A.rs, A.cs, B.p, B.rs, B.cs, C.p, C.rs, C.cs, C.m, C.n, A.n, alpha,
+                       beta ? 1 : 0, ca ? 1 : 0, cb ? 1 : 0, A.n, 0};
+            hipLaunchKernelGGL(lu_gemm_kernel, dim3((unsigned)ceil_div(C.m, 64), (unsigned)ceil_div(C.n, 64)),
+                               dim3(256), 0, st, g);
+            HM_HIP_CHECK(hipGetLastError());
+            return;
+        }
+        const int32_t kchunk = (int32_t)(ceil_div(ceil_div(A.n, nz), 16) * 16);
+        nz = (int32_t)ceil_div(A.n, kchunk);
+        const auto mk = F.tmp.mark();
+        const int64_t mn = (int64_t)C.m * C.n;
+        Z *P = F.tmp.alloc(mn * nz);
+        GemmArgs g{A.p, A.rs, A.cs, B.p, B.rs, B.cs, P, 1, C.m, C.m, C.n, A.n, alpha,
+                   0, ca ? 1 : 0, cb ? 1 : 0, kchunk, mn};
+        hipLaunchKernelGGL(lu_gemm_kernel,
+                           dim3((unsigned)ceil_div(C.m, 64), (unsigned)ceil_div(C.n, 64), (unsigned)nz),
                            dim3(256), 0, st, g);
+        hipLaunchKernelGGL(lu_ksum_kernel, dim3(grid_for(mn)), dim3(256), 0, st, C.p, C.rs, C.cs, P,
+                           C.m, C.n, nz, beta ? 1 : 0);
         HM_HIP_CHECK(hipGetLastError());
+        F.tmp.release(mk);
     }
     // Re sum a conj(b) per item (synchronous)
     std::vector<double> dots(const std::vector<DotItem> &items) {
@@ -464,7 +505,7 @@ struct GpuBackend {
             DeviceBuf d_ob;
             d_ob.alloc(ob.size() * sizeof(RsBlk));
             HM_HIP_CHECK(hipMemcpyAsync(d_ob.p, ob.data(), ob.size() * sizeof(RsBlk), hipMemcpyHostToDevice, st));
-            launch_orth(d_ob.as<RsBlk>(), (int32_t)ob.size(), base, st);
+            launch_orth(d_ob.as<RsBlk>(), (int32_t)ob.size(), base, st, true);
             std::vector<DotItem> dz;
             for (size_t l = 0; l < live.size(); ++l) {
                 const lu::RcItem &it = items[act[live[l]]];
@@ -546,7 +587,7 @@ struct GpuBackend {
         d_newrank.alloc(rc.size() * sizeof(int32_t));
         Z *work = F.tmp.alloc(goff);
         run_recompress<double>(rc, d_rc.as<RcBlk>(), base, reinterpret_cast<double *>(work),
-                               d_newrank.as<int32_t>(), eps, 0, st, false);
+                               d_newrank.as<int32_t>(), eps, 0, st, false, rc.size() < 256);
         std::vector<int32_t> keep(rc.size());
         HM_HIP_CHECK(hipMemcpyAsync(keep.data(), d_newrank.p, keep.size() * sizeof(int32_t),
                                     hipMemcpyDeviceToHost, st));

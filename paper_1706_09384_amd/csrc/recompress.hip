@@ -871,7 +871,7 @@ static void split_jacobi(const std::vector<RcBlk> &blk, const std::vector<int32_
 template <typename R>
 void run_recompress(const std::vector<RcBlk> &blk, RcBlk *d_blk, const cplx<R> *acaslab,
                     double *work, int32_t *d_newrank, double eps, int32_t rmax, hipStream_t st,
-                    bool unbatched) {
+                    bool unbatched, bool wide_small) {
     if (blk.empty()) return;
     std::vector<GramItem> items;
     std::vector<int64_t> item0(blk.size() + 1, 0);   // items of block i: item0[i] .. item0[i+1]
@@ -962,8 +962,10 @@ void run_recompress(const std::vector<RcBlk> &blk, RcBlk *d_blk, const cplx<R> *
         const int64_t lds_elems = bytes / (int64_t)sizeof(cplx<double>);
         // ranks above 64 leave room for one workgroup per CU (LDS): give it
         // 1024 threads (more lanes per Jacobi pair and per Cholesky column)
-        auto kern = rmax > 64 ? factor_kernel<R, 1024, 0> : factor_kernel<R, 256, 0>;
-        const unsigned nt = rmax > 64 ? 1024u : 256u;
+        // (wide_small: every class, for callers with few blocks per call)
+        const bool wide = rmax > 64 || wide_small;
+        auto kern = wide ? factor_kernel<R, 1024, 0> : factor_kernel<R, 256, 0>;
+        const unsigned nt = wide ? 1024u : 256u;
         if (unbatched) {
             for (size_t q = q0; q < q1; ++q)
                 hipLaunchKernelGGL(kern, dim3(1), dim3(nt), (size_t)bytes, st, d_blk,
@@ -1037,9 +1039,9 @@ void run_recompress_apply(const std::vector<RcBlk> &blk, RcBlk *d_blk, const cpl
 }
 
 template void run_recompress<float>(const std::vector<RcBlk> &, RcBlk *, const cplx<float> *,
-                                    double *, int32_t *, double, int32_t, hipStream_t, bool);
+                                    double *, int32_t *, double, int32_t, hipStream_t, bool, bool);
 template void run_recompress<double>(const std::vector<RcBlk> &, RcBlk *, const cplx<double> *,
-                                     double *, int32_t *, double, int32_t, hipStream_t, bool);
+                                     double *, int32_t *, double, int32_t, hipStream_t, bool, bool);
 template void run_recompress_apply<float>(const std::vector<RcBlk> &, RcBlk *,
                                           const cplx<float> *, const double *, const int64_t *,
                                           const int64_t *, const int32_t *, cplx<float> *,

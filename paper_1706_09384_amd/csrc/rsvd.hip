@@ -70,10 +70,23 @@ __global__ void __launch_bounds__(256) rs_y_kernel(const RsBlk *__restrict__ blk
 // In place Q = orth(Y), one workgroup per block: classical Gram-Schmidt with
 // one reorthogonalisation per column; a column whose norm falls below 1e-12 of
 // its norm before the projections is numerically dependent and becomes zero.
-__global__ void __launch_bounds__(256) rs_orth_kernel(const RsBlk *__restrict__ blks,
-                                                      cplx<double> *__restrict__ fp) {
+template <int NT>
+__global__ void __launch_bounds__(NT) rs_orth_kernel(const RsBlk *__restrict__ blks,
+                                                     cplx<double> *__restrict__ fp) {
+    constexpr int NW = NT / 64;
     __shared__ cplx<double> coef[kRsMaxK];
-    __shared__ double sh[4];
+    __shared__ double sh[NW];
+    // block-wide sum, partial sums added in wave order
+    auto bsum = [&](double v) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+        __syncthreads();
+        double t = 0;
+        for (int w = 0; w < NW; ++w) t += sh[w];
+        __syncthreads();
+        return t;
+    };
     const RsBlk b = blks[blockIdx.x];
     const int64_t rows = 3 * (int64_t)b.m;
     const int k = b.k;
@@ -82,10 +95,10 @@ __global__ void __launch_bounds__(256) rs_orth_kernel(const RsBlk *__restrict__ 
     for (int j = 0; j < k; ++j) {
         cplx<double> *yj = Y + (int64_t)j * rows;
         double n0 = 0;
-        for (int64_t r = tid; r < rows; r += 256) n0 += abs2(yj[r]);
-        n0 = block_sum256(n0, sh);
+        for (int64_t r = tid; r < rows; r += NT) n0 += abs2(yj[r]);
+        n0 = NT == 256 ? block_sum256(n0, sh) : bsum(n0);
         for (int pass = 0; pass < 2; ++pass) {
-            for (int i = wave; i < j; i += 4) {
+            for (int i = wave; i < j; i += NW) {
                 const cplx<double> *qi = Y + (int64_t)i * rows;
                 double dr = 0, di = 0;
                 for (int64_t r = lane; r < rows; r += 64) {
@@ -101,7 +114,7 @@ __global__ void __launch_bounds__(256) rs_orth_kernel(const RsBlk *__restrict__ 
                 if (lane == 0) coef[i] = {dr, di};
             }
             __syncthreads();
-            for (int64_t r = tid; r < rows; r += 256) {
+            for (int64_t r = tid; r < rows; r += NT) {
                 cplx<double> acc = yj[r];
                 for (int i = 0; i < j; ++i) acc = acc - coef[i] * Y[(int64_t)i * rows + r];
                 yj[r] = acc;
@@ -109,10 +122,10 @@ __global__ void __launch_bounds__(256) rs_orth_kernel(const RsBlk *__restrict__ 
             __syncthreads();
         }
         double n1 = 0;
-        for (int64_t r = tid; r < rows; r += 256) n1 += abs2(yj[r]);
-        n1 = block_sum256(n1, sh);
+        for (int64_t r = tid; r < rows; r += NT) n1 += abs2(yj[r]);
+        n1 = NT == 256 ? block_sum256(n1, sh) : bsum(n1);
         const double sc = (n1 > 1e-24 * n0 && n1 > 0.0) ? 1.0 / sqrt(n1) : 0.0;
-        for (int64_t r = tid; r < rows; r += 256) yj[r] = sc * yj[r];
+        for (int64_t r = tid; r < rows; r += NT) yj[r] = sc * yj[r];
         __syncthreads();
     }
 }
@@ -266,7 +279,7 @@ void run_rsvd(const Geometry &g, const GreenParams<R> &gp, std::vector<RsIn> &bl
         hipLaunchKernelGGL(rs_y_kernel<R>, dim3((unsigned)ty.size()), dim3(256), 0, st,
                            d_desc.as<RsBlk>(), d_ty.as<RsTask>(), d_dense.as<cplx<R>>(),
                            d_om.as<cplx<double>>(), buf->as<cplx<double>>(), d_py.as<double>());
-        hipLaunchKernelGGL(rs_orth_kernel, dim3((unsigned)act.size()), dim3(256), 0, st,
+        hipLaunchKernelGGL(rs_orth_kernel<256>, dim3((unsigned)act.size()), dim3(256), 0, st,
                            d_desc.as<RsBlk>(), buf->as<cplx<double>>());
         hipLaunchKernelGGL(rs_b_kernel<R>, dim3((unsigned)tb.size()), dim3(256), 0, st,
                            d_desc.as<RsBlk>(), d_tb.as<RsTask>(), d_dense.as<cplx<R>>(),
@@ -334,9 +347,12 @@ void run_rsvd(const Geometry &g, const GreenParams<R> &gp, std::vector<RsIn> &bl
     }
 }
 
-void launch_orth(const RsBlk *d_blk, int32_t nblk, cplx<double> *base, hipStream_t st) {
+void launch_orth(const RsBlk *d_blk, int32_t nblk, cplx<double> *base, hipStream_t st, bool wide) {
     if (nblk <= 0) return;
-    hipLaunchKernelGGL(rs_orth_kernel, dim3((unsigned)nblk), dim3(256), 0, st, d_blk, base);
+    if (wide)
+        hipLaunchKernelGGL(rs_orth_kernel<1024>, dim3((unsigned)nblk), dim3(1024), 0, st, d_blk, base);
+    else
+        hipLaunchKernelGGL(rs_orth_kernel<256>, dim3((unsigned)nblk), dim3(256), 0, st, d_blk, base);
     HM_HIP_CHECK(hipGetLastError());
 }
 
