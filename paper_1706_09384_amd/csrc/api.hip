@@ -424,10 +424,11 @@ void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vect
     M->off_a.assign(nb, -1);
     M->off_v.assign(nb, -1);
     // ---- padded row layout: every leaf segment (3 rows per point) is padded
-    // with zero rows to an even count, so that every segment of every column
-    // starts on a 16-byte boundary (complex64 row pairs).  (Padding to whole
-    // 128-byte lines was measured too: no faster, about 10% more storage.)
-    constexpr int32_t kSegRows = 2;
+    // with zero rows to a multiple of kSegRows, so that every segment of every
+    // column starts on a kSegRows-row boundary: 128-byte lines in complex128
+    // (8 rows), 16-byte row pairs in complex64 (2 rows; whole 128-byte lines,
+    // 16 rows, were measured there too: no faster, about 10% more storage).
+    constexpr int32_t kSegRows = sizeof(R) == 8 ? 8 : 2;
     M->rowpad.assign(nx + 1, 0);
     {
         int32_t acc = 0;
