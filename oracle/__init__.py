@@ -29,6 +29,9 @@ Contents, each following the paper (arXiv 1706.09384):
   F / R / H block formats with eps_LU recompression, and the certification
   estimator of Section 3.3.
 * ``mlp_*`` -- FP64 reference of the 6-64-64-1 rank-predictor network.
+* ``bem`` (module, imported as ``oracle.bem``) -- the P1 collocation matrix of
+  the single-layer equation (Section 4) on triangle meshes, its rows applied
+  to a vector, and the closed forms that pin it.
 
 Readings of the paper where it is silent or ambiguous are listed in the
 module-level docstrings of each function and in the design notes.

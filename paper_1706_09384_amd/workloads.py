@@ -227,6 +227,91 @@ def sweep_sphere(n: int, omega: float, kernel: int = KERNEL_U, eps: float = 1e-4
     return w
 
 
+# ---------------------------------------------------------------- meshes
+# The paper's sphere meshes (Section 7.1) have N_c = N / 3 = 2,562, 10,242 and
+# 40,962 vertices (Table max_rank_frequency), the vertex counts 10 4^L + 2 of
+# an icosahedron subdivided L = 4, 5, 6 times.
+
+
+def icosphere(level: int, radius: float = 1.0):
+    """Subdivided icosahedron on the sphere of the given radius.
+
+    Returns (nodes (10 4^level + 2, 3) float64, tri (20 4^level, 3) int32):
+    every subdivision splits each triangle into four at its edge midpoints,
+    which are pushed out onto the sphere.  Triangles keep one orientation
+    (counter-clockwise seen from outside).
+    """
+    t = (1.0 + math.sqrt(5.0)) / 2.0
+    v = [(-1, t, 0), (1, t, 0), (-1, -t, 0), (1, -t, 0), (0, -1, t), (0, 1, t), (0, -1, -t),
+         (0, 1, -t), (t, 0, -1), (t, 0, 1), (-t, 0, -1), (-t, 0, 1)]
+    f = [(0, 11, 5), (0, 5, 1), (0, 1, 7), (0, 7, 10), (0, 10, 11), (1, 5, 9), (5, 11, 4),
+         (11, 10, 2), (10, 7, 6), (7, 1, 8), (3, 9, 4), (3, 4, 2), (3, 2, 6), (3, 6, 8),
+         (3, 8, 9), (4, 9, 5), (2, 4, 11), (6, 2, 10), (8, 6, 7), (9, 8, 1)]
+    pts = [np.array(p, dtype=np.float64) / np.linalg.norm(p) for p in v]
+    for _ in range(level):
+        mid = {}
+
+        def midpoint(a, b):
+            key = (min(a, b), max(a, b))
+            if key not in mid:
+                m = pts[a] + pts[b]
+                pts.append(m / np.linalg.norm(m))
+                mid[key] = len(pts) - 1
+            return mid[key]
+
+        nf = []
+        for a, b, c in f:
+            ab, bc, ca = midpoint(a, b), midpoint(b, c), midpoint(c, a)
+            nf += [(a, ab, ca), (b, bc, ab), (c, ca, bc), (ab, bc, ca)]
+        f = nf
+    return radius * np.array(pts), np.array(f, dtype=np.int32)
+
+
+def p_wave(nodes: np.ndarray, omega: float, lam: float = 2.0, mu: float = 1.0, rho: float = 1.0,
+           direction=(0.0, 0.0, 1.0)) -> np.ndarray:
+    """Incident plane P wave u_inc(x) = d exp(i kappa_p d.x) sampled at the nodes,
+    interleaved (3 n,) complex128 (the vertical incidence of Section 7.1: d = e_z)."""
+    d = np.asarray(direction, dtype=np.float64)
+    d = d / np.linalg.norm(d)
+    kp = omega * math.sqrt(rho / (lam + 2.0 * mu))
+    ph = np.exp(1j * kp * (nodes @ d))
+    return (ph[:, None] * d[None, :]).ravel()
+
+
+@dataclass
+class Mesh:
+    """A collocation workload: icosphere of the given level, the Section 7.1
+    material, and the tree / tolerance parameters."""
+    name: str
+    level: int
+    omega: float
+    lam: float = 2.0
+    mu: float = 1.0
+    rho: float = 1.0
+    eta: float = 3.0
+    eps: float = 1e-4
+    leaf: int = 100
+    q_reg: int = 3
+    q_sing: int = 6
+
+    def mesh(self):
+        return icosphere(self.level)
+
+    @property
+    def n_nodes(self) -> int:
+        return 10 * 4**self.level + 2
+
+    def rhs(self) -> np.ndarray:
+        return p_wave(self.mesh()[0], self.omega, self.lam, self.mu, self.rho)
+
+
+def bem_sphere(level: int, omega: float = 3.0, eps: float = 1e-4, leaf: int = 100,
+               eta: float = 3.0) -> Mesh:
+    """P1 collocation of the single-layer equation on the unit icosphere (Section 7.1:
+    N_leaf = 100, eta-hat = 3, eps = 1e-4, mu = rho = 1, nu = 1/3)."""
+    return Mesh(f"bem_sphere_L{level}_w{omega:g}", level, omega, eps=eps, leaf=leaf, eta=eta)
+
+
 ALL = {
     "sphere1k": plain_sphere_1k,
     "sphere20k": precision_sphere_20k,
