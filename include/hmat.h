@@ -129,6 +129,36 @@ hm_status hm_build(const double *x, int64_t nx, const double *y, int64_t ny, con
                    const hm_params *p, void *stream, hm_matrix **out);
 
 /*
+ * Assemble the H-matrix of the P1 collocation matrix of the single-layer
+ * equation (Section 4, eqs. EFIE and discre_syst): a mesh of flat triangles,
+ * continuous piecewise-linear hat functions v_j on its vertices, collocation
+ * at the vertices.  Block (i, j) is
+ *     sum over the elements E around vertex j of  int_E U_w(x_i, y) v_j(y) dS(y),
+ * each element integral a collapsed (Duffy) Gauss-Legendre product rule with
+ * q x q points: collapsed onto x_i with q_sing points when x_i is a vertex of
+ * E (the surface Jacobian's factor cancels the 1/r singularity of U), onto
+ * the element's first vertex with q_reg points otherwise.  The clusters, the
+ * admissibility condition, the ACA and the recompression run on the vertices
+ * as in hm_build, with the entry blocks above in place of U_w(x_i, y_j); every
+ * other call (matvec, GMRES, H-LU, hm_frob_error) works on the result.
+ *   nodes   (nc, 3) float64 vertices (the collocation points)
+ *   tri     (ne, 3) int32 vertex indices of the elements, 0-based
+ *   q_reg, q_sing  Gauss-Legendre points per direction, 1 .. 32 (the paper
+ *           names no rule; 3 and 6 are the defaults of the Python binding)
+ *   p       as for hm_build; kernel must be HM_KERNEL_U; same, self_re,
+ *           self_im and rsvd are ignored (the operator is square on the
+ *           vertices and has no point self blocks).  nodes and tri are host
+ *           pointers when p->points_on_host, device pointers otherwise.
+ * Errors: HM_ERR_ARG for a T kernel, nc < 3, ne < 1, an element vertex out of
+ *   range or repeated, a vertex in no element, quadrature orders outside
+ *   1 .. 32, and every hm_build argument error; HM_ERR_ALLOC / HM_ERR_HIP on
+ *   device failure.  Nothing is retained from the caller's arrays.
+ */
+hm_status hm_build_colloc(const double *nodes, int64_t nc, const int32_t *tri, int64_t ne,
+                          int32_t q_reg, int32_t q_sing, const hm_params *p, void *stream,
+                          hm_matrix **out);
+
+/*
  * y = A_H x, Section 3.1 (leaf blocks: dense O(mn), low-rank O(r(m+n))).
  *   x  device, (3 ny, nrhs), complex64 for HM_C64 or complex128 for HM_C128
  *   y  device, (3 nx, nrhs), same type; overwritten.  x and y must not overlap.

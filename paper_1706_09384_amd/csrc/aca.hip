@@ -360,17 +360,21 @@ __device__ inline void row_store(const cplx<R> (&K)[9], cplx<R> *V, int64_t ldv,
 }
 
 // Kernel block A(i^, j) of column point pj and its squared Frobenius norm.
-template <typename R>
+template <typename R, bool Coll>
 __device__ inline double row_kernel_block(const Geometry &g, const GreenParams<R> &gp, bool isT,
-                                          double xi0, double xi1, double xi2, int pj,
+                                          int pi, double xi0, double xi1, double xi2, int pj,
                                           cplx<R> (&K)[9]) {
-    R nx = 0, ny = 0, nz = 0;
-    if (isT) {
-        nx = R(g.n[0][pj]);
-        ny = R(g.n[1][pj]);
-        nz = R(g.n[2][pj]);
+    if constexpr (Coll) {
+        colloc_block<R>(g, gp, pi, pj, K);
+    } else {
+        R nx = 0, ny = 0, nz = 0;
+        if (isT) {
+            nx = R(g.n[0][pj]);
+            ny = R(g.n[1][pj]);
+            nz = R(g.n[2][pj]);
+        }
+        green_block<R>(gp, xi0 - g.y[0][pj], xi1 - g.y[1][pj], xi2 - g.y[2][pj], nx, ny, nz, K);
     }
-    green_block<R>(gp, xi0 - g.y[0][pj], xi1 - g.y[1][pj], xi2 - g.y[2][pj], nx, ny, nz, K);
     double a2 = 0.0;
 #pragma unroll
     for (int e = 0; e < 9; ++e) a2 += (double)abs2(K[e]);
@@ -379,13 +383,13 @@ __device__ inline double row_kernel_block(const Geometry &g, const GreenParams<R
 
 // Residual row entries of column point j (local index; pj in cluster order):
 // the 3x3 block K = A(i^, j) - U(i^, :) V(j, :)^*, stored by row_store.
-template <typename R>
-__device__ inline void row_point(const Geometry &g, const GreenParams<R> &gp, bool isT, double xi0,
-                                 double xi1, double xi2, int pj, int j, const cplx<R> *piv,
-                                 cplx<R> *V, int64_t ldv, int r, bool unused, double nu2,
-                                 Best2 &best) {
+template <typename R, bool Coll>
+__device__ inline void row_point(const Geometry &g, const GreenParams<R> &gp, bool isT, int pi,
+                                 double xi0, double xi1, double xi2, int pj, int j,
+                                 const cplx<R> *piv, cplx<R> *V, int64_t ldv, int r, bool unused,
+                                 double nu2, Best2 &best) {
     cplx<R> K[9];
-    const double a2 = row_kernel_block<R>(g, gp, isT, xi0, xi1, xi2, pj, K);
+    const double a2 = row_kernel_block<R, Coll>(g, gp, isT, pi, xi0, xi1, xi2, pj, K);
     row_terms<R>(K, piv, V + 3 * j, ldv, r, 0, r);
     row_store<R>(K, V, ldv, j, r, unused, nu2, a2, best);
 }
@@ -449,12 +453,15 @@ __device__ inline void col_store(const cplx<R> (&K)[9], cplx<R> *U, int64_t ldu,
 }
 
 // Kernel block A(i, j^) of row point pii and its squared Frobenius norm.
-template <typename R>
+template <typename R, bool Coll>
 __device__ inline double col_kernel_block(const Geometry &g, const GreenParams<R> &gp, int pii,
-                                          double yj0, double yj1, double yj2, R njx, R njy,
-                                          R njz, cplx<R> (&K)[9]) {
-    green_block<R>(gp, g.x[0][pii] - yj0, g.x[1][pii] - yj1, g.x[2][pii] - yj2, njx, njy, njz,
-                   K);
+                                          int pj, double yj0, double yj1, double yj2, R njx,
+                                          R njy, R njz, cplx<R> (&K)[9]) {
+    if constexpr (Coll)
+        colloc_block<R>(g, gp, pii, pj, K);
+    else
+        green_block<R>(gp, g.x[0][pii] - yj0, g.x[1][pii] - yj1, g.x[2][pii] - yj2, njx, njy,
+                       njz, K);
     double a2 = 0.0;
 #pragma unroll
     for (int e = 0; e < 9; ++e) a2 += (double)abs2(K[e]);
@@ -463,18 +470,18 @@ __device__ inline double col_kernel_block(const Geometry &g, const GreenParams<R
 
 // Residual column entries of row point i (local index; pii in cluster order):
 // K = A(i, j^) - U(i, :) V(j^, :)^*, stored by col_store.
-template <typename R>
-__device__ inline void col_point(const Geometry &g, const GreenParams<R> &gp, int pii, double yj0,
-                                 double yj1, double yj2, R njx, R njy, R njz, int i,
+template <typename R, bool Coll>
+__device__ inline void col_point(const Geometry &g, const GreenParams<R> &gp, int pii, int pj,
+                                 double yj0, double yj1, double yj2, R njx, R njy, R njz, int i,
                                  const cplx<R> *piv, cplx<R> *U, int64_t ldu, int r, int p,
                                  const cplx<double> *T, bool unused, double nu2, Best2 &best) {
     cplx<R> K[9];
-    const double a2 = col_kernel_block<R>(g, gp, pii, yj0, yj1, yj2, njx, njy, njz, K);
+    const double a2 = col_kernel_block<R, Coll>(g, gp, pii, pj, yj0, yj1, yj2, njx, njy, njz, K);
     col_terms<R>(K, piv, U + 3 * i, ldu, r, 0, r);
     col_store<R>(K, U, ldu, i, r, p, T, unused, nu2, a2, best);
 }
 
-template <typename R, int NT>
+template <typename R, int NT, bool Coll>
 __global__ void __launch_bounds__(NT)
     aca_kernel(Geometry g, GreenParams<R> gp, const AcaBlk *__restrict__ blks,
                cplx<R> *__restrict__ fac, uint8_t *__restrict__ flags,
@@ -536,8 +543,8 @@ __global__ void __launch_bounds__(NT)
         const double xi0 = g.x[0][pi], xi1 = g.x[1][pi], xi2 = g.x[2][pi];
         Best2 best = {-1.0, INT_MAX, -1.0, INT_MAX};
         for (int j = tid; j < n; j += NT)
-            row_point<R>(g, gp, isT, xi0, xi1, xi2, b.cb + j, j, piv, V, ldv, r, !used_j[j], nu2,
-                         best);
+            row_point<R, Coll>(g, gp, isT, pi, xi0, xi1, xi2, b.cb + j, j, piv, V, ldv, r, !used_j[j],
+                         nu2, best);
         best = block_best2(best, sh_best);
         if (tid == 0) used_i[ih] = 1;
         if (best.ifro == INT_MAX) {  // no unused column left
@@ -590,16 +597,7 @@ __global__ void __launch_bounds__(NT)
             used_j[jh] = 1;
             const int pjh = b.cb + jh;
             cplx<R> K[9];
-            R nx = 0, ny = 0, nz = 0;
-            if (isT) {
-                nx = R(g.n[0][pjh]);
-                ny = R(g.n[1][pjh]);
-                nz = R(g.n[2][pjh]);
-            }
-            green_block<R>(gp, xi0 - g.y[0][pjh], xi1 - g.y[1][pjh], xi2 - g.y[2][pjh], nx, ny,
-                           nz, K);
-            double a2 = 0.0;
-            for (int e = 0; e < 9; ++e) a2 += (double)abs2(K[e]);
+            const double a2 = row_kernel_block<R, Coll>(g, gp, isT, pi, xi0, xi1, xi2, pjh, K);
             sh_anorm = sqrt(a2);
         }
         __syncthreads();
@@ -725,8 +723,8 @@ __global__ void __launch_bounds__(NT)
         }
         best = {-1.0, INT_MAX, -1.0, INT_MAX};
         for (int i = tid; i < m; i += NT)
-            col_point<R>(g, gp, b.rb + i, yj0, yj1, yj2, njx, njy, njz, i, piv, U, ldu, r, p, sh_T,
-                         !used_i[i], nu2, best);
+            col_point<R, Coll>(g, gp, b.rb + i, pj, yj0, yj1, yj2, njx, njy, njz, i, piv, U, ldu, r, p,
+                         sh_T, !used_i[i], nu2, best);
         best = block_best2(best, sh_best);
         int next_i = -1;
         if (best.ifro != INT_MAX)
@@ -943,7 +941,7 @@ __device__ inline void sa_fix_point(cplx<R> *V, int64_t ldv, int j, int r0, int 
 
 // Residual row pass, one workgroup per kSaTile column points.  Wave w of tile
 // t owns Gram slice 4 t + w: V(:, l)^* V(:, r - pq + c) for l < r, c < pq.
-template <typename R>
+template <typename R, bool Coll>
 __global__ void __launch_bounds__(256)
     sa_row_kernel(Geometry g, GreenParams<R> gp, const AcaBlk *__restrict__ blks,
                   const SaState *__restrict__ state, const SaTask *__restrict__ tasks,
@@ -977,7 +975,7 @@ __global__ void __launch_bounds__(256)
     double a2 = 0.0;
     if (in) {
         const int pi = b.rb + ih;
-        a2 = row_kernel_block<R>(g, gp, gp.kind == 1, g.x[0][pi], g.x[1][pi], g.x[2][pi],
+        a2 = row_kernel_block<R, Coll>(g, gp, gp.kind == 1, pi, g.x[0][pi], g.x[1][pi], g.x[2][pi],
                                  b.cb + j, K);
     } else {
 #pragma unroll
@@ -1083,7 +1081,7 @@ __global__ void __launch_bounds__(256)
 
 // Column pivot of the step, one workgroup per block: the row pass's best
 // candidate, the V Gram columns, the pivot block's (pseudo-)inverse.
-template <typename R>
+template <typename R, bool Coll>
 __global__ void __launch_bounds__(256)
     sa_pivot_kernel(Geometry g, GreenParams<R> gp, const AcaBlk *__restrict__ blks,
                     SaState *__restrict__ state, const Best2 *__restrict__ bests,
@@ -1151,16 +1149,8 @@ __global__ void __launch_bounds__(256)
         used_j[jh] = 1;
         const int pi = b.rb + ih, pjh = b.cb + jh;
         cplx<R> K[9];
-        R nx = 0, ny = 0, nz = 0;
-        if (gp.kind == 1) {
-            nx = R(g.n[0][pjh]);
-            ny = R(g.n[1][pjh]);
-            nz = R(g.n[2][pjh]);
-        }
-        green_block<R>(gp, g.x[0][pi] - g.y[0][pjh], g.x[1][pi] - g.y[1][pjh],
-                       g.x[2][pi] - g.y[2][pjh], nx, ny, nz, K);
-        double a2 = 0.0;
-        for (int e = 0; e < 9; ++e) a2 += (double)abs2(K[e]);
+        const double a2 = row_kernel_block<R, Coll>(g, gp, gp.kind == 1, pi, g.x[0][pi], g.x[1][pi],
+                                              g.x[2][pi], pjh, K);
         sh_anorm = sqrt(a2);
         cplx<double> M[9], G[9], Z[9];
         for (int e = 0; e < 9; ++e) M[e] = sh_M[e];
@@ -1246,7 +1236,7 @@ __global__ void __launch_bounds__(256)
 // Residual column pass and U_new, one workgroup per kSaTile row points.  Wave
 // w of tile t owns Gram slice 4 t + w: U(:, l)^* U(:, r - pq + c) for l < r,
 // c < pq.
-template <typename R>
+template <typename R, bool Coll>
 __global__ void __launch_bounds__(256)
     sa_col_kernel(Geometry g, GreenParams<R> gp, const AcaBlk *__restrict__ blks,
                   const SaState *__restrict__ state, const SaTask *__restrict__ tasks,
@@ -1288,8 +1278,8 @@ __global__ void __launch_bounds__(256)
             njy = R(g.n[1][pj]);
             njz = R(g.n[2][pj]);
         }
-        a2 = col_kernel_block<R>(g, gp, b.rb + i, g.y[0][pj], g.y[1][pj], g.y[2][pj], njx, njy,
-                                 njz, K);
+        a2 = col_kernel_block<R, Coll>(g, gp, b.rb + i, pj, g.y[0][pj], g.y[1][pj], g.y[2][pj], njx,
+                                 njy, njz, K);
     } else {
 #pragma unroll
         for (int e = 0; e < 9; ++e) K[e] = {R(0), R(0)};
@@ -1519,15 +1509,21 @@ static void run_aca_split(const Geometry &g, const GreenParams<R> &gp, const Aca
     hipLaunchKernelGGL(sa_init_kernel<R>, dim3((unsigned)nblk), dim3(256), 0, st, d_blk,
                        d_state.as<SaState>(), flags, d_out);
     HM_HIP_CHECK(hipGetLastError());
+    // collocation operators (Section 4) evaluate their entry blocks by element
+    // quadrature; point operators keep kernels without that code
+    const bool coll = g.mesh.tri != nullptr;
+    const auto k_row = coll ? sa_row_kernel<R, true> : sa_row_kernel<R, false>;
+    const auto k_piv = coll ? sa_pivot_kernel<R, true> : sa_pivot_kernel<R, false>;
+    const auto k_col = coll ? sa_col_kernel<R, true> : sa_col_kernel<R, false>;
     int running = 1;
     for (int step = 0; step < maxsteps && running > 0; ++step) {
-        hipLaunchKernelGGL(sa_row_kernel<R>, dim3((unsigned)rowt.size()), dim3(256), lds, st, g,
+        hipLaunchKernelGGL(k_row, dim3((unsigned)rowt.size()), dim3(256), lds, st, g,
                            gp, d_blk, d_state.as<SaState>(), d_row.as<SaTask>(), scratch, flags,
                            bests, d_sab.as<SaBlk>(), nu2, d_parts.as<double>());
-        hipLaunchKernelGGL(sa_pivot_kernel<R>, dim3((unsigned)nblk), dim3(256), 0, st, g, gp,
+        hipLaunchKernelGGL(k_piv, dim3((unsigned)nblk), dim3(256), 0, st, g, gp,
                            d_blk, d_state.as<SaState>(), bests, scratch, flags, d_sab.as<SaBlk>(),
                            d_out, tau_piv, nu2);
-        hipLaunchKernelGGL(sa_col_kernel<R>, dim3((unsigned)colt.size()), dim3(256), lds, st, g,
+        hipLaunchKernelGGL(k_col, dim3((unsigned)colt.size()), dim3(256), lds, st, g,
                            gp, d_blk, d_state.as<SaState>(), d_col.as<SaTask>(), scratch, flags,
                            bests, d_sab.as<SaBlk>(), nu2, d_parts.as<double>());
         hipLaunchKernelGGL(sa_gsum_kernel<0>, dim3((unsigned)(nblk * ngroups)), dim3(256), 0, st,
@@ -1562,6 +1558,7 @@ void run_aca(const Geometry &g, const GreenParams<R> &gp, const std::vector<AcaB
              hipStream_t aux) {
     if (blk.empty()) return;
     const size_t smem = 3 * (size_t)max_budget * (sizeof(cplx<R>) + sizeof(cplx<double>));
+    const auto k_aca = g.mesh.tri ? aca_kernel<R, kAcaThreads, true> : aca_kernel<R, kAcaThreads, false>;
     // Rounding-noise floor of a residual 3x3 block relative to the Frobenius
     // norm of the same block of A: float32 kernel evaluation and updates
     // leave about 1e-6 relative noise (3e-5 keeps a margin), float64 1e-15.
@@ -1583,7 +1580,7 @@ void run_aca(const Geometry &g, const GreenParams<R> &gp, const std::vector<AcaB
                 continue;
             }
             const size_t sm = 3 * (size_t)blk[q].budget * (sizeof(cplx<R>) + sizeof(cplx<double>));
-            hipLaunchKernelGGL((aca_kernel<R, kAcaThreads>), dim3(1), dim3(kAcaThreads), sm, st,
+            hipLaunchKernelGGL(k_aca, dim3(1), dim3(kAcaThreads), sm, st,
                                g, gp, d_blk + q, scratch, flags, d_out + q, eps, tau_piv, nu * nu,
                                blk[q].budget);
         }
@@ -1599,7 +1596,7 @@ void run_aca(const Geometry &g, const GreenParams<R> &gp, const std::vector<AcaB
         HM_HIP_CHECK(hipStreamWaitEvent(s_small, ev0.e, 0));
     }
     if (nbig < blk.size())
-        hipLaunchKernelGGL((aca_kernel<R, kAcaThreads>), dim3((unsigned)(blk.size() - nbig)),
+        hipLaunchKernelGGL(k_aca, dim3((unsigned)(blk.size() - nbig)),
                            dim3(kAcaThreads), smem, s_small, g, gp, d_blk + nbig, scratch, flags,
                            d_out + nbig, eps, tau_piv, nu * nu, max_budget);
     HM_HIP_CHECK(hipGetLastError());

@@ -208,6 +208,16 @@ hm::Geometry hm_matrix::geometry() const {
     const double *nb = base + 3 * nx + (p.same ? 0 : 3 * ny);
     for (int a = 0; a < 3; ++a) g.n[a] = (p.kernel == HM_KERNEL_T) ? nb + a * ny : nullptr;
     g.same = p.same;
+    if (!h_tri.empty() && d_mesh.p) {
+        const int64_t ne = (int64_t)h_tri.size() / 3;
+        const int32_t *mb = d_mesh.as<int32_t>();
+        g.mesh.tri = mb;
+        g.mesh.inc_ptr = mb + 3 * ne;
+        g.mesh.inc = mb + 3 * ne + nx + 1;
+        g.mesh.rule = d_rule.as<double>();
+        g.mesh.nreg = q_reg * q_reg;
+        g.mesh.nsing = q_sing * q_sing;
+    }
     return g;
 }
 
@@ -300,11 +310,129 @@ template <typename R>
 void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vector<double> &Y,
                      const std::vector<double> &Nrm, hipStream_t st);
 
+// Gauss-Legendre nodes and weights on [0, 1]: the roots of the Legendre
+// polynomial P_q by Newton's method from x = cos(pi (i + 3/4) / (q + 1/2)),
+// weights 2 / ((1 - x^2) P_q'(x)^2), both mapped from [-1, 1].
+void gauss_legendre01(int q, std::vector<double> &x, std::vector<double> &w) {
+    x.assign(q, 0.0);
+    w.assign(q, 0.0);
+    for (int i = 0; i < (q + 1) / 2; ++i) {
+        double z = std::cos(M_PI * (i + 0.75) / (q + 0.5)), dp = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = z;
+            for (int k = 2; k <= q; ++k) {
+                const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = q * (z * p1 - p0) / (z * z - 1.0);
+            const double dz = p1 / dp;
+            z -= dz;
+            if (std::fabs(dz) < 1e-16) break;
+        }
+        // recompute P_q' at the converged root
+        {
+            double p0 = 1.0, p1 = z;
+            for (int k = 2; k <= q; ++k) {
+                const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = q * (z * p1 - p0) / (z * z - 1.0);
+        }
+        const double wt = 1.0 / ((1.0 - z * z) * dp * dp);   // half of 2 / (...)
+        x[i] = 0.5 * (1.0 - z);
+        x[q - 1 - i] = 0.5 * (1.0 + z);
+        w[i] = w[q - 1 - i] = wt;
+    }
+}
+
+// Collapsed product rule: (s, t, w_s w_t s) for the q x q Gauss-Legendre points.
+void collapsed_rule(int q, std::vector<double> &out) {
+    std::vector<double> g, w;
+    gauss_legendre01(q, g, w);
+    for (int a = 0; a < q; ++a)
+        for (int b = 0; b < q; ++b) {
+            out.push_back(g[a]);
+            out.push_back(g[b]);
+            out.push_back(w[a] * w[b] * g[a]);
+        }
+}
+
+// Elements (cluster positions), the elements around each vertex and the two
+// quadrature rules of a collocation operator, uploaded for Colloc.
+void upload_mesh(hm_matrix *M, hipStream_t st) {
+    const ClusterTree &tx = M->rowtree();
+    const int64_t nc = M->nx, ne = (int64_t)M->h_tri.size() / 3;
+    std::vector<int32_t> pos(nc);
+    for (int64_t k = 0; k < nc; ++k) pos[tx.perm[k]] = (int32_t)k;
+    std::vector<int32_t> buf(3 * ne + nc + 1 + 3 * ne, 0);
+    int32_t *tri = buf.data(), *ptr = tri + 3 * ne, *inc = ptr + nc + 1;
+    for (int64_t q = 0; q < 3 * ne; ++q) tri[q] = pos[M->h_tri[q]];
+    for (int64_t q = 0; q < 3 * ne; ++q) ++ptr[tri[q] + 1];
+    for (int64_t v = 0; v < nc; ++v) ptr[v + 1] += ptr[v];
+    std::vector<int32_t> fill(ptr, ptr + nc);
+    for (int64_t e = 0; e < ne; ++e)
+        for (int k = 0; k < 3; ++k) inc[fill[tri[3 * e + k]]++] = (int32_t)(4 * e + k);
+    upload(M->d_mesh, buf, st);
+    std::vector<double> rule;
+    collapsed_rule(M->q_reg, rule);
+    collapsed_rule(M->q_sing, rule);
+    upload(M->d_rule, rule, st);
+}
+
+hm_status build_impl(const double *x, int64_t nx, const double *y, int64_t ny,
+                     const double *normals, const hm_params *p, void *stream, hm_matrix **out,
+                     const std::vector<int32_t> *tri, int32_t q_reg, int32_t q_sing);
+
 }  // namespace
 
 extern "C" hm_status hm_build(const double *x, int64_t nx, const double *y, int64_t ny,
                               const double *normals, const hm_params *p, void *stream,
                               hm_matrix **out) {
+    return build_impl(x, nx, y, ny, normals, p, stream, out, nullptr, 0, 0);
+}
+
+extern "C" hm_status hm_build_colloc(const double *nodes, int64_t nc, const int32_t *tri, int64_t ne,
+                                     int32_t q_reg, int32_t q_sing, const hm_params *p,
+                                     void *stream, hm_matrix **out) {
+    if (out) *out = nullptr;
+    hm::set_error("");
+    HM_API_BEGIN
+    require(p != nullptr, "params is NULL");
+    require(p->kernel == HM_KERNEL_U,
+            "collocation operators are built for the single-layer (U) kernel only");
+    require(nodes != nullptr && nc >= 3, "nodes must be non-NULL with nc >= 3");
+    require(tri != nullptr && ne >= 1 && ne < (int64_t)1 << 28, "tri must be non-NULL with ne >= 1");
+    require(q_reg >= 1 && q_reg <= 32 && q_sing >= 1 && q_sing <= 32,
+            "quadrature orders must lie in 1 .. 32");
+    std::vector<int32_t> t(3 * ne);
+    if (p->points_on_host)
+        std::memcpy(t.data(), tri, t.size() * sizeof(int32_t));
+    else
+        HM_HIP_CHECK(hipMemcpy(t.data(), tri, t.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+    std::vector<int32_t> deg(nc, 0);
+    for (int64_t e = 0; e < ne; ++e) {
+        const int32_t a = t[3 * e], b = t[3 * e + 1], c = t[3 * e + 2];
+        require(a >= 0 && a < nc && b >= 0 && b < nc && c >= 0 && c < nc,
+                "element vertex out of range");
+        require(a != b && b != c && a != c, "element with a repeated vertex");
+        ++deg[a], ++deg[b], ++deg[c];
+    }
+    for (int64_t v = 0; v < nc; ++v) require(deg[v] > 0, "a vertex belongs to no element");
+    hm_params q = *p;
+    q.same = 1;
+    q.self_re = q.self_im = 0.0;
+    q.rsvd = 0;
+    return build_impl(nodes, nc, nullptr, nc, nullptr, &q, stream, out, &t, q_reg, q_sing);
+    HM_API_END
+}
+
+namespace {
+
+hm_status build_impl(const double *x, int64_t nx, const double *y, int64_t ny,
+                     const double *normals, const hm_params *p, void *stream, hm_matrix **out,
+                     const std::vector<int32_t> *tri, int32_t q_reg, int32_t q_sing) {
     if (out) *out = nullptr;
     hm::set_error("");
     HM_API_BEGIN
@@ -334,6 +462,11 @@ extern "C" hm_status hm_build(const double *x, int64_t nx, const double *y, int6
     M->nx = nx;
     M->ny = ny;
     M->plan_only = p->plan_only != 0;
+    if (tri) {
+        M->h_tri = *tri;
+        M->q_reg = q_reg;
+        M->q_sing = q_sing;
+    }
     const double t0 = now_s();
     std::vector<double> X = fetch_points(x, nx, on_host, "x");
     std::vector<double> Y, Nrm;
@@ -385,8 +518,6 @@ extern "C" hm_status hm_build(const double *x, int64_t nx, const double *y, int6
     HM_API_END
 }
 
-namespace {
-
 template <typename R>
 void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vector<double> &Y,
                      const std::vector<double> &Nrm, hipStream_t st) {
@@ -413,6 +544,7 @@ void assemble_device(hm_matrix *M, const std::vector<double> &X, const std::vect
         upload(M->geo, h, st);
         upload(M->perm_x, tx.perm, st);
         if (!p.same) upload(M->perm_y, ty.perm, st);
+        if (!M->h_tri.empty()) upload_mesh(M, st);
     }
     const Geometry g = M->geometry();
     const GreenParams<R> gp = make_green_params<R>(p.kernel, p.omega, p.lambda, p.mu, p.rho);

@@ -107,15 +107,16 @@ __device__ inline void radial_coeffs(R a, R qa, R sa, R ca, R sq, R cq, const Gr
            (sa - a * ca) - g.q2 * (sq - qa * cq) - R(2) * B.im};
 }
 
-// 3x3 block, row-major out[3a + b].  d = x - y (nonzero, FP64), n = unit
-// normal at y.
+// Direction dh = d / r, 1 / r and the radial coefficients at d = x - y.
 template <typename R>
-__device__ inline void green_block(const GreenParams<R> &g, double dx, double dy, double dz, R nx,
-                                   R ny, R nz, cplx<R> out[9]) {
+__device__ inline void radial_at(const GreenParams<R> &g, double dx, double dy, double dz, R (&d)[3],
+                                 R &ir, cplx<R> &A, cplx<R> &B, cplx<R> &aAp, cplx<R> &aBp) {
     const double rd = sqrt(dx * dx + dy * dy + dz * dz);
     const double ird = 1.0 / rd;
-    const R ir = R(ird);
-    const R d[3] = {R(dx * ird), R(dy * ird), R(dz * ird)};
+    ir = R(ird);
+    d[0] = R(dx * ird);
+    d[1] = R(dy * ird);
+    d[2] = R(dz * ird);
     const double ad = g.ks_d * rd, qad = g.q_d * ad;
     R sa, ca, sq, cq;
     if constexpr (sizeof(R) == 4) {
@@ -125,8 +126,17 @@ __device__ inline void green_block(const GreenParams<R> &g, double dx, double dy
         sincos_(R(ad), &sa, &ca);
         sincos_(R(qad), &sq, &cq);
     }
-    cplx<R> A, B, aAp, aBp;
     radial_coeffs<R>(R(ad), R(qad), sa, ca, sq, cq, g, A, B, aAp, aBp);
+}
+
+// 3x3 block, row-major out[3a + b].  d = x - y (nonzero, FP64), n = unit
+// normal at y.
+template <typename R>
+__device__ inline void green_block(const GreenParams<R> &g, double dx, double dy, double dz, R nx,
+                                   R ny, R nz, cplx<R> out[9]) {
+    R d[3], ir;
+    cplx<R> A, B, aAp, aBp;
+    radial_at<R>(g, dx, dy, dz, d, ir, A, B, aAp, aBp);
     if (g.kind == 0) {
         const R s = g.inv4pimu * ir;
         const cplx<R> sA = s * A, sB = s * B;
@@ -179,12 +189,92 @@ inline GreenParams<R> make_green_params(int kind, double omega, double lambda, d
     return g;
 }
 
+// P1 collocation operator (Section 4) on a triangle mesh whose vertices are
+// both the collocation points and the column points.  All vertex numbers are
+// cluster positions.
+struct Colloc {
+    const int32_t *tri;       // 3 vertices per element
+    const int32_t *inc_ptr;   // elements around vertex j: inc[inc_ptr[j] .. inc_ptr[j + 1])
+    const int32_t *inc;       // 4 e + k: element e, whose local vertex k is j
+    const double *rule;       // (s, t, w) triples: nreg regular points, then nsing singular
+    int32_t nreg, nsing;
+};
+
 // Cluster-ordered structure-of-arrays geometry in HBM.
 struct Geometry {
     const double *x[3];   // row points
     const double *y[3];   // column points
     const double *n[3];   // normals at column points (T only)
     int same;
+    Colloc mesh;          // mesh.tri == nullptr: point operator (eq. syst_a)
 };
+
+// Entry block (x_pi, vertex pj) of the collocation operator, row-major K[3a + b]:
+//   sum over the elements e around pj of  int_{E_e} U(x_pi, y) v_pj(y) dS(y),
+// v_pj the hat function of pj.  Each element integral is a collapsed
+// Gauss-Legendre product rule: y = y_c + s (y_{c+1} - y_c) + s t (y_{c+2} -
+// y_{c+1}), dS = s |(y_{c+1} - y_c) x (y_{c+2} - y_{c+1})| ds dt, hat values
+// 1 - s, s (1 - t), s t at y_c, y_{c+1}, y_{c+2}; the rule collapses onto
+// x_pi (singular rule) when x_pi is a vertex of E_e, where the factor s cancels
+// the 1/r of U, and onto the element's first vertex (regular rule) otherwise.
+// U is symmetric: six sums are kept.
+template <typename R>
+__device__ inline void colloc_block(const Geometry &g, const GreenParams<R> &gp, int pi, int pj,
+                                    cplx<R> (&K)[9]) {
+    const Colloc &m = g.mesh;
+    const double x0 = g.x[0][pi], x1 = g.x[1][pi], x2 = g.x[2][pi];
+    cplx<R> S[6];   // xx, yy, zz, xy, xz, yz
+#pragma unroll
+    for (int u = 0; u < 6; ++u) S[u] = {R(0), R(0)};
+    const int32_t q1 = m.inc_ptr[pj + 1];
+    for (int32_t q = m.inc_ptr[pj]; q < q1; ++q) {
+        const int32_t ek = m.inc[q];
+        const int32_t e = ek >> 2, k = ek & 3;
+        const int32_t v0 = m.tri[3 * e], v1 = m.tri[3 * e + 1], v2 = m.tri[3 * e + 2];
+        const int c = v0 == pi ? 0 : v1 == pi ? 1 : v2 == pi ? 2 : -1;
+        const bool sing = c >= 0;
+        const int c0 = sing ? c : 0;
+        const int32_t va = c0 == 0 ? v0 : c0 == 1 ? v1 : v2;
+        const int32_t vb = c0 == 0 ? v1 : c0 == 1 ? v2 : v0;
+        const int32_t vc = c0 == 0 ? v2 : c0 == 1 ? v0 : v1;
+        const int rel = (k - c0 + 3) % 3;   // position of pj in (va, vb, vc)
+        double a[3], e1[3], e2[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            a[d] = g.y[d][va];
+            e1[d] = g.y[d][vb] - a[d];
+            e2[d] = g.y[d][vc] - g.y[d][vb];
+        }
+        const double cx = e1[1] * e2[2] - e1[2] * e2[1];
+        const double cy = e1[2] * e2[0] - e1[0] * e2[2];
+        const double cz = e1[0] * e2[1] - e1[1] * e2[0];
+        const double two_area = sqrt(cx * cx + cy * cy + cz * cz);
+        const double *rl = m.rule + (sing ? 3 * m.nreg : 0);
+        const int32_t nq = sing ? m.nsing : m.nreg;
+        for (int32_t qq = 0; qq < nq; ++qq) {
+            const double s = rl[3 * qq], t = rl[3 * qq + 1], w = rl[3 * qq + 2];
+            const double st = s * t;
+            const double hat = rel == 0 ? 1.0 - s : rel == 1 ? s - st : st;
+            R d[3], ir;
+            cplx<R> A, B, aAp, aBp;
+            radial_at<R>(gp, x0 - (a[0] + s * e1[0] + st * e2[0]), x1 - (a[1] + s * e1[1] + st * e2[1]),
+                         x2 - (a[2] + s * e1[2] + st * e2[2]), d, ir, A, B, aAp, aBp);
+            const R sc = R(w * two_area * hat) * gp.inv4pimu * ir;
+            const cplx<R> sA = sc * A, sB = sc * B;
+            S[0] = S[0] + (d[0] * d[0]) * sB + sA;
+            S[1] = S[1] + (d[1] * d[1]) * sB + sA;
+            S[2] = S[2] + (d[2] * d[2]) * sB + sA;
+            S[3] = S[3] + (d[0] * d[1]) * sB;
+            S[4] = S[4] + (d[0] * d[2]) * sB;
+            S[5] = S[5] + (d[1] * d[2]) * sB;
+        }
+    }
+    K[0] = S[0];
+    K[4] = S[1];
+    K[8] = S[2];
+    K[1] = K[3] = S[3];
+    K[2] = K[6] = S[4];
+    K[5] = K[7] = S[5];
+}
 
 }  // namespace hm

@@ -190,6 +190,13 @@ struct hm_matrix {
     std::vector<int64_t> off_a, off_v;    // per block storage offsets
     hm_stats stats{};
 
+    // P1 collocation operator (Section 4): elements in original vertex
+    // numbers and the quadrature orders; empty for a point operator
+    std::vector<int32_t> h_tri;
+    int32_t q_reg = 0, q_sing = 0;
+    hm::DeviceBuf d_mesh;     // int32: elements, incidence pointers, incidence (cluster order)
+    hm::DeviceBuf d_rule;     // float64 (s, t, w) triples: regular, then singular rule
+
     // device data
     hm::DeviceBuf geo;        // 9 SoA float64 arrays (x, y, n)
     hm::DeviceBuf perm_x, perm_y;

@@ -652,14 +652,15 @@ void import_leaves(hm_lu &F, const hm_matrix *A, const std::vector<std::pair<int
 }
 
 // ---------------------------------------------- |A_H - A|_F and |A|_F
-// One thread per point pair (p, q) of a block: the 3 x 3 kernel block is
-// evaluated in FP64 and compared with the stored one (dense tile, or the
-// rows of U and V for a low-rank block).  Partial sums per workgroup.
+// One thread per point pair (p, q) of a block: the 3 x 3 kernel block (or
+// the collocation operator's entry block, Coll) is evaluated in FP64 and
+// compared with the stored one (dense tile, or the rows of U and V for a
+// low-rank block).  Partial sums per workgroup.
 struct FrobTask {
     int32_t slot, kind, p0, np;   // block (dense or low-rank slot), pairs p0 .. p0 + np
 };
 
-template <typename S>
+template <typename S, bool Coll>
 __global__ void __launch_bounds__(256) frob_kernel(Geometry g, GreenParams<double> gp,
                                                    const FrobTask *__restrict__ tasks,
                                                    const DenseBlk *__restrict__ dblk,
@@ -686,7 +687,9 @@ __global__ void __launch_bounds__(256) frob_kernel(Geometry g, GreenParams<doubl
         const int32_t i = pq % m, j = pq / m;
         const int32_t pi = rb + i, pj = cb + j;
         cplx<double> K[9];
-        if (g.same && pi == pj) {
+        if constexpr (Coll) {
+            colloc_block<double>(g, gp, pi, pj, K);
+        } else if (g.same && pi == pj) {
 #pragma unroll
             for (int a = 0; a < 9; ++a) K[a] = {0, 0};
             K[0] = K[4] = K[8] = {self_re, self_im};
@@ -921,14 +924,17 @@ extern "C" hm_status hm_frob_error(const hm_matrix *A, void *stream, double *dif
     const GreenParams<double> gp =
         make_green_params<double>(A->p.kernel, A->p.omega, A->p.lambda, A->p.mu, A->p.rho);
     if (!tasks.empty()) {
+        const bool coll = !A->h_tri.empty();
+        const auto kf = coll ? frob_kernel<float, true> : frob_kernel<float, false>;
+        const auto kd = coll ? frob_kernel<double, true> : frob_kernel<double, false>;
         if (A->p.prec == HM_C64)
-            hipLaunchKernelGGL(frob_kernel<float>, dim3((unsigned)tasks.size()), dim3(256), 0, st,
+            hipLaunchKernelGGL(kf, dim3((unsigned)tasks.size()), dim3(256), 0, st,
                                A->geometry(), gp, d_tasks.as<FrobTask>(), d_d.as<DenseBlk>(),
                                d_l.as<LowRankBlk>(), A->dense.as<cplx<float>>(),
                                A->factors<cplx<float>>(), A->d_rowpad.as<int32_t>(), A->p.self_re,
                                A->p.self_im, part.as<double>());
         else
-            hipLaunchKernelGGL(frob_kernel<double>, dim3((unsigned)tasks.size()), dim3(256), 0, st,
+            hipLaunchKernelGGL(kd, dim3((unsigned)tasks.size()), dim3(256), 0, st,
                                A->geometry(), gp, d_tasks.as<FrobTask>(), d_d.as<DenseBlk>(),
                                d_l.as<LowRankBlk>(), A->dense.as<cplx<double>>(),
                                A->factors<cplx<double>>(), A->d_rowpad.as<int32_t>(), A->p.self_re,

@@ -1,5 +1,6 @@
 // Dense near-field tiles: every non-admissible leaf pair tau x sigma stores
-// the full 3m x 3n block of Green's tensors (Section 3.1, O(mn) part).
+// the full 3m x 3n block of Green's tensors (Section 3.1, O(mn) part), or of
+// the collocation operator's entry blocks (Section 4).
 //
 // One workgroup per tile; threads walk the m*n point pairs with the row
 // point fastest, so that each column of the column-major tile is written by
@@ -10,7 +11,7 @@
 
 namespace hm {
 
-template <typename R>
+template <typename R, bool Coll>
 __global__ void __launch_bounds__(256) nearfield_kernel(Geometry g, GreenParams<R> gp,
                                                         const DenseBlk *__restrict__ blk,
                                                         cplx<R> *__restrict__ slab, R self_re,
@@ -23,7 +24,9 @@ __global__ void __launch_bounds__(256) nearfield_kernel(Geometry g, GreenParams<
         const int32_t i = k % b.m, j = k / b.m;
         const int32_t pi = b.rb + i, pj = b.cb + j;
         cplx<R> K[9];
-        if (g.same && pi == pj) {
+        if constexpr (Coll) {
+            colloc_block<R>(g, gp, pi, pj, K);
+        } else if (g.same && pi == pj) {
 #pragma unroll
             for (int e = 0; e < 9; ++e) K[e] = {R(0), R(0)};
             K[0] = K[4] = K[8] = {self_re, self_im};
@@ -59,15 +62,16 @@ void launch_nearfield(const Geometry &g, const GreenParams<R> &gp, const DenseBl
                       int32_t nblk, cplx<R> *slab, R self_re, R self_im, int32_t *d_err,
                       hipStream_t st, bool unbatched) {
     if (nblk == 0) return;
+    const auto kern = g.mesh.tri ? nearfield_kernel<R, true> : nearfield_kernel<R, false>;
     if (unbatched) {
         // comparison baseline: one launch per tile
         for (int32_t i = 0; i < nblk; ++i)
-            hipLaunchKernelGGL(nearfield_kernel<R>, dim3(1), dim3(256), 0, st, g, gp, d_blk + i,
+            hipLaunchKernelGGL(kern, dim3(1), dim3(256), 0, st, g, gp, d_blk + i,
                                slab, self_re, self_im, d_err);
         HM_HIP_CHECK(hipGetLastError());
         return;
     }
-    hipLaunchKernelGGL(nearfield_kernel<R>, dim3(nblk), dim3(256), 0, st, g, gp, d_blk, slab,
+    hipLaunchKernelGGL(kern, dim3(nblk), dim3(256), 0, st, g, gp, d_blk, slab,
                        self_re, self_im, d_err);
     HM_HIP_CHECK(hipGetLastError());
 }

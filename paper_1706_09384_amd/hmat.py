@@ -125,6 +125,7 @@ def _load():
     sig = {
         "hm_params_default": ([P], i32),
         "hm_build": ([P, i64, P, i64, P, P, P, P], i32),
+        "hm_build_colloc": ([P, i64, P, i64, i32, i32, P, P, P], i32),
         "hm_matvec": ([P, P, P, i32, P], i32),
         "hm_matvec_noalloc": ([P, P, P, i32, P], i32),
         "hm_residual": ([P, P, P, P, i32, P], i32),
@@ -159,7 +160,7 @@ def _load():
 
 
 LIB = _load()
-EXPORTED = ["hm_params_default", "hm_build", "hm_matvec", "hm_matvec_noalloc", "hm_residual", "hm_gmres", "hm_info",
+EXPORTED = ["hm_params_default", "hm_build", "hm_build_colloc", "hm_matvec", "hm_matvec_noalloc", "hm_residual", "hm_gmres", "hm_info",
             "hm_profile_matvec", "hm_profile_matvec_multi", "hm_autotune",
             "hm_export_tree", "hm_export_blocklist", "hm_export_block", "hm_destroy",
             "hm_release_cache",
@@ -506,6 +507,34 @@ def build(x, y=None, normals=None, stream=None, **kw) -> HMatrix:
     rc = LIB.hm_build(_ptr(X), nx, _ptr(Y), ny, _ptr(Nn), ctypes.byref(p), st, ctypes.byref(h))
     _check(rc)
     return HMatrix(h, p)
+
+
+def build_colloc(nodes, tri, q_reg=3, q_sing=6, stream=None, **kw) -> HMatrix:
+    """hm_build_colloc.  nodes (nc, 3) float64 and tri (ne, 3) int32, numpy arrays
+    (host) or cuda tensors (device)."""
+    host = isinstance(nodes, np.ndarray)
+    if host:
+        kw["points_on_host"] = True
+        X = np.ascontiguousarray(nodes, np.float64)
+        T = np.ascontiguousarray(tri, np.int32)
+    else:
+        X, T = nodes.contiguous(), tri.contiguous()
+    kw["same"] = True
+    p = make_params(**kw)
+    h = ctypes.c_void_p()
+    st = ctypes.c_void_p(0) if p.plan_only and stream is None else _stream(stream)
+    _check(LIB.hm_build_colloc(_ptr(X), X.shape[0], _ptr(T), T.shape[0], int(q_reg), int(q_sing),
+                               ctypes.byref(p), st, ctypes.byref(h)))
+    return HMatrix(h, p)
+
+
+def build_mesh(m, prec=C128, **kw) -> HMatrix:
+    """Build the collocation operator of a :class:`workloads.Mesh`."""
+    P, T = m.mesh()
+    args = dict(kernel=0, prec=prec, omega=m.omega, lam=m.lam, mu=m.mu, rho=m.rho, eta=m.eta,
+                eps=m.eps, leaf=m.leaf)
+    args.update(kw)
+    return build_colloc(P, T, m.q_reg, m.q_sing, **args)
 
 
 def build_workload(w, device="cuda", prec=C128, X=None, N=None, **kw) -> HMatrix:
