@@ -591,6 +591,88 @@ def hlu_leg(hmat, W, large=False):
     return rows
 
 
+# The paper's rows for its sphere meshes (Tables max_rank_frequency and
+# error_freq_single; Section 7.1 problem): (DOFs, omega) -> max rank ACA /
+# recompressed at eps 1e-4, and per eps (I, residual, delta_H,F, |x0|/|b|, delta/|b|).
+PAPER_BEM = {
+    (7686, 3.0): {"ranks": (63, 39), 1e-4: (4.64e-4, 9.94e-6, 7.21e-5, 6.37, 4.62e-6),
+                  1e-6: (5.07e-6, 7.35e-8, 7.92e-7, 6.37, 2.48e-8)},
+    (30726, 3.0): {"ranks": (72, 39), 1e-4: (6.37e-4, 1.18e-5, 9.93e-5, 6.36, 5.53e-6),
+                   1e-6: (7.44e-6, 9.38e-8, 1.16e-6, 6.36, 2.93e-8)},
+    (7686, 14.0): {"ranks": (99, 73), 1e-4: (3.89e-3, 1.04e-4, 1.36e-4, 28.15, 4.73e-5),
+                   1e-6: (4.59e-5, 9.15e-7, 1.62e-6, 28.15, 2.03e-7)},
+    (30726, 14.0): {"ranks": (105, 75), 1e-4: (5.49e-3, 1.29e-4, 1.95e-4, 27.88, 5.48e-5),
+                    1e-6: (5.95e-5, 1.15e-6, 2.12e-6, 27.88, 2.44e-7)},
+}
+
+
+def bem_leg(hmat, W, large=False):
+    """P1 collocation of the single-layer equation (Section 4) on icospheres with the
+    paper's vertex counts (2562 and, with --bem-large, 10242: N = 7,686 / 30,726), the
+    Section 7.1 problem (unit sphere, mu = rho = 1, nu = 1/3, vertical incident P wave,
+    N_leaf = 100, eta-hat = 3), omega = 3 and 14, eps_ACA = eps_LU = 1e-4 and 1e-6,
+    complex128.  Per row: assembly time, maximum ACA / recompressed rank, storage rate,
+    |A_H - A|_F (absolute and relative, entries re-evaluated in FP64), the H-LU
+    solution's estimator I, true residual (A applied as an all-dense operator),
+    |x0| / |b| and delta / |b|, GMRES on A_H for comparison, and the paper's printed
+    values for the same (N, omega, eps)."""
+    import torch
+    rows = []
+    levels = [4, 5] if large else [4]
+    for level in levels:
+        for omega in (3.0, 14.0):
+            m0 = W.bem_sphere(level, omega=omega)
+            P, T = m0.mesh()
+            b = torch.from_numpy(W.p_wave(P, omega)).cuda()
+            Hd = hmat.build_mesh(m0, eta=0.0)      # the collocation matrix itself, all dense
+            for eps in (1e-4, 1e-6):
+                m = W.bem_sphere(level, omega=omega, eps=eps)
+                torch.cuda.synchronize()
+                tb = time.perf_counter()
+                H = hmat.build_mesh(m)
+                torch.cuda.synchronize()
+                t_build = time.perf_counter() - tb
+                info = H.info()
+                dh, af = H.frob_error()
+                F = H.lu(eps)
+                st = F.stats()
+                x = F.solve(b)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                x = F.solve(b)
+                torch.cuda.synchronize()
+                t_solve = time.perf_counter() - t0
+                est = H.lu_estimate(b, x, dh)
+                res = float(torch.linalg.vector_norm(Hd.residual(b, x))) / est["b_norm"]
+                tg = time.perf_counter()
+                xg, gi = H.gmres(b, tol=eps, restart=100, maxit=5000, check=False)
+                torch.cuda.synchronize()
+                t_gmres = time.perf_counter() - tg
+                n = 3 * P.shape[0]
+                paper = PAPER_BEM.get((n, omega), {})
+                rec = {"level": level, "N_c": P.shape[0], "dofs": n, "omega": omega, "eps": eps,
+                       "assembly_s": round(t_build, 3),
+                       "max_rank_aca": info["max_rank_aca"], "max_rank": info["max_rank"],
+                       "storage_rate": round((info["dense_entries"] + info["lowrank_entries"]) / n**2, 4),
+                       "delta_HF_abs": dh, "delta_HF_rel": dh / af,
+                       "I_estimate": est["estimate"], "residual_true": res,
+                       "x0_over_b": est["x0_norm"] / est["b_norm"],
+                       "delta_over_b": est["delta"] / est["b_norm"],
+                       "factor_s": round(st["t_factor"], 3), "solve_ms": round(t_solve * 1e3, 2),
+                       "gmres_s": round(t_gmres, 3), "gmres_iters": gi["iters"],
+                       "gmres_relres": gi["relres"],
+                       "paper_max_rank_aca_rc_eps1e-4": paper.get("ranks"),
+                       "paper_I_res_dHF_x0b_db": paper.get(eps)}
+                rows.append(rec)
+                log(f"[bench] bem {rec}")
+                F.close()
+                H.close()
+                hmat.release_cache()
+            Hd.close()
+            hmat.release_cache()
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -608,6 +690,10 @@ def main():
     ap.add_argument("--no-hlu", action="store_true")
     ap.add_argument("--hlu-only", action="store_true", help="run the H-LU leg alone")
     ap.add_argument("--hlu-large", action="store_true", help="add 10242 points to the H-LU leg")
+    ap.add_argument("--no-bem", action="store_true")
+    ap.add_argument("--bem-only", action="store_true", help="run the collocation leg alone")
+    ap.add_argument("--bem-large", action="store_true", help="add the 10242-vertex mesh to the "
+                                                             "collocation leg")
     ap.add_argument("--counters", action="store_true",
                     help="profiling mode: one headline build, the autotuner, 10 matvecs, then a "
                          "256 MiB device copy (x3) whose known byte count calibrates FETCH_SIZE / "
@@ -627,6 +713,9 @@ def main():
         return
     if args.hlu_only:
         print(json.dumps({"hlu": hlu_leg(hmat, W, large=args.hlu_large)}), flush=True)
+        return
+    if args.bem_only:
+        print(json.dumps({"bem": bem_leg(hmat, W, large=args.bem_large)}), flush=True)
         return
 
     w = W.multirhs_sphere_200k()
@@ -775,6 +864,8 @@ def main():
         out["sweep"] = sweep_leg(hmat, W, orc, max_points=170000, max_points_t=170000)
     if not args.no_hlu:
         out["hlu"] = hlu_leg(hmat, W, large=args.hlu_large)
+    if not args.no_bem:
+        out["bem"] = bem_leg(hmat, W, large=args.bem_large)
     print(json.dumps(out), flush=True)
 
 
