@@ -78,15 +78,22 @@ def measured_traffic(kernel):
     return None
 
 
-def sampled_error(orc, w, X, y, b, rows):
-    pb = orc.Problem.from_workload(w, X)
-    ref = orc.matvec_rows(pb, b, rows)
+def exact_rows(H, rows, b):
+    """Rows 3i..3i+2 (i in rows) of the exact operator times b, evaluated in FP64 by the
+    library's direct kernel (hm_exact_rows); shape (3 len(rows), nrhs)."""
+    import torch
+    B = np.ascontiguousarray(b.reshape(b.shape[0], -1), dtype=np.complex128)
+    return H.exact_rows(rows, torch.from_numpy(B).cuda()).cpu().numpy()
+
+
+def sampled_error(H, y, b, rows):
+    ref = exact_rows(H, rows, b)
     idx = (3 * rows[:, None] + np.arange(3)).ravel()
     yy = y.cpu().numpy().astype(np.complex128).reshape(-1, b.shape[1])[idx]
     return float(np.linalg.norm(yy - ref) / np.linalg.norm(ref)), ref
 
 
-def multirhs_leg(hmat, W, orc, H=None):
+def multirhs_leg(hmat, W, H=None):
     """Multi-RHS panels on the 200k-point T workload: 64 right-hand sides on FP32 matrix cores
     (on the given complex64 build of that workload, else a new one)."""
     import torch
@@ -123,8 +130,7 @@ def multirhs_leg(hmat, W, orc, H=None):
             "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s", "traffic": None}
     roof["frac"] = roof["achieved"] / roof["peak"]
     rows = np.random.default_rng(0).choice(w.n_points, 64, replace=False)
-    pb = orc.Problem.from_workload(w, X, N)
-    ref = orc.matvec_rows(pb, B, rows)
+    ref = exact_rows(H, rows, B)
     idx = (3 * rows[:, None] + np.arange(3)).ravel()
     y = Y.cpu().numpy().astype(np.complex128)[idx]
     err = float((np.linalg.norm(y - ref, axis=0) / np.linalg.norm(ref, axis=0)).max())
@@ -133,14 +139,14 @@ def multirhs_leg(hmat, W, orc, H=None):
            "storage_bytes": s["storage_bytes"], "max_rank": s["max_rank"],
            "panel_ms": round(ms, 3), "TFLOPs": round(flops / (ms * 1e-3) / 1e12, 2),
            "kernel_ms": [round(k, 4) for k in kms], "roofline": roof,
-           "err_vs_oracle_sampled_max_over_rhs": err}
+           "err_sampled_rows_max_over_rhs": err}
     log(f"[bench] multirhs {out}")
     if own:
         H.close()
     return out
 
 
-def batching_leg(hmat, W, orc):
+def batching_leg(hmat, W):
     """Batched assembly on the 100k cube (leaf 32 and 64) with autotuned and graph-captured
     matvecs; the per-block (unbatched) baseline on a 10k cube of the same recipe."""
     import torch
@@ -181,7 +187,7 @@ def batching_leg(hmat, W, orc):
         ms1, y = mv_time(H, x)
         s1 = H.info()
         rows = np.random.default_rng(0).choice(w.n_points, 256, replace=False)
-        ref = orc.matvec_rows(orc.Problem.from_workload(w, X, N), b[:, :1], rows)[:, 0]
+        ref = exact_rows(H, rows, b[:, :1])[:, 0]
         idx = (3 * rows[:, None] + np.arange(3)).ravel()
         yy = y.cpu().numpy().astype(np.complex128)[idx]
         H.close()
@@ -209,7 +215,7 @@ def batching_leg(hmat, W, orc):
                      "n_fallback": sr["n_fallback"], "max_rank": sr["max_rank"],
                      "sum_rank": sr["sum_rank"], "storage_bytes": sr["storage_bytes"],
                      "phases_s": {k: round(sr[k], 4) for k in ("t_aca", "t_recompress")},
-                     "err_vs_oracle_sampled": float(np.linalg.norm(yr - ref) / np.linalg.norm(ref))}
+                     "err_sampled_rows": float(np.linalg.norm(yr - ref) / np.linalg.norm(ref))}
         out[f"leaf{leaf}"] = {
             "form": "vector ACA with the singular-pivot fallback for every block (rsvd=0)",
             "assembly_s": round(float(np.median(times[1:])), 4),
@@ -221,7 +227,7 @@ def batching_leg(hmat, W, orc):
             "matvec_ms_graph_default_shape": round(msg, 4),
             "autotuned": {"acc_waves": s1["acc_waves"], "proj_rows": s1["proj_rows"]},
             "matvec_GBps_autotuned": round(s["matvec_bytes"] / (ms1 * 1e-3) / 1e9, 1),
-            "err_vs_oracle_sampled": float(np.linalg.norm(yy - ref) / np.linalg.norm(ref)),
+            "err_sampled_rows": float(np.linalg.norm(yy - ref) / np.linalg.norm(ref)),
             "sum_rank": s["sum_rank"], "rsvd_for_coplanar_blocks": rsvd_form}
         log(f"[bench] batching leaf {leaf}: {out[f'leaf{leaf}']}")
     n = 10000
@@ -279,7 +285,7 @@ def collect_rank_samples(hmat, W):
     return np.concatenate(fs), np.concatenate(rs)
 
 
-def learned_leg(hmat, W, orc):
+def learned_leg(hmat, W):
     """Rank model trained on the 1k and 20k spheres, used on the 50k prolate spheroid."""
     import torch
     t0 = time.perf_counter()
@@ -316,10 +322,9 @@ def learned_leg(hmat, W, orc):
             b = w.rhs()
             y = H.matvec(torch.from_numpy(b).cuda().to(torch.complex64)).cpu().numpy()
             rows = np.random.default_rng(0).choice(w.n_points, 128, replace=False)
-            pb = orc.Problem.from_workload(w, X)
-            ref = orc.matvec_rows(pb, b, rows)
+            ref = exact_rows(H, rows, b)
             idx = (3 * rows[:, None] + np.arange(3)).ravel()
-            res[tag]["err_vs_oracle_sampled"] = float(
+            res[tag]["err_sampled_rows"] = float(
                 np.linalg.norm(y.astype(np.complex128)[idx] - ref) / np.linalg.norm(ref))
         H.close()
     # The same model on a T-kernel workload it was not trained on (100k cube, leaf 32).
@@ -419,7 +424,7 @@ def cpu_oracle_leg(hmat, orc, H, x_host, budget_s=12.0):
     return out
 
 
-def sphere20k_leg(hmat, W, orc, do_gmres=True):
+def sphere20k_leg(hmat, W, do_gmres=True):
     """The 20,000-point U sphere (kappa_s = 25): the complex64 precision form at eps 1e-3,
     1e-4 and 1e-5 (assembly s, matvec GB/s, error each), the plain complex128 form at 1e-4,
     and GMRES with FP64 refinement to 1e-8."""
@@ -448,11 +453,11 @@ def sphere20k_leg(hmat, W, orc, do_gmres=True):
             ms, y = timed_matvecs(H, x)
             s = H.info()
             rows = np.random.default_rng(1).choice(w.n_points, 256, replace=False)
-            err, _ = sampled_error(orc, w, X, y, b, rows)
+            err, _ = sampled_error(H, y, b, rows)
             tag = f"{'c64' if prec == hmat.C64 else 'c128'}_eps{eps:.0e}"
             out[tag] = {"assembly_s": round(float(np.median(times)), 4), "matvec_ms": round(ms, 4),
                         "matvec_GBps": round(s["matvec_bytes"] / (ms * 1e-3) / 1e9, 1),
-                        "err_vs_oracle_sampled": err, "gate": 5 * eps,
+                        "err_sampled_rows": err, "gate": 5 * eps,
                         "max_rank": s["max_rank"], "storage_bytes": s["storage_bytes"],
                         "phases_s": {k: round(s[k], 4) for k in ("t_nearfield", "t_aca",
                                                                  "t_recompress", "t_plan")}}
@@ -478,13 +483,13 @@ def sphere20k_leg(hmat, W, orc, do_gmres=True):
     return out
 
 
-def sweep_leg(hmat, W, orc, max_points=400000, max_points_t=260000, kernels=(0, 1),
+def sweep_leg(hmat, W, max_points=400000, max_points_t=260000, kernels=(0, 1),
               fixed_omega=14.0):
     """Frequency sweeps of the paper's Section 8 on Fibonacci spheres (complex64, eps 1e-4,
     leaf 32): at the fixed density of Table table_corr (omega grows with sqrt(N_c)) and at
     the fixed frequency omega = 14 of Section 7.2.  Per point: maximum ACA and recompressed
     rank, storage, compression rate (stored entries / (3 N_c)^2), assembly seconds and the
-    sampled-row error against the oracle."""
+    sampled-row error against the exact operator (FP64 direct evaluation)."""
     import torch
     res = {"fixed_density": [], "fixed_frequency": []}
     series = [(n, w_) for n, w_ in W.fixed_density_series() if n <= max_points]
@@ -504,7 +509,7 @@ def sweep_leg(hmat, W, orc, max_points=400000, max_points_t=260000, kernels=(0, 
                 b = w.rhs()
                 y = H.matvec(torch.from_numpy(b[:, 0]).cuda().to(torch.complex64))
                 rows = np.random.default_rng(7).choice(n, 32, replace=False)
-                ref = orc.matvec_rows(orc.Problem.from_workload(w, X, N), b, rows)
+                ref = exact_rows(H, rows, b)
                 idx = (3 * rows[:, None] + np.arange(3)).ravel()
                 yy = y.cpu().numpy().astype(np.complex128)[idx]
                 err = float(np.linalg.norm(yy - ref[:, 0]) / np.linalg.norm(ref[:, 0]))
@@ -513,7 +518,7 @@ def sweep_leg(hmat, W, orc, max_points=400000, max_points_t=260000, kernels=(0, 
                        "max_rank_aca": s["max_rank_aca"], "max_rank": s["max_rank"],
                        "storage_bytes": s["storage_bytes"],
                        "compression_rate": round(ent / (3.0 * n) ** 2, 5),
-                       "assembly_s": round(tbuild, 3), "err_vs_oracle_sampled": err,
+                       "assembly_s": round(tbuild, 3), "err_sampled_rows": err,
                        "n_capped": s["n_capped"]}
                 res[key].append(rec)
                 log(f"[bench] sweep {key} {rec}")
@@ -708,8 +713,7 @@ def main():
     from paper_1706_09384_amd import hmat, workloads as W
 
     if args.sweep_only:
-        import oracle as orc
-        print(json.dumps({"sweep": sweep_leg(hmat, W, orc)}), flush=True)
+        print(json.dumps({"sweep": sweep_leg(hmat, W)}), flush=True)
         return
     if args.hlu_only:
         print(json.dumps({"hlu": hlu_leg(hmat, W, large=args.hlu_large)}), flush=True)
@@ -789,10 +793,8 @@ def main():
     roof["algorithmic_bytes"] = int(kbytes[dom])
     log(f"[bench] matvec {mv_ms:.3f} ms, {gbps:.1f} GB/s; kernels ms {kms} bytes {kbytes}")
 
-    import oracle as orc
     rows = np.random.default_rng(1).choice(w.n_points, 64, replace=False)
-    pb = orc.Problem.from_workload(w, X, N)
-    ref = orc.matvec_rows(pb, b, rows)
+    ref = exact_rows(H, rows, b)
     idx = (3 * rows[:, None] + np.arange(3)).ravel()
     yy = y.cpu().numpy().astype(np.complex128).reshape(-1, 1)[idx]
     err = float(np.linalg.norm(yy - ref) / np.linalg.norm(ref))
@@ -813,7 +815,7 @@ def main():
         "matvec_bytes": s["matvec_bytes"],
         "matvec_shape": {"acc_waves": s["acc_waves"], "proj_rows": s["proj_rows"]},
         "kernel_ms": {n: round(k, 4) for n, k in zip(names, kms)},
-        "err_vs_oracle_sampled": err,
+        "err_sampled_rows": err,
         "stats": {k: s[k] for k in ("n_dense", "n_lowrank", "max_rank_aca", "max_rank",
                                     "sum_rank", "storage_bytes", "n_overflow", "n_capped",
                                     "n_fallback", "aca_chunks", "t_tree", "t_nearfield", "t_aca",
@@ -821,6 +823,7 @@ def main():
         "roofline": roof,
     }
     if not args.no_cpu:
+        import oracle as orc   # the CPU baseline is the oracle itself, timed
         out["cpu_baseline"] = cpu_oracle_leg(hmat, orc, H, b[:, 0])
     H.close()
     hmat.release_cache()
@@ -843,25 +846,25 @@ def main():
         out["precision_form_c64"] = {
             "assembly_s": round(asm64, 4), "matvec_ms": round(mv64, 4),
             "matvec_GBps": round(s64["matvec_bytes"] / (mv64 * 1e-3) / 1e9, 1),
-            "storage_bytes": s64["storage_bytes"], "err_vs_oracle_sampled": err64,
+            "storage_bytes": s64["storage_bytes"], "err_sampled_rows": err64,
             "speedup_assembly_vs_c128": round(out["assembly_s"] / asm64, 3),
             "speedup_matvec_vs_c128": round(mv_ms / mv64, 3),
             "phases_s": {k: round(s64[k], 4) for k in ("t_nearfield", "t_aca", "t_recompress")}}
         log(f"[bench] c64 form {out['precision_form_c64']}")
     if not args.no_multirhs:
-        out["multirhs"] = multirhs_leg(hmat, W, orc, H64)
+        out["multirhs"] = multirhs_leg(hmat, W, H64)
     if H64 is not None:
         H64.close()
     hmat.release_cache()
     if not args.no_sphere20k:
-        out["sphere20k"] = sphere20k_leg(hmat, W, orc, do_gmres=not args.no_gmres)
+        out["sphere20k"] = sphere20k_leg(hmat, W, do_gmres=not args.no_gmres)
     if not args.no_learned:
-        out["learned"] = learned_leg(hmat, W, orc)
+        out["learned"] = learned_leg(hmat, W)
     if not args.no_batching:
-        out["batching"] = batching_leg(hmat, W, orc)
+        out["batching"] = batching_leg(hmat, W)
     if not args.no_sweep:
         # up to 163,543 points here; --sweep-only runs the whole table
-        out["sweep"] = sweep_leg(hmat, W, orc, max_points=170000, max_points_t=170000)
+        out["sweep"] = sweep_leg(hmat, W, max_points=170000, max_points_t=170000)
     if not args.no_hlu:
         out["hlu"] = hlu_leg(hmat, W, large=args.hlu_large)
     if not args.no_bem:

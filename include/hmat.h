@@ -414,6 +414,26 @@ void hm_lu_destroy(hm_lu *F);
  */
 hm_status hm_frob_error(const hm_matrix *A, void *stream, double *diff_fro, double *a_fro);
 
+/*
+ * Sampled rows of the exact operator times x, the reference for the error of
+ * the H-matrix product (Section 3.1) on those rows: for each sampled row
+ * point i, y(3r + a, c) = sum_j sum_b K_ab(x_i, y_j) x(3j + b, c), every
+ * entry block evaluated again in FP64 (the Green's tensor of eq. elasto_U /
+ * elasto_T with the self blocks of hm_params, or the collocation operator's
+ * element quadrature of Section 4) and never stored.  O(nrows * ny) kernel
+ * evaluations.
+ *   rows   host, nrows row point indices in the caller's order (0 .. nx - 1)
+ *   x      device complex128, (3 ny, nrhs) row-major, the caller's point order
+ *   y      device complex128, (3 nrows, nrhs) row-major: rows 3r .. 3r + 2 for rows[r]
+ * Whatever the operator's precision, the evaluation and the sums are FP64;
+ * partial sums over column chunks are added in a fixed order (deterministic).
+ * Synchronizes the stream.  Errors: HM_ERR_ARG for NULL pointers, nrows
+ * outside 1 .. 2^20, nrhs outside 1 .. 256, a row index out of range;
+ * HM_ERR_STATE for a plan-only matrix.
+ */
+hm_status hm_exact_rows(const hm_matrix *A, const int64_t *rows, int64_t nrows, const void *x,
+                        int32_t nrhs, void *y, void *stream);
+
 typedef struct {
     double delta;      /* |b - A_H x0|_2 (FP64 residual with the H-matvec) */
     double delta_h;    /* the delta_H passed in */

@@ -17,7 +17,7 @@ LIB = os.path.join(HERE, "libhmat.so")
 ARCH = os.environ.get("HMAT_ARCH", "gfx950")
 
 SOURCES = ["tree.cpp", "api.hip", "nearfield.hip", "aca.hip", "recompress.hip", "matvec.hip",
-           "matvec_mrhs.hip", "gmres.hip", "mlp.hip", "rsvd.hip", "lu.hip"]
+           "matvec_mrhs.hip", "gmres.hip", "mlp.hip", "rsvd.hip", "lu.hip", "exact.hip"]
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-I", INCLUDE, "-I", CSRC, "-Wall", "-Wno-unused-function",
           "-Wno-unused-variable", "-Wno-unused-but-set-variable"]

@@ -150,6 +150,7 @@ def _load():
         "hm_lu_export_dense": ([P, P], i32),
         "hm_lu_destroy": ([P], None),
         "hm_frob_error": ([P, P, P, P], i32),
+        "hm_exact_rows": ([P, P, i64, P, i32, P, P], i32),
         "hm_lu_estimate": ([P, P, P, d, P, P], i32),
     }
     for name, (args, res) in sig.items():
@@ -166,7 +167,7 @@ EXPORTED = ["hm_params_default", "hm_build", "hm_build_colloc", "hm_matvec", "hm
             "hm_release_cache",
             "hm_last_error", "hm_rank_samples", "hm_rank_model_train", "hm_rank_model_predict",
             "hm_rank_model_grad", "hm_lu_factor", "hm_lu_solve", "hm_lu_get_stats",
-            "hm_lu_export_dense", "hm_lu_destroy", "hm_frob_error", "hm_lu_estimate"]
+            "hm_lu_export_dense", "hm_lu_destroy", "hm_frob_error", "hm_lu_estimate", "hm_exact_rows"]
 
 
 def _check(rc):
@@ -328,6 +329,19 @@ class HMatrix:
         d, a = ctypes.c_double(), ctypes.c_double()
         _check(LIB.hm_frob_error(self._h, _stream(stream), ctypes.byref(d), ctypes.byref(a)))
         return d.value, a.value
+
+    def exact_rows(self, rows, x, stream=None):
+        """Rows of the exact operator times x (hm_exact_rows): x complex128 cuda tensor
+        (3 ny,) or (3 ny, nrhs); returns (3 len(rows),) or (3 len(rows), nrhs)."""
+        import torch
+        r = np.ascontiguousarray(rows, np.int64)
+        vec = x.dim() == 1
+        X = x.reshape(x.shape[0], -1).contiguous()
+        assert X.dtype == torch.complex128 and X.shape[0] == 3 * self.ny
+        Y = torch.empty((3 * r.size, X.shape[1]), dtype=torch.complex128, device=X.device)
+        _check(LIB.hm_exact_rows(self._h, _ptr(r), int(r.size), _ptr(X), X.shape[1], _ptr(Y),
+                                 _stream(stream)))
+        return Y.reshape(-1) if vec else Y
 
     def lu_estimate(self, b, x0, delta_h, stream=None) -> dict:
         """Estimator of eq. est_direct for one right-hand side (hm_lu_estimate)."""
