@@ -608,12 +608,51 @@ PAPER_BEM = {
                    1e-6: (4.59e-5, 9.15e-7, 1.62e-6, 28.15, 2.03e-7)},
     (30726, 14.0): {"ranks": (105, 75), 1e-4: (5.49e-3, 1.29e-4, 1.95e-4, 27.88, 5.48e-5),
                     1e-6: (5.95e-5, 1.15e-6, 2.12e-6, 27.88, 2.44e-7)},
+    (122886, 3.0): {"ranks": (75, 39)},
+    (122886, 14.0): {"ranks": (108, 76)},
 }
+
+
+def bem_large_rows(hmat, W, level=6):
+    """The 40,962-vertex icosphere (N = 122,886): operator only (no dense reference or
+    H-LU at this size): ranks, storage, |A_H - A|_F, one matvec and GMRES on the P wave."""
+    import torch
+    rows = []
+    for omega in (3.0, 14.0):
+        m = W.bem_sphere(level, omega=omega)
+        P, T = m.mesh()
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        H = hmat.build_mesh(m)
+        torch.cuda.synchronize()
+        t_build = time.perf_counter() - tb
+        info = H.info()
+        dh, af = H.frob_error()
+        b = torch.from_numpy(W.p_wave(P, omega)).cuda()
+        tg = time.perf_counter()
+        x, gi = H.gmres(b, tol=1e-6, restart=100, maxit=5000, check=False)
+        torch.cuda.synchronize()
+        t_gmres = time.perf_counter() - tg
+        n = 3 * P.shape[0]
+        rec = {"level": level, "N_c": P.shape[0], "dofs": n, "omega": omega, "eps": m.eps,
+               "assembly_s": round(t_build, 3), "max_rank_aca": info["max_rank_aca"],
+               "max_rank": info["max_rank"],
+               "storage_rate": round((info["dense_entries"] + info["lowrank_entries"]) / n**2, 5),
+               "delta_HF_abs": dh, "delta_HF_rel": dh / af,
+               "x_over_b_gmres": float(torch.linalg.vector_norm(x) / torch.linalg.vector_norm(b)),
+               "gmres_s": round(t_gmres, 3), "gmres_iters": gi["iters"], "gmres_relres": gi["relres"],
+               "paper_max_rank_aca_rc_eps1e-4": PAPER_BEM[(n, omega)]["ranks"]}
+        rows.append(rec)
+        log(f"[bench] bem {rec}")
+        H.close()
+        hmat.release_cache()
+    return rows
 
 
 def bem_leg(hmat, W, large=False):
     """P1 collocation of the single-layer equation (Section 4) on icospheres with the
-    paper's vertex counts (2562 and, with --bem-large, 10242: N = 7,686 / 30,726), the
+    paper's vertex counts (2562 and, with --bem-large, 10242 and 40962 (operator rows
+    only): N = 7,686 / 30,726 / 122,886), the
     Section 7.1 problem (unit sphere, mu = rho = 1, nu = 1/3, vertical incident P wave,
     N_leaf = 100, eta-hat = 3), omega = 3 and 14, eps_ACA = eps_LU = 1e-4 and 1e-6,
     complex128.  Per row: assembly time, maximum ACA / recompressed rank, storage rate,
@@ -675,6 +714,8 @@ def bem_leg(hmat, W, large=False):
                 hmat.release_cache()
             Hd.close()
             hmat.release_cache()
+    if large:
+        rows += bem_large_rows(hmat, W)
     return rows
 
 

@@ -373,6 +373,12 @@ typedef struct {
  * columns and eps_lu >= 1e-6, a randomized range finder (Liberty et al. 2007,
  * range error at most eps_lu / 2 in the Frobenius norm) reduces them first.  Dense diagonal leaves are eliminated
  * without pivoting.  Arithmetic is complex128 whatever A's precision.
+ * Independent branches of the recursion (steps 2 and 3, the block columns or
+ * rows of a substitution, the target blocks of an update) run on up to four
+ * streams: the caller's and three created for the call (default priority),
+ * joined back into the caller's stream by events; the environment variable
+ * HM_LU_STREAMS (1 .. 4, default 4) sets the number.  The factors do not
+ * depend on it.
  *   A       an assembled square operator (params.same = 1); read only, and
  *           not needed by the factors afterwards
  *   eps_lu  >= 0; values below 1e-13 act as 1e-13 (singular values at the

@@ -20,6 +20,7 @@
 // (released in stream order).
 #include <algorithm>
 #include <chrono>
+#include <cstdlib>
 #include <memory>
 #include <vector>
 
@@ -374,7 +375,7 @@ struct hm_lu {
     int64_t dofs = 0;
     std::vector<hm::lu::LuNode> nodes;
     hm::Arena keep{size_t(1) << 28};
-    hm::Arena tmp{size_t(1) << 28};
+    hm::Arena tmp{size_t(1) << 28};   // stack of the caller's stream (factor, solve, export)
     hm::DeviceBuf d_perm, d_zero_rowpad, d_flag;
     hm_lu_stats stats{};
     hipStream_t st = nullptr;
@@ -384,18 +385,84 @@ struct hm_lu {
 namespace hm {
 namespace {
 
+// Streams the factorisation spreads independent branches over: the caller's
+// stream and up to kLuStreams - 1 more.
+constexpr int kLuStreams = 4;
+
 // The H-LU's arithmetic on the device: kernels of this file, and the
 // assembly's QR + truncated SVD for the eps_LU recompressions.
+//
+// Independent branches of the recursion (fork / branch / join) run on
+// different streams: branch b of a fork taken on stream p goes to stream
+// (p + b) mod n, which first waits for an event recorded on p at the fork; at
+// the join p waits for an event recorded on every stream a branch used.  Each
+// stream has a stack arena of its own, and a branch allocates only from its
+// stream's arena, so stack memory is reused only in the order of the stream
+// that used it, or after a join that ordered every user before the reuse.
+// Every kernel's operands are the same whatever the schedule, so the factors
+// do not depend on the number of streams.
 struct GpuBackend {
     hm_lu &F;
-    hipStream_t st;
-    using Mark = Arena::Mark;
+    hipStream_t st;   // current stream
+    int cur = 0, nstreams = 1;
+    hipStream_t strm[kLuStreams] = {};
+    Arena *arena[kLuStreams] = {};
+    std::vector<hipEvent_t> *events = nullptr;   // owned by the caller, destroyed after a sync
+
+    GpuBackend(hm_lu &f, hipStream_t s) : F(f), st(s) {
+        strm[0] = s;
+        arena[0] = &f.tmp;
+    }
+    Arena &tmp() { return *arena[cur]; }
+    struct Mark {
+        int a;
+        Arena::Mark m;
+    };
 
     Z *keep_alloc(int64_t n) { return F.keep.alloc(n); }
-    Z *tmp_alloc(int64_t n) { return F.tmp.alloc(n); }
-    Mark tmp_mark() { return F.tmp.mark(); }
-    void tmp_release(Mark m) { F.tmp.release(m); }
+    Z *tmp_alloc(int64_t n) { return tmp().alloc(n); }
+    Mark tmp_mark() { return {cur, tmp().mark()}; }
+    void tmp_release(Mark m) { arena[m.a]->release(m.m); }
     hm_lu_stats &stats() { return F.stats; }
+
+    struct Fork {
+        int parent;
+        hipEvent_t ev;
+        unsigned used;
+    };
+    hipEvent_t new_event() {
+        hipEvent_t e = nullptr;
+        HM_HIP_CHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        events->push_back(e);
+        return e;
+    }
+    Fork fork() {
+        Fork f{cur, nullptr, 0u};
+        if (nstreams > 1) {
+            f.ev = new_event();
+            HM_HIP_CHECK(hipEventRecord(f.ev, strm[cur]));
+        }
+        return f;
+    }
+    void branch(Fork &f, int b) {
+        const int s = (f.parent + b) % nstreams;
+        if (s != f.parent && !((f.used >> s) & 1u)) {
+            HM_HIP_CHECK(hipStreamWaitEvent(strm[s], f.ev, 0));
+            f.used |= 1u << s;
+        }
+        cur = s;
+        st = strm[s];
+    }
+    void join(Fork &f) {
+        for (int s = 0; s < nstreams; ++s)
+            if ((f.used >> s) & 1u) {
+                hipEvent_t e = new_event();
+                HM_HIP_CHECK(hipEventRecord(e, strm[s]));
+                HM_HIP_CHECK(hipStreamWaitEvent(strm[f.parent], e, 0));
+            }
+        cur = f.parent;
+        st = strm[cur];
+    }
 
     void gemm(DMat C, DMat A, DMat B, Z alpha, bool beta) { gemm_c(C, A, false, B, false, alpha, beta); }
     // C = alpha op(A) op(B) (+ C), op = conj when the flag is set
@@ -419,9 +486,10 @@ struct GpuBackend {
         }
         const int32_t kchunk = (int32_t)(ceil_div(ceil_div(A.n, nz), 16) * 16);
         nz = (int32_t)ceil_div(A.n, kchunk);
-        const auto mk = F.tmp.mark();
+        Arena &ar = tmp();
+        const auto mk = ar.mark();
         const int64_t mn = (int64_t)C.m * C.n;
-        Z *P = F.tmp.alloc(mn * nz);
+        Z *P = ar.alloc(mn * nz);
         GemmArgs g{A.p, A.rs, A.cs, B.p, B.rs, B.cs, P, 1, C.m, C.m, C.n, A.n, alpha,
                    0, ca ? 1 : 0, cb ? 1 : 0, kchunk, mn};
         hipLaunchKernelGGL(lu_gemm_kernel,
@@ -430,7 +498,7 @@ struct GpuBackend {
         hipLaunchKernelGGL(lu_ksum_kernel, dim3(grid_for(mn)), dim3(256), 0, st, C.p, C.rs, C.cs, P,
                            C.m, C.n, nz, beta ? 1 : 0);
         HM_HIP_CHECK(hipGetLastError());
-        F.tmp.release(mk);
+        ar.release(mk);
     }
     // Re sum a conj(b) per item (synchronous)
     std::vector<double> dots(const std::vector<DotItem> &items) {
@@ -469,8 +537,8 @@ struct GpuBackend {
         for (size_t a : act) {
             const lu::RcItem &it = items[a];
             DMat U = cm_(it.U, it.m, it.K), V = cm_(it.V, it.n, it.K);
-            DMat GU = cm_(F.tmp.alloc((int64_t)it.K * it.K), it.K, it.K);
-            DMat GV = cm_(F.tmp.alloc((int64_t)it.K * it.K), it.K, it.K);
+            DMat GU = cm_(tmp().alloc((int64_t)it.K * it.K), it.K, it.K);
+            DMat GV = cm_(tmp().alloc((int64_t)it.K * it.K), it.K, it.K);
             gemm_c(GU, adj(U), true, U, false, Z{1, 0}, false);
             gemm_c(GV, adj(V), true, V, false, Z{1, 0}, false);
             di.push_back({GU.p, GV.p, (int64_t)it.K * it.K});
@@ -488,13 +556,13 @@ struct GpuBackend {
                 const lu::RcItem &it = items[act[live[l]]];
                 const int32_t k = s[live[l]];
                 DMat U = cm_(it.U, it.m, it.K), V = cm_(it.V, it.n, it.K);
-                DMat Om = cm_(F.tmp.alloc((int64_t)it.n * k), it.n, k);
+                DMat Om = cm_(tmp().alloc((int64_t)it.n * k), it.n, k);
                 hipLaunchKernelGGL(lu_gauss_kernel, dim3(grid_for((int64_t)it.n * k)), dim3(256), 0, st, Om.p,
                                    (int64_t)it.n * k, 0x9E3779B97F4A7C15ull * (++F.rng_calls));
                 HM_HIP_CHECK(hipGetLastError());
-                DMat T = cm_(F.tmp.alloc((int64_t)it.K * k), it.K, k);
+                DMat T = cm_(tmp().alloc((int64_t)it.K * k), it.K, k);
                 gemm_c(T, adj(V), true, Om, false, Z{1, 0}, false);       // V^* Omega
-                Q[l] = cm_(F.tmp.alloc((int64_t)it.m * k), it.m, k);
+                Q[l] = cm_(tmp().alloc((int64_t)it.m * k), it.m, k);
                 gemm_c(Q[l], U, false, T, false, Z{1, 0}, false);         // Y = U V^* Omega
                 RsBlk d{};
                 d.yoff = Q[l].p - base;
@@ -511,9 +579,9 @@ struct GpuBackend {
                 const lu::RcItem &it = items[act[live[l]]];
                 const int32_t k = s[live[l]];
                 DMat U = cm_(it.U, it.m, it.K), V = cm_(it.V, it.n, it.K);
-                DMat P = cm_(F.tmp.alloc((int64_t)it.K * k), it.K, k);
+                DMat P = cm_(tmp().alloc((int64_t)it.K * k), it.K, k);
                 gemm_c(P, adj(U), true, Q[l], false, Z{1, 0}, false);      // U^* Q
-                Zm[l] = cm_(F.tmp.alloc((int64_t)it.n * k), it.n, k);
+                Zm[l] = cm_(tmp().alloc((int64_t)it.n * k), it.n, k);
                 gemm_c(Zm[l], V, false, P, false, Z{1, 0}, false);         // Z = V U^* Q = B^* Q
                 dz.push_back({Zm[l].p, Zm[l].p, (int64_t)it.n * k});
             }
@@ -585,7 +653,7 @@ struct GpuBackend {
         d_rc.alloc(rc.size() * sizeof(RcBlk));
         HM_HIP_CHECK(hipMemcpyAsync(d_rc.p, rc.data(), rc.size() * sizeof(RcBlk), hipMemcpyHostToDevice, st));
         d_newrank.alloc(rc.size() * sizeof(int32_t));
-        Z *work = F.tmp.alloc(goff);
+        Z *work = tmp().alloc(goff);
         run_recompress<double>(rc, d_rc.as<RcBlk>(), base, reinterpret_cast<double *>(work),
                                d_newrank.as<int32_t>(), eps, 0, st, false, rc.size() < 256);
         std::vector<int32_t> keep(rc.size());
@@ -599,7 +667,7 @@ struct GpuBackend {
             it.keep = keep[i];
             if (!it.keep) continue;
             it.Uout = F.keep.alloc((int64_t)it.m * it.keep);
-            it.Vrow = F.tmp.alloc((int64_t)it.n * lu::even(it.keep));
+            it.Vrow = tmp().alloc((int64_t)it.n * lu::even(it.keep));
             ou[i] = it.Uout - base;
             ov[i] = it.Vrow - base;
         }
@@ -827,18 +895,52 @@ extern "C" hm_status hm_lu_factor(const hm_matrix *A, double eps_lu, void *strea
         import_leaves<double>(*F, A, leaves, leaf_block, st);
     HM_HIP_CHECK(hipStreamSynchronize(st));
     const auto t1 = std::chrono::steady_clock::now();
+    // HM_LU_STREAMS (1 .. kLuStreams) sets the number of streams; the factors are
+    // the same for every value
+    int ns = kLuStreams;
+    if (const char *env = std::getenv("HM_LU_STREAMS")) ns = std::max(1, std::min(kLuStreams, std::atoi(env)));
+    // The extra streams, their stacks and the fork / join events live for this
+    // call; on every exit path the streams are drained before anything is freed.
+    struct Pool {
+        std::vector<hipStream_t> streams;
+        std::vector<hipEvent_t> events;
+        std::vector<std::unique_ptr<Arena>> arenas;
+        size_t bytes = 0;
+        void drain() {
+            for (hipStream_t s : streams) (void)hipStreamSynchronize(s);
+            for (hipEvent_t e : events) (void)hipEventDestroy(e);
+            events.clear();
+            for (auto &a : arenas) bytes += a->total;
+            arenas.clear();
+            for (hipStream_t s : streams) (void)hipStreamDestroy(s);
+            streams.clear();
+        }
+        ~Pool() { drain(); }
+    } pool;
     GpuBackend be{*F, st};
+    be.nstreams = ns;
+    be.events = &pool.events;
+    for (int k = 1; k < ns; ++k) {
+        hipStream_t s = nullptr;
+        HM_HIP_CHECK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+        pool.streams.push_back(s);
+        pool.arenas.push_back(std::make_unique<Arena>(size_t(1) << 28));
+        be.strm[k] = s;
+        be.arena[k] = pool.arenas.back().get();
+    }
     GpuCore c(be, F->nodes, eps_lu);
     c.hlu(0);
+    need(be.cur == 0, "internal: unbalanced fork / join");
     int32_t zp = 0;
     HM_HIP_CHECK(hipMemcpyAsync(&zp, F->d_flag.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     HM_HIP_CHECK(hipStreamSynchronize(st));
+    pool.drain();
     if (zp) throw StatusError(HM_ERR_NOCONV, "zero pivot in a diagonal leaf (elimination without pivoting)");
     const auto t2 = std::chrono::steady_clock::now();
     c.tally(0);
     F->stats.t_import = std::chrono::duration<double>(t1 - t0).count();
     F->stats.t_factor = std::chrono::duration<double>(t2 - t1).count();
-    F->stats.device_bytes = (int64_t)(F->keep.total + F->tmp.total);
+    F->stats.device_bytes = (int64_t)(F->keep.total + F->tmp.total + pool.bytes);
     F->stats.n_nodes = (int32_t)F->nodes.size();
     *out = F.release();
     return HM_OK;

@@ -19,6 +19,10 @@
 //                                       column-major) and Vrow (tmp_alloc,
 //                                       n x even(keep) row-major)
 //   hm_lu_stats &stats()
+//   Fork fork(); void branch(Fork &, int b); void join(Fork &)
+//                                       independent branches of the recursion:
+//                                       branch b's work may run beside the others',
+//                                       join orders everything after them
 //
 // The device library runs it with HIP kernels; the tests also compile it for
 // the CPU with a backend that checks every access against its allocation.
@@ -299,18 +303,25 @@ struct Core {
             const bool ah = A.kind == FMT_H, bh = Bn.kind == FMT_H;
             const int nri = ah ? A.nr : 1, ncj = bh ? Bn.nc : 1, nk = ah ? A.nc : Bn.nr;
             need(!ah || !bh || A.nc == Bn.nr, "H-LU: inner block structure");
-            if (N[c].kind == FMT_H)
+            if (N[c].kind == FMT_H) {
                 need(N[c].nr == nri && N[c].nc == ncj && ro == 0 && co == 0, "H-LU: update structure");
-            for (int i = 0; i < nri; ++i)
-                for (int j = 0; j < ncj; ++j)
-                    for (int k = 0; k < nk; ++k) {
-                        const int ai = ah ? A.ch[i][k] : a, bj = bh ? Bn.ch[k][j] : b;
-                        if (N[c].kind == FMT_H)
-                            muladd(N[c].ch[i][j], 0, 0, ai, bj, alpha);
-                        else
-                            muladd(c, ro + (ah ? A.rofs[i] : 0), co + (bh ? Bn.cofs[j] : 0), ai, bj,
-                                   alpha);
+                // distinct target blocks are independent; the k terms of one
+                // target stay in order
+                auto f = be.fork();
+                for (int i = 0; i < nri; ++i)
+                    for (int j = 0; j < ncj; ++j) {
+                        be.branch(f, i * ncj + j);
+                        for (int k = 0; k < nk; ++k)
+                            muladd(N[c].ch[i][j], 0, 0, ah ? A.ch[i][k] : a, bh ? Bn.ch[k][j] : b, alpha);
                     }
+                be.join(f);
+            } else {
+                for (int i = 0; i < nri; ++i)
+                    for (int j = 0; j < ncj; ++j)
+                        for (int k = 0; k < nk; ++k)
+                            muladd(c, ro + (ah ? A.rofs[i] : 0), co + (bh ? Bn.cofs[j] : 0),
+                                   ah ? A.ch[i][k] : a, bh ? Bn.ch[k][j] : b, alpha);
+            }
         }
     }
 
@@ -377,15 +388,23 @@ struct Core {
             lower_solve(l, dview(Bn));
         } else if (N[l].kind == FMT_F) {
             need(Bn.nr == 1, "H-LU: block row split against a dense diagonal leaf");
-            for (int j = 0; j < Bn.nc; ++j) trsm_lower(l, Bn.ch[0][j]);
+            auto f = be.fork();   // the block columns are independent
+            for (int j = 0; j < Bn.nc; ++j) {
+                be.branch(f, j);
+                trsm_lower(l, Bn.ch[0][j]);
+            }
+            be.join(f);
         } else {
             const LuNode &L = N[l];
             need(Bn.nr == 2, "H-LU: block row not split like its diagonal block");
+            auto f = be.fork();
             for (int j = 0; j < Bn.nc; ++j) {
+                be.branch(f, j);
                 trsm_lower(L.ch[0][0], Bn.ch[0][j]);
                 muladd(Bn.ch[1][j], 0, 0, L.ch[1][0], Bn.ch[0][j], Z{-1, 0});
                 trsm_lower(L.ch[1][1], Bn.ch[1][j]);
             }
+            be.join(f);
         }
     }
     // step 3: B <- B U^-1
@@ -398,15 +417,23 @@ struct Core {
             upper_solve_right(u, dview(Bn));
         } else if (N[u].kind == FMT_F) {
             need(Bn.nc == 1, "H-LU: block column split against a dense diagonal leaf");
-            for (int i = 0; i < Bn.nr; ++i) trsm_upper(u, Bn.ch[i][0]);
+            auto f = be.fork();   // the block rows are independent
+            for (int i = 0; i < Bn.nr; ++i) {
+                be.branch(f, i);
+                trsm_upper(u, Bn.ch[i][0]);
+            }
+            be.join(f);
         } else {
             const LuNode &U = N[u];
             need(Bn.nc == 2, "H-LU: block column not split like its diagonal block");
+            auto f = be.fork();
             for (int i = 0; i < Bn.nr; ++i) {
+                be.branch(f, i);
                 trsm_upper(U.ch[0][0], Bn.ch[i][0]);
                 muladd(Bn.ch[i][1], 0, 0, Bn.ch[i][0], U.ch[0][1], Z{-1, 0});
                 trsm_upper(U.ch[1][1], Bn.ch[i][1]);
             }
+            be.join(f);
         }
     }
 
@@ -423,8 +450,12 @@ struct Core {
         need(X.kind == FMT_H && X.nr == 2 && X.nc == 2, "H-LU: diagonal block not 2 x 2");
         const int a11 = X.ch[0][0], a12 = X.ch[0][1], a21 = X.ch[1][0], a22 = X.ch[1][1];
         hlu(a11);                                   // 1
+        auto f = be.fork();                         // 2 and 3 are independent
+        be.branch(f, 0);
         trsm_lower(a11, a12);                       // 2
+        be.branch(f, 1);
         trsm_upper(a11, a21);                       // 3
+        be.join(f);
         muladd(a22, 0, 0, a21, a12, Z{-1, 0});      // 4
         hlu(a22);
     }

@@ -67,6 +67,11 @@ struct CpuBackend {
         }
     }
     hm_lu_stats &stats() { return st; }
+    // one host thread runs every branch in order: nothing to order
+    struct Fork {};
+    Fork fork() { return {}; }
+    void branch(Fork &, int) {}
+    void join(Fork &) {}
 
     void check(const DMat &v, const char *what) const {
         if (v.m == 0 || v.n == 0) return;

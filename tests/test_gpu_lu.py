@@ -174,3 +174,18 @@ def test_t_kernel_and_complex64_operator(hm):
     e = np.linalg.norm(L @ np.triu(Pk) - AH) / np.linalg.norm(AH)
     say("|LU - A_H| / |A_H|", e, F.stats())
     assert e <= 2e-6
+
+
+@pytest.mark.parametrize("eps_lu", [1e-4, 1e-6])
+def test_streams_do_not_change_the_factors(hm, sphere1k, eps_lu, monkeypatch):
+    """Independent branches run on up to four streams; every kernel's operands are
+    the same whatever the schedule, so one stream and four give identical factors."""
+    w, X, H, A = sphere1k
+    say(f"case lu streams 1 vs 4 eps {eps_lu}")
+    monkeypatch.setenv("HM_LU_STREAMS", "1")
+    P1 = H.lu(eps_lu).export_dense()
+    monkeypatch.setenv("HM_LU_STREAMS", "4")
+    F4 = H.lu(eps_lu)
+    P4 = F4.export_dense()
+    say(F4.stats())
+    assert np.array_equal(P1, P4)
