@@ -5,8 +5,11 @@
  * The library assembles an H-matrix approximation of the dense complex
  * 3Nx x 3Ny matrix of eq. (syst_a), whose 3x3 block (i, j) is the Green's
  * tensor U_w(x_i, y_j) (eq. elasto_U) or its traction T_w(x_i, y_j)
- * (eq. elasto_T, normal taken at y_j), and applies it in matrix-vector
- * products (Section 3.1) and in restarted GMRES.
+ * (eq. elasto_T, normal taken at y_j) -- or of the P1 collocation matrix of
+ * the single-layer equation on a triangle mesh (Section 4, hm_build_colloc)
+ * -- and applies it in matrix-vector products (Section 3.1), in restarted
+ * GMRES, and in the H-LU direct solver with its certification estimator
+ * (Sections 3.2, 3.3).
  *
  * Assembly (hm_build) runs: geometric-bisection cluster trees (Section 2.1),
  * the block partition with the box admissibility condition (Section 6.1,
