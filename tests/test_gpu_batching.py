@@ -96,6 +96,30 @@ def test_unbatched_assembly_is_bit_identical(hm, which):
     same_blocks(H0, H1)
 
 
+@pytest.mark.skip(reason="the persistent form of the one-workgroup ACA stopped making progress on its "
+                         "first GPU run (complex128, 6,000-point sphere) and was taken out of the "
+                         "library: no cause was found by reading it, so it stays off the GPU")
+@pytest.mark.parametrize("prec", [0, 1])
+def test_persistent_aca_is_bit_identical(hm, monkeypatch, prec):
+    """The persistent form of the one-workgroup ACA (a grid of one workgroup per CU
+    taking blocks from an atomic counter, selected by HM_ACA_PERSISTENT=1) would run
+    the same steps on every block as the dispatcher-fed launch: identical factors.
+    Also the collocation operator."""
+    say(f"case persistent ACA prec {prec}")
+    w = W.small_sphere(6000, omega=12.0, leaf=32, eps=1e-5)
+    X, _ = w.points()
+    H0 = hm.build_workload(w, X=X, prec=prec)
+    monkeypatch.setenv("HM_ACA_PERSISTENT", "1")
+    H1 = hm.build_workload(w, X=X, prec=prec)
+    same_blocks(H0, H1)
+    P, T = W.icosphere(3)
+    monkeypatch.delenv("HM_ACA_PERSISTENT")
+    C0 = hm.build_colloc(P, T, omega=3.0, leaf=16, prec=prec)
+    monkeypatch.setenv("HM_ACA_PERSISTENT", "1")
+    C1 = hm.build_colloc(P, T, omega=3.0, leaf=16, prec=prec)
+    same_blocks(C0, C1)
+
+
 def test_autotune_changes_shape_not_result(hm, orc):
     import torch
     say("case autotune sphere20k")
