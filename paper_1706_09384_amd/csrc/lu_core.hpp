@@ -30,6 +30,7 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <initializer_list>
 #include <stdexcept>
 #include <utility>
 #include <vector>
@@ -397,14 +398,23 @@ struct Core {
         } else {
             const LuNode &L = N[l];
             need(Bn.nr == 2, "H-LU: block row not split like its diagonal block");
+            // block column j: B0j <- L00^-1 B0j, B1j -= L10 B0j, B1j <- L11^-1 B1j.  The
+            // columns are independent; the sums that reach every B1j are recompressed
+            // together, between the two halves
             auto f = be.fork();
             for (int j = 0; j < Bn.nc; ++j) {
                 be.branch(f, j);
                 trsm_lower(L.ch[0][0], Bn.ch[0][j]);
                 muladd(Bn.ch[1][j], 0, 0, L.ch[1][0], Bn.ch[0][j], Z{-1, 0});
-                trsm_lower(L.ch[1][1], Bn.ch[1][j]);
             }
             be.join(f);
+            finalize_all({Bn.ch[1][0], Bn.nc > 1 ? Bn.ch[1][1] : -1});
+            auto f2 = be.fork();
+            for (int j = 0; j < Bn.nc; ++j) {
+                be.branch(f2, j);
+                trsm_lower(L.ch[1][1], Bn.ch[1][j]);
+            }
+            be.join(f2);
         }
     }
     // step 3: B <- B U^-1
@@ -426,14 +436,22 @@ struct Core {
         } else {
             const LuNode &U = N[u];
             need(Bn.nc == 2, "H-LU: block column not split like its diagonal block");
+            // block row i: Bi0 <- Bi0 U00^-1, Bi1 -= Bi0 U01, Bi1 <- Bi1 U11^-1, in two
+            // halves around one recompression of every Bi1 (as for the columns above)
             auto f = be.fork();
             for (int i = 0; i < Bn.nr; ++i) {
                 be.branch(f, i);
                 trsm_upper(U.ch[0][0], Bn.ch[i][0]);
                 muladd(Bn.ch[i][1], 0, 0, Bn.ch[i][0], U.ch[0][1], Z{-1, 0});
-                trsm_upper(U.ch[1][1], Bn.ch[i][1]);
             }
             be.join(f);
+            finalize_all({Bn.ch[0][1], Bn.nr > 1 ? Bn.ch[1][1] : -1});
+            auto f2 = be.fork();
+            for (int i = 0; i < Bn.nr; ++i) {
+                be.branch(f2, i);
+                trsm_upper(U.ch[1][1], Bn.ch[i][1]);
+            }
+            be.join(f2);
         }
     }
 
@@ -450,6 +468,7 @@ struct Core {
         need(X.kind == FMT_H && X.nr == 2 && X.nc == 2, "H-LU: diagonal block not 2 x 2");
         const int a11 = X.ch[0][0], a12 = X.ch[0][1], a21 = X.ch[1][0], a22 = X.ch[1][1];
         hlu(a11);                                   // 1
+        finalize_all({a12, a21});                   // the sums steps 2 and 3 read, in one batch
         auto f = be.fork();                         // 2 and 3 are independent
         be.branch(f, 0);
         trsm_lower(a11, a12);                       // 2
@@ -471,6 +490,13 @@ struct Core {
     void finalize(int x) {
         std::vector<int> q;
         collect(x, q);
+        if (!q.empty()) recompress(q);
+    }
+    // the pending sums under several blocks (-1: none), recompressed as one batch
+    void finalize_all(std::initializer_list<int> xs) {
+        std::vector<int> q;
+        for (int x : xs)
+            if (x >= 0) collect(x, q);
         if (!q.empty()) recompress(q);
     }
     // [U, pieces] [W; pieces] -> U' W' at eps_LU.  A block whose stacked
