@@ -30,7 +30,6 @@
 
 #include <algorithm>
 #include <cstdint>
-#include <initializer_list>
 #include <stdexcept>
 #include <utility>
 #include <vector>
@@ -379,82 +378,90 @@ struct Core {
         upper_solve_left(U.ch[0][0], X1);
     }
 
-    // step 2: B <- L^-1 B
-    void trsm_lower(int l, int b) {
-        finalize(b);
-        LuNode &Bn = N[b];
-        if (Bn.kind == FMT_R) {
-            if (Bn.k) lower_solve(l, uview(Bn));
-        } else if (Bn.kind == FMT_F) {
-            lower_solve(l, dview(Bn));
-        } else if (N[l].kind == FMT_F) {
-            need(Bn.nr == 1, "H-LU: block row split against a dense diagonal leaf");
-            auto f = be.fork();   // the block columns are independent
-            for (int j = 0; j < Bn.nc; ++j) {
-                be.branch(f, j);
-                trsm_lower(l, Bn.ch[0][j]);
-            }
-            be.join(f);
-        } else {
-            const LuNode &L = N[l];
-            need(Bn.nr == 2, "H-LU: block row not split like its diagonal block");
-            // block column j: B0j <- L00^-1 B0j, B1j -= L10 B0j, B1j <- L11^-1 B1j.  The
-            // columns are independent; the sums that reach every B1j are recompressed
-            // together, between the two halves
-            auto f = be.fork();
-            for (int j = 0; j < Bn.nc; ++j) {
-                be.branch(f, j);
-                trsm_lower(L.ch[0][0], Bn.ch[0][j]);
-                muladd(Bn.ch[1][j], 0, 0, L.ch[1][0], Bn.ch[0][j], Z{-1, 0});
-            }
-            be.join(f);
-            finalize_all({Bn.ch[1][0], Bn.nc > 1 ? Bn.ch[1][1] : -1});
-            auto f2 = be.fork();
-            for (int j = 0; j < Bn.nc; ++j) {
-                be.branch(f2, j);
-                trsm_lower(L.ch[1][1], Bn.ch[1][j]);
-            }
-            be.join(f2);
+    // Steps 2 and 3 for lists of blocks against the factors held by the
+    // diagonal block d: every block of `lo` (a block row to the right of d)
+    // becomes L^-1 B, every block of `up` (a block column below d) B U^-1.
+    // All blocks of both lists go down d's tree together, so that each level
+    // recompresses the pending sums of all of them in one batch (the blocks
+    // are independent: a sum into one of them reads only blocks of its own
+    // block row or column, and factors).
+    void trsm_multi(int d, const std::vector<int> &lo, const std::vector<int> &up) {
+        {
+            std::vector<int> q;
+            for (int b : lo) collect(b, q);
+            for (int b : up) collect(b, q);
+            if (!q.empty()) recompress(q);
         }
-    }
-    // step 3: B <- B U^-1
-    void trsm_upper(int u, int b) {
-        finalize(b);
-        LuNode &Bn = N[b];
-        if (Bn.kind == FMT_R) {
-            if (Bn.k) upper_solve_right(u, wview(Bn));
-        } else if (Bn.kind == FMT_F) {
-            upper_solve_right(u, dview(Bn));
-        } else if (N[u].kind == FMT_F) {
-            need(Bn.nc == 1, "H-LU: block column split against a dense diagonal leaf");
-            auto f = be.fork();   // the block rows are independent
-            for (int i = 0; i < Bn.nr; ++i) {
-                be.branch(f, i);
-                trsm_upper(u, Bn.ch[i][0]);
+        std::vector<int> hlo, hup;
+        auto f = be.fork();
+        int br = 0;
+        for (int b : lo) {
+            LuNode &Bn = N[b];
+            if (Bn.kind == FMT_H) {
+                hlo.push_back(b);
+            } else if (Bn.kind == FMT_F || Bn.k) {
+                be.branch(f, br++);
+                lower_solve(d, Bn.kind == FMT_F ? dview(Bn) : uview(Bn));
             }
-            be.join(f);
-        } else {
-            const LuNode &U = N[u];
-            need(Bn.nc == 2, "H-LU: block column not split like its diagonal block");
-            // block row i: Bi0 <- Bi0 U00^-1, Bi1 -= Bi0 U01, Bi1 <- Bi1 U11^-1, in two
-            // halves around one recompression of every Bi1 (as for the columns above)
-            auto f = be.fork();
-            for (int i = 0; i < Bn.nr; ++i) {
-                be.branch(f, i);
-                trsm_upper(U.ch[0][0], Bn.ch[i][0]);
-                muladd(Bn.ch[i][1], 0, 0, Bn.ch[i][0], U.ch[0][1], Z{-1, 0});
-            }
-            be.join(f);
-            finalize_all({Bn.ch[0][1], Bn.nr > 1 ? Bn.ch[1][1] : -1});
-            auto f2 = be.fork();
-            for (int i = 0; i < Bn.nr; ++i) {
-                be.branch(f2, i);
-                trsm_upper(U.ch[1][1], Bn.ch[i][1]);
-            }
-            be.join(f2);
         }
+        for (int b : up) {
+            LuNode &Bn = N[b];
+            if (Bn.kind == FMT_H) {
+                hup.push_back(b);
+            } else if (Bn.kind == FMT_F || Bn.k) {
+                be.branch(f, br++);
+                upper_solve_right(d, Bn.kind == FMT_F ? dview(Bn) : wview(Bn));
+            }
+        }
+        be.join(f);
+        if (hlo.empty() && hup.empty()) return;
+        if (N[d].kind == FMT_F) {
+            // a dense diagonal leaf: the subdivided blocks' children in turn
+            std::vector<int> klo, kup;
+            for (int b : hlo) {
+                need(N[b].nr == 1, "H-LU: block row split against a dense diagonal leaf");
+                for (int j = 0; j < N[b].nc; ++j) klo.push_back(N[b].ch[0][j]);
+            }
+            for (int b : hup) {
+                need(N[b].nc == 1, "H-LU: block column split against a dense diagonal leaf");
+                for (int i = 0; i < N[b].nr; ++i) kup.push_back(N[b].ch[i][0]);
+            }
+            trsm_multi(d, klo, kup);
+            return;
+        }
+        // d = [D00 D01; D10 D11] holds L00, L10, L11 and U00, U01, U11:
+        // B0j <- L00^-1 B0j, B1j -= L10 B0j, B1j <- L11^-1 B1j for the rows,
+        // Bi0 <- Bi0 U00^-1, Bi1 -= Bi0 U01, Bi1 <- Bi1 U11^-1 for the columns
+        const LuNode &D = N[d];
+        std::vector<int> lo0, lo1, up0, up1;
+        for (int b : hlo) {
+            need(N[b].nr == 2, "H-LU: block row not split like its diagonal block");
+            for (int j = 0; j < N[b].nc; ++j) {
+                lo0.push_back(N[b].ch[0][j]);
+                lo1.push_back(N[b].ch[1][j]);
+            }
+        }
+        for (int b : hup) {
+            need(N[b].nc == 2, "H-LU: block column not split like its diagonal block");
+            for (int i = 0; i < N[b].nr; ++i) {
+                up0.push_back(N[b].ch[i][0]);
+                up1.push_back(N[b].ch[i][1]);
+            }
+        }
+        trsm_multi(D.ch[0][0], lo0, up0);
+        auto g = be.fork();
+        br = 0;
+        for (size_t k = 0; k < lo0.size(); ++k) {
+            be.branch(g, br++);
+            muladd(lo1[k], 0, 0, D.ch[1][0], lo0[k], Z{-1, 0});
+        }
+        for (size_t k = 0; k < up0.size(); ++k) {
+            be.branch(g, br++);
+            muladd(up1[k], 0, 0, up0[k], D.ch[0][1], Z{-1, 0});
+        }
+        be.join(g);
+        trsm_multi(D.ch[1][1], lo1, up1);
     }
-
     void hlu(int x) {
         LuNode &X = N[x];
         if (X.kind == FMT_F) {
@@ -468,13 +475,7 @@ struct Core {
         need(X.kind == FMT_H && X.nr == 2 && X.nc == 2, "H-LU: diagonal block not 2 x 2");
         const int a11 = X.ch[0][0], a12 = X.ch[0][1], a21 = X.ch[1][0], a22 = X.ch[1][1];
         hlu(a11);                                   // 1
-        finalize_all({a12, a21});                   // the sums steps 2 and 3 read, in one batch
-        auto f = be.fork();                         // 2 and 3 are independent
-        be.branch(f, 0);
-        trsm_lower(a11, a12);                       // 2
-        be.branch(f, 1);
-        trsm_upper(a11, a21);                       // 3
-        be.join(f);
+        trsm_multi(a11, {a12}, {a21});              // 2 and 3, level by level together
         muladd(a22, 0, 0, a21, a12, Z{-1, 0});      // 4
         hlu(a22);
     }
@@ -490,13 +491,6 @@ struct Core {
     void finalize(int x) {
         std::vector<int> q;
         collect(x, q);
-        if (!q.empty()) recompress(q);
-    }
-    // the pending sums under several blocks (-1: none), recompressed as one batch
-    void finalize_all(std::initializer_list<int> xs) {
-        std::vector<int> q;
-        for (int x : xs)
-            if (x >= 0) collect(x, q);
         if (!q.empty()) recompress(q);
     }
     // [U, pieces] [W; pieces] -> U' W' at eps_LU.  A block whose stacked
