@@ -608,67 +608,37 @@ PAPER_BEM = {
                    1e-6: (4.59e-5, 9.15e-7, 1.62e-6, 28.15, 2.03e-7)},
     (30726, 14.0): {"ranks": (105, 75), 1e-4: (5.49e-3, 1.29e-4, 1.95e-4, 27.88, 5.48e-5),
                     1e-6: (5.95e-5, 1.15e-6, 2.12e-6, 27.88, 2.44e-7)},
-    (122886, 3.0): {"ranks": (75, 39)},
-    (122886, 14.0): {"ranks": (108, 76)},
+    (122886, 3.0): {"ranks": (75, 39), 1e-4: (8.14e-4, 1.47e-5, 1.27e-4, 6.36, 5.21e-6),
+                    1e-6: (9.25e-6, 9.82e-8, 1.45e-6, 6.36, 2.76e-8)},
+    (122886, 14.0): {"ranks": (108, 76), 1e-4: (6.24e-3, 1.49e-4, 2.22e-4, 27.82, 5.86e-5),
+                     1e-6: (6.42e-5, 1.26e-6, 2.3e-6, 27.82, 2.52e-7)},
+    (1926, 3.0): {1e-4: (3.25e-15, 3.64e-15, 9.16e-17, 6.4, 2.66e-15),
+                  1e-6: (3.25e-15, 3.64e-15, 9.16e-17, 6.4, 2.66e-15)},
+    (1926, 14.0): {1e-4: (5.69e-15, 4.69e-15, 7.16e-17, 29.29, 3.59e-15),
+                   1e-6: (5.69e-15, 4.69e-15, 7.16e-17, 29.29, 3.59e-15)},
 }
-
-
-def bem_large_rows(hmat, W, level=6):
-    """The 40,962-vertex icosphere (N = 122,886): operator only (no dense reference or
-    H-LU at this size): ranks, storage, |A_H - A|_F, one matvec and GMRES on the P wave."""
-    import torch
-    rows = []
-    for omega in (3.0, 14.0):
-        m = W.bem_sphere(level, omega=omega)
-        P, T = m.mesh()
-        torch.cuda.synchronize()
-        tb = time.perf_counter()
-        H = hmat.build_mesh(m)
-        torch.cuda.synchronize()
-        t_build = time.perf_counter() - tb
-        info = H.info()
-        dh, af = H.frob_error()
-        b = torch.from_numpy(W.p_wave(P, omega)).cuda()
-        tg = time.perf_counter()
-        x, gi = H.gmres(b, tol=1e-6, restart=100, maxit=5000, check=False)
-        torch.cuda.synchronize()
-        t_gmres = time.perf_counter() - tg
-        n = 3 * P.shape[0]
-        rec = {"level": level, "N_c": P.shape[0], "dofs": n, "omega": omega, "eps": m.eps,
-               "assembly_s": round(t_build, 3), "max_rank_aca": info["max_rank_aca"],
-               "max_rank": info["max_rank"],
-               "storage_rate": round((info["dense_entries"] + info["lowrank_entries"]) / n**2, 5),
-               "delta_HF_abs": dh, "delta_HF_rel": dh / af,
-               "x_over_b_gmres": float(torch.linalg.vector_norm(x) / torch.linalg.vector_norm(b)),
-               "gmres_s": round(t_gmres, 3), "gmres_iters": gi["iters"], "gmres_relres": gi["relres"],
-               "paper_max_rank_aca_rc_eps1e-4": PAPER_BEM[(n, omega)]["ranks"]}
-        rows.append(rec)
-        log(f"[bench] bem {rec}")
-        H.close()
-        hmat.release_cache()
-    return rows
 
 
 def bem_leg(hmat, W, large=False):
     """P1 collocation of the single-layer equation (Section 4) on icospheres with the
-    paper's vertex counts (2562 and, with --bem-large, 10242 and 40962 (operator rows
-    only): N = 7,686 / 30,726 / 122,886), the
-    Section 7.1 problem (unit sphere, mu = rho = 1, nu = 1/3, vertical incident P wave,
-    N_leaf = 100, eta-hat = 3), omega = 3 and 14, eps_ACA = eps_LU = 1e-4 and 1e-6,
-    complex128.  Per row: assembly time, maximum ACA / recompressed rank, storage rate,
-    |A_H - A|_F (absolute and relative, entries re-evaluated in FP64), the H-LU
-    solution's estimator I, true residual (A applied as an all-dense operator),
-    |x0| / |b| and delta / |b|, GMRES on A_H for comparison, and the paper's printed
-    values for the same (N, omega, eps)."""
+    paper's vertex counts (642 and 2562; with --bem-large also 10242 and 40962:
+    N = 1,926 / 7,686 / 30,726 / 122,886), the Section 7.1 problem (unit sphere,
+    mu = rho = 1, nu = 1/3, vertical incident P wave, N_leaf = 100, eta-hat = 3),
+    omega = 3 and 14, eps_ACA = eps_LU = 1e-4 and 1e-6, complex128.  Per row: assembly
+    time, maximum ACA / recompressed rank, storage rate, |A_H - A|_F (absolute and
+    relative, entries re-evaluated in FP64), the H-LU solution's estimator I, true
+    residual |b - A x0| / |b| (A x0 by direct FP64 evaluation of every row,
+    hm_exact_rows), |x0| / |b| and delta / |b|, GMRES on A_H for comparison, and the
+    paper's printed values for the same (N, omega, eps)."""
     import torch
     rows = []
-    levels = [4, 5] if large else [4]
+    levels = [3, 4, 5, 6] if large else [3, 4]
     for level in levels:
         for omega in (3.0, 14.0):
             m0 = W.bem_sphere(level, omega=omega)
             P, T = m0.mesh()
             b = torch.from_numpy(W.p_wave(P, omega)).cuda()
-            Hd = hmat.build_mesh(m0, eta=0.0)      # the collocation matrix itself, all dense
+            all_rows = np.arange(P.shape[0])
             for eps in (1e-4, 1e-6):
                 m = W.bem_sphere(level, omega=omega, eps=eps)
                 torch.cuda.synchronize()
@@ -687,7 +657,10 @@ def bem_leg(hmat, W, large=False):
                 torch.cuda.synchronize()
                 t_solve = time.perf_counter() - t0
                 est = H.lu_estimate(b, x, dh)
-                res = float(torch.linalg.vector_norm(Hd.residual(b, x))) / est["b_norm"]
+                tr = time.perf_counter()
+                ax = H.exact_rows(all_rows, x)
+                t_exact = time.perf_counter() - tr
+                res = float(torch.linalg.vector_norm(b - ax)) / est["b_norm"]
                 tg = time.perf_counter()
                 xg, gi = H.gmres(b, tol=eps, restart=100, maxit=5000, check=False)
                 torch.cuda.synchronize()
@@ -703,6 +676,8 @@ def bem_leg(hmat, W, large=False):
                        "x0_over_b": est["x0_norm"] / est["b_norm"],
                        "delta_over_b": est["delta"] / est["b_norm"],
                        "factor_s": round(st["t_factor"], 3), "solve_ms": round(t_solve * 1e3, 2),
+                       "lu_device_GB": round(st["device_bytes"] / 1e9, 2),
+                       "exact_product_s": round(t_exact, 3),
                        "gmres_s": round(t_gmres, 3), "gmres_iters": gi["iters"],
                        "gmres_relres": gi["relres"],
                        "paper_max_rank_aca_rc_eps1e-4": paper.get("ranks"),
@@ -712,10 +687,6 @@ def bem_leg(hmat, W, large=False):
                 F.close()
                 H.close()
                 hmat.release_cache()
-            Hd.close()
-            hmat.release_cache()
-    if large:
-        rows += bem_large_rows(hmat, W)
     return rows
 
 
@@ -738,8 +709,8 @@ def main():
     ap.add_argument("--hlu-large", action="store_true", help="add 10242 points to the H-LU leg")
     ap.add_argument("--no-bem", action="store_true")
     ap.add_argument("--bem-only", action="store_true", help="run the collocation leg alone")
-    ap.add_argument("--bem-large", action="store_true", help="add the 10242-vertex mesh to the "
-                                                             "collocation leg")
+    ap.add_argument("--bem-large", action="store_true", help="add the 10242- and 40962-vertex "
+                                                             "meshes to the collocation leg")
     ap.add_argument("--counters", action="store_true",
                     help="profiling mode: one headline build, the autotuner, 10 matvecs, then a "
                          "256 MiB device copy (x3) whose known byte count calibrates FETCH_SIZE / "

@@ -22,6 +22,7 @@
 #include <chrono>
 #include <cstdlib>
 #include <memory>
+#include <unordered_map>
 #include <vector>
 
 #include "green.hpp"
@@ -375,6 +376,8 @@ struct hm_lu {
     int64_t dofs = 0;
     std::vector<hm::lu::LuNode> nodes;
     hm::Arena keep{size_t(1) << 28};
+    // freed keep memory by size class (bytes), handed out again by keep_alloc
+    std::unordered_map<size_t, std::vector<hm::cplx<double> *>> keep_pool;
     hm::Arena tmp{size_t(1) << 28};   // stack of the caller's stream (factor, solve, export)
     hm::DeviceBuf d_perm, d_zero_rowpad, d_flag;
     hm_lu_stats stats{};
@@ -384,6 +387,26 @@ struct hm_lu {
 
 namespace hm {
 namespace {
+
+// Keep memory that may be freed and reused comes in size classes (the size
+// rounded up to 8 steps per power of two, at least 256 bytes), so that memory
+// freed by one block's recompression serves later requests of the same class.
+size_t keep_class(int64_t n) {
+    const size_t b = std::max<size_t>(256, (size_t)std::max<int64_t>(n, 1) * sizeof(Z));
+    const int e = 63 - __builtin_clzll((unsigned long long)b);
+    const size_t step = std::max<size_t>(256, size_t(1) << std::max(e - 3, 0));
+    return (b + step - 1) / step * step;
+}
+Z *keep_class_alloc(hm_lu &F, int64_t n) {
+    const size_t c = keep_class(n);
+    auto it = F.keep_pool.find(c);
+    if (it != F.keep_pool.end() && !it->second.empty()) {
+        Z *p = it->second.back();
+        it->second.pop_back();
+        return p;
+    }
+    return F.keep.alloc((int64_t)(c / sizeof(Z)));
+}
 
 // Streams the factorisation spreads independent branches over: the caller's
 // stream and up to kLuStreams - 1 more.
@@ -419,7 +442,13 @@ struct GpuBackend {
         Arena::Mark m;
     };
 
-    Z *keep_alloc(int64_t n) { return F.keep.alloc(n); }
+    Z *keep_alloc(int64_t n) { return keep_class_alloc(F, n); }
+    // keep_free is called once no kernel will touch the memory again (after a
+    // truncate, which drains its stream, and every stream that wrote the
+    // memory was joined into that one before), so reuse needs no ordering
+    void keep_free(Z *p, int64_t n) {
+        if (p) F.keep_pool[keep_class(n)].push_back(p);
+    }
     Z *tmp_alloc(int64_t n) { return tmp().alloc(n); }
     Mark tmp_mark() { return {cur, tmp().mark()}; }
     void tmp_release(Mark m) { arena[m.a]->release(m.m); }
@@ -666,7 +695,7 @@ struct GpuBackend {
             need(keep[i] >= 0 && keep[i] <= it.K, "H-LU: recompressed rank out of range");
             it.keep = keep[i];
             if (!it.keep) continue;
-            it.Uout = F.keep.alloc((int64_t)it.m * it.keep);
+            it.Uout = keep_class_alloc(F, (int64_t)it.m * it.keep);
             it.Vrow = tmp().alloc((int64_t)it.n * lu::even(it.keep));
             ou[i] = it.Uout - base;
             ov[i] = it.Vrow - base;
@@ -707,8 +736,8 @@ void import_leaves(hm_lu &F, const hm_matrix *A, const std::vector<std::pair<int
             X.kind = lu::FMT_R;
             X.k = L.r;
             if (L.r > 0) {
-                X.U = F.keep.alloc((int64_t)X.m * L.r);
-                X.W = F.keep.alloc((int64_t)L.r * X.n);
+                X.U = keep_class_alloc(F, (int64_t)X.m * L.r);
+                X.W = keep_class_alloc(F, (int64_t)L.r * X.n);
                 hipLaunchKernelGGL(lu_import_lr_kernel<S>,
                                    dim3(grid_for((int64_t)(X.m + X.n) * L.r)), dim3(256), 0, st,
                                    fac + L.uoff, (int64_t)L.ldu, fac + L.voff, (int64_t)L.ldv, rp,

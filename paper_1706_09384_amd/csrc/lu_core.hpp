@@ -5,6 +5,9 @@
 // recompressions.  Every arithmetic step is delegated to a backend B:
 //
 //   Z *keep_alloc(int64_t n)            memory that lives as long as the factors
+//   void keep_free(Z *p, int64_t n)     keep memory no kernel will touch again
+//                                       (called after a truncate, which ends
+//                                       with its stream drained)
 //   Z *tmp_alloc(int64_t n)             stack memory, released by tmp_release
 //   Mark tmp_mark(); void tmp_release(Mark)
 //   void gemm(DMat C, DMat A, DMat B, Z alpha, bool beta)   C = alpha A B (+ C)
@@ -546,6 +549,19 @@ struct Core {
             items.push_back(it);
         }
         be.truncate(items, eps);
+        // the superseded factors and the pieces were last read by the copies and
+        // products queued before the truncate: their memory goes back to the backend
+        for (int x : q) {
+            LuNode &X = N[x];
+            if (X.k) {
+                be.keep_free(X.U, (int64_t)X.m * X.k);
+                be.keep_free(X.W, (int64_t)X.k * X.n);
+            }
+            for (const Piece &p : X.pend) {
+                be.keep_free(p.U, (int64_t)p.mp * p.k);
+                be.keep_free(p.W, (int64_t)p.k * p.np);
+            }
+        }
         for (size_t i = 0; i < q.size(); ++i) {
             LuNode &X = N[q[i]];
             const RcItem &it = items[i];

@@ -53,6 +53,19 @@ struct CpuBackend {
         return p;
     }
     Z *keep_alloc(int64_t n) { return make(n); }
+    // freed keep memory is poisoned and marked dead, never reused: a later view
+    // into it is reported
+    void keep_free(Z *p, int64_t n) {
+        for (Alloc &a : reg)
+            if (a.lo == p) {
+                if (!a.live) throw std::runtime_error("keep memory freed twice");
+                if (a.n != n) throw std::runtime_error("keep memory freed with another size");
+                a.live = false;
+                for (int64_t i = 0; i < n; ++i) p[i] = Z{std::nan(""), std::nan("")};
+                return;
+            }
+        throw std::runtime_error("keep_free of memory that was never allocated");
+    }
     Z *tmp_alloc(int64_t n) {
         Z *p = make(n);
         tmp_stack.push_back(reg.size() - 1);
@@ -80,7 +93,7 @@ struct CpuBackend {
         const Z *lo = v.p, *hi = v.p + (v.m - 1) * v.rs + (v.n - 1) * v.cs;
         for (const Alloc &a : reg)
             if (lo >= a.lo && hi < a.lo + a.n) {
-                if (!a.live) throw std::runtime_error(std::string(what) + ": view into released stack memory");
+                if (!a.live) throw std::runtime_error(std::string(what) + ": view into released memory");
                 return;
             }
         throw std::runtime_error(std::string(what) + ": view outside every allocation");
