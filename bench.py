@@ -616,6 +616,13 @@ PAPER_BEM = {
                   1e-6: (3.25e-15, 3.64e-15, 9.16e-17, 6.4, 2.66e-15)},
     (1926, 14.0): {1e-4: (5.69e-15, 4.69e-15, 7.16e-17, 29.29, 3.59e-15),
                    1e-6: (5.69e-15, 4.69e-15, 7.16e-17, 29.29, 3.59e-15)},
+    # fixed density of points per S-wavelength (Table table_corr; Table error_dens_single)
+    (1926, 4.0): {1e-4: (3.12e-15, 3.42e-15, 9.07e-17, 8.37, 2.36e-15),
+                  1e-6: (3.12e-15, 3.42e-15, 9.07e-17, 8.37, 2.36e-15)},
+    (7686, 8.25): {1e-4: (1.73e-3, 4.28e-5, 1.02e-4, 16.83, 2.23e-5),
+                   1e-6: (1.79e-5, 2.61e-7, 1.06e-6, 16.83, 9.63e-8)},
+    (30726, 16.5): {1e-4: (6.42e-3, 1.68e-4, 1.94e-4, 32.66, 7.04e-5),
+                    1e-6: (7.14e-5, 1.36e-6, 2.18e-6, 32.66, 2.93e-7)},
 }
 
 
@@ -624,7 +631,8 @@ def bem_leg(hmat, W, large=False):
     paper's vertex counts (642 and 2562; with --bem-large also 10242 and 40962:
     N = 1,926 / 7,686 / 30,726 / 122,886), the Section 7.1 problem (unit sphere,
     mu = rho = 1, nu = 1/3, vertical incident P wave, N_leaf = 100, eta-hat = 3),
-    omega = 3 and 14, eps_ACA = eps_LU = 1e-4 and 1e-6, complex128.  Per row: assembly
+    omega = 3 and 14 and the fixed density of Section 8 (omega = 4, 8.25, 16.5),
+    eps_ACA = eps_LU = 1e-4 and 1e-6, complex128.  Per row: assembly
     time, maximum ACA / recompressed rank, storage rate, |A_H - A|_F (absolute and
     relative, entries re-evaluated in FP64), the H-LU solution's estimator I, true
     residual |b - A x0| / |b| (A x0 by direct FP64 evaluation of every row,
@@ -633,60 +641,64 @@ def bem_leg(hmat, W, large=False):
     import torch
     rows = []
     levels = [3, 4, 5, 6] if large else [3, 4]
-    for level in levels:
-        for omega in (3.0, 14.0):
-            m0 = W.bem_sphere(level, omega=omega)
-            P, T = m0.mesh()
-            b = torch.from_numpy(W.p_wave(P, omega)).cuda()
-            all_rows = np.arange(P.shape[0])
-            for eps in (1e-4, 1e-6):
-                m = W.bem_sphere(level, omega=omega, eps=eps)
-                torch.cuda.synchronize()
-                tb = time.perf_counter()
-                H = hmat.build_mesh(m)
-                torch.cuda.synchronize()
-                t_build = time.perf_counter() - tb
-                info = H.info()
-                dh, af = H.frob_error()
-                F = H.lu(eps)
-                st = F.stats()
-                x = F.solve(b)
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                x = F.solve(b)
-                torch.cuda.synchronize()
-                t_solve = time.perf_counter() - t0
-                est = H.lu_estimate(b, x, dh)
-                tr = time.perf_counter()
-                ax = H.exact_rows(all_rows, x)
-                t_exact = time.perf_counter() - tr
-                res = float(torch.linalg.vector_norm(b - ax)) / est["b_norm"]
-                tg = time.perf_counter()
-                xg, gi = H.gmres(b, tol=eps, restart=100, maxit=5000, check=False)
-                torch.cuda.synchronize()
-                t_gmres = time.perf_counter() - tg
-                n = 3 * P.shape[0]
-                paper = PAPER_BEM.get((n, omega), {})
-                rec = {"level": level, "N_c": P.shape[0], "dofs": n, "omega": omega, "eps": eps,
-                       "assembly_s": round(t_build, 3),
-                       "max_rank_aca": info["max_rank_aca"], "max_rank": info["max_rank"],
-                       "storage_rate": round((info["dense_entries"] + info["lowrank_entries"]) / n**2, 4),
-                       "delta_HF_abs": dh, "delta_HF_rel": dh / af,
-                       "I_estimate": est["estimate"], "residual_true": res,
-                       "x0_over_b": est["x0_norm"] / est["b_norm"],
-                       "delta_over_b": est["delta"] / est["b_norm"],
-                       "factor_s": round(st["t_factor"], 3), "solve_ms": round(t_solve * 1e3, 2),
-                       "lu_device_GB": round(st["device_bytes"] / 1e9, 2),
-                       "exact_product_s": round(t_exact, 3),
-                       "gmres_s": round(t_gmres, 3), "gmres_iters": gi["iters"],
-                       "gmres_relres": gi["relres"],
-                       "paper_max_rank_aca_rc_eps1e-4": paper.get("ranks"),
-                       "paper_I_res_dHF_x0b_db": paper.get(eps)}
-                rows.append(rec)
-                log(f"[bench] bem {rec}")
-                F.close()
-                H.close()
-                hmat.release_cache()
+    # fixed frequencies 3 and 14 (Section 7), and the fixed density of Section 8
+    # (omega = 4, 8.25, 16.5 on the 642-, 2562- and 10242-vertex meshes)
+    dens = {3: 4.0, 4: 8.25, 5: 16.5}
+    cases = [(lv, om) for lv in levels for om in (3.0, 14.0)]
+    cases += [(lv, dens[lv]) for lv in levels if lv in dens]
+    for level, omega in cases:
+        m0 = W.bem_sphere(level, omega=omega)
+        P, T = m0.mesh()
+        b = torch.from_numpy(W.p_wave(P, omega)).cuda()
+        all_rows = np.arange(P.shape[0])
+        for eps in (1e-4, 1e-6):
+            m = W.bem_sphere(level, omega=omega, eps=eps)
+            torch.cuda.synchronize()
+            tb = time.perf_counter()
+            H = hmat.build_mesh(m)
+            torch.cuda.synchronize()
+            t_build = time.perf_counter() - tb
+            info = H.info()
+            dh, af = H.frob_error()
+            F = H.lu(eps)
+            st = F.stats()
+            x = F.solve(b)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            x = F.solve(b)
+            torch.cuda.synchronize()
+            t_solve = time.perf_counter() - t0
+            est = H.lu_estimate(b, x, dh)
+            tr = time.perf_counter()
+            ax = H.exact_rows(all_rows, x)
+            t_exact = time.perf_counter() - tr
+            res = float(torch.linalg.vector_norm(b - ax)) / est["b_norm"]
+            tg = time.perf_counter()
+            xg, gi = H.gmres(b, tol=eps, restart=100, maxit=5000, check=False)
+            torch.cuda.synchronize()
+            t_gmres = time.perf_counter() - tg
+            n = 3 * P.shape[0]
+            paper = PAPER_BEM.get((n, omega), {})
+            rec = {"level": level, "N_c": P.shape[0], "dofs": n, "omega": omega, "eps": eps,
+                   "assembly_s": round(t_build, 3),
+                   "max_rank_aca": info["max_rank_aca"], "max_rank": info["max_rank"],
+                   "storage_rate": round((info["dense_entries"] + info["lowrank_entries"]) / n**2, 4),
+                   "delta_HF_abs": dh, "delta_HF_rel": dh / af,
+                   "I_estimate": est["estimate"], "residual_true": res,
+                   "x0_over_b": est["x0_norm"] / est["b_norm"],
+                   "delta_over_b": est["delta"] / est["b_norm"],
+                   "factor_s": round(st["t_factor"], 3), "solve_ms": round(t_solve * 1e3, 2),
+                   "lu_device_GB": round(st["device_bytes"] / 1e9, 2),
+                   "exact_product_s": round(t_exact, 3),
+                   "gmres_s": round(t_gmres, 3), "gmres_iters": gi["iters"],
+                   "gmres_relres": gi["relres"],
+                   "paper_max_rank_aca_rc_eps1e-4": paper.get("ranks"),
+                   "paper_I_res_dHF_x0b_db": paper.get(eps)}
+            rows.append(rec)
+            log(f"[bench] bem {rec}")
+            F.close()
+            H.close()
+            hmat.release_cache()
     return rows
 
 
