@@ -5,9 +5,12 @@ used for device memory (tensor data pointers) and streams.  If the shared
 library is missing the import of this module raises -- there is no fallback.
 
 Names mirror the C ABI in ``include/hmat.h``: :func:`build` (hm_build),
+:func:`build_colloc` (hm_build_colloc, the P1 collocation operator),
 :meth:`HMatrix.matvec` (hm_matvec), :meth:`HMatrix.residual` (hm_residual),
-:meth:`HMatrix.gmres` (hm_gmres), :meth:`HMatrix.info` (hm_info), exports and
-the rank-model calls.
+:meth:`HMatrix.gmres` (hm_gmres), :meth:`HMatrix.info` (hm_info),
+:meth:`HMatrix.exact_rows` (hm_exact_rows), :meth:`HMatrix.lu` (hm_lu_factor,
+with :class:`HLU` for the solve), :meth:`HMatrix.frob_error`,
+:meth:`HMatrix.lu_estimate`, exports and the rank-model calls.
 """
 from __future__ import annotations
 
