@@ -699,7 +699,46 @@ def bem_leg(hmat, W, large=False):
             F.close()
             H.close()
             hmat.release_cache()
+    if large:
+        # the next fixed-density point (omega = 33 on the 40962-vertex mesh), operator only
+        rows.append(bem_operator_row(hmat, W, 6, 33.0))
     return rows
+
+
+def bem_operator_row(hmat, W, level, omega):
+    """A collocation operator without the direct solver: ranks, storage, |A_H - A|_F,
+    and GMRES on the P wave with the true residual of its x (A x by direct FP64
+    evaluation of every row)."""
+    import torch
+    m = W.bem_sphere(level, omega=omega)
+    P, T = m.mesh()
+    b = torch.from_numpy(W.p_wave(P, m.omega)).cuda()
+    torch.cuda.synchronize()
+    tb = time.perf_counter()
+    H = hmat.build_mesh(m)
+    torch.cuda.synchronize()
+    t_build = time.perf_counter() - tb
+    info = H.info()
+    dh, af = H.frob_error()
+    tg = time.perf_counter()
+    xg, gi = H.gmres(b, tol=1e-6, restart=100, maxit=5000, check=False)
+    torch.cuda.synchronize()
+    t_gmres = time.perf_counter() - tg
+    ax = H.exact_rows(np.arange(P.shape[0]), xg)
+    n = 3 * P.shape[0]
+    rec = {"level": level, "N_c": P.shape[0], "dofs": n, "omega": m.omega, "eps": m.eps,
+           "assembly_s": round(t_build, 3), "max_rank_aca": info["max_rank_aca"],
+           "max_rank": info["max_rank"],
+           "storage_rate": round((info["dense_entries"] + info["lowrank_entries"]) / n**2, 5),
+           "delta_HF_abs": dh, "delta_HF_rel": dh / af,
+           "x_over_b_gmres": float(torch.linalg.vector_norm(xg) / torch.linalg.vector_norm(b)),
+           "residual_true_gmres": float(torch.linalg.vector_norm(b - ax) / torch.linalg.vector_norm(b)),
+           "gmres_s": round(t_gmres, 3), "gmres_iters": gi["iters"], "gmres_relres": gi["relres"],
+           "operator_only": True}
+    log(f"[bench] bem {rec}")
+    H.close()
+    hmat.release_cache()
+    return rec
 
 
 def main():
