@@ -170,3 +170,14 @@ def test_scattering_solve_gmres_and_hlu(hm, bem):
     say("H-LU estimate", est, "true residual", res, "|x0 - x| / |x|", rel(x0, xd))
     assert res <= est["estimate"]
     assert rel(x0, xd) <= 1e-3
+
+
+def test_device_pointer_inputs_match_host(hm):
+    """nodes and tri passed as device arrays (points_on_host = 0) build the same operator."""
+    import torch
+    P, T = W.icosphere(2)
+    say("case bem device pointers")
+    H0 = hm.build_colloc(P, T, omega=3.0, leaf=16)
+    H1 = hm.build_colloc(torch.from_numpy(P).cuda(), torch.from_numpy(T).cuda(), omega=3.0, leaf=16)
+    D0, D1 = densify(H0), densify(H1)
+    assert np.array_equal(D0, D1)
