@@ -22,7 +22,7 @@
 #include <chrono>
 #include <cstdlib>
 #include <memory>
-#include <unordered_map>
+#include <map>
 #include <vector>
 
 #include "green.hpp"
@@ -377,7 +377,7 @@ struct hm_lu {
     std::vector<hm::lu::LuNode> nodes;
     hm::Arena keep{size_t(1) << 28};
     // freed keep memory by size class (bytes), handed out again by keep_alloc
-    std::unordered_map<size_t, std::vector<hm::cplx<double> *>> keep_pool;
+    std::map<size_t, std::vector<hm::cplx<double> *>> keep_pool;
     hm::Arena tmp{size_t(1) << 28};   // stack of the caller's stream (factor, solve, export)
     hm::DeviceBuf d_perm, d_zero_rowpad, d_flag;
     hm_lu_stats stats{};
@@ -397,14 +397,17 @@ size_t keep_class(int64_t n) {
     const size_t step = std::max<size_t>(256, size_t(1) << std::max(e - 3, 0));
     return (b + step - 1) / step * step;
 }
+// The smallest freed block of class c to 2c serves a request of class c (a
+// larger block goes back under the class of the request it served: it is
+// then only handed out for requests it covers).
 Z *keep_class_alloc(hm_lu &F, int64_t n) {
     const size_t c = keep_class(n);
-    auto it = F.keep_pool.find(c);
-    if (it != F.keep_pool.end() && !it->second.empty()) {
-        Z *p = it->second.back();
-        it->second.pop_back();
-        return p;
-    }
+    for (auto it = F.keep_pool.lower_bound(c); it != F.keep_pool.end() && it->first <= 2 * c; ++it)
+        if (!it->second.empty()) {
+            Z *p = it->second.back();
+            it->second.pop_back();
+            return p;
+        }
     return F.keep.alloc((int64_t)(c / sizeof(Z)));
 }
 

@@ -498,7 +498,30 @@ struct Core {
     }
     // [U, pieces] [W; pieces] -> U' W' at eps_LU.  A block whose stacked
     // factors hold more columns than its rank can be is first summed densely.
+    // Stack memory one recompression batch may take (stacked factors, or the
+    // dense sum, and the core workspace); larger lists run as several batches.
+    int64_t batch_bytes = int64_t(8) << 30;
     void recompress(const std::vector<int> &q) {
+        size_t i0 = 0;
+        int64_t acc = 0;
+        for (size_t i = 0; i < q.size(); ++i) {
+            const LuNode &X = N[q[i]];
+            int64_t K = X.k;
+            for (const Piece &p : X.pend) K += p.k;
+            const int64_t Ke = std::min<int64_t>(K, std::min(X.m, X.n));
+            const int64_t b = (int64_t)sizeof(Z) * (K > Ke ? (int64_t)X.m * X.n + (X.m + X.n) * Ke
+                                                           : (X.m + X.n) * K) +
+                              (int64_t)sizeof(double) * (8 * Ke * Ke + 2 * Ke);
+            if (i > i0 && acc + b > batch_bytes) {
+                recompress_batch(std::vector<int>(q.begin() + i0, q.begin() + i));
+                i0 = i;
+                acc = 0;
+            }
+            acc += b;
+        }
+        recompress_batch(std::vector<int>(q.begin() + i0, q.end()));
+    }
+    void recompress_batch(const std::vector<int> &q) {
         const auto mk = be.tmp_mark();
         std::vector<RcItem> items;
         for (int x : q) {

@@ -260,6 +260,8 @@ int main(int argc, char **argv) {
         std::vector<Z> b(dofs);
         rd(f, b.data(), dofs);
         Core<CpuBackend> core(be, N, eps);
+        // one block per recompression batch: the split of a batch is exercised
+        if (std::getenv("LU_CPU_SMALL_BATCHES")) core.batch_bytes = 1;
         core.hlu(0);
         DMat P = cm(be.keep_alloc(dofs * dofs), (int32_t)dofs, (int32_t)dofs, dofs);
         core.densify(0, P);

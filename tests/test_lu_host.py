@@ -69,8 +69,12 @@ def run_lu_cpu(exe, tmp, t, blocks, leaves, b, eps=0.0):
     return P, x, stats
 
 
-@pytest.mark.parametrize("kernel", [W.KERNEL_U, W.KERNEL_T])
-def test_host_logic_exact_lu_in_bounds(orc, lu_cpu, tmp_path, kernel):
+@pytest.mark.parametrize("kernel,small", [(W.KERNEL_U, False), (W.KERNEL_T, False), (W.KERNEL_U, True)])
+def test_host_logic_exact_lu_in_bounds(orc, lu_cpu, tmp_path, kernel, small, monkeypatch):
+    """small: every recompression list split into batches of one block (the split a
+    stack-memory budget makes on large problems)."""
+    if small:
+        monkeypatch.setenv("LU_CPU_SMALL_BATCHES", "1")
     import sys
     sys.path.insert(0, HERE)
     from test_oracle_hlu import svd_leaves
@@ -86,6 +90,8 @@ def test_host_logic_exact_lu_in_bounds(orc, lu_cpu, tmp_path, kernel):
     P, x, stats = run_lu_cpu(lu_cpu, tmp_path, t, blocks, leaves, b)
     n_rec, n_batch, n_gemm, n_diag = stats
     assert n_rec > 100 and n_batch > 10 and n_diag == sum(1 for a, c, k in blocks if a == c)
+    if small:
+        assert n_batch == n_rec
     L = np.tril(P, -1) + np.eye(P.shape[0])
     U = np.triu(P)
     assert np.linalg.norm(L @ U - AH) <= 1e-13 * np.linalg.norm(AH)
