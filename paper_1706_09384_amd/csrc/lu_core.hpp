@@ -61,11 +61,15 @@ struct DMat {
 };
 inline DMat cm(Z *p, int32_t m, int32_t n, int64_t ld) { return {p, 1, ld, m, n}; }
 
-// A sum waiting in a low-rank block: U (mp x k) W (k x np), column-major, at
-// rows ro.., columns co.. of the block.
+// A sum waiting in a low-rank block: U (mp x k, column stride ldu) W (k x np,
+// column stride k), at rows ro.., columns co.. of the block.  A factor of a
+// finished block (never written again) is referenced rather than copied:
+// own_u / own_w say which parts the piece owns.
 struct Piece {
     Z *U, *W;
     int32_t k, ro, co, mp, np;
+    int64_t ldu;
+    bool own_u, own_w;
 };
 
 enum : int32_t { FMT_F = 0, FMT_R = 1, FMT_H = 2 };
@@ -233,8 +237,11 @@ struct Core {
     }
 
     // --------------------------------------------------- formatted sums
-    // C[ro:, co:] += alpha U W (C an F or R block, or a whole H block)
-    void add_lowrank(int c, int32_t ro, int32_t co, DMat U, DMat W, Z alpha) {
+    // C[ro:, co:] += alpha U W (C an F or R block, or a whole H block).  share:
+    // 'U' when U is a finished factor's U (column-major view, kept by
+    // reference), 'W' when W is a finished factor's W (column stride W.m, kept
+    // by reference), 0 when both are temporaries (copied).
+    void add_lowrank(int c, int32_t ro, int32_t co, DMat U, DMat W, Z alpha, char share = 0) {
         LuNode &C = N[c];
         need(ro >= 0 && co >= 0 && ro + U.m <= C.m && co + W.n <= C.n && U.n == W.m,
              "H-LU: low-rank sum outside its block");
@@ -242,16 +249,36 @@ struct Core {
         if (C.kind == FMT_F) {
             gemm(dview(C).sub(ro, co, U.m, W.n), U, W, alpha, true);
         } else if (C.kind == FMT_R) {
-            DMat Up = keepmat(U.m, U.n), Wp = keepmat(W.m, W.n);
-            copy(Up, U, alpha, false, false);
-            copy(Wp, W, Z{1, 0}, false, false);
-            C.pend.push_back({Up.p, Wp.p, U.n, ro, co, U.m, W.n});
+            Piece p{nullptr, nullptr, U.n, ro, co, U.m, W.n, U.m, true, true};
+            if (share == 'U') {
+                need(U.rs == 1, "H-LU: shared U not column-major");
+                p.U = U.p;
+                p.ldu = U.cs;
+                p.own_u = false;
+                DMat Wp = keepmat(W.m, W.n);
+                copy(Wp, W, alpha, false, false);
+                p.W = Wp.p;
+            } else if (share == 'W') {
+                need(W.rs == 1 && W.cs == W.m, "H-LU: shared W not packed column-major");
+                p.W = W.p;
+                p.own_w = false;
+                DMat Up = keepmat(U.m, U.n);
+                copy(Up, U, alpha, false, false);
+                p.U = Up.p;
+            } else {
+                DMat Up = keepmat(U.m, U.n), Wp = keepmat(W.m, W.n);
+                copy(Up, U, alpha, false, false);
+                copy(Wp, W, Z{1, 0}, false, false);
+                p.U = Up.p;
+                p.W = Wp.p;
+            }
+            C.pend.push_back(p);
         } else {
             need(ro == 0 && co == 0 && U.m == C.m && W.n == C.n, "H-LU: partial sum into H");
             for (int i = 0; i < C.nr; ++i)
                 for (int j = 0; j < C.nc; ++j)
                     add_lowrank(C.ch[i][j], 0, 0, U.sub(C.rofs[i], 0, C.rsz[i], U.n),
-                                W.sub(0, C.cofs[j], W.m, C.csz[j]), alpha);
+                                W.sub(0, C.cofs[j], W.m, C.csz[j]), alpha, share);
         }
     }
     // C[ro:, co:] += alpha D
@@ -265,7 +292,7 @@ struct Core {
             DMat Up = keepmat(D.m, D.n), Wp = keepmat(D.n, D.n);
             copy(Up, D, alpha, false, false);
             fill(Wp, Z{1, 0});
-            C.pend.push_back({Up.p, Wp.p, D.n, ro, co, D.m, D.n});
+            C.pend.push_back({Up.p, Wp.p, D.n, ro, co, D.m, D.n, D.m, true, true});
         } else {
             need(ro == 0 && co == 0 && D.m == C.m && D.n == C.n, "H-LU: partial sum into H");
             for (int i = 0; i < C.nr; ++i)
@@ -282,14 +309,14 @@ struct Core {
             const auto mk = be.tmp_mark();
             DMat Wn = tmpmat(A.k, Bn.n, true);
             matmat_right(wview(A), b, Wn, Z{1, 0});
-            add_lowrank(c, ro, co, uview(A), Wn, alpha);
+            add_lowrank(c, ro, co, uview(A), Wn, alpha, 'U');   // A is a finished factor
             be.tmp_release(mk);
         } else if (Bn.kind == FMT_R) {
             if (Bn.k == 0) return;
             const auto mk = be.tmp_mark();
             DMat Un = tmpmat(A.m, Bn.k, true);
             matmat(a, uview(Bn), Un, Z{1, 0});
-            add_lowrank(c, ro, co, Un, wview(Bn), alpha);
+            add_lowrank(c, ro, co, Un, wview(Bn), alpha, 'W');   // so is B
             be.tmp_release(mk);
         } else if (A.kind == FMT_F && Bn.kind == FMT_F) {
             if (N[c].kind == FMT_F) {
@@ -534,7 +561,7 @@ struct Core {
                 DMat D = tmpmat(X.m, X.n, true);
                 if (X.k) gemm(D, uview(X), wview(X), Z{1, 0}, true);
                 for (const Piece &p : X.pend)
-                    gemm(D.sub(p.ro, p.co, p.mp, p.np), cm(p.U, p.mp, p.k, p.mp),
+                    gemm(D.sub(p.ro, p.co, p.mp, p.np), cm(p.U, p.mp, p.k, p.ldu),
                          cm(p.W, p.k, p.np, p.k), Z{1, 0}, true);
                 if (X.n <= X.m) {
                     Uc = D;
@@ -557,7 +584,7 @@ struct Core {
                     k0 = X.k;
                 }
                 for (const Piece &p : X.pend) {
-                    copy(Uc.sub(p.ro, k0, p.mp, p.k), cm(p.U, p.mp, p.k, p.mp), Z{1, 0}, false, false);
+                    copy(Uc.sub(p.ro, k0, p.mp, p.k), cm(p.U, p.mp, p.k, p.ldu), Z{1, 0}, false, false);
                     copy(Vc.sub(p.co, k0, p.np, p.k), DMat{p.W, p.k, 1, p.np, p.k}, Z{1, 0}, true,
                          false);
                     k0 += p.k;
@@ -581,8 +608,8 @@ struct Core {
                 be.keep_free(X.W, (int64_t)X.k * X.n);
             }
             for (const Piece &p : X.pend) {
-                be.keep_free(p.U, (int64_t)p.mp * p.k);
-                be.keep_free(p.W, (int64_t)p.k * p.np);
+                if (p.own_u) be.keep_free(p.U, (int64_t)p.mp * p.k);
+                if (p.own_w) be.keep_free(p.W, (int64_t)p.k * p.np);
             }
         }
         for (size_t i = 0; i < q.size(); ++i) {
