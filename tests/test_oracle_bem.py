@@ -165,3 +165,15 @@ def test_p_wave_rhs():
     P, _ = W.icosphere(1)
     b = W.p_wave(P, 3.0).reshape(-1, 3)
     assert np.allclose(b[:, :2], 0) and np.allclose(b[:, 2], np.exp(1.5j * P[:, 2]))
+
+
+def test_rule_orders_converge(bem):
+    """Raising the regular and singular orders changes the matrix less and less:
+    the default (3, 6) is within 1e-3 of (8, 16) on a coarse mesh, and (5, 10)
+    is closer still (a rule mis-assembled for one of the two cases would not
+    converge)."""
+    P, T = W.icosphere(1)
+    ref = bem.collocation_matrix(P, T, 3.0, q_reg=8, q_sing=16)
+    e = [np.abs(bem.collocation_matrix(P, T, 3.0, q_reg=qr, q_sing=qs) - ref).max() / np.abs(ref).max()
+         for qr, qs in ((3, 6), (5, 10))]
+    assert e[0] <= 1e-3 and e[1] <= 0.2 * e[0]
