@@ -6,8 +6,9 @@
 // stream: every block of the factors is dense (F, column-major), low-rank
 // (R, U W with W = V^*, both column-major) or subdivided (H).  The device
 // work is
-//   * dense diagonal leaves: elimination without pivoting plus the inverses
-//     of both triangular factors, in one workgroup (lu_getrf_inv_kernel);
+//   * dense diagonal leaves: elimination without pivoting in one workgroup
+//     (lu_getrf_kernel), then the inverses of both triangular factors, one
+//     column per thread over several workgroups (lu_trinv_kernel);
 //   * every product (block substitutions against a diagonal leaf are
 //     products with its inverse factors, low-rank products, dense updates):
 //     a strided complex FP64 matrix-core GEMM (lu_gemm_kernel);
@@ -247,11 +248,9 @@ __global__ void lu_import_lr_kernel(const cplx<S> *__restrict__ U, int64_t ldu,
 }
 
 // In place: A (n x n, column-major) = L \ U by elimination without pivoting
-// (unit lower L), then Linv = L^-1 and Uinv = U^-1 by substitution, one
-// column per thread.  One workgroup.
-__global__ void __launch_bounds__(1024) lu_getrf_inv_kernel(Z *__restrict__ A, Z *__restrict__ Linv,
-                                                            Z *__restrict__ Uinv, int32_t n,
-                                                            int32_t *__restrict__ zero_pivot) {
+// (unit lower L).  One workgroup.
+__global__ void __launch_bounds__(1024) lu_getrf_kernel(Z *__restrict__ A, int32_t n,
+                                                        int32_t *__restrict__ zero_pivot) {
     const int tid = threadIdx.x, nt = blockDim.x;
     for (int k = 0; k < n; ++k) {
         const Z piv = A[k + (int64_t)k * n];
@@ -271,7 +270,16 @@ __global__ void __launch_bounds__(1024) lu_getrf_inv_kernel(Z *__restrict__ A, Z
         }
         __syncthreads();
     }
-    for (int j = tid; j < n; j += nt) {
+}
+
+// Linv = L^-1 (blockIdx.y = 0) and Uinv = U^-1 (blockIdx.y = 1) of the
+// factored A by substitution, one column per thread, the columns spread over
+// workgroups of 64.  (After a zero pivot the host discards the result.)
+__global__ void __launch_bounds__(64) lu_trinv_kernel(const Z *__restrict__ A, Z *__restrict__ Linv,
+                                                      Z *__restrict__ Uinv, int32_t n) {
+    const int j = blockIdx.x * 64 + threadIdx.x;
+    if (j >= n) return;
+    if (blockIdx.y == 0) {
         Z *x = Linv + (int64_t)j * n;
         for (int i = 0; i < j; ++i) x[i] = Z{0, 0};
         x[j] = Z{1, 0};
@@ -280,6 +288,7 @@ __global__ void __launch_bounds__(1024) lu_getrf_inv_kernel(Z *__restrict__ A, Z
             for (int k = j; k < i; ++k) fma_(s, A[i + (int64_t)k * n], x[k]);
             x[i] = Z{-s.re, -s.im};
         }
+    } else {
         Z *y = Uinv + (int64_t)j * n;
         for (int i = j + 1; i < n; ++i) y[i] = Z{0, 0};
         for (int i = j; i >= 0; --i) {
@@ -648,8 +657,9 @@ struct GpuBackend {
         HM_HIP_CHECK(hipGetLastError());
     }
     void getrf_inv(Z *D, Z *Linv, Z *Uinv, int32_t n) {
-        hipLaunchKernelGGL(lu_getrf_inv_kernel, dim3(1), dim3(1024), 0, st, D, Linv, Uinv, n,
-                           F.d_flag.as<int32_t>());
+        hipLaunchKernelGGL(lu_getrf_kernel, dim3(1), dim3(1024), 0, st, D, n, F.d_flag.as<int32_t>());
+        hipLaunchKernelGGL(lu_trinv_kernel, dim3((unsigned)ceil_div(n, 64), 2), dim3(64), 0, st, D, Linv,
+                           Uinv, n);
         HM_HIP_CHECK(hipGetLastError());
     }
     // Every item through run_recompress / run_recompress_apply (offsets
